@@ -1,0 +1,218 @@
+"""Benchmark of the IQP Monte Carlo expectation-value hot path on one MI355X.
+
+A step is one pass of the whole path over one batch of synthetic input that is
+already resident in HBM: the forward estimate (parity bits, phase
+contraction, cos / mean / standard error) and the hand-written backward
+(gradient of a loss of the estimates), i.e. iqp_expval + iqp_expval_grad.
+The MMD workload's step is iqp_mmd_loss_grad (loss and gradient).
+
+Prints ONE JSON line. The metric is phase terms per second, T = l * s * m
+(observables x samples x gates) per step divided by the step time; the
+headline value is split-BF16 fwd+bwd. Results are checked against the FP64
+oracle on sampled observables before the number is printed.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg4]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "phase terms/s (ops×samples×gates), fwd & fwd+bwd, split-BF16 vs FP32 at tol"
+PEAK = {"split_bf16": (2.5e15, 4.0), "fp32": (157.3e12, 2.0)}  # (peak flop/s, MFMA flop/term)
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    import workloads as W
+    if name == "cfg2":
+        return W.cfg2()
+    if name == "cfg3":
+        return W.cfg3()
+    if name == "cfg4":
+        return W.cfg4()
+    raise SystemExit("unknown workload %s" % name)
+
+
+class DevWorkload:
+    """A workload packed into the library's bit rows and moved to the GPU."""
+
+    def __init__(self, w):
+        import torch
+        import workloads as W
+        from paper_2501_04776_amd import packing
+
+        def rows(r):
+            return torch.from_numpy(packing.pack_index_rows(r.ptr, r.idx, w.n)
+                                    .view(np.int64)).cuda()
+
+        def dense(b):
+            return torch.from_numpy(packing.pack_dense(b).view(np.int64)).cuda()
+
+        self.gens = rows(w.gates)
+        self.theta = torch.from_numpy(w.theta).cuda()
+        self.ops = rows(w.ops)
+        self.samples = dense(w.samples)
+        self.data = dense(w.data) if w.data is not None else None
+        self.op_weight = torch.from_numpy(w.op_weight).cuda() if w.op_weight is not None else None
+        self.ops01 = W.rows_to_dense(w.ops, w.n)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-sample-ops", type=int, default=0,
+                    help="observables in the oracle's timed sample (0 = choose)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2501_04776_amd import api
+
+    t0 = time.time()
+    w = make_workload(args.workload)
+    dw = DevWorkload(w)
+    circ = api.Circuit(w.n, dw.gens, dw.theta)
+    T = w.terms
+    mmd = args.workload == "cfg4"
+    log("workload %s: n=%d m=%d l=%d s=%d T=%.4g (setup %.1fs)" % (w.name, w.n, w.m, w.l, w.s, T,
+                                                                   time.time() - t0))
+    u = torch.from_numpy(np.random.default_rng(7).normal(size=w.l) / w.l).cuda()
+
+    def step(prec, fwd_only=False):
+        if mmd:
+            return api.iqp_mmd_loss_grad(circ, dw.ops, dw.op_weight, dw.samples, dw.data, True,
+                                         not fwd_only, prec)
+        mean, se, ph = api.iqp_expval(circ, dw.ops, dw.samples, prec, phase_save=not fwd_only)
+        if fwd_only:
+            return mean, se
+        g = api.iqp_expval_grad(circ, dw.ops, dw.samples, u, ph, prec)
+        return mean, se, g
+
+    def timed(prec, fwd_only=False, steps=args.steps, warmup=args.warmup):
+        for _ in range(warmup):
+            step(prec, fwd_only)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            step(prec, fwd_only)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    def kernel_breakdown(prec, steps):
+        api.profile_reset()
+        api.profile_enable(True)
+        for _ in range(steps):
+            step(prec)
+        torch.cuda.synchronize()
+        out = {}
+        for name in ("parity", "theta_prep", "phase_fwd", "phase_epilogue", "finalize",
+                     "weights", "phase_bwd", "grad_reduce", "mmd"):
+            ms, n = api.profile_query(name)
+            if n:
+                out[name] = {"avg_ms": ms / n, "launches": n, "ms_per_step": ms / steps}
+        api.profile_enable(False)
+        return out
+
+    result = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+              "data": "synthetic"}
+
+    # --- headline: split-BF16 fwd+bwd -------------------------------------
+    ms = timed("split_bf16")
+    ms_fwd = timed("split_bf16", fwd_only=True)
+    log("split_bf16: fwd+bwd %.3f ms, fwd %.3f ms" % (ms, ms_fwd))
+    result["value"] = T / (ms * 1e-3)
+    result["unit"] = "terms/s"
+    result["ms_per_step"] = ms
+    result["fwd_terms_per_s"] = T / (ms_fwd * 1e-3)
+    result["fwd_ms"] = ms_fwd
+
+    kb = kernel_breakdown("split_bf16", max(3, min(args.steps, 10)))
+    result["kernels"] = kb
+    dom = max(("phase_fwd", "phase_bwd"), key=lambda k: kb.get(k, {}).get("avg_ms", 0.0))
+    peak, flop_per_term = PEAK["split_bf16"]
+    achieved = flop_per_term * T / (kb[dom]["avg_ms"] * 1e-3)
+    result["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12,
+                          "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+                          "traffic": None,
+                          "flops_per_launch": flop_per_term * T,
+                          "avg_launch_ms": kb[dom]["avg_ms"]}
+
+    # --- FP32 path ----------------------------------------------------------
+    if not args.no_fp32:
+        ms32 = timed("fp32", steps=max(3, args.steps // 4), warmup=2)
+        ms32f = timed("fp32", fwd_only=True, steps=max(3, args.steps // 4), warmup=1)
+        log("fp32: fwd+bwd %.3f ms, fwd %.3f ms" % (ms32, ms32f))
+        result["fp32"] = {"fwd_bwd_terms_per_s": T / (ms32 * 1e-3),
+                          "fwd_terms_per_s": T / (ms32f * 1e-3), "ms_per_step": ms32,
+                          "fwd_ms": ms32f,
+                          "mfma_frac_fwd": 2.0 * T / (ms32f * 1e-3) / PEAK["fp32"][0]}
+
+    # --- parity of the timed configuration against the oracle ---------------
+    import oracle
+    pick = np.random.default_rng(11).choice(w.l, size=min(8, w.l), replace=False)
+    parity = {}
+    for prec in (("split_bf16",) if args.no_fp32 else ("split_bf16", "fp32")):
+        if mmd:
+            break
+        mean, se = step(prec, fwd_only=True)
+        up = np.zeros(w.l)
+        up[pick] = np.random.default_rng(3).normal(size=pick.size)
+        _, _, ph = api.iqp_expval(circ, dw.ops, dw.samples, prec, phase_save=True)
+        g = api.iqp_expval_grad(circ, dw.ops, dw.samples, torch.from_numpy(up).cuda(), ph, prec)
+        torch.cuda.synchronize()
+        om, ose = oracle.expval(w.n, w.gates, w.theta, dw.ops01[pick], w.samples)
+        og = oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01[pick], w.samples, up[pick])
+        em = float(np.abs(mean.cpu().numpy()[pick] - om).max())
+        es = float(np.abs(se.cpu().numpy()[pick] - ose).max())
+        eg = float(np.abs(g.cpu().numpy() - og).max() / max(1.0, np.abs(og).max()))
+        parity[prec] = {"max_abs_err_mean": em, "max_abs_err_stderr": es,
+                        "max_rel_err_grad": eg, "tol": TOL[prec],
+                        "ok": bool(em < TOL[prec] and es < TOL[prec] and eg < TOL[prec]),
+                        "sampled_observables": int(pick.size)}
+    result["parity"] = parity
+
+    # --- oracle on the host cores -------------------------------------------
+    if not args.no_cpu_baseline and not mmd:
+        k = args.cpu_sample_ops or max(8, min(w.l, 96))
+        sel = np.arange(k)
+        uu = np.random.default_rng(5).normal(size=k)
+        t1 = time.time()
+        oracle.expval(w.n, w.gates, w.theta, dw.ops01[sel], w.samples)
+        oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01[sel], w.samples, uu)
+        dt = time.time() - t1
+        result["cpu_baseline"] = {"value": k * w.s * w.m / dt, "unit": "terms/s",
+                                  "cores": oracle.num_threads(), "kind": "oracle",
+                                  "sample": "fwd+bwd of the first %d of %d observables over all "
+                                            "%d samples and %d gates (%.1f s)" %
+                                            (k, w.l, w.s, w.m, dt)}
+    result["config"] = {"workload": w.name, "n_qubits": w.n, "gates": w.m, "observables": w.l,
+                        "samples": w.s, "precision": "split_bf16 (hi+lo BF16, FP32 accumulate)",
+                        "step": "iqp_mmd_loss_grad" if mmd else "iqp_expval + iqp_expval_grad",
+                        "terms_per_step": T}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * iqp.h — C-ABI of the MI355X (gfx950) Monte Carlo estimator of Pauli-Z
+ * expectation values of parameterized IQP circuits (arXiv 2501.04776).
+ *
+ * The method (Sec. 2.1-2.2, Prop. 1-2 of the paper): an n-qubit circuit of m
+ * commuting gates exp(i theta_j X_{g_j}) acting on |0>, and l observables
+ * Z_{a_k}. For s bitstrings z_i the estimator of <Z_{a_k}> is
+ *     mean_k = (1/s) sum_i cos(E_ki),   E = C Theta B^T            (eq. Emat)
+ * with B_ij = (-1)^{z_i . g_j}, C_kj = 1 - (-1)^{a_k . g_j} in {0, 2}, and
+ * Theta = diag(theta). Each call runs three GPU steps — bit-exact parity
+ * matrices, the phase contraction E, and a cos / mean / standard-error
+ * reduction — plus, for the gradient, the transposed contraction.
+ *
+ * Conventions shared by every entry point
+ *   - Bit rows: a binary vector of n qubits is packed into W = ceil(n/64)
+ *     little-endian uint64 words; qubit q is bit (q & 63) of word (q >> 6).
+ *     Bits at positions >= n ("pad bits") must be zero; they are not checked
+ *     on the device.
+ *   - Pointers marked "device" must be device (or managed) memory readable
+ *     from the GPU that is current when the call is made. The caller owns all
+ *     memory, including the workspace; the library keeps no pointer after a
+ *     call returns. Pointers marked "host" are read before the call returns.
+ *   - Every call validates its arguments on the host before it enqueues any
+ *     work and returns IQP_ERR_INVALID_ARG / IQP_ERR_WORKSPACE without touching
+ *     the GPU. Otherwise all work is enqueued asynchronously on `stream` (a
+ *     hipStream_t; NULL = the default stream) and the call returns before it
+ *     completes. Results are valid once the stream has been synchronised.
+ *   - HIP failures return IQP_ERR_HIP; iqp_last_error() gives the text.
+ *   - Calls are deterministic: the same inputs, precision and device give
+ *     bitwise-identical outputs (fixed-order reductions, no float atomics).
+ *   - Non-finite theta propagates NaN into the results.
+ *   - Calls that share one workspace must not overlap in time.
+ */
+#ifndef IQP_H
+#define IQP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IQP_OK = 0,
+    IQP_ERR_INVALID_ARG = -1, /* a null pointer, a size out of range, n/W mismatch */
+    IQP_ERR_WORKSPACE = -2,   /* ws_bytes smaller than iqp_workspace_bytes() */
+    IQP_ERR_HIP = -3,         /* a HIP runtime call failed (see iqp_last_error) */
+    IQP_ERR_UNSUPPORTED = -4  /* an option this build does not implement */
+} iqp_status;
+
+/* Arithmetic of the phase contraction E = C Theta B^T.
+ *   IQP_FP32:       2 theta_j in FP32, one FP32 matrix-core product per term.
+ *   IQP_SPLIT_BF16: 2 theta_j = hi + lo with hi, lo BF16 (round to nearest
+ *                   even), two BF16 matrix-core products per term (the +-1
+ *                   and 0/1 parity operands are exact in BF16), FP32
+ *                   accumulation.
+ * In both, theta is first reduced to [-pi/2, pi/2] by whole multiples of pi
+ * (exp(i(theta + pi) X) = -exp(i theta X) is a global phase, Sec. 2.1), and
+ * every phase is reduced modulo 2 pi in FP64 before its cos / sin. */
+typedef enum { IQP_FP32 = 0, IQP_SPLIT_BF16 = 1 } iqp_precision;
+
+/* A parameterized IQP circuit (Def. 1): generators g_j as bit rows and their
+ * parameters theta_j. */
+typedef struct {
+    int32_t n_qubits;      /* n >= 1 */
+    int32_t n_words;       /* W, must equal ceil(n / 64) */
+    int64_t n_gates;       /* m >= 1 */
+    const uint64_t *gens;  /* device, [m][W] bit rows g_j */
+    const double *theta;   /* device, [m] theta_j */
+} iqp_circuit;
+
+/* Which call a workspace is sized for. */
+enum {
+    IQP_CALL_EXPVAL = 0,
+    IQP_CALL_EXPVAL_GRAD = 1,      /* with phase_save supplied */
+    IQP_CALL_EXPVAL_GRAD_RECOMPUTE = 2, /* phase_save == NULL */
+    IQP_CALL_MMD = 3,
+    IQP_CALL_MMD_GRAD = 4
+};
+
+/* Bytes of workspace the given call needs for these sizes (N is only read for
+ * the MMD calls). Returns 0 for invalid sizes. */
+size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s, int64_t N,
+                           int precision);
+
+/* Parity bit matrix (the exponents of B = (-1)^{Z G^T} and of
+ * C = 1 - (-1)^{A G^T}, Sec. 2.2): bit (r, c) = popcount(row_r AND col_c) mod 2.
+ *   rows      device [n_rows][W], cols device [n_cols][W]
+ *   layout    IQP_BITS_ROW_MAJOR: out[r * ceil(n_cols/64) + c/64], bit c % 64;
+ *             IQP_BITS_TILED32:   rows padded to a multiple of 32,
+ *               out[((r / 32) * ceil(n_cols/64) + c/64) * 32 + r % 32], bit c % 64
+ *               (the layout the phase-contraction kernels read).
+ *   out       device, ceil(n_cols/64) words per row (rows padded to 32 for
+ *             TILED32; pad rows and bits at c >= n_cols are written as 0).
+ * n_rows >= 0, n_cols >= 0, W >= 1. Bit-exact. */
+enum { IQP_BITS_ROW_MAJOR = 0, IQP_BITS_TILED32 = 1 };
+int iqp_parity(int64_t n_rows, const uint64_t *rows, int64_t n_cols, const uint64_t *cols,
+               int32_t n_words, int layout, uint64_t *out, void *stream);
+
+/* Monte Carlo estimates of <Z_{a_k}> (eq. expvalsample, batched as Prop. 2).
+ *   ops        device [l][W] observables a_k, l >= 1
+ *   samples    device [s][W] bitstrings z_i, s >= 1 (drawn by the caller: the
+ *              estimator is unbiased when they are uniform, Prop. 1)
+ *   mean       device [l] (1/s) sum_i cos E_ki
+ *   stderr_    device [l] or NULL: population standard deviation of
+ *              cos E_ki over i, divided by sqrt(s)
+ *   phase_save device [l][s] float or NULL: E_ki reduced to [-pi, pi]
+ *              (row-major, k major), for iqp_expval_grad
+ *   ws         device workspace of ws_bytes >= iqp_workspace_bytes(IQP_CALL_EXPVAL, ...)
+ */
+int iqp_expval(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+               const uint64_t *samples, int precision, double *mean, double *stderr_,
+               float *phase_save, void *ws, size_t ws_bytes, void *stream);
+
+/* Gradient of a loss L(mean) through the estimator (the reverse pass of the
+ * computational graph of Fig. 3, written by hand):
+ *   dL/dtheta_j = -(1/s) sum_k u_k sum_i sin(E_ki) C_kj B_ij,  u_k = dL/dmean_k.
+ *   grad_mean  device [l] u_k
+ *   phase_save device [l][s] from iqp_expval with the same inputs and
+ *              precision, or NULL to recompute the phases (parities are always
+ *              recomputed, never stored)
+ *   grad_theta device [m], overwritten (not accumulated)
+ * Other arguments as iqp_expval. */
+int iqp_expval_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+                    const uint64_t *samples, int precision, const double *grad_mean,
+                    const float *phase_save, double *grad_theta, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* MMD^2 between training data and the circuit through Pauli-Z expectation
+ * values (eq. mmd_estimate, Sec. 3.3.1), and its gradient:
+ *   p_k = (1/N) sum_n (-1)^{a_k . x_n},   q_k = mean_k (eq. expvalsample)
+ *   unbiased != 0:  L = sum_k w_k [P2_k - 2 p_k q_k + Q2_k] with the
+ *                   U-statistics P2_k = ((N p_k)^2 - N) / (N (N-1)),
+ *                   Q2_k = ((sum_i c_ki)^2 - sum_i c_ki^2) / (s (s-1)),
+ *                   c_ki = cos E_ki (needs N >= 2 and s >= 2)
+ *   unbiased == 0:  L = sum_k w_k (p_k - q_k)^2
+ *   ops        device [l][W], operators drawn from P_sigma by the caller
+ *   op_weight  device [l] w_k (e.g. 1/(number of bandwidths * ops per bandwidth))
+ *   data       device [N][W] training bitstrings x_n, N >= 1
+ *   loss       device [1]
+ *   grad_theta device [m] or NULL (loss only), overwritten
+ * Other arguments as iqp_expval. */
+int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
+                      const double *op_weight, int64_t s, const uint64_t *samples, int64_t N,
+                      const uint64_t *data, int unbiased, int precision, double *loss,
+                      double *grad_theta, void *ws, size_t ws_bytes, void *stream);
+
+/* Static text for a status code. */
+const char *iqp_strerror(int status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *iqp_last_error(void);
+
+/* Per-kernel timing, for measurement only. When enabled, every kernel launch
+ * of the library is bracketed by HIP events on its stream; iqp_profile_query
+ * synchronises those events and returns the total milliseconds and the
+ * number of launches recorded for the kernel family `name` ("parity",
+ * "theta_prep", "phase_fwd", "phase_epilogue", "finalize", "weights",
+ * "phase_bwd", "grad_reduce", "mmd"). Not thread-safe; off by default. */
+int iqp_profile_enable(int on);
+int iqp_profile_query(const char *name, double *total_ms, int64_t *launches);
+int iqp_profile_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IQP_H */

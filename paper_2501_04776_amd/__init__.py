@@ -1,0 +1,17 @@
+"""MI355X-native Monte Carlo estimator of Pauli-Z expectation values of
+parameterized IQP circuits, its gradient and an MMD^2 loss (arXiv 2501.04776).
+
+The compute path is the gfx950 HIP library libiqp.so behind the C-ABI of
+include/iqp.h; this package only marshals arguments to it.
+"""
+from . import packing
+from ._lib import IqpError
+from .api import (FP32, ROW_MAJOR, SPLIT_BF16, TILED32, Circuit, iqp_expval, iqp_expval_grad,
+                  iqp_mmd_loss_grad, iqp_parity, profile_enable, profile_query, profile_reset,
+                  workspace_bytes)
+from .autograd import IQPExpval, IQPMMDLoss
+
+__all__ = ["packing", "IqpError", "FP32", "SPLIT_BF16", "ROW_MAJOR", "TILED32", "Circuit",
+           "iqp_expval", "iqp_expval_grad", "iqp_mmd_loss_grad", "iqp_parity",
+           "profile_enable", "profile_query", "profile_reset", "workspace_bytes", "IQPExpval",
+           "IQPMMDLoss"]

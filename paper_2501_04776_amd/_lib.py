@@ -1,0 +1,101 @@
+"""ctypes loader for libiqp.so (the C-ABI of include/iqp.h).
+
+The library must have been built in-tree (``python -m
+paper_2501_04776_amd.build`` or ``__graft_entry__.build()``). There is no
+fallback: if it is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libiqp.so")
+
+IQP_OK = 0
+IQP_ERR_INVALID_ARG = -1
+IQP_ERR_WORKSPACE = -2
+IQP_ERR_HIP = -3
+IQP_ERR_UNSUPPORTED = -4
+
+IQP_FP32 = 0
+IQP_SPLIT_BF16 = 1
+
+IQP_CALL_EXPVAL = 0
+IQP_CALL_EXPVAL_GRAD = 1
+IQP_CALL_EXPVAL_GRAD_RECOMPUTE = 2
+IQP_CALL_MMD = 3
+IQP_CALL_MMD_GRAD = 4
+
+IQP_BITS_ROW_MAJOR = 0
+IQP_BITS_TILED32 = 1
+
+# every symbol include/iqp.h declares
+EXPORTED = ("iqp_workspace_bytes", "iqp_parity", "iqp_expval", "iqp_expval_grad",
+            "iqp_mmd_loss_grad", "iqp_strerror", "iqp_last_error", "iqp_profile_enable",
+            "iqp_profile_query", "iqp_profile_reset")
+
+
+class IqpCircuit(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_words", ctypes.c_int32),
+                ("n_gates", ctypes.c_int64), ("gens", ctypes.c_void_p),
+                ("theta", ctypes.c_void_p)]
+
+
+class IqpError(RuntimeError):
+    def __init__(self, status, what, detail):
+        super().__init__("%s failed: %s (%d)%s" % (what, strerror(status), status,
+                                                   (": " + detail) if detail else ""))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libiqp.so is not built at %s; run `python -m "
+                           "paper_2501_04776_amd.build`" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp, sz = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    cp = ctypes.POINTER(IqpCircuit)
+    L.iqp_workspace_bytes.argtypes = [i32, cp, i64, i64, i64, i32]
+    L.iqp_workspace_bytes.restype = sz
+    L.iqp_parity.argtypes = [i64, vp, i64, vp, ctypes.c_int32, i32, vp, vp]
+    L.iqp_parity.restype = i32
+    L.iqp_expval.argtypes = [cp, i64, vp, i64, vp, i32, vp, vp, vp, vp, sz, vp]
+    L.iqp_expval.restype = i32
+    L.iqp_expval_grad.argtypes = [cp, i64, vp, i64, vp, i32, vp, vp, vp, vp, sz, vp]
+    L.iqp_expval_grad.restype = i32
+    L.iqp_mmd_loss_grad.argtypes = [cp, i64, vp, vp, i64, vp, i64, vp, i32, i32, vp, vp, vp,
+                                    sz, vp]
+    L.iqp_mmd_loss_grad.restype = i32
+    L.iqp_strerror.argtypes = [i32]
+    L.iqp_strerror.restype = ctypes.c_char_p
+    L.iqp_last_error.argtypes = []
+    L.iqp_last_error.restype = ctypes.c_char_p
+    L.iqp_profile_enable.argtypes = [i32]
+    L.iqp_profile_enable.restype = i32
+    L.iqp_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64)]
+    L.iqp_profile_query.restype = i32
+    L.iqp_profile_reset.argtypes = []
+    L.iqp_profile_reset.restype = i32
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return lib().iqp_strerror(status).decode()
+
+
+def last_error() -> str:
+    return lib().iqp_last_error().decode()
+
+
+def check(status: int, what: str) -> None:
+    if status != IQP_OK:
+        raise IqpError(status, what, last_error())

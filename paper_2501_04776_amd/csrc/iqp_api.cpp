@@ -1,0 +1,474 @@
+// Host runtime of the C-ABI declared in include/iqp.h: argument validation,
+// workspace planning and carving, kernel dispatch on the caller's stream, and
+// the optional per-kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <string.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "iqp.h"
+#include "iqp_internal.h"
+
+namespace iqp {
+
+static thread_local std::string g_last_error;
+
+static int fail(int status, const std::string &msg) {
+    g_last_error = msg;
+    return status;
+}
+
+static int hip_fail(hipError_t e, const char *where) {
+    g_last_error = std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) +
+                   ")";
+    return IQP_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// per-kernel timing
+struct Timing {
+    bool on = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[KF_COUNT] = {};
+    int64_t launches[KF_COUNT] = {};
+};
+static Timing g_timing;
+
+static hipEvent_t take_event() {
+    if (!g_timing.pool.empty()) {
+        hipEvent_t e = g_timing.pool.back();
+        g_timing.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Event failures only lose a timing sample: the launch itself is unaffected.
+void timed_begin(const LaunchCtx &lc, int, hipEvent_t *ev) {
+    *ev = nullptr;
+    if (!lc.timing) return;
+    hipEvent_t e = take_event();
+    if (e && hipEventRecord(e, lc.stream) == hipSuccess) *ev = e;
+    else if (e) g_timing.pool.push_back(e);
+}
+
+void timed_end(const LaunchCtx &lc, int family, hipEvent_t ev) {
+    if (!lc.timing || !ev) return;
+    hipEvent_t e2 = take_event();
+    if (e2 && hipEventRecord(e2, lc.stream) == hipSuccess) {
+        g_timing.pending.push_back({family, {ev, e2}});
+        return;
+    }
+    g_timing.pool.push_back(ev);
+    if (e2) g_timing.pool.push_back(e2);
+}
+
+static hipError_t drain_timing() {
+    hipError_t first = hipSuccess;
+    for (auto &p : g_timing.pending) {
+        hipError_t e = hipEventSynchronize(p.second.second);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.second.first, p.second.second);
+        if (e == hipSuccess) {
+            g_timing.total_ms[p.first] += ms;
+            g_timing.launches[p.first] += 1;
+        } else if (first == hipSuccess) {
+            first = e;
+        }
+        g_timing.pool.push_back(p.second.first);
+        g_timing.pool.push_back(p.second.second);
+    }
+    g_timing.pending.clear();
+    return first;
+}
+
+static const char *kFamilyNames[KF_COUNT] = {"parity", "theta_prep", "phase_fwd",
+                                             "phase_epilogue", "finalize", "weights",
+                                             "phase_bwd", "grad_reduce", "mmd"};
+
+// ---------------------------------------------------------------------------
+// device check: the kernels are built for gfx950 only
+static int check_device() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    static int checked_dev = -1;
+    static bool ok = false;
+    if (checked_dev != dev) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+        checked_dev = dev;
+        if (!ok)
+            return fail(IQP_ERR_UNSUPPORTED,
+                        std::string("device arch ") + prop.gcnArchName + " is not gfx950");
+    }
+    return ok ? IQP_OK : fail(IQP_ERR_UNSUPPORTED, "device is not gfx950");
+}
+
+// ---------------------------------------------------------------------------
+// workspace plan
+struct Plan {
+    int prec = 0;
+    int64_t n = 0, W = 0, m = 0, l = 0, s = 0, N = 0;
+    int64_t m_pad = 0, l_pad = 0, s_pad = 0, mw = 0, lw = 0, Nw = 0;
+    TileCfg tc;
+    int64_t nchunk = 0;
+    bool fwd = false, phi = false, bwd = false, mmd = false;
+    size_t o_thh = 0, o_thl = 0, o_t32 = 0, o_cbits = 0, o_bbits = 0, o_E = 0, o_part = 0;
+    size_t o_rowsum = 0, o_phi = 0, o_coef = 0, o_ctbits = 0, o_shi = 0, o_slo = 0, o_s32 = 0;
+    size_t o_gpart = 0, o_dbits = 0, o_pstat = 0;
+    size_t total = 0;
+};
+
+static int64_t choose_splits(int64_t tiles, int64_t mw) {
+    int64_t best = 1;
+    double best_eff = -1.0;
+    for (int64_t sp = 1; sp <= 16; ++sp) {
+        if (sp > 1 && mw < 8 * sp) break;  // keep >= 8 gate words per split
+        const int64_t units = tiles * sp;
+        const double eff =
+            (double)units / (double)(ceil_div(units, kWaveSlots) * kWaveSlots);
+        if (eff >= 0.9) return sp;
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            best = sp;
+        }
+    }
+    return best;
+}
+
+static size_t carve(size_t &cur, size_t bytes) {
+    const size_t o = cur;
+    cur += (bytes + 255) & ~(size_t)255;
+    return o;
+}
+
+static void make_plan(Plan &P, int call, int64_t n, int64_t m, int64_t l, int64_t s, int64_t N,
+                      int prec) {
+    P.prec = prec;
+    P.n = n;
+    P.W = ceil_div(n, 64);
+    P.m = m;
+    P.l = l;
+    P.s = s;
+    P.N = N;
+    P.m_pad = round_up(m, kPad);
+    P.l_pad = round_up(l, kPad);
+    P.s_pad = round_up(s, kPad);
+    P.mw = P.m_pad / 64;
+    P.lw = P.l_pad / 64;
+    P.Nw = ceil_div(N > 0 ? N : 1, 64);
+    P.nchunk = ceil_div(s, kEpiChunk);
+    const int64_t tiles = (P.l_pad / (32 * P.tc.fm)) * (P.s_pad / (32 * P.tc.fn));
+    P.tc.splits = choose_splits(tiles, P.mw);
+    P.fwd = call != IQP_CALL_EXPVAL_GRAD;
+    P.bwd = call == IQP_CALL_EXPVAL_GRAD || call == IQP_CALL_EXPVAL_GRAD_RECOMPUTE ||
+            call == IQP_CALL_MMD_GRAD;
+    P.phi = call == IQP_CALL_EXPVAL_GRAD_RECOMPUTE || call == IQP_CALL_MMD_GRAD;
+    P.mmd = call == IQP_CALL_MMD || call == IQP_CALL_MMD_GRAD;
+    size_t cur = 0;
+    // B parity bits serve both contractions
+    P.o_bbits = carve(cur, (size_t)P.s_pad * P.mw * 8);
+    if (P.fwd) {
+        if (prec == IQP_SPLIT_BF16) {
+            P.o_thh = carve(cur, (size_t)P.m_pad * 2);
+            P.o_thl = carve(cur, (size_t)P.m_pad * 2);
+        } else {
+            P.o_t32 = carve(cur, (size_t)P.m_pad * 4);
+        }
+        P.o_cbits = carve(cur, (size_t)P.l_pad * P.mw * 8);
+        P.o_E = carve(cur, (size_t)P.tc.splits * P.l_pad * P.s_pad * 4);
+        P.o_part = carve(cur, (size_t)l * P.nchunk * 2 * 8);
+        P.o_rowsum = carve(cur, (size_t)l * 2 * 8);
+    }
+    if (P.phi) P.o_phi = carve(cur, (size_t)l * s * 4);
+    if (P.bwd) {
+        P.o_coef = carve(cur, (size_t)l * 2 * 8);
+        P.o_ctbits = carve(cur, (size_t)P.m_pad * P.lw * 8);
+        if (prec == IQP_SPLIT_BF16) {
+            P.o_shi = carve(cur, (size_t)P.s_pad * P.l_pad * 2);
+            P.o_slo = carve(cur, (size_t)P.s_pad * P.l_pad * 2);
+        } else {
+            P.o_s32 = carve(cur, (size_t)P.s_pad * P.l_pad * 4);
+        }
+        P.o_gpart = carve(cur, (size_t)(P.s_pad / (32 * P.tc.bfn)) * P.m_pad * 4);
+    }
+    if (P.mmd) {
+        P.o_dbits = carve(cur, (size_t)l * P.Nw * 8);
+        P.o_pstat = carve(cur, (size_t)l * 2 * 8);
+    }
+    P.total = cur;
+}
+
+template <typename T>
+static T *at(void *ws, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+// size limits that keep every grid dimension and index in range
+static const int64_t kMaxRows = (int64_t)1 << 24;
+
+static int check_circuit(const iqp_circuit *c) {
+    if (!c) return fail(IQP_ERR_INVALID_ARG, "circuit is NULL");
+    if (c->n_qubits < 1) return fail(IQP_ERR_INVALID_ARG, "n_qubits must be >= 1");
+    if (c->n_words != (int32_t)ceil_div(c->n_qubits, 64))
+        return fail(IQP_ERR_INVALID_ARG, "n_words must equal ceil(n_qubits / 64)");
+    if (c->n_gates < 1 || c->n_gates > kMaxRows)
+        return fail(IQP_ERR_INVALID_ARG, "n_gates out of range [1, 2^24]");
+    if (!c->gens) return fail(IQP_ERR_INVALID_ARG, "gens is NULL");
+    if (!c->theta) return fail(IQP_ERR_INVALID_ARG, "theta is NULL");
+    return IQP_OK;
+}
+
+static int check_common(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+                        const uint64_t *samples, int precision) {
+    int st = check_circuit(c);
+    if (st) return st;
+    if (l < 1 || l > kMaxRows) return fail(IQP_ERR_INVALID_ARG, "l out of range [1, 2^24]");
+    if (s < 1 || s > kMaxRows) return fail(IQP_ERR_INVALID_ARG, "s out of range [1, 2^24]");
+    if (!ops) return fail(IQP_ERR_INVALID_ARG, "ops is NULL");
+    if (!samples) return fail(IQP_ERR_INVALID_ARG, "samples is NULL");
+    if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16)
+        return fail(IQP_ERR_INVALID_ARG, "precision must be IQP_FP32 or IQP_SPLIT_BF16");
+    return IQP_OK;
+}
+
+static int check_ws(const Plan &P, void *ws, size_t ws_bytes) {
+    if (ws_bytes < P.total)
+        return fail(IQP_ERR_WORKSPACE, "workspace of " + std::to_string(ws_bytes) +
+                                           " bytes, need " + std::to_string(P.total));
+    if (!ws) return fail(IQP_ERR_INVALID_ARG, "ws is NULL");
+    return IQP_OK;
+}
+
+#define IQP_TRY(call, where)                        \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+static int run_forward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
+                       const uint64_t *samples, void *ws, const LaunchCtx &lc, float *phase_out,
+                       double *mean, double *se, double *rowsum) {
+    const int W = (int)P.W;
+    IQP_TRY(launch_theta_prep(lc, c->theta, P.m, P.m_pad, P.prec, at<uint16_t>(ws, P.o_thh),
+                              at<uint16_t>(ws, P.o_thl), at<float>(ws, P.o_t32)),
+            "theta_prep");
+    IQP_TRY(launch_parity(lc, ops, P.l, P.l_pad, c->gens, P.m, P.mw, W, IQP_BITS_TILED32,
+                          at<uint64_t>(ws, P.o_cbits)),
+            "parity(C)");
+    IQP_TRY(launch_parity(lc, samples, P.s, P.s_pad, c->gens, P.m, P.mw, W, IQP_BITS_TILED32,
+                          at<uint64_t>(ws, P.o_bbits)),
+            "parity(B)");
+    IQP_TRY(launch_phase_fwd(lc, P.prec, P.tc.fm, P.tc.fn, at<uint64_t>(ws, P.o_cbits),
+                             at<uint64_t>(ws, P.o_bbits), at<uint16_t>(ws, P.o_thh),
+                             at<uint16_t>(ws, P.o_thl), at<float>(ws, P.o_t32), P.m_pad, P.l_pad,
+                             P.s_pad, P.tc.splits, at<float>(ws, P.o_E)),
+            "phase_fwd");
+    IQP_TRY(launch_epilogue(lc, at<float>(ws, P.o_E), P.tc.splits, P.l, P.s, P.l_pad, P.s_pad,
+                            phase_out, at<double>(ws, P.o_part)),
+            "phase_epilogue");
+    IQP_TRY(launch_finalize(lc, at<double>(ws, P.o_part), P.l, P.s, mean, se, rowsum),
+            "finalize");
+    return IQP_OK;
+}
+
+// Backward from the coefficients at o_coef and the phases `phase`.
+static int run_backward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
+                        const uint64_t *samples, const float *phase, bool bbits_ready, void *ws,
+                        const LaunchCtx &lc, double *grad_theta) {
+    const int W = (int)P.W;
+    IQP_TRY(launch_weights(lc, P.prec, phase, at<double>(ws, P.o_coef), P.l, P.s, P.l_pad,
+                           P.s_pad, at<uint16_t>(ws, P.o_shi), at<uint16_t>(ws, P.o_slo),
+                           at<float>(ws, P.o_s32)),
+            "weights");
+    IQP_TRY(launch_parity(lc, c->gens, P.m, P.m_pad, ops, P.l, P.lw, W, IQP_BITS_TILED32,
+                          at<uint64_t>(ws, P.o_ctbits)),
+            "parity(C^T)");
+    if (!bbits_ready)
+        IQP_TRY(launch_parity(lc, samples, P.s, P.s_pad, c->gens, P.m, P.mw, W, IQP_BITS_TILED32,
+                              at<uint64_t>(ws, P.o_bbits)),
+                "parity(B)");
+    IQP_TRY(launch_phase_bwd(lc, P.prec, P.tc.bfm, P.tc.bfn, at<uint64_t>(ws, P.o_ctbits),
+                             at<uint16_t>(ws, P.o_shi), at<uint16_t>(ws, P.o_slo),
+                             at<float>(ws, P.o_s32), at<uint64_t>(ws, P.o_bbits), P.m_pad,
+                             P.l_pad, P.s_pad, at<float>(ws, P.o_gpart)),
+            "phase_bwd");
+    IQP_TRY(launch_grad_reduce(lc, at<float>(ws, P.o_gpart), P.s_pad / (32 * P.tc.bfn), P.m,
+                               P.m_pad, grad_theta),
+            "grad_reduce");
+    return IQP_OK;
+}
+
+static LaunchCtx make_ctx(void *stream) {
+    LaunchCtx lc;
+    lc.stream = reinterpret_cast<hipStream_t>(stream);
+    lc.timing = g_timing.on;
+    return lc;
+}
+
+}  // namespace iqp
+
+using namespace iqp;
+
+extern "C" {
+
+size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s, int64_t N,
+                           int precision) {
+    if (!c || c->n_qubits < 1 || c->n_gates < 1 || l < 1 || s < 1) return 0;
+    if (call < IQP_CALL_EXPVAL || call > IQP_CALL_MMD_GRAD) return 0;
+    if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16) return 0;
+    if ((call == IQP_CALL_MMD || call == IQP_CALL_MMD_GRAD) && N < 1) return 0;
+    Plan P;
+    make_plan(P, call, c->n_qubits, c->n_gates, l, s, N, precision);
+    return P.total;
+}
+
+int iqp_parity(int64_t n_rows, const uint64_t *rows, int64_t n_cols, const uint64_t *cols,
+               int32_t n_words, int layout, uint64_t *out, void *stream) {
+    g_last_error.clear();
+    if (n_rows < 0 || n_rows > kMaxRows * 4) return fail(IQP_ERR_INVALID_ARG, "n_rows out of range");
+    if (n_cols < 0 || n_cols > kMaxRows * 4) return fail(IQP_ERR_INVALID_ARG, "n_cols out of range");
+    if (n_words < 1) return fail(IQP_ERR_INVALID_ARG, "n_words must be >= 1");
+    if (layout != IQP_BITS_ROW_MAJOR && layout != IQP_BITS_TILED32)
+        return fail(IQP_ERR_INVALID_ARG, "unknown layout");
+    if (n_rows == 0 || n_cols == 0) return IQP_OK;
+    if (!rows || !cols || !out) return fail(IQP_ERR_INVALID_ARG, "NULL pointer");
+    int st = check_device();
+    if (st) return st;
+    const int64_t R_out = layout == IQP_BITS_TILED32 ? round_up(n_rows, 32) : n_rows;
+    IQP_TRY(launch_parity(make_ctx(stream), rows, n_rows, R_out, cols, n_cols,
+                          ceil_div(n_cols, 64), n_words, layout, out),
+            "parity");
+    return IQP_OK;
+}
+
+int iqp_expval(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+               const uint64_t *samples, int precision, double *mean, double *stderr_,
+               float *phase_save, void *ws, size_t ws_bytes, void *stream) {
+    g_last_error.clear();
+    int st = check_common(c, l, ops, s, samples, precision);
+    if (st) return st;
+    if (!mean) return fail(IQP_ERR_INVALID_ARG, "mean is NULL");
+    Plan P;
+    make_plan(P, IQP_CALL_EXPVAL, c->n_qubits, c->n_gates, l, s, 0, precision);
+    if ((st = check_ws(P, ws, ws_bytes))) return st;
+    if ((st = check_device())) return st;
+    return run_forward(P, c, ops, samples, ws, make_ctx(stream), phase_save, mean, stderr_,
+                       at<double>(ws, P.o_rowsum));
+}
+
+int iqp_expval_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+                    const uint64_t *samples, int precision, const double *grad_mean,
+                    const float *phase_save, double *grad_theta, void *ws, size_t ws_bytes,
+                    void *stream) {
+    g_last_error.clear();
+    int st = check_common(c, l, ops, s, samples, precision);
+    if (st) return st;
+    if (!grad_mean) return fail(IQP_ERR_INVALID_ARG, "grad_mean is NULL");
+    if (!grad_theta) return fail(IQP_ERR_INVALID_ARG, "grad_theta is NULL");
+    Plan P;
+    const int call = phase_save ? IQP_CALL_EXPVAL_GRAD : IQP_CALL_EXPVAL_GRAD_RECOMPUTE;
+    make_plan(P, call, c->n_qubits, c->n_gates, l, s, 0, precision);
+    if ((st = check_ws(P, ws, ws_bytes))) return st;
+    if ((st = check_device())) return st;
+    LaunchCtx lc = make_ctx(stream);
+    const float *phase = phase_save;
+    if (!phase) {
+        st = run_forward(P, c, ops, samples, ws, lc, at<float>(ws, P.o_phi), nullptr, nullptr,
+                         at<double>(ws, P.o_rowsum));
+        if (st) return st;
+        phase = at<float>(ws, P.o_phi);
+    }
+    IQP_TRY(launch_coef_plain(lc, grad_mean, l, s, at<double>(ws, P.o_coef)), "coef");
+    return run_backward(P, c, ops, samples, phase, phase_save == nullptr, ws, lc, grad_theta);
+}
+
+int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
+                      const double *op_weight, int64_t s, const uint64_t *samples, int64_t N,
+                      const uint64_t *data, int unbiased, int precision, double *loss,
+                      double *grad_theta, void *ws, size_t ws_bytes, void *stream) {
+    g_last_error.clear();
+    int st = check_common(c, l, ops, s, samples, precision);
+    if (st) return st;
+    if (!op_weight) return fail(IQP_ERR_INVALID_ARG, "op_weight is NULL");
+    if (N < 1 || N > kMaxRows) return fail(IQP_ERR_INVALID_ARG, "N out of range [1, 2^24]");
+    if (!data) return fail(IQP_ERR_INVALID_ARG, "data is NULL");
+    if (!loss) return fail(IQP_ERR_INVALID_ARG, "loss is NULL");
+    if (unbiased && (N < 2 || s < 2))
+        return fail(IQP_ERR_INVALID_ARG, "the unbiased estimator needs N >= 2 and s >= 2");
+    Plan P;
+    make_plan(P, grad_theta ? IQP_CALL_MMD_GRAD : IQP_CALL_MMD, c->n_qubits, c->n_gates, l, s, N,
+              precision);
+    if ((st = check_ws(P, ws, ws_bytes))) return st;
+    if ((st = check_device())) return st;
+    LaunchCtx lc = make_ctx(stream);
+    float *phi = grad_theta ? at<float>(ws, P.o_phi) : nullptr;
+    st = run_forward(P, c, ops, samples, ws, lc, phi, nullptr, nullptr, at<double>(ws, P.o_rowsum));
+    if (st) return st;
+    IQP_TRY(launch_parity(lc, ops, l, l, data, N, P.Nw, (int)P.W, IQP_BITS_ROW_MAJOR,
+                          at<uint64_t>(ws, P.o_dbits)),
+            "parity(data)");
+    IQP_TRY(launch_data_stats(lc, at<uint64_t>(ws, P.o_dbits), l, P.Nw, N,
+                              at<double>(ws, P.o_pstat)),
+            "data_stats");
+    IQP_TRY(launch_mmd_loss(lc, at<double>(ws, P.o_pstat), at<double>(ws, P.o_rowsum), op_weight,
+                            l, s, N, unbiased, loss),
+            "mmd_loss");
+    if (!grad_theta) return IQP_OK;
+    IQP_TRY(launch_coef_mmd(lc, at<double>(ws, P.o_pstat), at<double>(ws, P.o_rowsum), op_weight,
+                            l, s, unbiased, at<double>(ws, P.o_coef)),
+            "coef_mmd");
+    return run_backward(P, c, ops, samples, phi, true, ws, lc, grad_theta);
+}
+
+const char *iqp_strerror(int status) {
+    switch (status) {
+        case IQP_OK: return "success";
+        case IQP_ERR_INVALID_ARG: return "invalid argument";
+        case IQP_ERR_WORKSPACE: return "workspace too small";
+        case IQP_ERR_HIP: return "HIP runtime error";
+        case IQP_ERR_UNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+const char *iqp_last_error(void) { return g_last_error.c_str(); }
+
+int iqp_profile_enable(int on) {
+    g_timing.on = on != 0;
+    return IQP_OK;
+}
+
+int iqp_profile_query(const char *name, double *total_ms, int64_t *launches) {
+    if (!name || !total_ms || !launches) return fail(IQP_ERR_INVALID_ARG, "NULL pointer");
+    hipError_t e = drain_timing();
+    if (e != hipSuccess) return hip_fail(e, "profile drain");
+    for (int f = 0; f < KF_COUNT; ++f) {
+        if (strcmp(name, kFamilyNames[f]) == 0) {
+            *total_ms = g_timing.total_ms[f];
+            *launches = g_timing.launches[f];
+            return IQP_OK;
+        }
+    }
+    return fail(IQP_ERR_INVALID_ARG, std::string("unknown kernel family ") + name);
+}
+
+int iqp_profile_reset(void) {
+    hipError_t e = drain_timing();
+    for (int f = 0; f < KF_COUNT; ++f) {
+        g_timing.total_ms[f] = 0.0;
+        g_timing.launches[f] = 0;
+    }
+    return e == hipSuccess ? IQP_OK : hip_fail(e, "profile drain");
+}
+
+}  // extern "C"

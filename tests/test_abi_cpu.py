@@ -1,0 +1,155 @@
+"""Host-side checks of the C-ABI: the library loads, exports every symbol the
+header declares, validates arguments before any device work, and the bit
+packing round-trips. No GPU needed: invalid arguments are rejected before the
+library touches the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2501_04776_amd import _lib as L
+from paper_2501_04776_amd import packing
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "iqp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(iqp_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = header_functions()
+    assert set(names) == set(L.EXPORTED)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_strerror_texts():
+    assert L.strerror(0) == "success"
+    assert L.strerror(-1) == "invalid argument"
+    assert L.strerror(-2) == "workspace too small"
+    assert L.strerror(-3) == "HIP runtime error"
+    assert L.strerror(-4) == "unsupported"
+
+
+def _circ(n=70, m=10, gens=1, theta=1):
+    return L.IqpCircuit(n, (n + 63) // 64, m, gens, theta)
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+def _expval(c, l=4, ops=FAKE, s=8, samples=FAKE, prec=1, mean=FAKE, ws=FAKE, nb=1 << 40):
+    return L.lib().iqp_expval(ctypes.byref(c) if c is not None else None, l, ops, s, samples,
+                              prec, mean, None, None, ws, nb, None)
+
+
+@pytest.mark.parametrize("kwargs,msg", [
+    (dict(c=None), "circuit is NULL"),
+    (dict(c=_circ(n=0)), "n_qubits"),
+    (dict(c=L.IqpCircuit(70, 1, 10, 1, 1)), "n_words"),
+    (dict(c=_circ(m=0)), "n_gates"),
+    (dict(c=_circ(gens=None)), "gens is NULL"),
+    (dict(c=_circ(theta=None)), "theta is NULL"),
+    (dict(l=0), "l out of range"),
+    (dict(s=0), "s out of range"),
+    (dict(ops=None), "ops is NULL"),
+    (dict(samples=None), "samples is NULL"),
+    (dict(prec=7), "precision"),
+    (dict(mean=None), "mean is NULL"),
+])
+def test_expval_rejects_invalid_arguments(kwargs, msg):
+    kw = dict(c=_circ())
+    kw.update(kwargs)
+    st = _expval(**kw)
+    assert st == L.IQP_ERR_INVALID_ARG
+    assert msg in L.last_error()
+
+
+def test_expval_rejects_small_workspace():
+    st = _expval(_circ(), nb=16)
+    assert st == L.IQP_ERR_WORKSPACE
+    assert "need" in L.last_error()
+
+
+def test_grad_and_mmd_validation():
+    c = _circ()
+    lib = L.lib()
+    st = lib.iqp_expval_grad(ctypes.byref(c), 4, FAKE, 8, FAKE, 1, None, None, FAKE, FAKE,
+                             1 << 40, None)
+    assert st == L.IQP_ERR_INVALID_ARG and "grad_mean" in L.last_error()
+    st = lib.iqp_expval_grad(ctypes.byref(c), 4, FAKE, 8, FAKE, 1, FAKE, None, None, FAKE,
+                             1 << 40, None)
+    assert st == L.IQP_ERR_INVALID_ARG and "grad_theta" in L.last_error()
+    st = lib.iqp_mmd_loss_grad(ctypes.byref(c), 4, FAKE, None, 8, FAKE, 5, FAKE, 1, 1, FAKE,
+                               None, FAKE, 1 << 40, None)
+    assert st == L.IQP_ERR_INVALID_ARG and "op_weight" in L.last_error()
+    st = lib.iqp_mmd_loss_grad(ctypes.byref(c), 4, FAKE, FAKE, 8, FAKE, 1, FAKE, 1, 1, FAKE,
+                               None, FAKE, 1 << 40, None)
+    assert st == L.IQP_ERR_INVALID_ARG and "unbiased" in L.last_error()
+    st = lib.iqp_mmd_loss_grad(ctypes.byref(c), 4, FAKE, FAKE, 1, FAKE, 5, FAKE, 1, 1, FAKE,
+                               None, FAKE, 1 << 40, None)
+    assert st == L.IQP_ERR_INVALID_ARG
+    st = lib.iqp_mmd_loss_grad(ctypes.byref(c), 4, FAKE, FAKE, 8, FAKE, 0, FAKE, 0, 1, FAKE,
+                               None, FAKE, 1 << 40, None)
+    assert st == L.IQP_ERR_INVALID_ARG and "N out of range" in L.last_error()
+    st = lib.iqp_mmd_loss_grad(ctypes.byref(c), 4, FAKE, FAKE, 8, FAKE, 5, None, 0, 1, FAKE,
+                               None, FAKE, 1 << 40, None)
+    assert st == L.IQP_ERR_INVALID_ARG and "data is NULL" in L.last_error()
+
+
+def test_parity_validation_and_empty():
+    lib = L.lib()
+    assert lib.iqp_parity(-1, FAKE, 3, FAKE, 1, 0, FAKE, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_parity(3, FAKE, 3, FAKE, 0, 0, FAKE, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_parity(3, FAKE, 3, FAKE, 1, 5, FAKE, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_parity(3, None, 3, FAKE, 1, 0, FAKE, None) == L.IQP_ERR_INVALID_ARG
+    # empty inputs are a no-op that never touches the device
+    assert lib.iqp_parity(0, None, 3, None, 1, 0, None, None) == L.IQP_OK
+    assert lib.iqp_parity(3, None, 0, None, 1, 1, None, None) == L.IQP_OK
+
+
+def test_workspace_bytes_query():
+    lib = L.lib()
+    c = _circ(n=300, m=45150)
+    a = lib.iqp_workspace_bytes(L.IQP_CALL_EXPVAL, ctypes.byref(c), 1000, 10000, 0, 1)
+    b = lib.iqp_workspace_bytes(L.IQP_CALL_EXPVAL_GRAD_RECOMPUTE, ctypes.byref(c), 1000, 10000,
+                                0, 1)
+    d = lib.iqp_workspace_bytes(L.IQP_CALL_MMD_GRAD, ctypes.byref(c), 1000, 10000, 2000, 1)
+    assert 0 < a < b < d
+    assert lib.iqp_workspace_bytes(L.IQP_CALL_EXPVAL, ctypes.byref(c), 0, 10, 0, 1) == 0
+    assert lib.iqp_workspace_bytes(L.IQP_CALL_MMD, ctypes.byref(c), 10, 10, 0, 1) == 0
+    assert lib.iqp_workspace_bytes(9, ctypes.byref(c), 10, 10, 0, 1) == 0
+    assert lib.iqp_workspace_bytes(0, None, 10, 10, 0, 1) == 0
+
+
+def test_profile_query_unknown_name():
+    assert L.lib().iqp_profile_query(b"nope", ctypes.byref(ctypes.c_double()),
+                                     ctypes.byref(ctypes.c_int64())) == L.IQP_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 130, 300, 1000])
+def test_packing_round_trip(n):
+    rng = np.random.default_rng(n)
+    bits = W.uniform_bits(rng, 17, n)
+    words = packing.pack_dense(bits)
+    assert words.shape == (17, (n + 63) // 64)
+    assert np.array_equal(packing.unpack(words, n), bits)
+    # pad bits are zero
+    if n % 64:
+        assert np.all((words[:, -1] >> np.uint64(n % 64)) == 0)
+    rows = W.dense_to_rows(bits)
+    assert np.array_equal(packing.pack_index_rows(rows.ptr, rows.idx, n), words)
+
+
+def test_packing_bit_order():
+    # qubit q is bit (q & 63) of word (q >> 6)
+    w = packing.pack_index_rows(np.array([0, 3]), np.array([0, 63, 64]), 130)
+    assert w[0, 0] == np.uint64(1) | (np.uint64(1) << np.uint64(63))
+    assert w[0, 1] == np.uint64(1) and w[0, 2] == 0

@@ -1,0 +1,156 @@
+"""GPU vs oracle: the hand-written backward (gradient of a loss of the
+estimates), the MMD^2 chain and its gradient, central differences and the
+torch.autograd wrappers."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from paper_2501_04776_amd import IQPExpval, IQPMMDLoss, api
+from tests.gpu_util import TOL, DevWorkload
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp32", "split_bf16"]
+
+
+def _grad(dw, u, prec, saved):
+    circ = api.Circuit(dw.n, dw.gens, dw.theta)
+    ph = None
+    if saved:
+        _, _, ph = api.iqp_expval(circ, dw.ops, dw.samples, prec, phase_save=True)
+    g = api.iqp_expval_grad(circ, dw.ops, dw.samples, torch.from_numpy(u).cuda(), ph, prec)
+    torch.cuda.synchronize()
+    return g.cpu().numpy()
+
+
+def _gtol(prec, g):
+    return TOL[prec] * max(1.0, np.abs(g).max())
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("saved", [True, False])
+@pytest.mark.parametrize("shape", [(10, 55, 100, 1000), (70, 1000, 300, 700),
+                                   (130, 2100, 129, 1025)])
+def test_grad_matches_oracle(prec, saved, shape):
+    n, m, l, s = shape
+    w = W.small_random(3 * sum(shape), n, m, l, s)
+    dw = DevWorkload(w)
+    u = np.random.default_rng(1).normal(size=l)
+    g = _grad(dw, u, prec, saved)
+    og = oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01, w.samples, u)
+    err = np.abs(g - og).max()
+    print("grad %s %s saved=%s: max|d| = %.3g (|g|max %.3g)" % (shape, prec, saved, err,
+                                                                np.abs(og).max()))
+    assert err < _gtol(prec, og)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_grad_matches_central_differences_on_gpu(prec):
+    # the n = 10 all-local circuit; finite differences of the GPU forward, eps = 1e-3
+    w = W.cfg1(enumerate_samples=False)
+    dw = DevWorkload(w)
+    u = np.random.default_rng(2).normal(size=w.l)
+    g = _grad(dw, u, "fp32", True)
+    eps = 1e-3
+    circ_theta = w.theta.copy()
+    fd = np.zeros(w.m)
+    for j in range(w.m):
+        vals = []
+        for sgn in (1, -1):
+            t = circ_theta.copy()
+            t[j] += sgn * eps
+            c = api.Circuit(w.n, dw.gens, torch.from_numpy(t).cuda())
+            mean, _, _ = api.iqp_expval(c, dw.ops, dw.samples, "fp32")
+            vals.append(float(u @ mean.cpu().numpy()))
+        fd[j] = (vals[0] - vals[1]) / (2 * eps)
+    gp = _grad(dw, u, prec, True)
+    # FP32 phases carry ~1e-7 relative rounding, amplified by 1/(2 eps) in the FD
+    assert np.abs(g - fd).max() < 2e-3 * max(1.0, np.abs(g).max())
+    assert np.abs(gp - g).max() < _gtol(prec, g)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("unbiased", [True, False])
+def test_mmd_loss_and_grad_match_oracle(prec, unbiased):
+    n = 60
+    w = W.small_random(77, n, 700, 190, 600, with_data=150)
+    dw = DevWorkload(w)
+    circ = api.Circuit(w.n, dw.gens, dw.theta)
+    loss, g = api.iqp_mmd_loss_grad(circ, dw.ops, dw.op_weight, dw.samples, dw.data, unbiased,
+                                    True, prec)
+    loss_only, none = api.iqp_mmd_loss_grad(circ, dw.ops, dw.op_weight, dw.samples, dw.data,
+                                            unbiased, False, prec)
+    torch.cuda.synchronize()
+    assert none is None
+    ol, og = oracle.mmd_loss_grad(w.n, w.gates, w.theta, dw.ops01, w.op_weight, w.samples, w.data,
+                                  unbiased)
+    print("mmd %s unbiased=%s: loss %.6g vs %.6g, grad max|d| %.3g" %
+          (prec, unbiased, loss.item(), ol, np.abs(g.cpu().numpy() - og).max()))
+    assert abs(loss.item() - ol) < TOL[prec]
+    assert loss.item() == loss_only.item()
+    assert np.abs(g.cpu().numpy() - og).max() < _gtol(prec, og)
+
+
+def test_mmd_cfg4_shape_sampled():
+    # the differentiation workload's circuit (n = 300, 45150 gates), data
+    # (2000 Bernoulli(0.3) strings) and operator distribution (3 bandwidths),
+    # with 200 observables per bandwidth and s = 1000 so that the oracle's
+    # full loss and gradient stay within seconds
+    w = W.cfg4(ops_per_sigma=200, s=1000)
+    dw = DevWorkload(w)
+    circ = api.Circuit(w.n, dw.gens, dw.theta)
+    for prec in PRECS:
+        loss, g = api.iqp_mmd_loss_grad(circ, dw.ops, dw.op_weight, dw.samples, dw.data, True,
+                                        True, prec)
+        torch.cuda.synchronize()
+        if prec == "fp32":
+            ol, og = oracle.mmd_loss_grad(w.n, w.gates, w.theta, dw.ops01, w.op_weight,
+                                          w.samples, w.data, True)
+        print("cfg4(200/sigma, s=1000) %s: loss %.8g vs %.8g, grad max|d| %.3g of %.3g" %
+              (prec, loss.item(), ol, np.abs(g.cpu().numpy() - og).max(), np.abs(og).max()))
+        assert abs(loss.item() - ol) < TOL[prec]
+        assert np.abs(g.cpu().numpy() - og).max() < _gtol(prec, og)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_autograd_expval_end_to_end(prec):
+    w = W.small_random(88, 40, 300, 50, 400)
+    dw = DevWorkload(w)
+    theta = dw.theta.clone().requires_grad_(True)
+    mean, se = IQPExpval.apply(theta, dw.gens, dw.ops, dw.samples, w.n, prec)
+    u = torch.linspace(-1, 1, w.l, dtype=torch.float64, device="cuda")
+    loss = (mean * u).sum() + (mean ** 2).sum()
+    loss.backward()
+    ug = (u + 2 * mean.detach()).cpu().numpy()
+    og = oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01, w.samples, ug)
+    assert np.abs(theta.grad.cpu().numpy() - og).max() < _gtol(prec, og)
+    with pytest.raises(RuntimeError):
+        theta2 = dw.theta.clone().requires_grad_(True)
+        m2, s2 = IQPExpval.apply(theta2, dw.gens, dw.ops, dw.samples, w.n, prec)
+        s2.sum().backward()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_autograd_mmd_end_to_end(prec):
+    w = W.small_random(99, 30, 200, 60, 300, with_data=80)
+    dw = DevWorkload(w)
+    theta = dw.theta.clone().requires_grad_(True)
+    loss = IQPMMDLoss.apply(theta, dw.gens, dw.ops, dw.op_weight, dw.samples, dw.data, w.n, True,
+                            prec)
+    (3.0 * loss).backward()
+    ol, og = oracle.mmd_loss_grad(w.n, w.gates, w.theta, dw.ops01, w.op_weight, w.samples, w.data,
+                                  True)
+    assert abs(loss.item() - ol) < TOL[prec]
+    assert np.abs(theta.grad.cpu().numpy() - 3.0 * og).max() < _gtol(prec, 3.0 * og)
+
+
+def test_grad_deterministic_repeat():
+    w = W.small_random(111, 150, 2500, 300, 800)
+    dw = DevWorkload(w)
+    u = np.random.default_rng(5).normal(size=w.l)
+    for prec in PRECS:
+        a = _grad(dw, u, prec, False)
+        b = _grad(dw, u, prec, False)
+        assert np.array_equal(a, b)
