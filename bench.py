@@ -194,16 +194,27 @@ def main():
     result["parity"] = parity
 
     # --- oracle on the host cores -------------------------------------------
+    # a bounded sample of the same workload: fwd + bwd for the first k
+    # observables over all samples and gates, k sized for ~15 s of CPU time
     if not args.no_cpu_baseline and not mmd:
-        k = args.cpu_sample_ops or max(8, min(w.l, 96))
-        sel = np.arange(k)
-        uu = np.random.default_rng(5).normal(size=k)
-        t1 = time.time()
-        oracle.expval(w.n, w.gates, w.theta, dw.ops01[sel], w.samples)
-        oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01[sel], w.samples, uu)
-        dt = time.time() - t1
+        def oracle_run(k):
+            sel = np.arange(k)
+            uu = np.random.default_rng(5).normal(size=k)
+            t1 = time.time()
+            oracle.expval(w.n, w.gates, w.theta, dw.ops01[sel], w.samples)
+            oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01[sel], w.samples, uu)
+            return time.time() - t1
+        nth = oracle.num_threads()
+        k = args.cpu_sample_ops
+        if not k:
+            k0 = min(w.l, max(nth, 8))
+            dt0 = oracle_run(k0)
+            k = int(min(w.l, max(k0, round(k0 * 15.0 / max(dt0, 1e-3)))))
+            k = max(nth, (k // nth) * nth) if k >= nth else k
+        dt = oracle_run(k)
+        log("oracle: %d observables in %.2f s on %d threads" % (k, dt, nth))
         result["cpu_baseline"] = {"value": k * w.s * w.m / dt, "unit": "terms/s",
-                                  "cores": oracle.num_threads(), "kind": "oracle",
+                                  "cores": min(nth, k), "kind": "oracle",
                                   "sample": "fwd+bwd of the first %d of %d observables over all "
                                             "%d samples and %d gates (%.1f s)" %
                                             (k, w.l, w.s, w.m, dt)}

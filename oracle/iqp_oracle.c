@@ -17,8 +17,11 @@
  * Parity unpinned: none. Every routine here is pinned by a CPU test against
  * the paper's closed forms, a state-vector simulation or brute force.
  */
+#define _GNU_SOURCE
 #include <complex.h>
 #include <math.h>
+#include <sched.h>
+#include <stdio.h>
 #include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -45,10 +48,23 @@ static double sign_of(const uint8_t *x, const int64_t *gptr, const int32_t *gidx
     return (overlap(x, gptr, gidx, j) & 1) ? -1.0 : 1.0;
 }
 
+/* Threads = CPUs in this process's affinity mask, capped by OMP_NUM_THREADS
+ * when that is set (the host's share of cores for this job). */
 int orc_num_threads(void)
 {
-    long n = sysconf(_SC_NPROCESSORS_ONLN);
-    return n > 0 ? (int)n : 1;
+    int n = 0;
+    cpu_set_t set;
+    if (sched_getaffinity(0, sizeof(set), &set) == 0) n = CPU_COUNT(&set);
+    if (n <= 0) {
+        long c = sysconf(_SC_NPROCESSORS_ONLN);
+        n = c > 0 ? (int)c : 1;
+    }
+    const char *env = getenv("OMP_NUM_THREADS");
+    if (env) {
+        int cap = atoi(env);
+        if (cap > 0 && cap < n) n = cap;
+    }
+    return n;
 }
 
 /* ------------------------------------------------------------------------ */
