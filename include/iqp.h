@@ -86,17 +86,26 @@ size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s,
 
 /* Parity bit matrix (the exponents of B = (-1)^{Z G^T} and of
  * C = 1 - (-1)^{A G^T}, Sec. 2.2): bit (r, c) = popcount(row_r AND col_c) mod 2.
+ * Computed bit-sliced: the rows are transposed into per-qubit bit columns and
+ * the parity against col_c is the XOR of the columns in col_c's support, so
+ * the cost grows with the weight of the col rows (pass the sparse operand,
+ * e.g. the generators, as cols).
  *   rows      device [n_rows][W], cols device [n_cols][W]
- *   layout    IQP_BITS_ROW_MAJOR: out[r * ceil(n_cols/64) + c/64], bit c % 64;
- *             IQP_BITS_TILED32:   rows padded to a multiple of 32,
+ *   layout    IQP_BITS_ROW_MAJOR:  out[r * ceil(n_cols/64) + c/64], bit c % 64
+ *             IQP_BITS_TILED32:    rows padded to a multiple of 32,
  *               out[((r / 32) * ceil(n_cols/64) + c/64) * 32 + r % 32], bit c % 64
- *               (the layout the phase-contraction kernels read).
- *   out       device, ceil(n_cols/64) words per row (rows padded to 32 for
- *             TILED32; pad rows and bits at c >= n_cols are written as 0).
- * n_rows >= 0, n_cols >= 0, W >= 1. Bit-exact. */
-enum { IQP_BITS_ROW_MAJOR = 0, IQP_BITS_TILED32 = 1 };
+ *               (the layout the phase-contraction kernels read)
+ *             IQP_BITS_TILED32_T:  the transposed matrix, tiled32 over the
+ *               columns padded to a multiple of 64:
+ *               out[((c / 32) * ceil(n_rows/64) + r/64) * 32 + c % 32], bit r % 64
+ *   out       device; pad rows and bits past the last row/column are written 0
+ *   ws        device workspace of ws_bytes >= iqp_parity_workspace_bytes(n_rows, W, layout)
+ * n_rows >= 0, n_cols >= 0, W >= 1 (n_rows or n_cols = 0 is a no-op). Bit-exact. */
+enum { IQP_BITS_ROW_MAJOR = 0, IQP_BITS_TILED32 = 1, IQP_BITS_TILED32_T = 2 };
+size_t iqp_parity_workspace_bytes(int64_t n_rows, int32_t n_words, int layout);
 int iqp_parity(int64_t n_rows, const uint64_t *rows, int64_t n_cols, const uint64_t *cols,
-               int32_t n_words, int layout, uint64_t *out, void *stream);
+               int32_t n_words, int layout, uint64_t *out, void *ws, size_t ws_bytes,
+               void *stream);
 
 /* Monte Carlo estimates of <Z_{a_k}> (eq. expvalsample, batched as Prop. 2).
  *   ops        device [l][W] observables a_k, l >= 1

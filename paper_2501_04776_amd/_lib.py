@@ -29,9 +29,10 @@ IQP_CALL_MMD_GRAD = 4
 
 IQP_BITS_ROW_MAJOR = 0
 IQP_BITS_TILED32 = 1
+IQP_BITS_TILED32_T = 2
 
 # every symbol include/iqp.h declares
-EXPORTED = ("iqp_workspace_bytes", "iqp_parity", "iqp_expval", "iqp_expval_grad",
+EXPORTED = ("iqp_workspace_bytes", "iqp_parity_workspace_bytes", "iqp_parity", "iqp_expval", "iqp_expval_grad",
             "iqp_mmd_loss_grad", "iqp_strerror", "iqp_last_error", "iqp_profile_enable",
             "iqp_profile_query", "iqp_profile_reset")
 
@@ -64,7 +65,9 @@ def lib():
     cp = ctypes.POINTER(IqpCircuit)
     L.iqp_workspace_bytes.argtypes = [i32, cp, i64, i64, i64, i32]
     L.iqp_workspace_bytes.restype = sz
-    L.iqp_parity.argtypes = [i64, vp, i64, vp, ctypes.c_int32, i32, vp, vp]
+    L.iqp_parity_workspace_bytes.argtypes = [i64, ctypes.c_int32, i32]
+    L.iqp_parity_workspace_bytes.restype = sz
+    L.iqp_parity.argtypes = [i64, vp, i64, vp, ctypes.c_int32, i32, vp, vp, sz, vp]
     L.iqp_parity.restype = i32
     L.iqp_expval.argtypes = [cp, i64, vp, i64, vp, i32, vp, vp, vp, vp, sz, vp]
     L.iqp_expval.restype = i32

@@ -18,6 +18,7 @@ FP32 = L.IQP_FP32
 SPLIT_BF16 = L.IQP_SPLIT_BF16
 ROW_MAJOR = L.IQP_BITS_ROW_MAJOR
 TILED32 = L.IQP_BITS_TILED32
+TILED32_T = L.IQP_BITS_TILED32_T
 
 _PRECISIONS = {"fp32": FP32, "split_bf16": SPLIT_BF16, FP32: FP32, SPLIT_BF16: SPLIT_BF16}
 
@@ -92,15 +93,20 @@ def workspace_bytes(call: int, n: int, m: int, l: int, s: int, N: int = 0,
 
 def iqp_parity(rows: torch.Tensor, cols: torch.Tensor, n_qubits: int,
                layout: int = ROW_MAJOR) -> torch.Tensor:
-    """Bits (r, c) = popcount(rows[r] & cols[c]) mod 2 (see include/iqp.h)."""
+    """Bits (r, c) = popcount(rows[r] & cols[c]) mod 2 in one of the layouts
+    of include/iqp.h (cost grows with the weight of the cols rows)."""
     W = (n_qubits + 63) // 64
     rows = _rows(rows, "rows", W)
     cols = _rows(cols, "cols", W)
     R, C = rows.shape[0], cols.shape[0]
-    Cw = (C + 63) // 64
-    Rout = (R + 31) // 32 * 32 if layout == TILED32 else R
-    out = torch.empty((Rout, Cw), dtype=torch.int64, device=rows.device)
-    L.check(L.lib().iqp_parity(R, _ptr(rows), C, _ptr(cols), W, layout, _ptr(out),
+    if layout == TILED32_T:
+        shape = ((C + 63) // 64 * 64, (R + 63) // 64)
+    else:
+        shape = ((R + 31) // 32 * 32 if layout == TILED32 else R, (C + 63) // 64)
+    out = torch.empty(shape, dtype=torch.int64, device=rows.device)
+    need = int(L.lib().iqp_parity_workspace_bytes(R, W, layout))
+    ws, nb = workspace.get(rows.device, need)
+    L.check(L.lib().iqp_parity(R, _ptr(rows), C, _ptr(cols), W, layout, _ptr(out), _ptr(ws), nb,
                                _stream(rows)), "iqp_parity")
     return out
 

@@ -3,6 +3,8 @@
 // the optional per-kernel timing.
 #include <hip/hip_runtime.h>
 
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <string>
@@ -125,6 +127,9 @@ struct Plan {
     size_t o_thh = 0, o_thl = 0, o_t32 = 0, o_cbits = 0, o_bbits = 0, o_E = 0, o_part = 0;
     size_t o_rowsum = 0, o_phi = 0, o_coef = 0, o_ctbits = 0, o_shi = 0, o_slo = 0, o_s32 = 0;
     size_t o_gpart = 0, o_dbits = 0, o_pstat = 0;
+    size_t o_xz = 0, o_xa = 0, o_xd = 0;  // bit columns of samples, ops, data
+    size_t o_btbits = 0;                  // B^T: samples against generators, transposed
+    int64_t ldz = 0, lda = 0, ldd = 0;
     size_t total = 0;
 };
 
@@ -151,8 +156,30 @@ static size_t carve(size_t &cur, size_t bytes) {
     return o;
 }
 
+// Tile overrides for measurement sweeps: IQP_FWD_TILE / IQP_BWD_TILE = "FMxFN"
+// (one of 4x4, 2x4, 2x2) and
+// IQP_FWD_SPLITS = number of gate-word splits of the forward.
+static void apply_env_tiles(TileCfg &tc) {
+    const char *f = getenv("IQP_FWD_TILE");
+    int a = 0, b = 0;
+    if (f && sscanf(f, "%dx%d", &a, &b) == 2 &&
+        ((a == 4 && b == 4) || (a == 2 && b == 4) || (a == 2 && b == 2))) {
+        tc.fm = a;
+        tc.fn = b;
+    }
+    const char *g = getenv("IQP_BWD_TILE");
+    if (g && sscanf(g, "%dx%d", &a, &b) == 2 &&
+        ((a == 4 && b == 4) || (a == 2 && b == 4) || (a == 2 && b == 2))) {
+        tc.bfm = a;
+        tc.bfn = b;
+    }
+    const char *sp = getenv("IQP_FWD_SPLITS");
+    if (sp && atoi(sp) > 0) tc.splits = atoi(sp);
+}
+
 static void make_plan(Plan &P, int call, int64_t n, int64_t m, int64_t l, int64_t s, int64_t N,
                       int prec) {
+    apply_env_tiles(P.tc);
     P.prec = prec;
     P.n = n;
     P.W = ceil_div(n, 64);
@@ -168,16 +195,22 @@ static void make_plan(Plan &P, int call, int64_t n, int64_t m, int64_t l, int64_
     P.Nw = ceil_div(N > 0 ? N : 1, 64);
     P.nchunk = ceil_div(s, kEpiChunk);
     const int64_t tiles = (P.l_pad / (32 * P.tc.fm)) * (P.s_pad / (32 * P.tc.fn));
-    P.tc.splits = choose_splits(tiles, P.mw);
+    if (P.tc.splits <= 0) P.tc.splits = choose_splits(tiles, P.mw);
+    if (P.tc.splits > P.mw) P.tc.splits = P.mw;
     P.fwd = call != IQP_CALL_EXPVAL_GRAD;
     P.bwd = call == IQP_CALL_EXPVAL_GRAD || call == IQP_CALL_EXPVAL_GRAD_RECOMPUTE ||
             call == IQP_CALL_MMD_GRAD;
     P.phi = call == IQP_CALL_EXPVAL_GRAD_RECOMPUTE || call == IQP_CALL_MMD_GRAD;
     P.mmd = call == IQP_CALL_MMD || call == IQP_CALL_MMD_GRAD;
     size_t cur = 0;
-    // B parity bits serve both contractions
-    P.o_bbits = carve(cur, (size_t)P.s_pad * P.mw * 8);
+    // bit columns (64 W qubits x ld words of 64 rows) for the bit-sliced parity
+    P.ldz = round_up(P.s_pad / 64, 4);
+    P.lda = round_up(P.l_pad / 64, 4);
+    P.ldd = round_up(P.Nw, 4);
+    P.o_xz = carve(cur, (size_t)64 * P.W * P.ldz * 8);
+    P.o_xa = carve(cur, (size_t)64 * P.W * P.lda * 8);
     if (P.fwd) {
+        P.o_bbits = carve(cur, (size_t)P.s_pad * P.mw * 8);
         if (prec == IQP_SPLIT_BF16) {
             P.o_thh = carve(cur, (size_t)P.m_pad * 2);
             P.o_thl = carve(cur, (size_t)P.m_pad * 2);
@@ -193,16 +226,18 @@ static void make_plan(Plan &P, int call, int64_t n, int64_t m, int64_t l, int64_
     if (P.bwd) {
         P.o_coef = carve(cur, (size_t)l * 2 * 8);
         P.o_ctbits = carve(cur, (size_t)P.m_pad * P.lw * 8);
+        P.o_btbits = carve(cur, (size_t)P.m_pad * (P.s_pad / 64) * 8);
         if (prec == IQP_SPLIT_BF16) {
             P.o_shi = carve(cur, (size_t)P.s_pad * P.l_pad * 2);
             P.o_slo = carve(cur, (size_t)P.s_pad * P.l_pad * 2);
         } else {
             P.o_s32 = carve(cur, (size_t)P.s_pad * P.l_pad * 4);
         }
-        P.o_gpart = carve(cur, (size_t)(P.s_pad / (32 * P.tc.bfn)) * P.m_pad * 4);
+        P.o_gpart = carve(cur, (size_t)(P.l_pad / (32 * P.tc.bfm)) * P.m_pad * 4);
     }
     if (P.mmd) {
-        P.o_dbits = carve(cur, (size_t)l * P.Nw * 8);
+        P.o_xd = carve(cur, (size_t)64 * P.W * P.ldd * 8);
+        P.o_dbits = carve(cur, (size_t)round_up(l, 64) * P.Nw * 8);
         P.o_pstat = carve(cur, (size_t)l * 2 * 8);
     }
     P.total = cur;
@@ -262,11 +297,14 @@ static int run_forward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
     IQP_TRY(launch_theta_prep(lc, c->theta, P.m, P.m_pad, P.prec, at<uint16_t>(ws, P.o_thh),
                               at<uint16_t>(ws, P.o_thl), at<float>(ws, P.o_t32)),
             "theta_prep");
-    IQP_TRY(launch_parity(lc, ops, P.l, P.l_pad, c->gens, P.m, P.mw, W, IQP_BITS_TILED32,
-                          at<uint64_t>(ws, P.o_cbits)),
+    IQP_TRY(launch_bitslice(lc, ops, P.l, W, P.lda, at<uint64_t>(ws, P.o_xa)), "bitslice(A)");
+    IQP_TRY(launch_parity_bs(lc, c->gens, P.m, W, at<uint64_t>(ws, P.o_xa), P.l_pad / 64, P.lda,
+                             P.l_pad, P.mw, IQP_BITS_TILED32, at<uint64_t>(ws, P.o_cbits)),
             "parity(C)");
-    IQP_TRY(launch_parity(lc, samples, P.s, P.s_pad, c->gens, P.m, P.mw, W, IQP_BITS_TILED32,
-                          at<uint64_t>(ws, P.o_bbits)),
+    IQP_TRY(launch_bitslice(lc, samples, P.s, W, P.ldz, at<uint64_t>(ws, P.o_xz)),
+            "bitslice(Z)");
+    IQP_TRY(launch_parity_bs(lc, c->gens, P.m, W, at<uint64_t>(ws, P.o_xz), P.s_pad / 64, P.ldz,
+                             P.s_pad, P.mw, IQP_BITS_TILED32, at<uint64_t>(ws, P.o_bbits)),
             "parity(B)");
     IQP_TRY(launch_phase_fwd(lc, P.prec, P.tc.fm, P.tc.fn, at<uint64_t>(ws, P.o_cbits),
                              at<uint64_t>(ws, P.o_bbits), at<uint16_t>(ws, P.o_thh),
@@ -281,28 +319,35 @@ static int run_forward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
     return IQP_OK;
 }
 
-// Backward from the coefficients at o_coef and the phases `phase`.
+// Backward from the coefficients at o_coef and the phases `phase`. When the
+// forward ran in the same call, the bit columns of A and Z are already in the
+// workspace.
 static int run_backward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
-                        const uint64_t *samples, const float *phase, bool bbits_ready, void *ws,
+                        const uint64_t *samples, const float *phase, bool bitcols_ready, void *ws,
                         const LaunchCtx &lc, double *grad_theta) {
     const int W = (int)P.W;
     IQP_TRY(launch_weights(lc, P.prec, phase, at<double>(ws, P.o_coef), P.l, P.s, P.l_pad,
                            P.s_pad, at<uint16_t>(ws, P.o_shi), at<uint16_t>(ws, P.o_slo),
                            at<float>(ws, P.o_s32)),
             "weights");
-    IQP_TRY(launch_parity(lc, c->gens, P.m, P.m_pad, ops, P.l, P.lw, W, IQP_BITS_TILED32,
-                          at<uint64_t>(ws, P.o_ctbits)),
+    if (!bitcols_ready) {
+        IQP_TRY(launch_bitslice(lc, ops, P.l, W, P.lda, at<uint64_t>(ws, P.o_xa)),
+                "bitslice(A)");
+        IQP_TRY(launch_bitslice(lc, samples, P.s, W, P.ldz, at<uint64_t>(ws, P.o_xz)),
+                "bitslice(Z)");
+    }
+    IQP_TRY(launch_parity_bs(lc, c->gens, P.m, W, at<uint64_t>(ws, P.o_xz), P.s_pad / 64, P.ldz,
+                             0, P.mw, IQP_BITS_TILED32_T, at<uint64_t>(ws, P.o_btbits)),
+            "parity(B^T)");
+    IQP_TRY(launch_parity_bs(lc, c->gens, P.m, W, at<uint64_t>(ws, P.o_xa), P.lw, P.lda, 0, P.mw,
+                             IQP_BITS_TILED32_T, at<uint64_t>(ws, P.o_ctbits)),
             "parity(C^T)");
-    if (!bbits_ready)
-        IQP_TRY(launch_parity(lc, samples, P.s, P.s_pad, c->gens, P.m, P.mw, W, IQP_BITS_TILED32,
-                              at<uint64_t>(ws, P.o_bbits)),
-                "parity(B)");
-    IQP_TRY(launch_phase_bwd(lc, P.prec, P.tc.bfm, P.tc.bfn, at<uint64_t>(ws, P.o_ctbits),
-                             at<uint16_t>(ws, P.o_shi), at<uint16_t>(ws, P.o_slo),
-                             at<float>(ws, P.o_s32), at<uint64_t>(ws, P.o_bbits), P.m_pad,
+    IQP_TRY(launch_phase_bwd(lc, P.prec, P.tc.bfm, P.tc.bfn, at<uint16_t>(ws, P.o_shi),
+                             at<uint16_t>(ws, P.o_slo), at<float>(ws, P.o_s32),
+                             at<uint64_t>(ws, P.o_btbits), at<uint64_t>(ws, P.o_ctbits), P.m_pad,
                              P.l_pad, P.s_pad, at<float>(ws, P.o_gpart)),
             "phase_bwd");
-    IQP_TRY(launch_grad_reduce(lc, at<float>(ws, P.o_gpart), P.s_pad / (32 * P.tc.bfn), P.m,
+    IQP_TRY(launch_grad_reduce(lc, at<float>(ws, P.o_gpart), P.l_pad / (32 * P.tc.bfm), P.m,
                                P.m_pad, grad_theta),
             "grad_reduce");
     return IQP_OK;
@@ -332,22 +377,48 @@ size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s,
     return P.total;
 }
 
+static int64_t parity_rows_out(int64_t n_rows, int layout) {
+    return layout == IQP_BITS_ROW_MAJOR ? n_rows : round_up(n_rows, 32);
+}
+
+size_t iqp_parity_workspace_bytes(int64_t n_rows, int32_t n_words, int layout) {
+    if (n_rows < 0 || n_words < 1) return 0;
+    const int64_t rw = ceil_div(parity_rows_out(n_rows, layout), 64);
+    return (size_t)64 * n_words * round_up(rw, 4) * 8 + 256;
+}
+
 int iqp_parity(int64_t n_rows, const uint64_t *rows, int64_t n_cols, const uint64_t *cols,
-               int32_t n_words, int layout, uint64_t *out, void *stream) {
+               int32_t n_words, int layout, uint64_t *out, void *ws, size_t ws_bytes,
+               void *stream) {
     g_last_error.clear();
     if (n_rows < 0 || n_rows > kMaxRows * 4) return fail(IQP_ERR_INVALID_ARG, "n_rows out of range");
     if (n_cols < 0 || n_cols > kMaxRows * 4) return fail(IQP_ERR_INVALID_ARG, "n_cols out of range");
     if (n_words < 1) return fail(IQP_ERR_INVALID_ARG, "n_words must be >= 1");
-    if (layout != IQP_BITS_ROW_MAJOR && layout != IQP_BITS_TILED32)
+    if (layout != IQP_BITS_ROW_MAJOR && layout != IQP_BITS_TILED32 && layout != IQP_BITS_TILED32_T)
         return fail(IQP_ERR_INVALID_ARG, "unknown layout");
     if (n_rows == 0 || n_cols == 0) return IQP_OK;
     if (!rows || !cols || !out) return fail(IQP_ERR_INVALID_ARG, "NULL pointer");
+    const size_t need = iqp_parity_workspace_bytes(n_rows, n_words, layout);
+    if (ws_bytes < need)
+        return fail(IQP_ERR_WORKSPACE, "workspace of " + std::to_string(ws_bytes) +
+                                           " bytes, need " + std::to_string(need));
+    if (!ws) return fail(IQP_ERR_INVALID_ARG, "ws is NULL");
     int st = check_device();
     if (st) return st;
-    const int64_t R_out = layout == IQP_BITS_TILED32 ? round_up(n_rows, 32) : n_rows;
-    IQP_TRY(launch_parity(make_ctx(stream), rows, n_rows, R_out, cols, n_cols,
-                          ceil_div(n_cols, 64), n_words, layout, out),
-            "parity");
+    LaunchCtx lc = make_ctx(stream);
+    const int64_t R_out = parity_rows_out(n_rows, layout);
+    const int64_t rw = ceil_div(R_out, 64);
+    const int64_t ldx = round_up(rw, 4);
+    uint64_t *xt = static_cast<uint64_t *>(ws);
+    IQP_TRY(launch_bitslice(lc, rows, n_rows, n_words, ldx, xt), "bitslice");
+    if (layout == IQP_BITS_TILED32_T)
+        IQP_TRY(launch_parity_bs(lc, cols, n_cols, n_words, xt, ceil_div(n_rows, 64), ldx, 0,
+                                 ceil_div(n_cols, 64), layout, out),
+                "parity");
+    else
+        IQP_TRY(launch_parity_bs(lc, cols, n_cols, n_words, xt, rw, ldx, R_out,
+                                 ceil_div(n_cols, 64), layout, out),
+                "parity");
     return IQP_OK;
 }
 
@@ -414,8 +485,10 @@ int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
     float *phi = grad_theta ? at<float>(ws, P.o_phi) : nullptr;
     st = run_forward(P, c, ops, samples, ws, lc, phi, nullptr, nullptr, at<double>(ws, P.o_rowsum));
     if (st) return st;
-    IQP_TRY(launch_parity(lc, ops, l, l, data, N, P.Nw, (int)P.W, IQP_BITS_ROW_MAJOR,
-                          at<uint64_t>(ws, P.o_dbits)),
+    IQP_TRY(launch_bitslice(lc, data, N, (int)P.W, P.ldd, at<uint64_t>(ws, P.o_xd)),
+            "bitslice(data)");
+    IQP_TRY(launch_parity_bs(lc, ops, l, (int)P.W, at<uint64_t>(ws, P.o_xd), P.Nw, P.ldd, 0,
+                             ceil_div(l, 64), IQP_BITS_TILED32_T, at<uint64_t>(ws, P.o_dbits)),
             "parity(data)");
     IQP_TRY(launch_data_stats(lc, at<uint64_t>(ws, P.o_dbits), l, P.Nw, N,
                               at<double>(ws, P.o_pstat)),

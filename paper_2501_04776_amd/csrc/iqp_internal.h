@@ -24,7 +24,7 @@ __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_
 // Tile configuration of the two contractions (wave tile = 32*fm x 32*fn).
 struct TileCfg {
     int fm = 4, fn = 4;      // forward: observables x samples
-    int bfm = 4, bfn = 4;    // backward: gates x samples
+    int bfm = 4, bfn = 4;    // backward: observables x gates
     int64_t splits = 0;      // forward split over gate words; 0 = choose
 };
 
@@ -47,9 +47,16 @@ void timed_end(const LaunchCtx &lc, int family, hipEvent_t ev);
 hipError_t launch_theta_prep(const LaunchCtx &lc, const double *theta, int64_t m, int64_t m_pad,
                              int prec, uint16_t *hi, uint16_t *lo, float *t32);
 
-hipError_t launch_parity(const LaunchCtx &lc, const uint64_t *rows, int64_t R, int64_t R_out,
-                         const uint64_t *cols, int64_t C, int64_t Cw, int W, int layout,
-                         uint64_t *out);
+// Bit columns of `rows`: Xt[q * ldx + rw], q < 64 W, rw < ldx (>= ceil(R/64)).
+hipError_t launch_bitslice(const LaunchCtx &lc, const uint64_t *rows, int64_t R, int W,
+                           int64_t ldx, uint64_t *Xt);
+
+// Parity of each generator (m of them, W words each) against the rows behind
+// Xt (Rw words of 64 rows), in layout 0 (row-major), 1 (tiled32) or 2
+// (transposed tiled32); Gw = output words per row in layouts 0/1.
+hipError_t launch_parity_bs(const LaunchCtx &lc, const uint64_t *gens, int64_t m, int W,
+                            const uint64_t *Xt, int64_t Rw, int64_t ldx, int64_t R_out,
+                            int64_t Gw, int layout, uint64_t *out);
 
 hipError_t launch_phase_fwd(const LaunchCtx &lc, int prec, int fm, int fn, const uint64_t *cbits,
                             const uint64_t *bbits, const uint16_t *thh, const uint16_t *thl,
@@ -70,9 +77,12 @@ hipError_t launch_weights(const LaunchCtx &lc, int prec, const float *phase, con
                           int64_t l, int64_t s, int64_t l_pad, int64_t s_pad, uint16_t *shi,
                           uint16_t *slo, float *s32);
 
-hipError_t launch_phase_bwd(const LaunchCtx &lc, int prec, int fm, int fn, const uint64_t *ctbits,
-                            const uint16_t *shi, const uint16_t *slo, const float *s32,
-                            const uint64_t *bbits, int64_t m_pad, int64_t l_pad, int64_t s_pad,
+// T = S B (observables x gates, K = samples) and the gradient partials
+// gpart[l_pad / (32 fm)][m_pad]; btbits / ctbits are the transposed tiled32
+// parities of the samples / observables against the generators.
+hipError_t launch_phase_bwd(const LaunchCtx &lc, int prec, int fm, int fn, const uint16_t *shi,
+                            const uint16_t *slo, const float *s32, const uint64_t *btbits,
+                            const uint64_t *ctbits, int64_t m_pad, int64_t l_pad, int64_t s_pad,
                             float *gpart);
 
 hipError_t launch_grad_reduce(const LaunchCtx &lc, const float *gpart, int64_t n_parts,

@@ -2,9 +2,9 @@
 //
 //   theta_prep      theta -> 2 theta' (theta' = theta reduced to [-pi/2, pi/2]
 //                   by whole multiples of pi), as FP32 or BF16 hi + lo
-//   parity          bit-exact popcount(row AND col) mod 2 matrices (the
-//                   exponents of B and C, Sec. 2.2), one wave per 64 columns
-//                   x 32 rows, packed with a 64-lane ballot
+//   bitslice,       bit-exact popcount(row AND col) mod 2 matrices (the
+//   parity_bs       exponents of B and C, Sec. 2.2) as XORs of per-qubit bit
+//                   columns, with in-register 64x64 bit transposes
 //   phase_fwd       E = C Theta B^T (eq. Emat) on the matrix cores, operands
 //                   expanded from parity bits in registers
 //   epilogue        FP64 reduction of E modulo 2 pi, cos, per-chunk sums of
@@ -95,78 +95,136 @@ hipError_t launch_theta_prep(const LaunchCtx &lc, const double *theta, int64_t m
 }
 
 // ---------------------------------------------------------------------------
-// parity: out bit (r, c) = popcount(rows[r] AND cols[c]) mod 2.
-// One wave owns 64 columns (one per lane) and 32 rows. Row words are
-// wave-uniform (scalar loads); the AND is XOR-folded over the W words so one
-// popcount per entry remains. A ballot packs the 64 column parities of a row
-// into one word, which lane (r mod 32) then stores: 32 consecutive words per
-// wave for the tiled layout.
-template <int LAYOUT>
-__global__ __launch_bounds__(256) void parity_kernel(const uint64_t *__restrict__ rows, int64_t R,
-                                                     int64_t R_out,
-                                                     const uint64_t *__restrict__ cols,
-                                                     int64_t C, int64_t Cw, int W,
-                                                     uint64_t *__restrict__ out) {
+// Parity bits, bit-sliced. parity(x, g) = XOR over the qubits q of g of x_q,
+// so with the rows transposed into per-qubit bit columns Xt[q] (bit r = qubit
+// q of row r), the parities of one generator g against 64 rows are the XOR of
+// |g| words. Cost grows with the weight of g (1..4 in the circuits of the
+// paper), not with n.
+//
+// transpose64: lane r holds row r of a 64x64 bit matrix (bit c = column c)
+// and receives row r of its transpose. Six butterfly stages: at block size k
+// lanes r and r^k swap the off-diagonal k x k blocks of their 2k x 2k block.
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int k) {
+    const int lo = __shfl_xor((int)(uint32_t)x, k, 64);
+    const int hi = __shfl_xor((int)(uint32_t)(x >> 32), k, 64);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ uint64_t transpose64(uint64_t x, int lane) {
+    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull,
+                               0x00FF00FF00FF00FFull, 0x0F0F0F0F0F0F0F0Full,
+                               0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int k = 32 >> st;
+        const uint64_t m = masks[st];
+        const uint64_t p = shfl_xor_u64(x, k);
+        x = (lane & k) ? ((x & ~m) | ((p & ~m) >> k)) : ((x & m) | ((p & m) << k));
+    }
+    return x;
+}
+
+// Xt[q * ldx + rw]: bit r = qubit q of row 64 rw + r (rows >= R read as 0),
+// for q < 64 W and rw < ldx.
+__global__ __launch_bounds__(256) void bitslice_kernel(const uint64_t *__restrict__ rows,
+                                                       int64_t R, int W, int64_t ldx,
+                                                       uint64_t *__restrict__ Xt) {
     const int lane = threadIdx.x & 63;
     const int64_t unit = (int64_t)blockIdx.x * 4 + wave_id();
-    const int64_t nrb = ceil_div(R_out, 32);
-    if (unit >= nrb * Cw) return;
-    const int64_t rb = unit / Cw, cw = unit - rb * Cw;
-    const int64_t c = cw * 64 + lane;
-    const bool cvalid = c < C;
-    const int64_t r0 = rb * 32;
-    int64_t nr64 = R - r0;
-    const int nr = nr64 <= 0 ? 0 : (nr64 >= 32 ? 32 : (int)nr64);
-    uint64_t acc[32];
+    if (unit >= ldx * W) return;
+    const int64_t w = unit / ldx, rw = unit - w * ldx;
+    const int64_t r = rw * 64 + lane;
+    const uint64_t x = r < R ? rows[r * W + w] : 0ull;
+    Xt[(w * 64 + lane) * ldx + rw] = transpose64(x, lane);
+}
+
+// One wave: 64 generators (lane j) x kRowWords words of 64 rows.
+//   LAYOUT 0: row-major    out[r * Gw + j/64], bit j%64
+//   LAYOUT 1: tiled32      out[((r/32) * Gw + j/64) * 32 + r%32], bit j%64
+//   LAYOUT 2: transposed tiled32 (rows = generators)
+//             out[((j/32) * Rw + r/64) * 32 + j%32], bit r%64
+// Layouts 0 and 1 transpose each 64x64 block in registers; layout 2 stores
+// the XOR words as they are. Generators j >= m, and rows beyond the bit
+// columns, give zero bits.
+constexpr int kRowWords = 4;
+
+template <int LAYOUT>
+__global__ __launch_bounds__(256) void parity_bs_kernel(const uint64_t *__restrict__ gens,
+                                                        int64_t m, int W,
+                                                        const uint64_t *__restrict__ Xt,
+                                                        int64_t Rw, int64_t ldx, int64_t R_out,
+                                                        int64_t Gw, uint64_t *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t n_rg = ceil_div(Rw, kRowWords);
+    const int64_t unit = (int64_t)blockIdx.x * 4 + wave_id();
+    if (unit >= Gw * n_rg) return;
+    const int64_t rg = unit / Gw, gb = unit - rg * Gw;
+    const int64_t j = gb * 64 + lane;
+    const int64_t rw0 = rg * kRowWords;
+    uint64_t acc[kRowWords];
 #pragma unroll
-    for (int r = 0; r < 32; ++r) acc[r] = 0;
-    if (nr == 32) {
+    for (int t = 0; t < kRowWords; ++t) acc[t] = 0;
+    if (j < m) {
         for (int w = 0; w < W; ++w) {
-            const uint64_t g = cvalid ? cols[c * W + w] : 0ull;
-            const uint64_t *rp = rows + r0 * W + w;
+            uint64_t x = gens[j * W + w];
+            while (x) {
+                const int64_t q = (int64_t)w * 64 + __builtin_ctzll(x);
+                x &= x - 1;
+                const uint64_t *xp = Xt + q * ldx + rw0;
 #pragma unroll
-            for (int r = 0; r < 32; ++r) acc[r] ^= rp[(int64_t)r * W] & g;
-        }
-    } else if (nr > 0) {
-        for (int w = 0; w < W; ++w) {
-            const uint64_t g = cvalid ? cols[c * W + w] : 0ull;
-            const uint64_t *rp = rows + r0 * W + w;
-#pragma unroll
-            for (int r = 0; r < 32; ++r)
-                if (r < nr) acc[r] ^= rp[(int64_t)r * W] & g;
+                for (int t = 0; t < kRowWords; ++t) acc[t] ^= xp[t];
+            }
         }
     }
-    uint64_t mine = 0;
 #pragma unroll
-    for (int r = 0; r < 32; ++r) {
-        const uint64_t mask = __ballot((int)(__popcll(acc[r]) & 1));
-        mine = (lane == r) ? mask : mine;
-    }
-    if (lane < 32) {
-        const int64_t rr = r0 + lane;
-        if (rr < R_out) {
-            if (LAYOUT == 1)
-                out[(rb * Cw + cw) * 32 + lane] = mine;
-            else
-                out[rr * Cw + cw] = mine;
+    for (int t = 0; t < kRowWords; ++t) {
+        const int64_t rw = rw0 + t;
+        if (rw >= Rw) break;
+        if (LAYOUT == 2) {
+            out[((j >> 5) * Rw + rw) * 32 + (j & 31)] = acc[t];
+        } else {
+            const uint64_t y = transpose64(acc[t], lane);
+            const int64_t r = rw * 64 + lane;
+            if (r < R_out) {
+                if (LAYOUT == 1)
+                    out[((r >> 5) * Gw + gb) * 32 + (r & 31)] = y;
+                else
+                    out[r * Gw + gb] = y;
+            }
         }
     }
 }
 
-hipError_t launch_parity(const LaunchCtx &lc, const uint64_t *rows, int64_t R, int64_t R_out,
-                         const uint64_t *cols, int64_t C, int64_t Cw, int W, int layout,
-                         uint64_t *out) {
-    const int64_t units = ceil_div(R_out, 32) * Cw;
+hipError_t launch_bitslice(const LaunchCtx &lc, const uint64_t *rows, int64_t R, int W,
+                           int64_t ldx, uint64_t *Xt) {
+    const int64_t units = ldx * W;
+    if (units == 0) return hipSuccess;
+    hipEvent_t ev;
+    timed_begin(lc, KF_PARITY, &ev);
+    hipLaunchKernelGGL(bitslice_kernel, dim3((unsigned)ceil_div(units, 4)), dim3(256), 0,
+                       lc.stream, rows, R, W, ldx, Xt);
+    hipError_t e = hipGetLastError();
+    timed_end(lc, KF_PARITY, ev);
+    return e;
+}
+
+hipError_t launch_parity_bs(const LaunchCtx &lc, const uint64_t *gens, int64_t m, int W,
+                            const uint64_t *Xt, int64_t Rw, int64_t ldx, int64_t R_out,
+                            int64_t Gw, int layout, uint64_t *out) {
+    const int64_t units = Gw * ceil_div(Rw, kRowWords);
     if (units == 0) return hipSuccess;
     hipEvent_t ev;
     timed_begin(lc, KF_PARITY, &ev);
     dim3 grid((unsigned)ceil_div(units, 4));
-    if (layout == 1)
-        hipLaunchKernelGGL(parity_kernel<1>, grid, dim3(256), 0, lc.stream, rows, R, R_out, cols,
-                           C, Cw, W, out);
+    if (layout == 0)
+        hipLaunchKernelGGL(parity_bs_kernel<0>, grid, dim3(256), 0, lc.stream, gens, m, W, Xt, Rw,
+                           ldx, R_out, Gw, out);
+    else if (layout == 1)
+        hipLaunchKernelGGL(parity_bs_kernel<1>, grid, dim3(256), 0, lc.stream, gens, m, W, Xt, Rw,
+                           ldx, R_out, Gw, out);
     else
-        hipLaunchKernelGGL(parity_kernel<0>, grid, dim3(256), 0, lc.stream, rows, R, R_out, cols,
-                           C, Cw, W, out);
+        hipLaunchKernelGGL(parity_bs_kernel<2>, grid, dim3(256), 0, lc.stream, gens, m, W, Xt, Rw,
+                           ldx, R_out, Gw, out);
     hipError_t e = hipGetLastError();
     timed_end(lc, KF_PARITY, ev);
     return e;
@@ -181,14 +239,15 @@ hipError_t launch_parity(const LaunchCtx &lc, const uint64_t *rows, int64_t R, i
 // value (bits 8..15 are ignored). A packed 16-bit shift by (15 - 2v, 14 - 2v)
 // moves bits 2v and 2v+1 to the sign positions 15 and 31 of dword v.
 
-// B_ij = (-1)^{bit}: +1.0 = 0x3F80, -1.0 = 0xBF80.
-__device__ __forceinline__ bf16x8 expand_pm1(uint32_t x16) {
+// B_ij = (-1)^{bit}: +1.0 = 0x3F80, -1.0 = 0xBF80. `ones` holds 0x3F803F80 in
+// a vector register so that mask-and-or is one instruction.
+__device__ __forceinline__ bf16x8 expand_pm1(uint32_t x16, uint32_t ones) {
     const u16x2 xv = {(unsigned short)x16, (unsigned short)x16};
     uint32_t d[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const u16x2 sh = {(unsigned short)(15 - 2 * v), (unsigned short)(14 - 2 * v)};
-        d[v] = (__builtin_bit_cast(uint32_t, (u16x2)(xv << sh)) & 0x80008000u) | 0x3F803F80u;
+        d[v] = (__builtin_bit_cast(uint32_t, (u16x2)(xv << sh)) & 0x80008000u) | ones;
     }
     return __builtin_bit_cast(bf16x8, d);
 }
@@ -224,93 +283,120 @@ __device__ __forceinline__ bf16x8 expand_01(uint32_t x16) {
     return __builtin_bit_cast(bf16x8, d);
 }
 
+// Direct global -> LDS copy of 16 bytes per lane: lane l's bytes land at
+// lds_block + 16 l. Completion is tracked by the vector-memory counter.
+typedef __attribute__((address_space(3))) void lds_void;
+__device__ __forceinline__ void dma16(const void *gsrc, void *lds_block) {
+    __builtin_amdgcn_global_load_lds(gsrc, (lds_void *)lds_block, 16, 0, 0);
+}
+
+// Wait for this wave's outstanding vector-memory operations (including the
+// global -> LDS copies above), then synchronise the workgroup.
+__device__ __forceinline__ void dma_wait_barrier() {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+}
+
+// A value the compiler must keep in a vector register.
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // The 16 accumulators of a 32x32 product in lane l hold column l % 32 and
 // rows 8*(a/4) + 4*(l/32) + (a%4), a = 0..15.
 __device__ __forceinline__ int acc_row(int a, int h) { return 8 * (a >> 2) + 4 * h + (a & 3); }
 
 // ---------------------------------------------------------------------------
 // phase_fwd: E[k][i] = sum_j (c_kj * 2 theta'_j) * (-1)^{b_ij}.
-// Units are (split, observable block, sample block); one wave computes a
-// (32 FM) x (32 FN) tile over its range of gate words. C and B parity bits
-// are tiled32, so each 32-row fragment of a 64-gate word is 256 contiguous
-// bytes. Within a word, K-step t (16 gates) uses byte 2t + h of the lane's
-// word (h = lane / 32): the word is pre-shifted right by 8h.
+// A workgroup is 4 waves that share a gate range (split) and an observable
+// block and take 4 consecutive sample blocks; each wave computes a
+// (32 FM) x (32 FN) tile. C and B parity bits are tiled32, so each 32-row
+// fragment of a 64-gate word is 256 contiguous bytes. Within a word, K-step t
+// (16 gates) uses byte 2t + h of the lane's word (h = lane / 32): the word is
+// pre-shifted right by 8h.
+//
+// Memory discipline: the theta limbs, shared by the 4 waves, are staged
+// through LDS in chunks of kChunkWords gate words (double-buffered, one
+// barrier per chunk), so the only vector loads in the loop are the bit words
+// of word w+1, requested at the start of word w and consumed in issue order;
+// no wait on a later load ever covers them early.
+constexpr int kChunkWords = 32;
+
+// Operands of one K-step: the +-1 B fragments and the masked hi / lo theta
+// A fragments.
 template <int FM, int FN>
-__global__ __launch_bounds__(256, 1) void phase_fwd_bf16_kernel(
-    const uint64_t *__restrict__ cbits, const uint64_t *__restrict__ bbits,
-    const u32x4 *__restrict__ thh, const u32x4 *__restrict__ thl, int64_t mw, int64_t n_ob,
-    int64_t n_sb, int64_t units, int64_t wps, float *__restrict__ E, int64_t l_pad,
-    int64_t s_pad) {
-    const int lane = threadIdx.x & 63;
-    const int64_t u = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave_id();
-    if (u >= units) return;
-    const int64_t sb = u % n_sb;
-    const int64_t t0 = u / n_sb;
-    const int64_t ob = t0 % n_ob;
-    const int64_t split = t0 / n_ob;
-    const int64_t w0 = split * wps;
-    const int64_t w1 = (w0 + wps < mw) ? w0 + wps : mw;
-    const int h = lane >> 5, r = lane & 31;
+struct FwdOps {
+    bf16x8 bv[FN], ah[FM], al[FM];
+};
 
-    const uint64_t *cp[FM];
-    const uint64_t *bp[FN];
+template <int FM, int FN, int T>
+__device__ __forceinline__ void fwd_expand(FwdOps<FM, FN> &o, const uint64_t (&cw)[FM],
+                                           const uint64_t (&bw)[FN], const u32x4 &th,
+                                           const u32x4 &tl, uint32_t ones) {
 #pragma unroll
-    for (int f = 0; f < FM; ++f) cp[f] = cbits + (ob * FM + f) * mw * 32 + r;
+    for (int g = 0; g < FN; ++g) {
+        const uint32_t d = (uint32_t)(bw[g] >> (32 * (T >> 1)));
+        o.bv[g] = expand_pm1((T & 1) ? (d >> 16) : d, ones);
+    }
 #pragma unroll
-    for (int g = 0; g < FN; ++g) bp[g] = bbits + (sb * FN + g) * mw * 32 + r;
+    for (int f = 0; f < FM; ++f) {
+        const uint32_t d = (uint32_t)(cw[f] >> (32 * (T >> 1)));
+        expand_masked((T & 1) ? (d >> 16) : d, th, tl, o.ah[f], o.al[f]);
+    }
+}
 
-    f32x16 acc[FM][FN];
+template <int FM, int FN>
+__device__ __forceinline__ void fwd_mfma(const FwdOps<FM, FN> &o, f32x16 (&acc)[FM][FN]) {
 #pragma unroll
     for (int f = 0; f < FM; ++f)
 #pragma unroll
         for (int g = 0; g < FN; ++g)
+            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[f], o.bv[g], acc[f][g], 0, 0, 0);
 #pragma unroll
-            for (int a = 0; a < 16; ++a) acc[f][g][a] = 0.0f;
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int g = 0; g < FN; ++g)
+            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.al[f], o.bv[g], acc[f][g], 0, 0, 0);
+}
 
-    uint64_t cwn[FM], bwn[FN];
-    if (w0 < w1) {
+// Interleave of one pipeline region: the LDS reads for the next K-step
+// first, then each matrix product followed by a few of the next K-step's
+// expansion instructions, so the matrix core never waits for a run of VALU.
+template <int NMFMA, int NVALU>
+__device__ __forceinline__ void interleave_region() {
+    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // LDS reads
 #pragma unroll
-        for (int f = 0; f < FM; ++f) cwn[f] = cp[f][w0 * 32];
-#pragma unroll
-        for (int g = 0; g < FN; ++g) bwn[g] = bp[g][w0 * 32];
+    for (int i = 0; i < NMFMA; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix product
+        __builtin_amdgcn_sched_group_barrier(0x002, (NVALU + NMFMA - 1) / NMFMA, 0);
     }
-    for (int64_t w = w0; w < w1; ++w) {
-        uint64_t cw[FM], bw[FN];
-#pragma unroll
-        for (int f = 0; f < FM; ++f) cw[f] = cwn[f] >> (8 * h);
-#pragma unroll
-        for (int g = 0; g < FN; ++g) bw[g] = bwn[g] >> (8 * h);
-        if (w + 1 < w1) {
-#pragma unroll
-            for (int f = 0; f < FM; ++f) cwn[f] = cp[f][(w + 1) * 32];
-#pragma unroll
-            for (int g = 0; g < FN; ++g) bwn[g] = bp[g][(w + 1) * 32];
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const u32x4 th = thh[8 * w + 2 * t + h];
-            const u32x4 tl = thl[8 * w + 2 * t + h];
-            bf16x8 bv[FN];
-#pragma unroll
-            for (int g = 0; g < FN; ++g) {
-                const uint32_t d = (uint32_t)(bw[g] >> (32 * (t >> 1)));
-                bv[g] = expand_pm1((t & 1) ? (d >> 16) : d);
-            }
-#pragma unroll
-            for (int f = 0; f < FM; ++f) {
-                const uint32_t d = (uint32_t)(cw[f] >> (32 * (t >> 1)));
-                bf16x8 ah, al;
-                expand_masked((t & 1) ? (d >> 16) : d, th, tl, ah, al);
-#pragma unroll
-                for (int g = 0; g < FN; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bv[g], acc[f][g], 0, 0, 0);
-#pragma unroll
-                for (int g = 0; g < FN; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bv[g], acc[f][g], 0, 0, 0);
-            }
-        }
-    }
-    float *Ep = E + split * l_pad * s_pad;
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Decomposition shared by both forward kernels.
+struct FwdUnit {
+    int64_t sb, ob, split, w0, w1;
+    bool active;
+};
+
+__device__ __forceinline__ bool fwd_unit(FwdUnit &U, int64_t gu, int64_t n_ob, int64_t n_sb,
+                                         int64_t mw, int64_t wps) {
+    const int64_t n_sbg = ceil_div(n_sb, 4);
+    const int64_t sbg = gu % n_sbg;
+    const int64_t t0 = gu / n_sbg;
+    U.ob = t0 % n_ob;
+    U.split = t0 / n_ob;
+    U.sb = sbg * 4 + wave_id();
+    U.active = U.sb < n_sb;
+    U.w0 = U.split * wps;
+    U.w1 = (U.w0 + wps < mw) ? U.w0 + wps : mw;
+    return true;
+}
+
+template <int FM, int FN>
+__device__ __forceinline__ void store_tile(const f32x16 (&acc)[FM][FN], float *Ep, int64_t ob,
+                                           int64_t sb, int64_t s_pad, int h, int r) {
 #pragma unroll
     for (int f = 0; f < FM; ++f)
 #pragma unroll
@@ -324,32 +410,25 @@ __global__ __launch_bounds__(256, 1) void phase_fwd_bf16_kernel(
         }
 }
 
-// FP32 form: 32x32x2 products, lane l reads K value l / 32. The word is
-// pre-shifted right by h, so K-step t (gates 2t, 2t+1) uses bit 2t. theta is
-// split by gate parity: t32[h][32 w + t] = 2 theta'_{64 w + 2 t + h}.
 template <int FM, int FN>
-__global__ __launch_bounds__(256, 1) void phase_fwd_f32_kernel(
+__global__ __launch_bounds__(256, 1) void phase_fwd_bf16_kernel(
     const uint64_t *__restrict__ cbits, const uint64_t *__restrict__ bbits,
-    const float *__restrict__ t32, int64_t m_pad, int64_t mw, int64_t n_ob, int64_t n_sb,
-    int64_t units, int64_t wps, float *__restrict__ E, int64_t l_pad, int64_t s_pad) {
+    const u32x4 *__restrict__ thh, const u32x4 *__restrict__ thl, int64_t mw, int64_t n_ob,
+    int64_t n_sb, int64_t wg_units, int64_t wps, float *__restrict__ E, int64_t l_pad,
+    int64_t s_pad) {
+    // per word 8 units of 16 bytes: K-step t, half h at 2t + h
+    __shared__ u32x4 lth[2][kChunkWords * 8], ltl[2][kChunkWords * 8];
+    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
+    if (gu >= wg_units) return;  // uniform over the workgroup
+    FwdUnit U;
+    fwd_unit(U, gu, n_ob, n_sb, mw, wps);
     const int lane = threadIdx.x & 63;
-    const int64_t u = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave_id();
-    if (u >= units) return;
-    const int64_t sb = u % n_sb;
-    const int64_t t0 = u / n_sb;
-    const int64_t ob = t0 % n_ob;
-    const int64_t split = t0 / n_ob;
-    const int64_t w0 = split * wps;
-    const int64_t w1 = (w0 + wps < mw) ? w0 + wps : mw;
     const int h = lane >> 5, r = lane & 31;
-    const float4 *thp = reinterpret_cast<const float4 *>(t32 + h * (m_pad >> 1));
-
-    const uint64_t *cp[FM];
-    const uint64_t *bp[FN];
-#pragma unroll
-    for (int f = 0; f < FM; ++f) cp[f] = cbits + (ob * FM + f) * mw * 32 + r;
-#pragma unroll
-    for (int g = 0; g < FN; ++g) bp[g] = bbits + (sb * FN + g) * mw * 32 + r;
+    const uint32_t ones = in_vgpr(0x3F803F80u);
+    const uint64_t *cbase = cbits + U.ob * FM * mw * 32;
+    const uint64_t *bbase = bbits + (U.active ? U.sb : 0) * FN * mw * 32;
+    const int64_t nwords = U.w1 > U.w0 ? U.w1 - U.w0 : 0;
+    const int64_t nchunks = ceil_div(nwords, kChunkWords);
 
     f32x16 acc[FM][FN];
 #pragma unroll
@@ -359,47 +438,187 @@ __global__ __launch_bounds__(256, 1) void phase_fwd_f32_kernel(
 #pragma unroll
             for (int a = 0; a < 16; ++a) acc[f][g][a] = 0.0f;
 
-    for (int64_t w = w0; w < w1; ++w) {
-        uint64_t cw[FM], bw[FN];
+    // stage a chunk: wave v copies units [64 v, 64 v + 64) of both limbs
+    const int wv = wave_id();
+    auto stage = [&](int64_t cw0, int buf) {
+        const int64_t src = cw0 * 8 + wv * 64 + lane;
+        if (src < U.w1 * 8) {
+            dma16(thh + src, &lth[buf][wv * 64]);
+            dma16(thl + src, &ltl[buf][wv * 64]);
+        }
+    };
+    constexpr int kMfma = 2 * FM * FN;
+    constexpr int kValu = 16 * FM + 8 * FN + 8;
+    if (nchunks > 0) stage(U.w0, 0);
+    uint64_t nxt_c[FM], nxt_b[FN], cur_c[FM], cur_b[FN];
+    if (nwords > 0) {
 #pragma unroll
-        for (int f = 0; f < FM; ++f) cw[f] = cp[f][w * 32] >> h;
+        for (int f = 0; f < FM; ++f) nxt_c[f] = (cbase + (f * mw + U.w0) * 32)[r];
 #pragma unroll
-        for (int g = 0; g < FN; ++g) bw[g] = bp[g][w * 32] >> h;
+        for (int g = 0; g < FN; ++g) nxt_b[g] = (bbase + (g * mw + U.w0) * 32)[r];
+    }
+    dma_wait_barrier();
+    FwdOps<FM, FN> opA, opB;
+    for (int64_t c = 0; c < nchunks; ++c) {
+        const int buf = (int)(c & 1);
+        const int64_t cw0 = U.w0 + c * kChunkWords;
+        const int64_t cw1 = (cw0 + kChunkWords < U.w1) ? cw0 + kChunkWords : U.w1;
+        if (c + 1 < nchunks) stage(cw1, buf ^ 1);
+        const u32x4 *Th = lth[buf] + h, *Tl = ltl[buf] + h;
+        // K-step 0 of the chunk's first word
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float4 tv = thp[8 * w + q];
-            const float tq[4] = {tv.x, tv.y, tv.z, tv.w};
+        for (int f = 0; f < FM; ++f) cur_c[f] = nxt_c[f] >> (8 * h);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int t = 4 * q + e;
-                float bv[FN];
+        for (int g = 0; g < FN; ++g) cur_b[g] = nxt_b[g] >> (8 * h);
+        fwd_expand<FM, FN, 0>(opA, cur_c, cur_b, Th[0], Tl[0], ones);
+        for (int64_t w = cw0; w < cw1; ++w) {
+            const int o = (int)(w - cw0) * 8;
+            if (w + 1 < U.w1) {
 #pragma unroll
-                for (int g = 0; g < FN; ++g)
-                    bv[g] = __uint_as_float((((uint32_t)(bw[g] >> (2 * t)) & 1u) << 31) |
-                                            0x3F800000u);
+                for (int f = 0; f < FM; ++f) nxt_c[f] = (cbase + (f * mw + w + 1) * 32)[r];
 #pragma unroll
-                for (int f = 0; f < FM; ++f) {
-                    const uint32_t msk = 0u - ((uint32_t)(cw[f] >> (2 * t)) & 1u);
-                    const float av = __uint_as_float(__float_as_uint(tq[e]) & msk);
-#pragma unroll
-                    for (int g = 0; g < FN; ++g)
-                        acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[g], acc[f][g], 0, 0, 0);
-                }
+                for (int g = 0; g < FN; ++g) nxt_b[g] = (bbase + (g * mw + w + 1) * 32)[r];
             }
+            // region t: products of K-step t, expansion of K-step t+1
+            fwd_expand<FM, FN, 1>(opB, cur_c, cur_b, Th[o + 2], Tl[o + 2], ones);
+            fwd_mfma<FM, FN>(opA, acc);
+            interleave_region<kMfma, kValu>();
+            fwd_expand<FM, FN, 2>(opA, cur_c, cur_b, Th[o + 4], Tl[o + 4], ones);
+            fwd_mfma<FM, FN>(opB, acc);
+            interleave_region<kMfma, kValu>();
+            fwd_expand<FM, FN, 3>(opB, cur_c, cur_b, Th[o + 6], Tl[o + 6], ones);
+            fwd_mfma<FM, FN>(opA, acc);
+            interleave_region<kMfma, kValu>();
+            // K-step 0 of word w+1, unconditionally so that it interleaves with
+            // the products below: past the chunk's last word it reads inside
+            // the chunk's buffer and is recomputed after the barrier
+            const int on = (w + 1 < cw1) ? o + 8 : o;
+#pragma unroll
+            for (int f = 0; f < FM; ++f) cur_c[f] = nxt_c[f] >> (8 * h);
+#pragma unroll
+            for (int g = 0; g < FN; ++g) cur_b[g] = nxt_b[g] >> (8 * h);
+            fwd_expand<FM, FN, 0>(opA, cur_c, cur_b, Th[on], Tl[on], ones);
+            fwd_mfma<FM, FN>(opB, acc);
+            interleave_region<kMfma, kValu>();
+        }
+        dma_wait_barrier();
+    }
+    if (U.active) store_tile<FM, FN>(acc, E + U.split * l_pad * s_pad, U.ob, U.sb, s_pad, h, r);
+}
+
+// FP32 form: 32x32x2 products, lane l reads K value l / 32. The word is
+// pre-shifted right by h, so K-step t (gates 2t, 2t+1) uses bit 2t. theta is
+// split by gate parity, t32[h][32 w + t] = 2 theta'_{64 w + 2 t + h}, and
+// staged per word as 16 float4: half h at 8h + q holds K-steps 4q..4q+3.
+template <int FM, int FN, int Q>
+__device__ __forceinline__ void fwd32_group(const uint64_t (&cw)[FM], const uint64_t (&bw)[FN],
+                                            const float4 &tv, f32x16 (&acc)[FM][FN]) {
+    const float tq[4] = {tv.x, tv.y, tv.z, tv.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int t = 4 * Q + e;
+        float bv[FN];
+#pragma unroll
+        for (int g = 0; g < FN; ++g)
+            bv[g] = __uint_as_float((((uint32_t)(bw[g] >> (2 * t)) & 1u) << 31) | 0x3F800000u);
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+            const uint32_t msk = 0u - ((uint32_t)(cw[f] >> (2 * t)) & 1u);
+            const float av = __uint_as_float(__float_as_uint(tq[e]) & msk);
+#pragma unroll
+            for (int g = 0; g < FN; ++g)
+                acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[g], acc[f][g], 0, 0, 0);
         }
     }
-    float *Ep = E + split * l_pad * s_pad;
+}
+
+template <int FM, int FN>
+__global__ __launch_bounds__(256, 1) void phase_fwd_f32_kernel(
+    const uint64_t *__restrict__ cbits, const uint64_t *__restrict__ bbits,
+    const float *__restrict__ t32, int64_t m_pad, int64_t mw, int64_t n_ob, int64_t n_sb,
+    int64_t wg_units, int64_t wps, float *__restrict__ E, int64_t l_pad, int64_t s_pad) {
+    __shared__ float4 lt[2][kChunkWords * 16];
+    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
+    if (gu >= wg_units) return;
+    FwdUnit U;
+    fwd_unit(U, gu, n_ob, n_sb, mw, wps);
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5, r = lane & 31;
+    const float4 *tp4 = reinterpret_cast<const float4 *>(t32);
+    const int64_t half4 = m_pad >> 3;  // float4 units per parity half
+    const uint64_t *cbase = cbits + U.ob * FM * mw * 32;
+    const uint64_t *bbase = bbits + (U.active ? U.sb : 0) * FN * mw * 32;
+    const int64_t nwords = U.w1 > U.w0 ? U.w1 - U.w0 : 0;
+    const int64_t nchunks = ceil_div(nwords, kChunkWords);
+
+    f32x16 acc[FM][FN];
 #pragma unroll
     for (int f = 0; f < FM; ++f)
 #pragma unroll
-        for (int g = 0; g < FN; ++g) {
-            const int64_t col = (sb * FN + g) * 32 + r;
+        for (int g = 0; g < FN; ++g)
 #pragma unroll
-            for (int a = 0; a < 16; ++a) {
-                const int64_t row = (ob * FM + f) * 32 + acc_row(a, h);
-                Ep[row * s_pad + col] = acc[f][g][a];
+            for (int a = 0; a < 16; ++a) acc[f][g][a] = 0.0f;
+
+    // staging unit u = 16 (word) + 8 hh + q  <-  t32 half hh, float4 8 w + q;
+    // wave v copies units [64 (v + 4 k), +64) for k = 0, 1
+    const int wv = wave_id();
+    auto stage = [&](int64_t cw0, int buf) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int uidx = (wv + 4 * k) * 64 + lane;
+            const int64_t w = cw0 + (uidx >> 4);
+            const int hh = (uidx >> 3) & 1, q = uidx & 7;
+            if (w < U.w1) dma16(tp4 + hh * half4 + 8 * w + q, &lt[buf][(wv + 4 * k) * 64]);
+        }
+    };
+    if (nchunks > 0) stage(U.w0, 0);
+    uint64_t nxt_c[FM], nxt_b[FN], cur_c[FM], cur_b[FN];
+    if (nwords > 0) {
+#pragma unroll
+        for (int f = 0; f < FM; ++f) nxt_c[f] = (cbase + (f * mw + U.w0) * 32)[r];
+#pragma unroll
+        for (int g = 0; g < FN; ++g) nxt_b[g] = (bbase + (g * mw + U.w0) * 32)[r];
+    }
+    dma_wait_barrier();
+    for (int64_t c = 0; c < nchunks; ++c) {
+        const int buf = (int)(c & 1);
+        const int64_t cw0 = U.w0 + c * kChunkWords;
+        const int64_t cw1 = (cw0 + kChunkWords < U.w1) ? cw0 + kChunkWords : U.w1;
+        if (c + 1 < nchunks) stage(cw1, buf ^ 1);
+        for (int64_t w = cw0; w < cw1; ++w) {
+#pragma unroll
+            for (int f = 0; f < FM; ++f) cur_c[f] = nxt_c[f] >> h;
+#pragma unroll
+            for (int g = 0; g < FN; ++g) cur_b[g] = nxt_b[g] >> h;
+            if (w + 1 < U.w1) {
+#pragma unroll
+                for (int f = 0; f < FM; ++f) nxt_c[f] = (cbase + (f * mw + w + 1) * 32)[r];
+#pragma unroll
+                for (int g = 0; g < FN; ++g) nxt_b[g] = (bbase + (g * mw + w + 1) * 32)[r];
+            }
+            {
+                const float4 *tl = &lt[buf][(int)(w - cw0) * 16 + 8 * h];
+                fwd32_group<FM, FN, 0>(cur_c, cur_b, tl[0], acc);
+                __builtin_amdgcn_sched_barrier(0);
+                fwd32_group<FM, FN, 1>(cur_c, cur_b, tl[1], acc);
+                __builtin_amdgcn_sched_barrier(0);
+                fwd32_group<FM, FN, 2>(cur_c, cur_b, tl[2], acc);
+                __builtin_amdgcn_sched_barrier(0);
+                fwd32_group<FM, FN, 3>(cur_c, cur_b, tl[3], acc);
+                __builtin_amdgcn_sched_barrier(0);
+                fwd32_group<FM, FN, 4>(cur_c, cur_b, tl[4], acc);
+                __builtin_amdgcn_sched_barrier(0);
+                fwd32_group<FM, FN, 5>(cur_c, cur_b, tl[5], acc);
+                __builtin_amdgcn_sched_barrier(0);
+                fwd32_group<FM, FN, 6>(cur_c, cur_b, tl[6], acc);
+                __builtin_amdgcn_sched_barrier(0);
+                fwd32_group<FM, FN, 7>(cur_c, cur_b, tl[7], acc);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
+        dma_wait_barrier();
+    }
+    if (U.active) store_tile<FM, FN>(acc, E + U.split * l_pad * s_pad, U.ob, U.sb, s_pad, h, r);
 }
 
 template <int FM, int FN>
@@ -410,16 +629,16 @@ static void fwd_dispatch(const LaunchCtx &lc, int prec, const uint64_t *cbits,
     const int64_t mw = m_pad / 64;
     const int64_t n_ob = l_pad / (32 * FM), n_sb = s_pad / (32 * FN);
     const int64_t wps = ceil_div(mw, splits);
-    const int64_t units = n_ob * n_sb * splits;
-    dim3 grid((unsigned)ceil_div(units, 4));
+    const int64_t wg_units = n_ob * ceil_div(n_sb, 4) * splits;
+    dim3 grid((unsigned)wg_units);
     if (prec == 1)
         hipLaunchKernelGGL((phase_fwd_bf16_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, cbits,
                            bbits, reinterpret_cast<const u32x4 *>(thh),
-                           reinterpret_cast<const u32x4 *>(thl), mw, n_ob, n_sb, units, wps, E,
+                           reinterpret_cast<const u32x4 *>(thl), mw, n_ob, n_sb, wg_units, wps, E,
                            l_pad, s_pad);
     else
         hipLaunchKernelGGL((phase_fwd_f32_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, cbits,
-                           bbits, t32, m_pad, mw, n_ob, n_sb, units, wps, E, l_pad, s_pad);
+                           bbits, t32, m_pad, mw, n_ob, n_sb, wg_units, wps, E, l_pad, s_pad);
 }
 
 hipError_t launch_phase_fwd(const LaunchCtx &lc, int prec, int fm, int fn, const uint64_t *cbits,
@@ -561,14 +780,16 @@ hipError_t launch_coef_plain(const LaunchCtx &lc, const double *grad_mean, int64
 }
 
 // One block per 64 observables x 64 samples: S values are staged in LDS and
-// written out in the register image of the backward product's B operand.
-//   BF16: 16-byte unit ((ib * KT + kt) * 64 + h*32 + i%32) holds
-//         S[i][16 kt + 8 h + e], e = 0..7 (ib = i / 32, KT = l_pad / 16)
-//   FP32: float ((ib * KT2 + t) * 64 + h*32 + i%32) holds S[i][2 t + h]
-//         (KT2 = l_pad / 2)
+// written out in the register image of the backward product's A operand
+// (rows = observables, K = samples):
+//   BF16: 16-byte unit ((k/32) * KTs + i/16) * 64 + ((i/8)&1) * 32 + k%32 holds
+//         S[k][i..i+7] (i a multiple of 8, KTs = s_pad / 16); hi and lo limbs
+//         in two arrays
+//   FP32: float (((k/32) * KT4s + i/8) * 64 + (i&1) * 32 + k%32) * 4 + (i/2)%4
+//         holds S[k][i] (KT4s = s_pad / 8): four K-steps per 16-byte load
 __global__ __launch_bounds__(256) void weights_kernel(const float *__restrict__ phase,
                                                       const double *__restrict__ coef, int64_t l,
-                                                      int64_t s, int64_t l_pad, int prec,
+                                                      int64_t s, int64_t s_pad, int prec,
                                                       uint16_t *__restrict__ shi,
                                                       uint16_t *__restrict__ slo,
                                                       float *__restrict__ s32) {
@@ -591,24 +812,21 @@ __global__ __launch_bounds__(256) void weights_kernel(const float *__restrict__ 
     }
     __syncthreads();
     if (prec == 1) {
-        const int64_t KT = l_pad / 16;
-        // 64 samples x 8 groups of 8 observables = 512 units, 2 per thread
+        const int64_t KTs = s_pad / 16;
+        // 64 observables x 8 groups of 8 samples = 512 units, 2 per thread
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int unit = q * 256 + threadIdx.x;
-            const int il = unit & 63, kg = unit >> 6;  // kg = 0..7: observables 8 kg ..
-            const int64_t i = i0 + il;
-            const int64_t kabs = k0 + 8 * kg;
-            const int64_t kt = kabs >> 4;
-            const int hh = (int)((kabs >> 3) & 1);
-            const int64_t idx = ((i >> 5) * KT + kt) * 64 + hh * 32 + (i & 31);
+            const int kl = unit & 63, sg = unit >> 6;
+            const int64_t k = k0 + kl, i = i0 + 8 * sg;
+            const int64_t idx = ((k >> 5) * KTs + (i >> 4)) * 64 + ((i >> 3) & 1) * 32 + (k & 31);
             uint32_t dh[4], dl[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 uint16_t hv[2], lv[2];
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
-                    const float x = tile[8 * kg + 2 * v + e][il];
+                    const float x = tile[kl][8 * sg + 2 * v + e];
                     hv[e] = f2bf_rne(x);
                     lv[e] = f2bf_rne(x - bf2f(hv[e]));
                 }
@@ -619,16 +837,14 @@ __global__ __launch_bounds__(256) void weights_kernel(const float *__restrict__ 
             reinterpret_cast<u32x4 *>(slo)[idx] = (u32x4){dl[0], dl[1], dl[2], dl[3]};
         }
     } else {
-        const int64_t KT2 = l_pad / 2;
-        // 64 samples x 64 observables = 4096 floats, 16 per thread
+        const int64_t KT4s = s_pad / 8;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int unit = q * 256 + threadIdx.x;
-            const int il = unit & 63, kl = unit >> 6;
-            const int64_t i = i0 + il, kabs = k0 + kl;
-            const int64_t t = kabs >> 1;
-            const int hh = (int)(kabs & 1);
-            s32[((i >> 5) * KT2 + t) * 64 + hh * 32 + (i & 31)] = tile[kl][il];
+            const int kl = unit & 63, il = unit >> 6;
+            const int64_t k = k0 + kl, i = i0 + il;
+            s32[(((k >> 5) * KT4s + (i >> 3)) * 64 + (i & 1) * 32 + (k & 31)) * 4 + ((i >> 1) & 3)] =
+                tile[kl][il];
         }
     }
 }
@@ -639,7 +855,7 @@ hipError_t launch_weights(const LaunchCtx &lc, int prec, const float *phase, con
     hipEvent_t ev;
     timed_begin(lc, KF_WEIGHTS, &ev);
     dim3 grid((unsigned)(s_pad / 64), (unsigned)(l_pad / 64));
-    hipLaunchKernelGGL(weights_kernel, grid, dim3(256), 0, lc.stream, phase, coef, l, s, l_pad,
+    hipLaunchKernelGGL(weights_kernel, grid, dim3(256), 0, lc.stream, phase, coef, l, s, s_pad,
                        prec, shi, slo, s32);
     hipError_t e = hipGetLastError();
     timed_end(lc, KF_WEIGHTS, ev);
@@ -647,29 +863,102 @@ hipError_t launch_weights(const LaunchCtx &lc, int prec, const float *phase, con
 }
 
 // ---------------------------------------------------------------------------
-// phase_bwd: D[j][i] = sum_k c_kj S_ki (gates x samples, K = observables),
-// then per gate sum_i (-1)^{b_ij} D[j][i] over the wave's samples. A operand
-// from tiled32 C^T bits (rows = gates, bits over observables), B operand the
-// S register image. Units are (sample block, gate block), gate fastest, so
-// the waves of an XCD share the S strip of one sample block.
+// phase_bwd: T[k][j] = sum_i S_ki (-1)^{b_ij} (observables x gates, K =
+// samples), then dtheta_j = -2 sum_k c_kj T[k][j]. The contraction runs over
+// the long sample dimension, so each tile amortises its prologue and
+// epilogue; the epilogue is a masked sum over the tile's observable rows and
+// one cross-lane add.
+//   A operand: S in the register image written by weights_kernel
+//   B operand: +-1 from the sample-contiguous B^T bits (transposed tiled32:
+//              row = gate j, bits over samples), K-step t of a sample word
+//              is byte 2t + h of the lane's word
+//   epilogue:  c_kj from the C^T bits (row = gate j, bits over observables)
+// A workgroup is 4 waves that share an observable block (the S strip,
+// staged through LDS per sample word, double-buffered) and take 4
+// consecutive gate blocks. Workgroups are ordered gate block fastest, so an
+// XCD's workgroups share one S strip in L2. As in the forward, the last
+// region of a word runs after the barrier that validates the next word's
+// buffer, so it already expands the next word's first K-step.
+template <int FM, int FN>
+struct BwdOps {
+    bf16x8 ah[FM], al[FM], bv[FN];
+};
+
+template <int FM, int FN, int T>
+__device__ __forceinline__ void bwd_expand(BwdOps<FM, FN> &o, const u32x4 *ls,
+                                           const uint64_t (&bw)[FN], int lane, uint32_t ones) {
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+        o.ah[f] = __builtin_bit_cast(bf16x8, ls[((0 * FM + f) * 4 + T) * 64 + lane]);
+        o.al[f] = __builtin_bit_cast(bf16x8, ls[((1 * FM + f) * 4 + T) * 64 + lane]);
+    }
+#pragma unroll
+    for (int g = 0; g < FN; ++g) {
+        const uint32_t d = (uint32_t)(bw[g] >> (32 * (T >> 1)));
+        o.bv[g] = expand_pm1((T & 1) ? (d >> 16) : d, ones);
+    }
+}
+
+template <int FM, int FN>
+__device__ __forceinline__ void bwd_mfma(const BwdOps<FM, FN> &o, f32x16 (&acc)[FM][FN]) {
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int g = 0; g < FN; ++g)
+            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[f], o.bv[g], acc[f][g], 0, 0, 0);
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int g = 0; g < FN; ++g)
+            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.al[f], o.bv[g], acc[f][g], 0, 0, 0);
+}
+
+// sum_k c_kj T[k][j] over this wave's observable rows, per gate column.
+template <int FM, int FN>
+__device__ __forceinline__ void bwd_epilogue(const f32x16 (&acc)[FM][FN],
+                                             const uint64_t *__restrict__ ctbits, int64_t ob,
+                                             int64_t jb, int64_t lw, int h, int r, bool active,
+                                             float *__restrict__ gpart, int64_t m_pad) {
+#pragma unroll
+    for (int g = 0; g < FN; ++g) {
+        const int64_t j = (jb * FN + g) * 32 + r;
+        float gs = 0.0f;
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+            const int64_t k0 = (ob * FM + f) * 32;
+            const uint64_t cw = ctbits[((j >> 5) * lw + (k0 >> 6)) * 32 + (j & 31)];
+            const uint32_t c32 = (uint32_t)(cw >> (k0 & 63)) >> (4 * h);
+#pragma unroll
+            for (int a = 0; a < 16; ++a)
+                gs += ((c32 >> (8 * (a >> 2) + (a & 3))) & 1u) ? acc[f][g][a] : 0.0f;
+        }
+        gs += __shfl_xor(gs, 32, 64);
+        if (active && h == 0) gpart[ob * m_pad + j] = gs;
+    }
+}
+
 template <int FM, int FN>
 __global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(
-    const uint64_t *__restrict__ ctbits, const u32x4 *__restrict__ shi,
-    const u32x4 *__restrict__ slo, const uint64_t *__restrict__ bbits, int64_t lw, int64_t mw,
-    int64_t n_jb, int64_t units, float *__restrict__ gpart, int64_t m_pad) {
+    const u32x4 *__restrict__ shi, const u32x4 *__restrict__ slo,
+    const uint64_t *__restrict__ btbits, const uint64_t *__restrict__ ctbits, int64_t sw,
+    int64_t lw, int64_t n_jb, int64_t wg_units, float *__restrict__ gpart, int64_t m_pad) {
+    // one sample word: [limb][f][t][lane], 16 bytes each
+    constexpr int kUnits = 2 * FM * 4 * 64;
+    __shared__ u32x4 ls[2][kUnits];
+    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
+    if (gu >= wg_units) return;  // uniform over the workgroup
+    const int64_t n_jbg = ceil_div(n_jb, 4);
+    const int64_t ob = gu / n_jbg, jbg = gu - ob * n_jbg;
+    const int64_t jb_raw = jbg * 4 + wave_id();
+    const bool active = jb_raw < n_jb;
+    const int64_t jb = active ? jb_raw : n_jb - 1;
     const int lane = threadIdx.x & 63;
-    const int64_t u = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave_id();
-    if (u >= units) return;
-    const int64_t ib = u / n_jb, jb = u - ib * n_jb;
     const int h = lane >> 5, r = lane & 31;
-    const int64_t KT = lw * 4;
-
-    const uint64_t *cp[FM];
-#pragma unroll
-    for (int f = 0; f < FM; ++f) cp[f] = ctbits + (jb * FM + f) * lw * 32 + r;
-    int64_t sp[FN];
-#pragma unroll
-    for (int g = 0; g < FN; ++g) sp[g] = (ib * FN + g) * KT * 64 + lane;
+    const uint32_t ones = in_vgpr(0x3F803F80u);
+    const int64_t KTs = sw * 4;
+    const uint64_t *bbase = btbits + jb * FN * sw * 32;
+    const u32x4 *sbase_h = shi + ob * FM * KTs * 64;
+    const u32x4 *sbase_l = slo + ob * FM * KTs * 64;
 
     f32x16 acc[FM][FN];
 #pragma unroll
@@ -679,90 +968,85 @@ __global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(
 #pragma unroll
             for (int a = 0; a < 16; ++a) acc[f][g][a] = 0.0f;
 
-    uint64_t cwn[FM];
+    // staging block b = (limb * FM + f) * 4 + t (64 units of 16 bytes)
+    //   <- S(limb)[(f * KTs + 4 w + t) * 64 + ln]; wave v copies blocks v, v+4, ...
+    const int wv = wave_id();
+    auto stage = [&](int64_t w, int buf) {
 #pragma unroll
-    for (int f = 0; f < FM; ++f) cwn[f] = cp[f][0];
-    for (int64_t w = 0; w < lw; ++w) {
-        uint64_t cw[FM];
-#pragma unroll
-        for (int f = 0; f < FM; ++f) cw[f] = cwn[f] >> (8 * h);
-        if (w + 1 < lw) {
-#pragma unroll
-            for (int f = 0; f < FM; ++f) cwn[f] = cp[f][(w + 1) * 32];
+        for (int k = 0; k < kUnits / 256; ++k) {
+            const int b = wv + 4 * k;
+            const int t = b & 3, f = (b >> 2) % FM, limb = b / (4 * FM);
+            const int64_t src = ((int64_t)f * KTs + 4 * w + t) * 64 + lane;
+            dma16((limb ? sbase_l : sbase_h) + src, &ls[buf][b * 64]);
         }
+    };
+    constexpr int kMfma = 2 * FM * FN;
+    constexpr int kValu = 8 * FN + 4;
+    stage(0, 0);
+    if (sw > 1) stage(1, 1);
+    uint64_t nxt[FN], cur[FN];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t kt = 4 * w + t;
-            bf16x8 bh[FN], bl[FN];
+    for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw) * 32)[r];
+    dma_wait_barrier();
 #pragma unroll
-            for (int g = 0; g < FN; ++g) {
-                bh[g] = __builtin_bit_cast(bf16x8, shi[sp[g] + kt * 64]);
-                bl[g] = __builtin_bit_cast(bf16x8, slo[sp[g] + kt * 64]);
-            }
+    for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> (8 * h);
+    if (sw > 1) {
 #pragma unroll
-            for (int f = 0; f < FM; ++f) {
-                const uint32_t d = (uint32_t)(cw[f] >> (32 * (t >> 1)));
-                const bf16x8 av = expand_01((t & 1) ? (d >> 16) : d);
-#pragma unroll
-                for (int g = 0; g < FN; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bh[g], acc[f][g], 0, 0, 0);
-#pragma unroll
-                for (int g = 0; g < FN; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bl[g], acc[f][g], 0, 0, 0);
-            }
-        }
+        for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + 1) * 32)[r];
     }
-    // epilogue: signs (-1)^{b_ij} from the tiled32 B bits of sample i
+    BwdOps<FM, FN> opA, opB;
+    bwd_expand<FM, FN, 0>(opA, ls[0], cur, lane, ones);
+    for (int64_t w = 0; w < sw; ++w) {
+        const int buf = (int)(w & 1);
+        const u32x4 *lsb = ls[buf];
+        bwd_expand<FM, FN, 1>(opB, lsb, cur, lane, ones);
+        bwd_mfma<FM, FN>(opA, acc);
+        interleave_region<kMfma, kValu>();
+        bwd_expand<FM, FN, 2>(opA, lsb, cur, lane, ones);
+        bwd_mfma<FM, FN>(opB, acc);
+        interleave_region<kMfma, kValu>();
+        bwd_expand<FM, FN, 3>(opB, lsb, cur, lane, ones);
+        bwd_mfma<FM, FN>(opA, acc);
+        interleave_region<kMfma, kValu>();
+        // word w+1's copy and bit words have landed; nobody reads buffer
+        // `buf` any more
+        dma_wait_barrier();
+        if (w + 2 < sw) stage(w + 2, buf);
 #pragma unroll
-    for (int f = 0; f < FM; ++f) {
-        const int64_t j0 = (jb * FM + f) * 32;
-        const int64_t jw = j0 >> 6;
-        const int jo = (int)(j0 & 63);
-        float gs[16];
+        for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> (8 * h);
+        if (w + 2 < sw) {
 #pragma unroll
-        for (int a = 0; a < 16; ++a) gs[a] = 0.0f;
-#pragma unroll
-        for (int g = 0; g < FN; ++g) {
-            const uint64_t bw = bbits[((ib * FN + g) * mw + jw) * 32 + r];
-            const uint32_t b32 = (uint32_t)(bw >> jo) >> (4 * h);
-#pragma unroll
-            for (int a = 0; a < 16; ++a) {
-                const uint32_t sgn = ((b32 >> (8 * (a >> 2) + (a & 3))) & 1u) << 31;
-                gs[a] += __uint_as_float(__float_as_uint(acc[f][g][a]) ^ sgn);
-            }
+            for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w + 2) * 32)[r];
         }
-#pragma unroll
-        for (int a = 0; a < 16; ++a) {
-            float x = gs[a];
-#pragma unroll
-            for (int d = 1; d < 32; d <<= 1) x += __shfl_xor(x, d, 64);
-            gs[a] = x;
-        }
-        if (r == 0) {
-#pragma unroll
-            for (int a = 0; a < 16; ++a) gpart[ib * m_pad + j0 + acc_row(a, h)] = gs[a];
-        }
+        // past the last word this expands a stale buffer and is never used
+        bwd_expand<FM, FN, 0>(opA, ls[buf ^ 1], cur, lane, ones);
+        bwd_mfma<FM, FN>(opB, acc);
+        interleave_region<kMfma, kValu>();
     }
+    bwd_epilogue<FM, FN>(acc, ctbits, ob, jb, lw, h, r, active, gpart, m_pad);
 }
 
+// FP32 form: A operand S[k][2t + h] from the float4 image (four K-steps per
+// lane and load), staged per sample word as [f][q][lane]; B operand +-1.0f.
 template <int FM, int FN>
 __global__ __launch_bounds__(256, 1) void phase_bwd_f32_kernel(
-    const uint64_t *__restrict__ ctbits, const float *__restrict__ s32,
-    const uint64_t *__restrict__ bbits, int64_t lw, int64_t mw, int64_t n_jb, int64_t units,
+    const float4 *__restrict__ s32, const uint64_t *__restrict__ btbits,
+    const uint64_t *__restrict__ ctbits, int64_t sw, int64_t lw, int64_t n_jb, int64_t wg_units,
     float *__restrict__ gpart, int64_t m_pad) {
+    constexpr int kUnits = FM * 8 * 64;
+    __shared__ float4 ls[2][kUnits];
+    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
+    if (gu >= wg_units) return;
+    const int64_t n_jbg = ceil_div(n_jb, 4);
+    const int64_t ob = gu / n_jbg, jbg = gu - ob * n_jbg;
+    const int64_t jb_raw = jbg * 4 + wave_id();
+    const bool active = jb_raw < n_jb;
+    const int64_t jb = active ? jb_raw : n_jb - 1;
     const int lane = threadIdx.x & 63;
-    const int64_t u = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave_id();
-    if (u >= units) return;
-    const int64_t ib = u / n_jb, jb = u - ib * n_jb;
     const int h = lane >> 5, r = lane & 31;
-    const int64_t KT2 = lw * 32;
-
-    const uint64_t *cp[FM];
-#pragma unroll
-    for (int f = 0; f < FM; ++f) cp[f] = ctbits + (jb * FM + f) * lw * 32 + r;
-    int64_t sp[FN];
-#pragma unroll
-    for (int g = 0; g < FN; ++g) sp[g] = (ib * FN + g) * KT2 * 64 + lane;
+    const int64_t KT4s = sw * 8;
+    const uint64_t *bbase = btbits + jb * FN * sw * 32;
+    const float4 *sbase = s32 + ob * FM * KT4s * 64;
 
     f32x16 acc[FM][FN];
 #pragma unroll
@@ -772,86 +1056,90 @@ __global__ __launch_bounds__(256, 1) void phase_bwd_f32_kernel(
 #pragma unroll
             for (int a = 0; a < 16; ++a) acc[f][g][a] = 0.0f;
 
-    for (int64_t w = 0; w < lw; ++w) {
-        uint64_t cw[FM];
+    // staging block b = f * 8 + q (64 float4) <- S[(f * KT4s + 8 w + q) * 64 + ln]
+    const int wv = wave_id();
+    auto stage = [&](int64_t w, int buf) {
 #pragma unroll
-        for (int f = 0; f < FM; ++f) cw[f] = cp[f][w * 32] >> h;
-#pragma unroll 8
-        for (int t = 0; t < 32; ++t) {
-            const int64_t kt = 32 * w + t;
-            float bv[FN];
+        for (int k = 0; k < kUnits / 256; ++k) {
+            const int b = wv + 4 * k;
+            const int q = b & 7, f = b >> 3;
+            dma16(sbase + ((int64_t)f * KT4s + 8 * w + q) * 64 + lane, &ls[buf][b * 64]);
+        }
+    };
+    stage(0, 0);
+    uint64_t nxt[FN], cur[FN];
 #pragma unroll
-            for (int g = 0; g < FN; ++g) bv[g] = s32[sp[g] + kt * 64];
+    for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw) * 32)[r];
+    dma_wait_barrier();
+    for (int64_t w = 0; w < sw; ++w) {
+        const int buf = (int)(w & 1);
+        const bool more = w + 1 < sw;
+        if (more) stage(w + 1, buf ^ 1);
 #pragma unroll
-            for (int f = 0; f < FM; ++f) {
-                const float av = ((cw[f] >> (2 * t)) & 1ull) ? 1.0f : 0.0f;
+        for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> h;
+        if (more) {
+#pragma unroll
+            for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w + 1) * 32)[r];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            float4 sv[FM];
+#pragma unroll
+            for (int f = 0; f < FM; ++f) sv[f] = ls[buf][(f * 8 + q) * 64 + lane];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int t = 4 * q + e;
+                float bv[FN];
 #pragma unroll
                 for (int g = 0; g < FN; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[g], acc[f][g], 0, 0, 0);
+                    bv[g] = __uint_as_float((((uint32_t)(cur[g] >> (2 * t)) & 1u) << 31) |
+                                            0x3F800000u);
+#pragma unroll
+                for (int f = 0; f < FM; ++f) {
+                    const float av = e == 0 ? sv[f].x : e == 1 ? sv[f].y : e == 2 ? sv[f].z : sv[f].w;
+#pragma unroll
+                    for (int g = 0; g < FN; ++g)
+                        acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[g], acc[f][g], 0, 0, 0);
+                }
             }
         }
+        dma_wait_barrier();
     }
-#pragma unroll
-    for (int f = 0; f < FM; ++f) {
-        const int64_t j0 = (jb * FM + f) * 32;
-        const int64_t jw = j0 >> 6;
-        const int jo = (int)(j0 & 63);
-        float gs[16];
-#pragma unroll
-        for (int a = 0; a < 16; ++a) gs[a] = 0.0f;
-#pragma unroll
-        for (int g = 0; g < FN; ++g) {
-            const uint64_t bw = bbits[((ib * FN + g) * mw + jw) * 32 + r];
-            const uint32_t b32 = (uint32_t)(bw >> jo) >> (4 * h);
-#pragma unroll
-            for (int a = 0; a < 16; ++a) {
-                const uint32_t sgn = ((b32 >> (8 * (a >> 2) + (a & 3))) & 1u) << 31;
-                gs[a] += __uint_as_float(__float_as_uint(acc[f][g][a]) ^ sgn);
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < 16; ++a) {
-            float x = gs[a];
-#pragma unroll
-            for (int d = 1; d < 32; d <<= 1) x += __shfl_xor(x, d, 64);
-            gs[a] = x;
-        }
-        if (r == 0) {
-#pragma unroll
-            for (int a = 0; a < 16; ++a) gpart[ib * m_pad + j0 + acc_row(a, h)] = gs[a];
-        }
-    }
+    bwd_epilogue<FM, FN>(acc, ctbits, ob, jb, lw, h, r, active, gpart, m_pad);
 }
 
 template <int FM, int FN>
-static void bwd_dispatch(const LaunchCtx &lc, int prec, const uint64_t *ctbits,
-                         const uint16_t *shi, const uint16_t *slo, const float *s32,
-                         const uint64_t *bbits, int64_t m_pad, int64_t l_pad, int64_t s_pad,
-                         float *gpart) {
-    const int64_t lw = l_pad / 64, mw = m_pad / 64;
-    const int64_t n_jb = m_pad / (32 * FM), n_ib = s_pad / (32 * FN);
-    const int64_t units = n_jb * n_ib;
-    dim3 grid((unsigned)ceil_div(units, 4));
+static void bwd_dispatch(const LaunchCtx &lc, int prec, const uint16_t *shi, const uint16_t *slo,
+                         const float *s32, const uint64_t *btbits, const uint64_t *ctbits,
+                         int64_t m_pad, int64_t l_pad, int64_t s_pad, float *gpart) {
+    const int64_t sw = s_pad / 64, lw = l_pad / 64;
+    const int64_t n_ob = l_pad / (32 * FM), n_jb = m_pad / (32 * FN);
+    const int64_t wg_units = ceil_div(n_jb, 4) * n_ob;
+    dim3 grid((unsigned)wg_units);
     if (prec == 1)
-        hipLaunchKernelGGL((phase_bwd_bf16_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, ctbits,
+        hipLaunchKernelGGL((phase_bwd_bf16_kernel<FM, FN>), grid, dim3(256), 0, lc.stream,
                            reinterpret_cast<const u32x4 *>(shi),
-                           reinterpret_cast<const u32x4 *>(slo), bbits, lw, mw, n_jb, units,
-                           gpart, m_pad);
+                           reinterpret_cast<const u32x4 *>(slo), btbits, ctbits, sw, lw, n_jb,
+                           wg_units, gpart, m_pad);
     else
-        hipLaunchKernelGGL((phase_bwd_f32_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, ctbits,
-                           s32, bbits, lw, mw, n_jb, units, gpart, m_pad);
+        hipLaunchKernelGGL((phase_bwd_f32_kernel<FM, FN>), grid, dim3(256), 0, lc.stream,
+                           reinterpret_cast<const float4 *>(s32), btbits, ctbits, sw, lw, n_jb,
+                           wg_units, gpart, m_pad);
 }
 
-hipError_t launch_phase_bwd(const LaunchCtx &lc, int prec, int fm, int fn, const uint64_t *ctbits,
-                            const uint16_t *shi, const uint16_t *slo, const float *s32,
-                            const uint64_t *bbits, int64_t m_pad, int64_t l_pad, int64_t s_pad,
+hipError_t launch_phase_bwd(const LaunchCtx &lc, int prec, int fm, int fn, const uint16_t *shi,
+                            const uint16_t *slo, const float *s32, const uint64_t *btbits,
+                            const uint64_t *ctbits, int64_t m_pad, int64_t l_pad, int64_t s_pad,
                             float *gpart) {
     hipEvent_t ev;
     timed_begin(lc, KF_BWD, &ev);
     if (fm == 4 && fn == 4)
-        bwd_dispatch<4, 4>(lc, prec, ctbits, shi, slo, s32, bbits, m_pad, l_pad, s_pad, gpart);
+        bwd_dispatch<4, 4>(lc, prec, shi, slo, s32, btbits, ctbits, m_pad, l_pad, s_pad, gpart);
     else if (fm == 2 && fn == 2)
-        bwd_dispatch<2, 2>(lc, prec, ctbits, shi, slo, s32, bbits, m_pad, l_pad, s_pad, gpart);
+        bwd_dispatch<2, 2>(lc, prec, shi, slo, s32, btbits, ctbits, m_pad, l_pad, s_pad, gpart);
+    else if (fm == 2 && fn == 4)
+        bwd_dispatch<2, 4>(lc, prec, shi, slo, s32, btbits, ctbits, m_pad, l_pad, s_pad, gpart);
     else
         return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
@@ -882,8 +1170,9 @@ hipError_t launch_grad_reduce(const LaunchCtx &lc, const float *gpart, int64_t n
 }
 
 // ---------------------------------------------------------------------------
-// MMD^2 chain. data_stats: from row-major parity bits (rows = observables,
-// bits over the N training strings) pstat[2k] = sum_n (-1)^{a_k . x_n} and
+// MMD^2 chain. data_stats: from the transposed tiled32 parity bits of the
+// observables against the N training strings (word ((k/32) Nw + w) 32 + k%32,
+// bit n%64 of word w = n/64) pstat[2k] = sum_n (-1)^{a_k . x_n} and
 // pstat[2k+1] = p_k = that sum / N.
 __global__ __launch_bounds__(256) void data_stats_kernel(const uint64_t *__restrict__ dbits,
                                                          int64_t l, int64_t Nw, int64_t N,
@@ -891,7 +1180,7 @@ __global__ __launch_bounds__(256) void data_stats_kernel(const uint64_t *__restr
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= l) return;
     int64_t odd = 0;
-    for (int64_t w = 0; w < Nw; ++w) odd += __popcll(dbits[k * Nw + w]);
+    for (int64_t w = 0; w < Nw; ++w) odd += __popcll(dbits[((k >> 5) * Nw + w) * 32 + (k & 31)]);
     const double sv = (double)(N - 2 * odd);
     pstat[2 * k] = sv;
     pstat[2 * k + 1] = sv / (double)N;

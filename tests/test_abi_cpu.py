@@ -106,13 +106,18 @@ def test_grad_and_mmd_validation():
 
 def test_parity_validation_and_empty():
     lib = L.lib()
-    assert lib.iqp_parity(-1, FAKE, 3, FAKE, 1, 0, FAKE, None) == L.IQP_ERR_INVALID_ARG
-    assert lib.iqp_parity(3, FAKE, 3, FAKE, 0, 0, FAKE, None) == L.IQP_ERR_INVALID_ARG
-    assert lib.iqp_parity(3, FAKE, 3, FAKE, 1, 5, FAKE, None) == L.IQP_ERR_INVALID_ARG
-    assert lib.iqp_parity(3, None, 3, FAKE, 1, 0, FAKE, None) == L.IQP_ERR_INVALID_ARG
+    big = 1 << 30
+    assert lib.iqp_parity(-1, FAKE, 3, FAKE, 1, 0, FAKE, FAKE, big, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_parity(3, FAKE, 3, FAKE, 0, 0, FAKE, FAKE, big, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_parity(3, FAKE, 3, FAKE, 1, 5, FAKE, FAKE, big, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_parity(3, None, 3, FAKE, 1, 0, FAKE, FAKE, big, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_parity(3, FAKE, 3, FAKE, 1, 0, FAKE, FAKE, 8, None) == L.IQP_ERR_WORKSPACE
+    assert lib.iqp_parity(3, FAKE, 3, FAKE, 1, 0, FAKE, None, big, None) == L.IQP_ERR_INVALID_ARG
     # empty inputs are a no-op that never touches the device
-    assert lib.iqp_parity(0, None, 3, None, 1, 0, None, None) == L.IQP_OK
-    assert lib.iqp_parity(3, None, 0, None, 1, 1, None, None) == L.IQP_OK
+    assert lib.iqp_parity(0, None, 3, None, 1, 0, None, None, 0, None) == L.IQP_OK
+    assert lib.iqp_parity(3, None, 0, None, 1, 1, None, None, 0, None) == L.IQP_OK
+    assert lib.iqp_parity_workspace_bytes(100, 2, 1) > 0
+    assert lib.iqp_parity_workspace_bytes(100, 0, 1) == 0
 
 
 def test_workspace_bytes_query():

@@ -24,14 +24,30 @@ def _unpack_tiled(out, R, C):
     return ((words[idx] >> (c % 64).astype(np.uint64)) & np.uint64(1)).astype(np.uint8)
 
 
+def _unpack_tiled_t(out, R, C):
+    """TILED32_T words -> bits [R][C]: word ((c/32)*Rw + r/64)*32 + c%32, bit r%64."""
+    Rw = (R + 63) // 64
+    words = out.cpu().numpy().view(np.uint64).reshape(-1)
+    r = np.arange(R)[:, None]
+    c = np.arange(C)[None, :]
+    idx = ((c // 32) * Rw + r // 64) * 32 + c % 32
+    return ((words[idx] >> (r % 64).astype(np.uint64)) & np.uint64(1)).astype(np.uint8)
+
+
 @pytest.mark.parametrize("n", [1, 10, 63, 64, 65, 300, 1000, 2000])
-@pytest.mark.parametrize("layout", [api.ROW_MAJOR, api.TILED32])
+@pytest.mark.parametrize("layout", [api.ROW_MAJOR, api.TILED32, api.TILED32_T])
 def test_parity_bit_exact(n, layout):
     rng = np.random.default_rng(1000 + n)
     R, C = 77, 130  # ragged in both directions
     rows = W.uniform_bits(rng, R, n)
     rows[5] = 0  # weight-0 row
     cols = W.random_weight_rows(rng, C, n, 1, min(n, 9))
+    if n >= 300:
+        # dense columns too: the bit-sliced cost grows with their weight
+        dense = W.dense_to_rows(W.uniform_bits(rng, 20, n))
+        cols = W.rows_from_lists([list(cols.row(i)) for i in range(C - 20)] +
+                                 [list(dense.row(i)) for i in range(20)])
+        cols.idx = cols.idx.astype(np.int32)
     out = api.iqp_parity(dev_rows_from_dense(rows), dev_rows_from_index(cols, n), n, layout)
     torch.cuda.synchronize()
     expect = oracle.parity(n, rows, cols)
@@ -41,10 +57,14 @@ def test_parity_bit_exact(n, layout):
         words = out.cpu().numpy().view(np.uint64)
         if C % 64:
             assert np.all((words[:, -1] >> np.uint64(C % 64)) == 0)
-    else:
+    elif layout == api.TILED32:
         got = _unpack_tiled(out, R, C)
         pad = _unpack_tiled(out, (R + 31) // 32 * 32, C)[R:]
         assert not pad.any()
+    else:
+        got = _unpack_tiled_t(out, R, C)
+        full = _unpack_tiled_t(out, (R + 63) // 64 * 64, (C + 63) // 64 * 64)
+        assert not full[R:].any() and not full[:, C:].any()
     assert np.array_equal(got, expect)
 
 
