@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample-ops", type=int, default=0,
                     help="observables in the oracle's timed sample (0 = choose)")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="only --steps split-BF16 steps and one plain 256 MiB device copy "
+                         "(the reference for hardware byte counters); prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -133,6 +136,17 @@ def main():
                 out[name] = {"avg_ms": ms / n, "launches": n, "ms_per_step": ms / steps}
         api.profile_enable(False)
         return out
+
+    if args.profile_pass:
+        for _ in range(args.steps):
+            step("split_bf16")
+        torch.cuda.synchronize()
+        src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("profile pass done: %d steps, copy of %d bytes" % (args.steps, src.numel() * 4))
+        return
 
     result = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",

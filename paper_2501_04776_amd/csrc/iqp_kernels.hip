@@ -323,6 +323,24 @@ __device__ __forceinline__ int acc_row(int a, int h) { return 8 * (a >> 2) + 4 *
 // no wait on a later load ever covers them early.
 constexpr int kChunkWords = 32;
 
+// Interleave of one half-region of the pipeline: optional LDS reads for the
+// next K-step first, then each matrix product followed by a few of the next
+// K-step's expansion instructions, so the matrix core never waits for a run
+// of VALU. A region issues the hi-limb products of all accumulators in one
+// half and the lo-limb products in the other, fenced, so two products into
+// the same accumulator are always a full pass apart.
+template <int NDS, int NMFMA, int NVALU>
+__device__ __forceinline__ void interleave_half() {
+    if (NDS > 0) __builtin_amdgcn_sched_group_barrier(0x100, NDS, 0);  // LDS reads
+#pragma unroll
+    for (int i = 0; i < NMFMA; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix product
+        if (NVALU > 0)
+            __builtin_amdgcn_sched_group_barrier(0x002, (NVALU + NMFMA - 1) / NMFMA, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // Operands of one K-step: the +-1 B fragments and the masked hi / lo theta
 // A fragments.
 template <int FM, int FN>
@@ -331,14 +349,18 @@ struct FwdOps {
 };
 
 template <int FM, int FN, int T>
-__device__ __forceinline__ void fwd_expand(FwdOps<FM, FN> &o, const uint64_t (&cw)[FM],
-                                           const uint64_t (&bw)[FN], const u32x4 &th,
-                                           const u32x4 &tl, uint32_t ones) {
+__device__ __forceinline__ void fwd_expand_b(FwdOps<FM, FN> &o, const uint64_t (&bw)[FN],
+                                             uint32_t ones) {
 #pragma unroll
     for (int g = 0; g < FN; ++g) {
         const uint32_t d = (uint32_t)(bw[g] >> (32 * (T >> 1)));
         o.bv[g] = expand_pm1((T & 1) ? (d >> 16) : d, ones);
     }
+}
+
+template <int FM, int FN, int T>
+__device__ __forceinline__ void fwd_expand_a(FwdOps<FM, FN> &o, const uint64_t (&cw)[FM],
+                                             const u32x4 &th, const u32x4 &tl) {
 #pragma unroll
     for (int f = 0; f < FM; ++f) {
         const uint32_t d = (uint32_t)(cw[f] >> (32 * (T >> 1)));
@@ -346,32 +368,37 @@ __device__ __forceinline__ void fwd_expand(FwdOps<FM, FN> &o, const uint64_t (&c
     }
 }
 
-template <int FM, int FN>
-__device__ __forceinline__ void fwd_mfma(const FwdOps<FM, FN> &o, f32x16 (&acc)[FM][FN]) {
-#pragma unroll
-    for (int f = 0; f < FM; ++f)
-#pragma unroll
-        for (int g = 0; g < FN; ++g)
-            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[f], o.bv[g], acc[f][g], 0, 0, 0);
-#pragma unroll
-    for (int f = 0; f < FM; ++f)
-#pragma unroll
-        for (int g = 0; g < FN; ++g)
-            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.al[f], o.bv[g], acc[f][g], 0, 0, 0);
+template <int FM, int FN, int T>
+__device__ __forceinline__ void fwd_expand(FwdOps<FM, FN> &o, const uint64_t (&cw)[FM],
+                                           const uint64_t (&bw)[FN], const u32x4 &th,
+                                           const u32x4 &tl, uint32_t ones) {
+    fwd_expand_b<FM, FN, T>(o, bw, ones);
+    fwd_expand_a<FM, FN, T>(o, cw, th, tl);
 }
 
-// Interleave of one pipeline region: the LDS reads for the next K-step
-// first, then each matrix product followed by a few of the next K-step's
-// expansion instructions, so the matrix core never waits for a run of VALU.
-template <int NMFMA, int NVALU>
-__device__ __forceinline__ void interleave_region() {
-    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // LDS reads
+template <int FM, int FN, int LIMB>
+__device__ __forceinline__ void fwd_mfma_half(const FwdOps<FM, FN> &o, f32x16 (&acc)[FM][FN]) {
 #pragma unroll
-    for (int i = 0; i < NMFMA; ++i) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix product
-        __builtin_amdgcn_sched_group_barrier(0x002, (NVALU + NMFMA - 1) / NMFMA, 0);
-    }
-    __builtin_amdgcn_sched_barrier(0);
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int g = 0; g < FN; ++g)
+            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(LIMB ? o.al[f] : o.ah[f], o.bv[g],
+                                                                acc[f][g], 0, 0, 0);
+}
+
+// One pipeline region: the products of K-step t (operands `cur`) while the
+// operands of K-step T1 are expanded into `nxt` (theta limbs th, tl).
+template <int FM, int FN, int T1>
+__device__ __forceinline__ void fwd_region(const FwdOps<FM, FN> &cur, FwdOps<FM, FN> &nxt,
+                                           const uint64_t (&cw)[FM], const uint64_t (&bw)[FN],
+                                           const u32x4 &th, const u32x4 &tl, uint32_t ones,
+                                           f32x16 (&acc)[FM][FN]) {
+    fwd_expand_b<FM, FN, T1>(nxt, bw, ones);
+    fwd_mfma_half<FM, FN, 0>(cur, acc);
+    interleave_half<2, FM * FN, 8 * FN + 4>();
+    fwd_expand_a<FM, FN, T1>(nxt, cw, th, tl);
+    fwd_mfma_half<FM, FN, 1>(cur, acc);
+    interleave_half<0, FM * FN, 16 * FM + 4>();
 }
 
 // Decomposition shared by both forward kernels.
@@ -447,8 +474,6 @@ __global__ __launch_bounds__(256, 1) void phase_fwd_bf16_kernel(
             dma16(thl + src, &ltl[buf][wv * 64]);
         }
     };
-    constexpr int kMfma = 2 * FM * FN;
-    constexpr int kValu = 16 * FM + 8 * FN + 8;
     if (nchunks > 0) stage(U.w0, 0);
     uint64_t nxt_c[FM], nxt_b[FN], cur_c[FM], cur_b[FN];
     if (nwords > 0) {
@@ -480,15 +505,9 @@ __global__ __launch_bounds__(256, 1) void phase_fwd_bf16_kernel(
                 for (int g = 0; g < FN; ++g) nxt_b[g] = (bbase + (g * mw + w + 1) * 32)[r];
             }
             // region t: products of K-step t, expansion of K-step t+1
-            fwd_expand<FM, FN, 1>(opB, cur_c, cur_b, Th[o + 2], Tl[o + 2], ones);
-            fwd_mfma<FM, FN>(opA, acc);
-            interleave_region<kMfma, kValu>();
-            fwd_expand<FM, FN, 2>(opA, cur_c, cur_b, Th[o + 4], Tl[o + 4], ones);
-            fwd_mfma<FM, FN>(opB, acc);
-            interleave_region<kMfma, kValu>();
-            fwd_expand<FM, FN, 3>(opB, cur_c, cur_b, Th[o + 6], Tl[o + 6], ones);
-            fwd_mfma<FM, FN>(opA, acc);
-            interleave_region<kMfma, kValu>();
+            fwd_region<FM, FN, 1>(opA, opB, cur_c, cur_b, Th[o + 2], Tl[o + 2], ones, acc);
+            fwd_region<FM, FN, 2>(opB, opA, cur_c, cur_b, Th[o + 4], Tl[o + 4], ones, acc);
+            fwd_region<FM, FN, 3>(opA, opB, cur_c, cur_b, Th[o + 6], Tl[o + 6], ones, acc);
             // K-step 0 of word w+1, unconditionally so that it interleaves with
             // the products below: past the chunk's last word it reads inside
             // the chunk's buffer and is recomputed after the barrier
@@ -497,9 +516,7 @@ __global__ __launch_bounds__(256, 1) void phase_fwd_bf16_kernel(
             for (int f = 0; f < FM; ++f) cur_c[f] = nxt_c[f] >> (8 * h);
 #pragma unroll
             for (int g = 0; g < FN; ++g) cur_b[g] = nxt_b[g] >> (8 * h);
-            fwd_expand<FM, FN, 0>(opA, cur_c, cur_b, Th[on], Tl[on], ones);
-            fwd_mfma<FM, FN>(opB, acc);
-            interleave_region<kMfma, kValu>();
+            fwd_region<FM, FN, 0>(opB, opA, cur_c, cur_b, Th[on], Tl[on], ones, acc);
         }
         dma_wait_barrier();
     }
@@ -885,32 +902,54 @@ struct BwdOps {
 };
 
 template <int FM, int FN, int T>
-__device__ __forceinline__ void bwd_expand(BwdOps<FM, FN> &o, const u32x4 *ls,
-                                           const uint64_t (&bw)[FN], int lane, uint32_t ones) {
+__device__ __forceinline__ void bwd_expand_a(BwdOps<FM, FN> &o, const u32x4 *ls, int lane) {
 #pragma unroll
     for (int f = 0; f < FM; ++f) {
         o.ah[f] = __builtin_bit_cast(bf16x8, ls[((0 * FM + f) * 4 + T) * 64 + lane]);
         o.al[f] = __builtin_bit_cast(bf16x8, ls[((1 * FM + f) * 4 + T) * 64 + lane]);
     }
+}
+
+template <int FM, int FN, int T, int G0, int G1>
+__device__ __forceinline__ void bwd_expand_b(BwdOps<FM, FN> &o, const uint64_t (&bw)[FN],
+                                             uint32_t ones) {
 #pragma unroll
-    for (int g = 0; g < FN; ++g) {
+    for (int g = G0; g < G1; ++g) {
         const uint32_t d = (uint32_t)(bw[g] >> (32 * (T >> 1)));
         o.bv[g] = expand_pm1((T & 1) ? (d >> 16) : d, ones);
     }
 }
 
-template <int FM, int FN>
-__device__ __forceinline__ void bwd_mfma(const BwdOps<FM, FN> &o, f32x16 (&acc)[FM][FN]) {
+template <int FM, int FN, int T>
+__device__ __forceinline__ void bwd_expand(BwdOps<FM, FN> &o, const u32x4 *ls,
+                                           const uint64_t (&bw)[FN], int lane, uint32_t ones) {
+    bwd_expand_a<FM, FN, T>(o, ls, lane);
+    bwd_expand_b<FM, FN, T, 0, FN>(o, bw, ones);
+}
+
+template <int FM, int FN, int LIMB>
+__device__ __forceinline__ void bwd_mfma_half(const BwdOps<FM, FN> &o, f32x16 (&acc)[FM][FN]) {
 #pragma unroll
     for (int f = 0; f < FM; ++f)
 #pragma unroll
         for (int g = 0; g < FN; ++g)
-            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[f], o.bv[g], acc[f][g], 0, 0, 0);
-#pragma unroll
-    for (int f = 0; f < FM; ++f)
-#pragma unroll
-        for (int g = 0; g < FN; ++g)
-            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.al[f], o.bv[g], acc[f][g], 0, 0, 0);
+            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(LIMB ? o.al[f] : o.ah[f], o.bv[g],
+                                                                acc[f][g], 0, 0, 0);
+}
+
+// One pipeline region: the products of K-step t (operands `cur`) while the
+// operands of K-step T1 are read from `lsn` and expanded into `nxt`.
+template <int FM, int FN, int T1>
+__device__ __forceinline__ void bwd_region(const BwdOps<FM, FN> &cur, BwdOps<FM, FN> &nxt,
+                                           const u32x4 *lsn, const uint64_t (&bw)[FN], int lane,
+                                           uint32_t ones, f32x16 (&acc)[FM][FN]) {
+    bwd_expand_a<FM, FN, T1>(nxt, lsn, lane);
+    bwd_expand_b<FM, FN, T1, 0, FN / 2>(nxt, bw, ones);
+    bwd_mfma_half<FM, FN, 0>(cur, acc);
+    interleave_half<2 * FM, FM * FN, 4 * FN + 2>();
+    bwd_expand_b<FM, FN, T1, FN / 2, FN>(nxt, bw, ones);
+    bwd_mfma_half<FM, FN, 1>(cur, acc);
+    interleave_half<0, FM * FN, 4 * FN + 2>();
 }
 
 // sum_k c_kj T[k][j] over this wave's observable rows, per gate column.
@@ -980,8 +1019,6 @@ __global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(
             dma16((limb ? sbase_l : sbase_h) + src, &ls[buf][b * 64]);
         }
     };
-    constexpr int kMfma = 2 * FM * FN;
-    constexpr int kValu = 8 * FN + 4;
     stage(0, 0);
     if (sw > 1) stage(1, 1);
     uint64_t nxt[FN], cur[FN];
@@ -999,15 +1036,9 @@ __global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(
     for (int64_t w = 0; w < sw; ++w) {
         const int buf = (int)(w & 1);
         const u32x4 *lsb = ls[buf];
-        bwd_expand<FM, FN, 1>(opB, lsb, cur, lane, ones);
-        bwd_mfma<FM, FN>(opA, acc);
-        interleave_region<kMfma, kValu>();
-        bwd_expand<FM, FN, 2>(opA, lsb, cur, lane, ones);
-        bwd_mfma<FM, FN>(opB, acc);
-        interleave_region<kMfma, kValu>();
-        bwd_expand<FM, FN, 3>(opB, lsb, cur, lane, ones);
-        bwd_mfma<FM, FN>(opA, acc);
-        interleave_region<kMfma, kValu>();
+        bwd_region<FM, FN, 1>(opA, opB, lsb, cur, lane, ones, acc);
+        bwd_region<FM, FN, 2>(opB, opA, lsb, cur, lane, ones, acc);
+        bwd_region<FM, FN, 3>(opA, opB, lsb, cur, lane, ones, acc);
         // word w+1's copy and bit words have landed; nobody reads buffer
         // `buf` any more
         dma_wait_barrier();
@@ -1019,9 +1050,7 @@ __global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(
             for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w + 2) * 32)[r];
         }
         // past the last word this expands a stale buffer and is never used
-        bwd_expand<FM, FN, 0>(opA, ls[buf ^ 1], cur, lane, ones);
-        bwd_mfma<FM, FN>(opB, acc);
-        interleave_region<kMfma, kValu>();
+        bwd_region<FM, FN, 0>(opB, opA, ls[buf ^ 1], cur, lane, ones, acc);
     }
     bwd_epilogue<FM, FN>(acc, ctbits, ob, jb, lw, h, r, active, gpart, m_pad);
 }
