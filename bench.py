@@ -28,8 +28,32 @@ PEAK = {"split_bf16": (2.5e15, 4.0), "fp32": (157.3e12, 2.0)}  # (peak flop/s, M
 TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2501_04776_amd", "csrc", "iqp_kernels.hip")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def recorded_traffic(workload_name, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 byte-counter
+    summary of this workload (FETCH_SIZE and WRITE_SIZE, each scaled by what the
+    counter reads for a plain device copy of known size), or None when there is
+    none or the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s.md" % workload_name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if "```json" not in text:
+        return None
+    rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if rec.get("kernel_source_sha256") != sha or kernel not in rec.get("kernels", {}):
+        return None
+    k = rec["kernels"][kernel]
+    return k["fetch_bytes"] + k["write_bytes"]
 
 
 def make_workload(name):
@@ -169,7 +193,8 @@ def main():
     achieved = flop_per_term * T / (kb[dom]["avg_ms"] * 1e-3)
     result["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12,
                           "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-                          "traffic": None,
+                          "traffic": recorded_traffic(w.name, dom),
+                          "traffic_unit": "bytes per launch (HBM read + write)",
                           "flops_per_launch": flop_per_term * T,
                           "avg_launch_ms": kb[dom]["avg_ms"]}
 

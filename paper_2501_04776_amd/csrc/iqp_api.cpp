@@ -156,8 +156,8 @@ static size_t carve(size_t &cur, size_t bytes) {
     return o;
 }
 
-// Tile overrides for measurement sweeps: IQP_FWD_TILE / IQP_BWD_TILE = "FMxFN"
-// (one of 4x4, 2x4, 2x2) and
+// Tile overrides for measurement sweeps: IQP_FWD_TILE = "FMxFN" (4x4, 2x4,
+// 2x2), IQP_BWD_TILE (2x4, 2x2) and
 // IQP_FWD_SPLITS = number of gate-word splits of the forward.
 static void apply_env_tiles(TileCfg &tc) {
     const char *f = getenv("IQP_FWD_TILE");
@@ -168,8 +168,7 @@ static void apply_env_tiles(TileCfg &tc) {
         tc.fn = b;
     }
     const char *g = getenv("IQP_BWD_TILE");
-    if (g && sscanf(g, "%dx%d", &a, &b) == 2 &&
-        ((a == 4 && b == 4) || (a == 2 && b == 4) || (a == 2 && b == 2))) {
+    if (g && sscanf(g, "%dx%d", &a, &b) == 2 && ((a == 2 && b == 4) || (a == 2 && b == 2))) {
         tc.bfm = a;
         tc.bfn = b;
     }

@@ -24,7 +24,7 @@ __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_
 // Tile configuration of the two contractions (wave tile = 32*fm x 32*fn).
 struct TileCfg {
     int fm = 4, fn = 4;      // forward: observables x samples
-    int bfm = 4, bfn = 4;    // backward: observables x gates
+    int bfm = 2, bfn = 2;    // backward: observables x gates
     int64_t splits = 0;      // forward split over gate words; 0 = choose
 };
 

@@ -292,8 +292,11 @@ __device__ __forceinline__ void dma16(const void *gsrc, void *lds_block) {
 
 // Wait for this wave's outstanding vector-memory operations (including the
 // global -> LDS copies above), then synchronise the workgroup.
+// (The builtin, unlike inline assembly, is visible to the compiler's own
+// wait-count tracking, so it does not wait again for loads this covered.)
 __device__ __forceinline__ void dma_wait_barrier() {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // vmcnt(0), expcnt and lgkmcnt left at their maxima (gfx9 encoding)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
 }
 
@@ -981,9 +984,12 @@ __global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(
     const u32x4 *__restrict__ shi, const u32x4 *__restrict__ slo,
     const uint64_t *__restrict__ btbits, const uint64_t *__restrict__ ctbits, int64_t sw,
     int64_t lw, int64_t n_jb, int64_t wg_units, float *__restrict__ gpart, int64_t m_pad) {
-    // one sample word: [limb][f][t][lane], 16 bytes each
+    // one sample word: [limb][f][t][lane], 16 bytes each. The two buffers
+    // are distinct objects selected at compile time (the word loop is
+    // unrolled by two), so the compiler can tell that reads of one never
+    // alias the global -> LDS copy in flight into the other.
     constexpr int kUnits = 2 * FM * 4 * 64;
-    __shared__ u32x4 ls[2][kUnits];
+    __shared__ u32x4 ls0[kUnits], ls1[kUnits];
     const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
     if (gu >= wg_units) return;  // uniform over the workgroup
     const int64_t n_jbg = ceil_div(n_jb, 4);
@@ -1010,17 +1016,17 @@ __global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(
     // staging block b = (limb * FM + f) * 4 + t (64 units of 16 bytes)
     //   <- S(limb)[(f * KTs + 4 w + t) * 64 + ln]; wave v copies blocks v, v+4, ...
     const int wv = wave_id();
-    auto stage = [&](int64_t w, int buf) {
+    auto stage = [&](int64_t w, u32x4 *dst) {
 #pragma unroll
         for (int k = 0; k < kUnits / 256; ++k) {
             const int b = wv + 4 * k;
             const int t = b & 3, f = (b >> 2) % FM, limb = b / (4 * FM);
             const int64_t src = ((int64_t)f * KTs + 4 * w + t) * 64 + lane;
-            dma16((limb ? sbase_l : sbase_h) + src, &ls[buf][b * 64]);
+            dma16((limb ? sbase_l : sbase_h) + src, &dst[b * 64]);
         }
     };
-    stage(0, 0);
-    if (sw > 1) stage(1, 1);
+    stage(0, ls0);
+    if (sw > 1) stage(1, ls1);
     uint64_t nxt[FN], cur[FN];
 #pragma unroll
     for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw) * 32)[r];
@@ -1032,17 +1038,17 @@ __global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(
         for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + 1) * 32)[r];
     }
     BwdOps<FM, FN> opA, opB;
-    bwd_expand<FM, FN, 0>(opA, ls[0], cur, lane, ones);
-    for (int64_t w = 0; w < sw; ++w) {
-        const int buf = (int)(w & 1);
-        const u32x4 *lsb = ls[buf];
-        bwd_region<FM, FN, 1>(opA, opB, lsb, cur, lane, ones, acc);
-        bwd_region<FM, FN, 2>(opB, opA, lsb, cur, lane, ones, acc);
-        bwd_region<FM, FN, 3>(opA, opB, lsb, cur, lane, ones, acc);
-        // word w+1's copy and bit words have landed; nobody reads buffer
-        // `buf` any more
+    bwd_expand<FM, FN, 0>(opA, ls0, cur, lane, ones);
+    // Word w reads `mine`; its last region runs after a barrier that makes
+    // word w+1's buffer `other` valid, so that region already expands word
+    // w+1's first K-step; the copy of word w+2 into `mine` is issued right
+    // after that barrier.
+    auto word = [&](int64_t w, u32x4 *mine, const u32x4 *other) {
+        bwd_region<FM, FN, 1>(opA, opB, mine, cur, lane, ones, acc);
+        bwd_region<FM, FN, 2>(opB, opA, mine, cur, lane, ones, acc);
+        bwd_region<FM, FN, 3>(opA, opB, mine, cur, lane, ones, acc);
         dma_wait_barrier();
-        if (w + 2 < sw) stage(w + 2, buf);
+        if (w + 2 < sw) stage(w + 2, mine);
 #pragma unroll
         for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> (8 * h);
         if (w + 2 < sw) {
@@ -1050,7 +1056,11 @@ __global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(
             for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w + 2) * 32)[r];
         }
         // past the last word this expands a stale buffer and is never used
-        bwd_region<FM, FN, 0>(opB, opA, ls[buf ^ 1], cur, lane, ones, acc);
+        bwd_region<FM, FN, 0>(opB, opA, other, cur, lane, ones, acc);
+    };
+    for (int64_t w = 0; w < sw; w += 2) {
+        word(w, ls0, ls1);
+        if (w + 1 < sw) word(w + 1, ls1, ls0);
     }
     bwd_epilogue<FM, FN>(acc, ctbits, ob, jb, lw, h, r, active, gpart, m_pad);
 }
@@ -1163,9 +1173,9 @@ hipError_t launch_phase_bwd(const LaunchCtx &lc, int prec, int fm, int fn, const
                             float *gpart) {
     hipEvent_t ev;
     timed_begin(lc, KF_BWD, &ev);
-    if (fm == 4 && fn == 4)
-        bwd_dispatch<4, 4>(lc, prec, shi, slo, s32, btbits, ctbits, m_pad, l_pad, s_pad, gpart);
-    else if (fm == 2 && fn == 2)
+    // (a 128x128 backward tile cannot hold the double-buffered pipeline in
+    // 512 registers without spilling, so it is not offered)
+    if (fm == 2 && fn == 2)
         bwd_dispatch<2, 2>(lc, prec, shi, slo, s32, btbits, ctbits, m_pad, l_pad, s_pad, gpart);
     else if (fm == 2 && fn == 4)
         bwd_dispatch<2, 4>(lc, prec, shi, slo, s32, btbits, ctbits, m_pad, l_pad, s_pad, gpart);
