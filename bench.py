@@ -11,7 +11,12 @@ Prints ONE JSON line. The metric is phase terms per second, T = l * s * m
 headline value is split-BF16 fwd+bwd. Results are checked against the FP64
 oracle on sampled observables before the number is printed.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg4]
+The batched workload (64 circuits of uneven size, --workload cfg5) runs as
+one BatchPlan: a step is the forward and the backward pass over all circuits,
+each pass one graph replay with persistent contraction kernels, tiles from
+the autotuner.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg4|cfg5]
 """
 from __future__ import annotations
 
@@ -109,6 +114,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "cfg5":
+        return main_batch(args)
 
     import torch
     from paper_2501_04776_amd import api
@@ -261,6 +269,176 @@ def main():
                         "samples": w.s, "precision": "split_bf16 (hi+lo BF16, FP32 accumulate)",
                         "step": "iqp_mmd_loss_grad" if mmd else "iqp_expval + iqp_expval_grad",
                         "terms_per_step": T}
+    print(json.dumps(result), flush=True)
+
+
+def main_batch(args):
+    """The 64-circuit batched workload: n ~ U{50..2000}, m ~ U{1e3..2e5},
+    l ~ U{100..5000}, s = 4096, all circuits in one pass per direction."""
+    import torch
+    import oracle
+    import workloads as W
+    from paper_2501_04776_amd import api
+
+    t0 = time.time()
+    ws = [W.cfg5_circuit(i) for i in range(64)]
+    dws = [DevWorkload(w) for w in ws]
+    T = float(sum(w.terms for w in ws))
+    name = "batch64_s4096_seed505"
+    log("workload %s: 64 circuits, T=%.4g terms per pass (setup %.1fs)" % (name, T,
+                                                                           time.time() - t0))
+    rng = np.random.default_rng(7)
+    us = [torch.from_numpy(rng.normal(size=w.l) / w.l).cuda() for w in ws]
+
+    def make_plan(prec):
+        plan = api.BatchPlan([(api.Circuit(w.n, d.gens, d.theta), d.ops, d.samples)
+                              for w, d in zip(ws, dws)], prec)
+        t1 = time.time()
+        plan.expval()
+        cfg = plan.tune(us)
+        log("%s: workspace %.2f GB, tuned %s in %.1fs" % (prec, plan.ws_bytes / 1e9, cfg,
+                                                          time.time() - t1))
+        return plan
+
+    def timed(plan, fwd_only=False, steps=args.steps, warmup=args.warmup):
+        def one():
+            plan.expval()
+            if not fwd_only:
+                plan.expval_grad(us)
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            one()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    plan = make_plan("split_bf16")
+    if args.profile_pass:
+        for _ in range(args.steps):
+            plan.expval()
+            plan.expval_grad(us)
+        torch.cuda.synchronize()
+        src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("profile pass done: %d steps, copy of %d bytes" % (args.steps, src.numel() * 4))
+        return
+
+    result = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+              "data": "synthetic"}
+    ms = timed(plan)
+    ms_fwd = timed(plan, fwd_only=True)
+    log("split_bf16 batched: fwd+bwd %.3f ms, fwd %.3f ms" % (ms, ms_fwd))
+    result.update({"value": T / (ms * 1e-3), "unit": "terms/s", "ms_per_step": ms,
+                   "fwd_terms_per_s": T / (ms_fwd * 1e-3), "fwd_ms": ms_fwd,
+                   "tiles": plan.config()})
+
+    # per-kernel times: with timing on, a pass runs its launches one by one,
+    # each bracketed by events on its stream
+    api.profile_reset()
+    api.profile_enable(True)
+    nprof = max(2, min(args.steps, 4))
+    for _ in range(nprof):
+        plan.expval()
+        plan.expval_grad(us)
+    torch.cuda.synchronize()
+    kb = {}
+    for k in ("parity", "theta_prep", "phase_fwd", "phase_epilogue", "finalize", "weights",
+              "phase_bwd", "grad_reduce"):
+        tot, n = api.profile_query(k)
+        if n:
+            kb[k] = {"avg_ms": tot / n, "launches": n, "ms_per_step": tot / nprof}
+    api.profile_enable(False)
+    result["kernels"] = kb
+    dom = max(("phase_fwd", "phase_bwd"), key=lambda k: kb[k]["avg_ms"])
+    peak, fpt = PEAK["split_bf16"]
+    achieved = fpt * T / (kb[dom]["avg_ms"] * 1e-3)
+    result["roofline"] = {"bound": "mfma", "kernel": dom + " (persistent, all 64 circuits)",
+                          "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                          "frac": achieved / peak, "traffic": recorded_traffic(name, dom),
+                          "traffic_unit": "bytes per launch (HBM read + write)",
+                          "flops_per_launch": fpt * T, "avg_launch_ms": kb[dom]["avg_ms"]}
+
+    if not args.no_fp32:
+        plan32 = make_plan("fp32")
+        ms32 = timed(plan32, steps=max(2, args.steps // 4), warmup=1)
+        ms32f = timed(plan32, fwd_only=True, steps=max(2, args.steps // 4), warmup=1)
+        log("fp32 batched: fwd+bwd %.3f ms, fwd %.3f ms" % (ms32, ms32f))
+        result["fp32"] = {"fwd_bwd_terms_per_s": T / (ms32 * 1e-3),
+                          "fwd_terms_per_s": T / (ms32f * 1e-3), "ms_per_step": ms32,
+                          "fwd_ms": ms32f, "tiles": plan32.config(),
+                          "mfma_frac_fwd": 2.0 * T / (ms32f * 1e-3) / PEAK["fp32"][0]}
+        plan32.close()
+        del plan32
+
+    # parity: 3 sampled observables of 8 sampled circuits, means and the
+    # gradient of a loss that weights only those observables
+    pick_c = np.random.default_rng(0).choice(64, size=8, replace=False)
+    errs = {"max_abs_err_mean": 0.0, "max_abs_err_stderr": 0.0, "max_rel_err_grad": 0.0}
+    prng = np.random.default_rng(1)
+    sel, upick = {}, []
+    for i, w in enumerate(ws):
+        u = np.zeros(w.l)
+        if i in pick_c:
+            sel[i] = prng.choice(w.l, size=3, replace=False)
+            u[sel[i]] = prng.normal(size=3)
+        upick.append(torch.from_numpy(u).cuda())
+    plan.expval()
+    plan.expval_grad(upick)
+    torch.cuda.synchronize()
+    for i, k in sel.items():
+        w, d = ws[i], dws[i]
+        om, ose = oracle.expval(w.n, w.gates, w.theta, d.ops01[k], w.samples)
+        og = oracle.expval_grad(w.n, w.gates, w.theta, d.ops01[k], w.samples,
+                                upick[i].cpu().numpy()[k])
+        errs["max_abs_err_mean"] = max(errs["max_abs_err_mean"],
+                                       float(np.abs(plan.means[i].cpu().numpy()[k] - om).max()))
+        errs["max_abs_err_stderr"] = max(errs["max_abs_err_stderr"],
+                                         float(np.abs(plan.stderrs[i].cpu().numpy()[k] - ose).max()))
+        errs["max_rel_err_grad"] = max(errs["max_rel_err_grad"],
+                                       float(np.abs(plan.grads[i].cpu().numpy() - og).max() /
+                                             max(1.0, np.abs(og).max())))
+    tol = TOL["split_bf16"]
+    result["parity"] = {"split_bf16": dict(errs, tol=tol, ok=bool(max(errs.values()) < tol),
+                                           sampled="3 observables of 8 circuits")}
+
+    if not args.no_cpu_baseline:
+        # the oracle on a bounded sample: fwd + bwd of the first k observables
+        # of circuit 0 over all its samples and gates, k sized for ~15 s
+        w, d = ws[0], dws[0]
+
+        def oracle_run(k):
+            uu = np.random.default_rng(5).normal(size=k)
+            t1 = time.time()
+            oracle.expval(w.n, w.gates, w.theta, d.ops01[:k], w.samples)
+            oracle.expval_grad(w.n, w.gates, w.theta, d.ops01[:k], w.samples, uu)
+            return time.time() - t1
+        nth = oracle.num_threads()
+        k0 = min(w.l, max(nth, 8))
+        dt0 = oracle_run(k0)
+        k = int(min(w.l, max(k0, round(k0 * 15.0 / max(dt0, 1e-3)))))
+        k = max(nth, (k // nth) * nth) if k >= nth else k
+        dt = oracle_run(k)
+        log("oracle: %d observables of circuit 0 in %.2f s on %d threads" % (k, dt, nth))
+        result["cpu_baseline"] = {"value": k * w.s * w.m / dt, "unit": "terms/s",
+                                  "cores": min(nth, k), "kind": "oracle",
+                                  "sample": "fwd+bwd of the first %d of %d observables of circuit "
+                                            "0 (n=%d, m=%d) over its %d samples (%.1f s)" %
+                                            (k, w.l, w.n, w.m, w.s, dt)}
+    result["config"] = {"workload": name, "circuits": 64, "samples": 4096,
+                        "n_qubits": "U{50..2000}", "gates": "U{1e3..2e5}",
+                        "observables": "U{100..5000}",
+                        "precision": "split_bf16 (hi+lo BF16, FP32 accumulate)",
+                        "step": "BatchPlan.expval + BatchPlan.expval_grad (graph replays)",
+                        "terms_per_step": T}
+    plan.close()
     print(json.dumps(result), flush=True)
 
 

@@ -99,10 +99,11 @@ size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s,
  *               columns padded to a multiple of 64:
  *               out[((c / 32) * ceil(n_rows/64) + r/64) * 32 + c % 32], bit r % 64
  *   out       device; pad rows and bits past the last row/column are written 0
- *   ws        device workspace of ws_bytes >= iqp_parity_workspace_bytes(n_rows, W, layout)
+ *   ws        device workspace of ws_bytes >=
+ *             iqp_parity_workspace_bytes(n_rows, n_cols, W, layout)
  * n_rows >= 0, n_cols >= 0, W >= 1 (n_rows or n_cols = 0 is a no-op). Bit-exact. */
 enum { IQP_BITS_ROW_MAJOR = 0, IQP_BITS_TILED32 = 1, IQP_BITS_TILED32_T = 2 };
-size_t iqp_parity_workspace_bytes(int64_t n_rows, int32_t n_words, int layout);
+size_t iqp_parity_workspace_bytes(int64_t n_rows, int64_t n_cols, int32_t n_words, int layout);
 int iqp_parity(int64_t n_rows, const uint64_t *rows, int64_t n_cols, const uint64_t *cols,
                int32_t n_words, int layout, uint64_t *out, void *ws, size_t ws_bytes,
                void *stream);
@@ -154,6 +155,90 @@ int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
                       const double *op_weight, int64_t s, const uint64_t *samples, int64_t N,
                       const uint64_t *data, int unbiased, int precision, double *loss,
                       double *grad_theta, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent problems (circuit, observables, samples) of
+ * uneven size in one pass. Each step of the estimator runs as one launch over
+ * all problems; the two phase contractions run as persistent kernels that take
+ * work units (tiles of every problem, longest first) from a queue, so small
+ * and large circuits share the matrix cores without a tail per circuit. A pass
+ * is captured once in a HIP graph and replayed. Results equal those of the
+ * single-problem calls up to the order of FP32 accumulation (the gate-word
+ * split of the forward may differ) and are deterministic for a fixed
+ * configuration.
+ *
+ * One problem. Device pointers, conventions as the single-problem calls:
+ *   circuit               n, W, m, gens [m][W], theta [m]
+ *   n_ops / ops           l >= 1, [l][W]
+ *   n_samples / samples   s >= 1, [s][W]
+ *   mean, stderr_         [l] outputs of iqp_batch_expval (stderr_ may be NULL)
+ *   phase_save            [l][s] float: written by iqp_batch_expval when not
+ *                         NULL, read by iqp_batch_expval_grad (required there)
+ *   grad_mean             [l] dL/dmean, input of iqp_batch_expval_grad
+ *   grad_theta            [m] output of iqp_batch_expval_grad, overwritten
+ */
+typedef struct {
+    iqp_circuit circuit;
+    int64_t n_ops;
+    const uint64_t *ops;
+    int64_t n_samples;
+    const uint64_t *samples;
+    double *mean;
+    double *stderr_;
+    float *phase_save;
+    const double *grad_mean;
+    double *grad_theta;
+} iqp_problem;
+
+/* A plan holds the shapes of a problem list, the workspace layout, the tile
+ * configuration and the captured graphs. Host object, owned by the caller
+ * through create / destroy; not thread-safe. */
+typedef struct iqp_batch_plan iqp_batch_plan;
+
+/* flags of iqp_batch_plan_create */
+enum {
+    IQP_BATCH_NO_GRAPH = 1 /* launch the steps one by one instead of replaying a graph */
+};
+
+/* Creates a plan for n_problems >= 1 problems; only the shapes of `probs`
+ * (host array) are read: n_qubits, n_words, n_gates, n_ops, n_samples. The
+ * tile configuration is the one recorded for these shapes by iqp_batch_tune
+ * in this process (or in the file named by the environment variable
+ * IQP_TUNE_CACHE), else a default. The current device must be gfx950. */
+int iqp_batch_plan_create(int32_t n_problems, const iqp_problem *probs, int precision,
+                          int flags, iqp_batch_plan **plan);
+int iqp_batch_plan_destroy(iqp_batch_plan *plan);
+
+/* Workspace bytes of a plan (enough for every configuration the tuner tries). */
+size_t iqp_batch_workspace_bytes(const iqp_batch_plan *plan);
+
+/* Forward pass of every problem: mean, stderr_ and (if not NULL) phase_save.
+ * `probs` (host array) must have the plan's shapes; its pointers may change
+ * from call to call. The pointer table is copied to the workspace on
+ * `stream` before the pass; calls on one plan must be ordered on one stream. */
+int iqp_batch_expval(iqp_batch_plan *plan, const iqp_problem *probs, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* Backward pass of every problem: grad_theta from grad_mean and phase_save
+ * (the forward's phases with the same inputs and precision). */
+int iqp_batch_expval_grad(iqp_batch_plan *plan, const iqp_problem *probs, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* Autotuner: times each candidate tile configuration of the forward (bit 0
+ * of `passes`) and of the backward (bit 1; needs grad_mean and phase_save) on
+ * these very problems, keeps the fastest in the plan and records it for the
+ * shapes (in this process, and appended to IQP_TUNE_CACHE when set).
+ * Synchronises `stream`; outputs are left unspecified. */
+int iqp_batch_tune(iqp_batch_plan *plan, const iqp_problem *probs, int passes, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/* Tile configuration as 6 int32: forward tile rows and columns in 32-blocks
+ * (4x4, 2x4 or 2x2), forward split mode (0: no gate-word split; 1, 2: split
+ * long problems so that no work unit exceeds 1/4 or 1/16 of a workgroup's
+ * share), backward tile (2x2 or 2x4), and whether it came from the tuner.
+ * set_config takes the first five. */
+int iqp_batch_get_config(const iqp_batch_plan *plan, int32_t *cfg6);
+int iqp_batch_set_config(iqp_batch_plan *plan, const int32_t *cfg5);
 
 /* Static text for a status code. */
 const char *iqp_strerror(int status);

@@ -32,15 +32,28 @@ IQP_BITS_TILED32 = 1
 IQP_BITS_TILED32_T = 2
 
 # every symbol include/iqp.h declares
-EXPORTED = ("iqp_workspace_bytes", "iqp_parity_workspace_bytes", "iqp_parity", "iqp_expval", "iqp_expval_grad",
-            "iqp_mmd_loss_grad", "iqp_strerror", "iqp_last_error", "iqp_profile_enable",
+EXPORTED = ("iqp_workspace_bytes", "iqp_parity_workspace_bytes", "iqp_parity", "iqp_expval",
+            "iqp_expval_grad", "iqp_mmd_loss_grad", "iqp_batch_plan_create",
+            "iqp_batch_plan_destroy", "iqp_batch_workspace_bytes", "iqp_batch_expval",
+            "iqp_batch_expval_grad", "iqp_batch_tune", "iqp_batch_get_config",
+            "iqp_batch_set_config", "iqp_strerror", "iqp_last_error", "iqp_profile_enable",
             "iqp_profile_query", "iqp_profile_reset")
+
+IQP_BATCH_NO_GRAPH = 1
 
 
 class IqpCircuit(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_int32), ("n_words", ctypes.c_int32),
                 ("n_gates", ctypes.c_int64), ("gens", ctypes.c_void_p),
                 ("theta", ctypes.c_void_p)]
+
+
+class IqpProblem(ctypes.Structure):
+    _fields_ = [("circuit", IqpCircuit), ("n_ops", ctypes.c_int64), ("ops", ctypes.c_void_p),
+                ("n_samples", ctypes.c_int64), ("samples", ctypes.c_void_p),
+                ("mean", ctypes.c_void_p), ("stderr_", ctypes.c_void_p),
+                ("phase_save", ctypes.c_void_p), ("grad_mean", ctypes.c_void_p),
+                ("grad_theta", ctypes.c_void_p)]
 
 
 class IqpError(RuntimeError):
@@ -65,7 +78,7 @@ def lib():
     cp = ctypes.POINTER(IqpCircuit)
     L.iqp_workspace_bytes.argtypes = [i32, cp, i64, i64, i64, i32]
     L.iqp_workspace_bytes.restype = sz
-    L.iqp_parity_workspace_bytes.argtypes = [i64, ctypes.c_int32, i32]
+    L.iqp_parity_workspace_bytes.argtypes = [i64, i64, ctypes.c_int32, i32]
     L.iqp_parity_workspace_bytes.restype = sz
     L.iqp_parity.argtypes = [i64, vp, i64, vp, ctypes.c_int32, i32, vp, vp, sz, vp]
     L.iqp_parity.restype = i32
@@ -76,6 +89,23 @@ def lib():
     L.iqp_mmd_loss_grad.argtypes = [cp, i64, vp, vp, i64, vp, i64, vp, i32, i32, vp, vp, vp,
                                     sz, vp]
     L.iqp_mmd_loss_grad.restype = i32
+    pp = ctypes.POINTER(IqpProblem)
+    L.iqp_batch_plan_create.argtypes = [ctypes.c_int32, pp, i32, i32, ctypes.POINTER(vp)]
+    L.iqp_batch_plan_create.restype = i32
+    L.iqp_batch_plan_destroy.argtypes = [vp]
+    L.iqp_batch_plan_destroy.restype = i32
+    L.iqp_batch_workspace_bytes.argtypes = [vp]
+    L.iqp_batch_workspace_bytes.restype = sz
+    L.iqp_batch_expval.argtypes = [vp, pp, vp, sz, vp]
+    L.iqp_batch_expval.restype = i32
+    L.iqp_batch_expval_grad.argtypes = [vp, pp, vp, sz, vp]
+    L.iqp_batch_expval_grad.restype = i32
+    L.iqp_batch_tune.argtypes = [vp, pp, i32, vp, sz, vp]
+    L.iqp_batch_tune.restype = i32
+    L.iqp_batch_get_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.iqp_batch_get_config.restype = i32
+    L.iqp_batch_set_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.iqp_batch_set_config.restype = i32
     L.iqp_strerror.argtypes = [i32]
     L.iqp_strerror.restype = ctypes.c_char_p
     L.iqp_last_error.argtypes = []

@@ -104,7 +104,7 @@ def iqp_parity(rows: torch.Tensor, cols: torch.Tensor, n_qubits: int,
     else:
         shape = ((R + 31) // 32 * 32 if layout == TILED32 else R, (C + 63) // 64)
     out = torch.empty(shape, dtype=torch.int64, device=rows.device)
-    need = int(L.lib().iqp_parity_workspace_bytes(R, W, layout))
+    need = int(L.lib().iqp_parity_workspace_bytes(R, C, W, layout))
     ws, nb = workspace.get(rows.device, need)
     L.check(L.lib().iqp_parity(R, _ptr(rows), C, _ptr(cols), W, layout, _ptr(out), _ptr(ws), nb,
                                _stream(rows)), "iqp_parity")
@@ -172,6 +172,117 @@ def iqp_mmd_loss_grad(circ: Circuit, ops: torch.Tensor, op_weight: torch.Tensor,
                                       N, _ptr(data), int(bool(unbiased)), p, _ptr(loss), _ptr(g),
                                       _ptr(ws), nb, _stream(ops)), "iqp_mmd_loss_grad")
     return loss, g
+
+
+# --- batched form -------------------------------------------------------------
+class BatchPlan:
+    """Many problems (circuit, observables, samples) of uneven size run as one
+    pass per direction (iqp_batch_* of include/iqp.h). The plan owns its
+    workspace (the captured graphs are bound to it) and the output buffers:
+    ``means``, ``stderrs``, ``phases`` (forward) and ``grads`` (backward),
+    one tensor per problem, overwritten by each pass. Calls run on torch's
+    current stream and return without synchronising. Circuit parameters may
+    be updated in place between calls."""
+
+    def __init__(self, problems, precision=SPLIT_BF16, graph: bool = True,
+                 save_phases: bool = True):
+        if not problems:
+            raise ValueError("a batch needs at least one problem")
+        self.p = precision_id(precision)
+        self.circuits, self.ops, self.samples = [], [], []
+        for circ, ops, samples in problems:
+            if not isinstance(circ, Circuit):
+                raise ValueError("each problem is (Circuit, ops, samples)")
+            self.circuits.append(circ)
+            self.ops.append(_rows(ops, "ops", circ.W))
+            self.samples.append(_rows(samples, "samples", circ.W))
+        self.device = self.circuits[0].device
+        if any(c.device != self.device for c in self.circuits):
+            raise ValueError("all problems must be on one device")
+        self.n = len(problems)
+        dev = self.device
+        self.means = [torch.empty(o.shape[0], dtype=torch.float64, device=dev) for o in self.ops]
+        self.stderrs = [torch.empty(o.shape[0], dtype=torch.float64, device=dev) for o in self.ops]
+        self.phases = ([torch.empty((o.shape[0], z.shape[0]), dtype=torch.float32, device=dev)
+                        for o, z in zip(self.ops, self.samples)] if save_phases else None)
+        self.grads = [torch.empty(c.m, dtype=torch.float64, device=dev) for c in self.circuits]
+        self._grad_means = [None] * self.n
+        self._handle = ctypes.c_void_p()
+        flags = 0 if graph else L.IQP_BATCH_NO_GRAPH
+        L.check(L.lib().iqp_batch_plan_create(self.n, self._table(), self.p, flags,
+                                              ctypes.byref(self._handle)),
+                "iqp_batch_plan_create")
+        self.ws_bytes = int(L.lib().iqp_batch_workspace_bytes(self._handle))
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=dev)
+
+    def _table(self):
+        arr = (L.IqpProblem * self.n)()
+        for i, c in enumerate(self.circuits):
+            q = arr[i]
+            q.circuit = c.struct()
+            q.n_ops, q.ops = self.ops[i].shape[0], self.ops[i].data_ptr()
+            q.n_samples, q.samples = self.samples[i].shape[0], self.samples[i].data_ptr()
+            q.mean, q.stderr_ = self.means[i].data_ptr(), self.stderrs[i].data_ptr()
+            q.phase_save = self.phases[i].data_ptr() if self.phases is not None else None
+            u = self._grad_means[i]
+            q.grad_mean = u.data_ptr() if u is not None else None
+            q.grad_theta = self.grads[i].data_ptr()
+        return arr
+
+    def _set_grad_means(self, grad_means):
+        if self.phases is None:
+            raise ValueError("the backward pass needs a plan with save_phases=True")
+        if len(grad_means) != self.n:
+            raise ValueError("one grad_mean per problem")
+        self._grad_means = [_vec(u, "grad_mean", o.shape[0]) for u, o in zip(grad_means, self.ops)]
+
+    def expval(self):
+        """Forward pass: (means, stderrs), lists of [l] tensors."""
+        L.check(L.lib().iqp_batch_expval(self._handle, self._table(), _ptr(self.ws), self.ws_bytes,
+                                         _stream(self.ws)), "iqp_batch_expval")
+        return self.means, self.stderrs
+
+    def expval_grad(self, grad_means):
+        """Backward pass from dL/dmean per problem (after ``expval`` with the
+        same parameters): list of dL/dtheta [m] tensors."""
+        self._set_grad_means(grad_means)
+        L.check(L.lib().iqp_batch_expval_grad(self._handle, self._table(), _ptr(self.ws),
+                                              self.ws_bytes, _stream(self.ws)),
+                "iqp_batch_expval_grad")
+        return self.grads
+
+    def tune(self, grad_means=None) -> dict:
+        """Autotune the forward (and the backward when grad_means is given)
+        on these problems; synchronises. Returns the chosen configuration."""
+        passes = 1
+        if grad_means is not None:
+            self._set_grad_means(grad_means)
+            passes = 3
+        L.check(L.lib().iqp_batch_tune(self._handle, self._table(), passes, _ptr(self.ws),
+                                       self.ws_bytes, _stream(self.ws)), "iqp_batch_tune")
+        return self.config()
+
+    def config(self) -> dict:
+        c = (ctypes.c_int32 * 6)()
+        L.check(L.lib().iqp_batch_get_config(self._handle, c), "iqp_batch_get_config")
+        return {"fwd_tile": (c[0], c[1]), "fwd_split": c[2], "bwd_tile": (c[3], c[4]),
+                "tuned": bool(c[5])}
+
+    def set_config(self, fwd_tile=(4, 4), fwd_split=1, bwd_tile=(2, 2)) -> None:
+        c = (ctypes.c_int32 * 5)(fwd_tile[0], fwd_tile[1], fwd_split, bwd_tile[0], bwd_tile[1])
+        L.check(L.lib().iqp_batch_set_config(self._handle, c), "iqp_batch_set_config")
+
+    def close(self) -> None:
+        if self._handle:
+            torch.cuda.synchronize(self.device)
+            L.lib().iqp_batch_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # --- per-kernel timing (measurement only) ----------------------------------

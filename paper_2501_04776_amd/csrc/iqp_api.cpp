@@ -13,17 +13,20 @@
 
 #include "iqp.h"
 #include "iqp_internal.h"
+#include "iqp_plan.h"
 
 namespace iqp {
 
 static thread_local std::string g_last_error;
 
-static int fail(int status, const std::string &msg) {
+int fail(int status, const std::string &msg) {
     g_last_error = msg;
     return status;
 }
 
-static int hip_fail(hipError_t e, const char *where) {
+void clear_error() { g_last_error.clear(); }
+
+int hip_fail(hipError_t e, const char *where) {
     g_last_error = std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) +
                    ")";
     return IQP_ERR_HIP;
@@ -96,7 +99,7 @@ static const char *kFamilyNames[KF_COUNT] = {"parity", "theta_prep", "phase_fwd"
 
 // ---------------------------------------------------------------------------
 // device check: the kernels are built for gfx950 only
-static int check_device() {
+int check_device() {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -117,23 +120,7 @@ static int check_device() {
 
 // ---------------------------------------------------------------------------
 // workspace plan
-struct Plan {
-    int prec = 0;
-    int64_t n = 0, W = 0, m = 0, l = 0, s = 0, N = 0;
-    int64_t m_pad = 0, l_pad = 0, s_pad = 0, mw = 0, lw = 0, Nw = 0;
-    TileCfg tc;
-    int64_t nchunk = 0;
-    bool fwd = false, phi = false, bwd = false, mmd = false;
-    size_t o_thh = 0, o_thl = 0, o_t32 = 0, o_cbits = 0, o_bbits = 0, o_E = 0, o_part = 0;
-    size_t o_rowsum = 0, o_phi = 0, o_coef = 0, o_ctbits = 0, o_shi = 0, o_slo = 0, o_s32 = 0;
-    size_t o_gpart = 0, o_dbits = 0, o_pstat = 0;
-    size_t o_xz = 0, o_xa = 0, o_xd = 0;  // bit columns of samples, ops, data
-    size_t o_btbits = 0;                  // B^T: samples against generators, transposed
-    int64_t ldz = 0, lda = 0, ldd = 0;
-    size_t total = 0;
-};
-
-static int64_t choose_splits(int64_t tiles, int64_t mw) {
+int64_t choose_splits(int64_t tiles, int64_t mw) {
     int64_t best = 1;
     double best_eff = -1.0;
     for (int64_t sp = 1; sp <= 16; ++sp) {
@@ -176,9 +163,9 @@ static void apply_env_tiles(TileCfg &tc) {
     if (sp && atoi(sp) > 0) tc.splits = atoi(sp);
 }
 
-static void make_plan(Plan &P, int call, int64_t n, int64_t m, int64_t l, int64_t s, int64_t N,
-                      int prec) {
-    apply_env_tiles(P.tc);
+void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l, int64_t s,
+               int64_t N, int prec, const TileCfg &tc) {
+    P.tc = tc;
     P.prec = prec;
     P.n = n;
     P.W = ceil_div(n, 64);
@@ -196,18 +183,19 @@ static void make_plan(Plan &P, int call, int64_t n, int64_t m, int64_t l, int64_
     const int64_t tiles = (P.l_pad / (32 * P.tc.fm)) * (P.s_pad / (32 * P.tc.fn));
     if (P.tc.splits <= 0) P.tc.splits = choose_splits(tiles, P.mw);
     if (P.tc.splits > P.mw) P.tc.splits = P.mw;
-    P.fwd = call != IQP_CALL_EXPVAL_GRAD;
-    P.bwd = call == IQP_CALL_EXPVAL_GRAD || call == IQP_CALL_EXPVAL_GRAD_RECOMPUTE ||
-            call == IQP_CALL_MMD_GRAD;
-    P.phi = call == IQP_CALL_EXPVAL_GRAD_RECOMPUTE || call == IQP_CALL_MMD_GRAD;
-    P.mmd = call == IQP_CALL_MMD || call == IQP_CALL_MMD_GRAD;
+    P.fwd = parts.fwd;
+    P.bwd = parts.bwd;
+    P.phi = parts.phi;
+    P.mmd = parts.mmd;
     size_t cur = 0;
-    // bit columns (64 W qubits x ld words of 64 rows) for the bit-sliced parity
+    // bit columns (64 W qubits, plus one zero column, x ld words of 64 rows)
+    // for the bit-sliced parity
     P.ldz = round_up(P.s_pad / 64, 4);
     P.lda = round_up(P.l_pad / 64, 4);
     P.ldd = round_up(P.Nw, 4);
-    P.o_xz = carve(cur, (size_t)64 * P.W * P.ldz * 8);
-    P.o_xa = carve(cur, (size_t)64 * P.W * P.lda * 8);
+    P.o_xz = carve(cur, (size_t)(64 * P.W + 1) * P.ldz * 8);
+    P.o_xa = carve(cur, (size_t)(64 * P.W + 1) * P.lda * 8);
+    P.o_sup = carve(cur, (size_t)P.m_pad * kSupCap * 4);
     if (P.fwd) {
         P.o_bbits = carve(cur, (size_t)P.s_pad * P.mw * 8);
         if (prec == IQP_SPLIT_BF16) {
@@ -235,22 +223,30 @@ static void make_plan(Plan &P, int call, int64_t n, int64_t m, int64_t l, int64_
         P.o_gpart = carve(cur, (size_t)(P.l_pad / (32 * P.tc.bfm)) * P.m_pad * 4);
     }
     if (P.mmd) {
-        P.o_xd = carve(cur, (size_t)64 * P.W * P.ldd * 8);
+        P.o_xd = carve(cur, (size_t)(64 * P.W + 1) * P.ldd * 8);
+        P.o_dsup = carve(cur, (size_t)round_up(l, 64) * kSupCap * 4);
         P.o_dbits = carve(cur, (size_t)round_up(l, 64) * P.Nw * 8);
         P.o_pstat = carve(cur, (size_t)l * 2 * 8);
     }
     P.total = cur;
 }
 
-template <typename T>
-static T *at(void *ws, size_t off) {
-    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+// Plan of a single-problem call: its parts, the default tiles and any
+// override from the environment.
+static void make_call_plan(Plan &P, int call, int64_t n, int64_t m, int64_t l, int64_t s,
+                           int64_t N, int prec) {
+    PlanParts parts;
+    parts.fwd = call != IQP_CALL_EXPVAL_GRAD;
+    parts.bwd = call == IQP_CALL_EXPVAL_GRAD || call == IQP_CALL_EXPVAL_GRAD_RECOMPUTE ||
+                call == IQP_CALL_MMD_GRAD;
+    parts.phi = call == IQP_CALL_EXPVAL_GRAD_RECOMPUTE || call == IQP_CALL_MMD_GRAD;
+    parts.mmd = call == IQP_CALL_MMD || call == IQP_CALL_MMD_GRAD;
+    TileCfg tc;
+    apply_env_tiles(tc);
+    make_plan(P, parts, n, m, l, s, N, prec, tc);
 }
 
-// size limits that keep every grid dimension and index in range
-static const int64_t kMaxRows = (int64_t)1 << 24;
-
-static int check_circuit(const iqp_circuit *c) {
+int check_circuit(const iqp_circuit *c) {
     if (!c) return fail(IQP_ERR_INVALID_ARG, "circuit is NULL");
     if (c->n_qubits < 1) return fail(IQP_ERR_INVALID_ARG, "n_qubits must be >= 1");
     if (c->n_words != (int32_t)ceil_div(c->n_qubits, 64))
@@ -283,38 +279,20 @@ static int check_ws(const Plan &P, void *ws, size_t ws_bytes) {
     return IQP_OK;
 }
 
-#define IQP_TRY(call, where)                        \
-    do {                                            \
-        hipError_t e_ = (call);                     \
-        if (e_ != hipSuccess) return hip_fail(e_, where); \
-    } while (0)
 
 static int run_forward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
                        const uint64_t *samples, void *ws, const LaunchCtx &lc, float *phase_out,
                        double *mean, double *se, double *rowsum) {
-    const int W = (int)P.W;
-    IQP_TRY(launch_theta_prep(lc, c->theta, P.m, P.m_pad, P.prec, at<uint16_t>(ws, P.o_thh),
-                              at<uint16_t>(ws, P.o_thl), at<float>(ws, P.o_t32)),
-            "theta_prep");
-    IQP_TRY(launch_bitslice(lc, ops, P.l, W, P.lda, at<uint64_t>(ws, P.o_xa)), "bitslice(A)");
-    IQP_TRY(launch_parity_bs(lc, c->gens, P.m, W, at<uint64_t>(ws, P.o_xa), P.l_pad / 64, P.lda,
-                             P.l_pad, P.mw, IQP_BITS_TILED32, at<uint64_t>(ws, P.o_cbits)),
-            "parity(C)");
-    IQP_TRY(launch_bitslice(lc, samples, P.s, W, P.ldz, at<uint64_t>(ws, P.o_xz)),
-            "bitslice(Z)");
-    IQP_TRY(launch_parity_bs(lc, c->gens, P.m, W, at<uint64_t>(ws, P.o_xz), P.s_pad / 64, P.ldz,
-                             P.s_pad, P.mw, IQP_BITS_TILED32, at<uint64_t>(ws, P.o_bbits)),
-            "parity(B)");
-    IQP_TRY(launch_phase_fwd(lc, P.prec, P.tc.fm, P.tc.fn, at<uint64_t>(ws, P.o_cbits),
-                             at<uint64_t>(ws, P.o_bbits), at<uint16_t>(ws, P.o_thh),
-                             at<uint16_t>(ws, P.o_thl), at<float>(ws, P.o_t32), P.m_pad, P.l_pad,
-                             P.s_pad, P.tc.splits, at<float>(ws, P.o_E)),
+    IQP_TRY(launch_theta_prep(lc, theta_args(P, c->theta, ws)), "theta_prep");
+    IQP_TRY(launch_support(lc, support_args(P, c->gens, ws)), "support");
+    IQP_TRY(launch_bitslice(lc, bitslice_ops_args(P, ops, ws)), "bitslice(A)");
+    IQP_TRY(launch_parity_bs(lc, IQP_BITS_TILED32, parity_c_args(P, c->gens, ws)), "parity(C)");
+    IQP_TRY(launch_bitslice(lc, bitslice_samples_args(P, samples, ws)), "bitslice(Z)");
+    IQP_TRY(launch_parity_bs(lc, IQP_BITS_TILED32, parity_b_args(P, c->gens, ws)), "parity(B)");
+    IQP_TRY(launch_phase_fwd(lc, P.prec, P.tc.fm, P.tc.fn, fwd_args(P, ws, P.tc.splits)),
             "phase_fwd");
-    IQP_TRY(launch_epilogue(lc, at<float>(ws, P.o_E), P.tc.splits, P.l, P.s, P.l_pad, P.s_pad,
-                            phase_out, at<double>(ws, P.o_part)),
-            "phase_epilogue");
-    IQP_TRY(launch_finalize(lc, at<double>(ws, P.o_part), P.l, P.s, mean, se, rowsum),
-            "finalize");
+    IQP_TRY(launch_epilogue(lc, epi_args(P, ws, P.tc.splits, phase_out)), "phase_epilogue");
+    IQP_TRY(launch_finalize(lc, fin_args(P, ws, mean, se, rowsum)), "finalize");
     return IQP_OK;
 }
 
@@ -324,40 +302,29 @@ static int run_forward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
 static int run_backward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
                         const uint64_t *samples, const float *phase, bool bitcols_ready, void *ws,
                         const LaunchCtx &lc, double *grad_theta) {
-    const int W = (int)P.W;
-    IQP_TRY(launch_weights(lc, P.prec, phase, at<double>(ws, P.o_coef), P.l, P.s, P.l_pad,
-                           P.s_pad, at<uint16_t>(ws, P.o_shi), at<uint16_t>(ws, P.o_slo),
-                           at<float>(ws, P.o_s32)),
-            "weights");
+    IQP_TRY(launch_weights(lc, weights_args(P, phase, ws)), "weights");
     if (!bitcols_ready) {
-        IQP_TRY(launch_bitslice(lc, ops, P.l, W, P.lda, at<uint64_t>(ws, P.o_xa)),
-                "bitslice(A)");
-        IQP_TRY(launch_bitslice(lc, samples, P.s, W, P.ldz, at<uint64_t>(ws, P.o_xz)),
-                "bitslice(Z)");
+        IQP_TRY(launch_support(lc, support_args(P, c->gens, ws)), "support");
+        IQP_TRY(launch_bitslice(lc, bitslice_ops_args(P, ops, ws)), "bitslice(A)");
+        IQP_TRY(launch_bitslice(lc, bitslice_samples_args(P, samples, ws)), "bitslice(Z)");
     }
-    IQP_TRY(launch_parity_bs(lc, c->gens, P.m, W, at<uint64_t>(ws, P.o_xz), P.s_pad / 64, P.ldz,
-                             0, P.mw, IQP_BITS_TILED32_T, at<uint64_t>(ws, P.o_btbits)),
+    IQP_TRY(launch_parity_bs(lc, IQP_BITS_TILED32_T, parity_bt_args(P, c->gens, ws)),
             "parity(B^T)");
-    IQP_TRY(launch_parity_bs(lc, c->gens, P.m, W, at<uint64_t>(ws, P.o_xa), P.lw, P.lda, 0, P.mw,
-                             IQP_BITS_TILED32_T, at<uint64_t>(ws, P.o_ctbits)),
+    IQP_TRY(launch_parity_bs(lc, IQP_BITS_TILED32_T, parity_ct_args(P, c->gens, ws)),
             "parity(C^T)");
-    IQP_TRY(launch_phase_bwd(lc, P.prec, P.tc.bfm, P.tc.bfn, at<uint16_t>(ws, P.o_shi),
-                             at<uint16_t>(ws, P.o_slo), at<float>(ws, P.o_s32),
-                             at<uint64_t>(ws, P.o_btbits), at<uint64_t>(ws, P.o_ctbits), P.m_pad,
-                             P.l_pad, P.s_pad, at<float>(ws, P.o_gpart)),
-            "phase_bwd");
-    IQP_TRY(launch_grad_reduce(lc, at<float>(ws, P.o_gpart), P.l_pad / (32 * P.tc.bfm), P.m,
-                               P.m_pad, grad_theta),
-            "grad_reduce");
+    IQP_TRY(launch_phase_bwd(lc, P.prec, P.tc.bfm, P.tc.bfn, bwd_args(P, ws)), "phase_bwd");
+    IQP_TRY(launch_grad_reduce(lc, grad_args(P, ws, P.tc.bfm, grad_theta)), "grad_reduce");
     return IQP_OK;
 }
 
-static LaunchCtx make_ctx(void *stream) {
+LaunchCtx make_ctx(void *stream) {
     LaunchCtx lc;
     lc.stream = reinterpret_cast<hipStream_t>(stream);
     lc.timing = g_timing.on;
     return lc;
 }
+
+bool timing_enabled() { return g_timing.on; }
 
 }  // namespace iqp
 
@@ -372,7 +339,7 @@ size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s,
     if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16) return 0;
     if ((call == IQP_CALL_MMD || call == IQP_CALL_MMD_GRAD) && N < 1) return 0;
     Plan P;
-    make_plan(P, call, c->n_qubits, c->n_gates, l, s, N, precision);
+    make_call_plan(P, call, c->n_qubits, c->n_gates, l, s, N, precision);
     return P.total;
 }
 
@@ -380,10 +347,17 @@ static int64_t parity_rows_out(int64_t n_rows, int layout) {
     return layout == IQP_BITS_ROW_MAJOR ? n_rows : round_up(n_rows, 32);
 }
 
-size_t iqp_parity_workspace_bytes(int64_t n_rows, int32_t n_words, int layout) {
-    if (n_rows < 0 || n_words < 1) return 0;
+// iqp_parity workspace: bit columns of the rows, then the support lists of
+// the columns (n_cols rounded up to 64).
+static size_t parity_xt_bytes(int64_t n_rows, int32_t n_words, int layout) {
     const int64_t rw = ceil_div(parity_rows_out(n_rows, layout), 64);
-    return (size_t)64 * n_words * round_up(rw, 4) * 8 + 256;
+    return ((size_t)(64 * (int64_t)n_words + 1) * round_up(rw, 4) * 8 + 255) & ~(size_t)255;
+}
+
+size_t iqp_parity_workspace_bytes(int64_t n_rows, int64_t n_cols, int32_t n_words, int layout) {
+    if (n_rows < 0 || n_cols < 0 || n_words < 1) return 0;
+    return parity_xt_bytes(n_rows, n_words, layout) +
+           (size_t)round_up(n_cols, 64) * kSupCap * 4 + 256;
 }
 
 int iqp_parity(int64_t n_rows, const uint64_t *rows, int64_t n_cols, const uint64_t *cols,
@@ -397,7 +371,7 @@ int iqp_parity(int64_t n_rows, const uint64_t *rows, int64_t n_cols, const uint6
         return fail(IQP_ERR_INVALID_ARG, "unknown layout");
     if (n_rows == 0 || n_cols == 0) return IQP_OK;
     if (!rows || !cols || !out) return fail(IQP_ERR_INVALID_ARG, "NULL pointer");
-    const size_t need = iqp_parity_workspace_bytes(n_rows, n_words, layout);
+    const size_t need = iqp_parity_workspace_bytes(n_rows, n_cols, n_words, layout);
     if (ws_bytes < need)
         return fail(IQP_ERR_WORKSPACE, "workspace of " + std::to_string(ws_bytes) +
                                            " bytes, need " + std::to_string(need));
@@ -409,14 +383,19 @@ int iqp_parity(int64_t n_rows, const uint64_t *rows, int64_t n_cols, const uint6
     const int64_t rw = ceil_div(R_out, 64);
     const int64_t ldx = round_up(rw, 4);
     uint64_t *xt = static_cast<uint64_t *>(ws);
-    IQP_TRY(launch_bitslice(lc, rows, n_rows, n_words, ldx, xt), "bitslice");
+    int32_t *sup = at<int32_t>(ws, parity_xt_bytes(n_rows, n_words, layout));
+    const int64_t Gw = ceil_div(n_cols, 64);
+    IQP_TRY(launch_bitslice(lc, BitsliceArgs{rows, n_rows, n_words, ldx, xt}), "bitslice");
+    IQP_TRY(launch_support(lc, SupportArgs{cols, n_cols, n_words, Gw * 64, sup}), "support");
     if (layout == IQP_BITS_TILED32_T)
-        IQP_TRY(launch_parity_bs(lc, cols, n_cols, n_words, xt, ceil_div(n_rows, 64), ldx, 0,
-                                 ceil_div(n_cols, 64), layout, out),
+        IQP_TRY(launch_parity_bs(lc, layout,
+                                 ParityArgs{cols, sup, n_cols, n_words, xt, ceil_div(n_rows, 64),
+                                            ldx, 0, Gw, out}),
                 "parity");
     else
-        IQP_TRY(launch_parity_bs(lc, cols, n_cols, n_words, xt, rw, ldx, R_out,
-                                 ceil_div(n_cols, 64), layout, out),
+        IQP_TRY(launch_parity_bs(lc, layout,
+                                 ParityArgs{cols, sup, n_cols, n_words, xt, rw, ldx, R_out, Gw,
+                                            out}),
                 "parity");
     return IQP_OK;
 }
@@ -429,7 +408,7 @@ int iqp_expval(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
     if (st) return st;
     if (!mean) return fail(IQP_ERR_INVALID_ARG, "mean is NULL");
     Plan P;
-    make_plan(P, IQP_CALL_EXPVAL, c->n_qubits, c->n_gates, l, s, 0, precision);
+    make_call_plan(P, IQP_CALL_EXPVAL, c->n_qubits, c->n_gates, l, s, 0, precision);
     if ((st = check_ws(P, ws, ws_bytes))) return st;
     if ((st = check_device())) return st;
     return run_forward(P, c, ops, samples, ws, make_ctx(stream), phase_save, mean, stderr_,
@@ -447,7 +426,7 @@ int iqp_expval_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_
     if (!grad_theta) return fail(IQP_ERR_INVALID_ARG, "grad_theta is NULL");
     Plan P;
     const int call = phase_save ? IQP_CALL_EXPVAL_GRAD : IQP_CALL_EXPVAL_GRAD_RECOMPUTE;
-    make_plan(P, call, c->n_qubits, c->n_gates, l, s, 0, precision);
+    make_call_plan(P, call, c->n_qubits, c->n_gates, l, s, 0, precision);
     if ((st = check_ws(P, ws, ws_bytes))) return st;
     if ((st = check_device())) return st;
     LaunchCtx lc = make_ctx(stream);
@@ -458,7 +437,7 @@ int iqp_expval_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_
         if (st) return st;
         phase = at<float>(ws, P.o_phi);
     }
-    IQP_TRY(launch_coef_plain(lc, grad_mean, l, s, at<double>(ws, P.o_coef)), "coef");
+    IQP_TRY(launch_coef_plain(lc, coef_args(P, grad_mean, ws)), "coef");
     return run_backward(P, c, ops, samples, phase, phase_save == nullptr, ws, lc, grad_theta);
 }
 
@@ -476,7 +455,7 @@ int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
     if (unbiased && (N < 2 || s < 2))
         return fail(IQP_ERR_INVALID_ARG, "the unbiased estimator needs N >= 2 and s >= 2");
     Plan P;
-    make_plan(P, grad_theta ? IQP_CALL_MMD_GRAD : IQP_CALL_MMD, c->n_qubits, c->n_gates, l, s, N,
+    make_call_plan(P, grad_theta ? IQP_CALL_MMD_GRAD : IQP_CALL_MMD, c->n_qubits, c->n_gates, l, s, N,
               precision);
     if ((st = check_ws(P, ws, ws_bytes))) return st;
     if ((st = check_device())) return st;
@@ -484,10 +463,15 @@ int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
     float *phi = grad_theta ? at<float>(ws, P.o_phi) : nullptr;
     st = run_forward(P, c, ops, samples, ws, lc, phi, nullptr, nullptr, at<double>(ws, P.o_rowsum));
     if (st) return st;
-    IQP_TRY(launch_bitslice(lc, data, N, (int)P.W, P.ldd, at<uint64_t>(ws, P.o_xd)),
+    IQP_TRY(launch_bitslice(lc, BitsliceArgs{data, N, (int)P.W, P.ldd, at<uint64_t>(ws, P.o_xd)}),
             "bitslice(data)");
-    IQP_TRY(launch_parity_bs(lc, ops, l, (int)P.W, at<uint64_t>(ws, P.o_xd), P.Nw, P.ldd, 0,
-                             ceil_div(l, 64), IQP_BITS_TILED32_T, at<uint64_t>(ws, P.o_dbits)),
+    IQP_TRY(launch_support(lc, SupportArgs{ops, l, (int)P.W, round_up(l, 64),
+                                           at<int32_t>(ws, P.o_dsup)}),
+            "support(ops)");
+    IQP_TRY(launch_parity_bs(lc, IQP_BITS_TILED32_T,
+                             ParityArgs{ops, at<int32_t>(ws, P.o_dsup), l, (int)P.W,
+                                        at<uint64_t>(ws, P.o_xd), P.Nw, P.ldd, 0, ceil_div(l, 64),
+                                        at<uint64_t>(ws, P.o_dbits)}),
             "parity(data)");
     IQP_TRY(launch_data_stats(lc, at<uint64_t>(ws, P.o_dbits), l, P.Nw, N,
                               at<double>(ws, P.o_pstat)),

@@ -43,50 +43,169 @@ struct LaunchCtx {
 void timed_begin(const LaunchCtx &lc, int family, hipEvent_t *ev);
 void timed_end(const LaunchCtx &lc, int family, hipEvent_t ev);
 
-// ---- launchers (iqp_kernels.hip); each returns hipGetLastError() ----
-hipError_t launch_theta_prep(const LaunchCtx &lc, const double *theta, int64_t m, int64_t m_pad,
-                             int prec, uint16_t *hi, uint16_t *lo, float *t32);
+// Support-list capacity: the qubits of a generator of weight <= kSupCap are
+// listed; heavier generators are read from their bit rows.
+constexpr int kSupCap = 8;
 
-// Bit columns of `rows`: Xt[q * ldx + rw], q < 64 W, rw < ldx (>= ceil(R/64)).
-hipError_t launch_bitslice(const LaunchCtx &lc, const uint64_t *rows, int64_t R, int W,
-                           int64_t ldx, uint64_t *Xt);
+// ---- per-step arguments -----------------------------------------------------
+// Each step's kernel body takes one of these and a block (or work-unit)
+// index. A single-problem launch passes the struct as the kernel argument; a
+// batched launch reads one struct per problem from a device array and maps
+// its flat block index to (problem, local block) through a prefix sum of the
+// per-problem block counts.
 
-// Parity of each generator (m of them, W words each) against the rows behind
-// Xt (Rw words of 64 rows), in layout 0 (row-major), 1 (tiled32) or 2
-// (transposed tiled32); Gw = output words per row in layouts 0/1.
-hipError_t launch_parity_bs(const LaunchCtx &lc, const uint64_t *gens, int64_t m, int W,
-                            const uint64_t *Xt, int64_t Rw, int64_t ldx, int64_t R_out,
-                            int64_t Gw, int layout, uint64_t *out);
+struct ThetaArgs {
+    const double *theta;
+    int64_t m, m_pad;
+    int prec;
+    uint16_t *hi, *lo;
+    float *t32;
+};
+inline int64_t blocks_of(const ThetaArgs &a) { return ceil_div(a.m_pad, 256); }
 
-hipError_t launch_phase_fwd(const LaunchCtx &lc, int prec, int fm, int fn, const uint64_t *cbits,
-                            const uint64_t *bbits, const uint16_t *thh, const uint16_t *thl,
-                            const float *t32, int64_t m_pad, int64_t l_pad, int64_t s_pad,
-                            int64_t splits, float *E);
+// Bit columns of `rows`: Xt[q * ldx + rw], q < 64 W, rw < ldx (>= ceil(R/64)),
+// and a zero column q = 64 W (Xt holds 64 W + 1 columns).
+struct BitsliceArgs {
+    const uint64_t *rows;
+    int64_t R;
+    int W;
+    int64_t ldx;
+    uint64_t *Xt;
+};
+inline int64_t blocks_of(const BitsliceArgs &a) { return ceil_div(a.ldx * a.W, 4); }
 
-hipError_t launch_epilogue(const LaunchCtx &lc, const float *E, int64_t splits, int64_t l,
-                           int64_t s, int64_t l_pad, int64_t s_pad, float *phase_out,
-                           double *part);
+// Support lists of `rows` generators (m real ones, W words each; rows >= m
+// are written as weight 0): sup[j * kSupCap + k] = qubit of the k-th set bit
+// of generator j, -1 past its weight, and sup[j * kSupCap] = -2 for a
+// generator heavier than kSupCap.
+struct SupportArgs {
+    const uint64_t *gens;
+    int64_t m;
+    int W;
+    int64_t rows;
+    int32_t *sup;
+};
+inline int64_t blocks_of(const SupportArgs &a) { return ceil_div(a.rows, 256); }
 
-hipError_t launch_finalize(const LaunchCtx &lc, const double *part, int64_t l, int64_t s,
-                           double *mean, double *stderr_, double *rowsum);
+// Parity of each generator (m of them, W words each, support lists `sup`
+// covering 64 Gw rows) against the rows behind Xt (Rw words of 64 rows), in
+// layout 0 (row-major), 1 (tiled32) or 2 (transposed tiled32); Gw = output
+// words per row in layouts 0/1, generator words in layout 2. One wave per 64
+// generators x 64 row words.
+struct ParityArgs {
+    const uint64_t *gens;
+    const int32_t *sup;
+    int64_t m;
+    int W;
+    const uint64_t *Xt;
+    int64_t Rw, ldx, R_out, Gw;
+    uint64_t *out;
+};
+inline int64_t blocks_of(const ParityArgs &a) { return ceil_div(a.Gw * ceil_div(a.Rw, 64), 4); }
 
-hipError_t launch_coef_plain(const LaunchCtx &lc, const double *grad_mean, int64_t l, int64_t s,
-                             double *coef);
+// E = C Theta B^T, tiled over observables x samples, gate words split
+// `splits` ways (partials E[split][l_pad][s_pad]).
+struct FwdArgs {
+    const uint64_t *cbits, *bbits;
+    const uint16_t *thh, *thl;
+    const float *t32;
+    int64_t m_pad, l_pad, s_pad, splits;
+    float *E;
+};
+inline int64_t fwd_units(const FwdArgs &a, int fm, int fn) {
+    return (a.l_pad / (32 * fm)) * ceil_div(a.s_pad / (32 * fn), 4) * a.splits;
+}
 
-hipError_t launch_weights(const LaunchCtx &lc, int prec, const float *phase, const double *coef,
-                          int64_t l, int64_t s, int64_t l_pad, int64_t s_pad, uint16_t *shi,
-                          uint16_t *slo, float *s32);
+struct EpiArgs {
+    const float *E;
+    int64_t splits, l, s, l_pad, s_pad;
+    float *phase_out;
+    double *part;
+};
+inline int64_t blocks_of(const EpiArgs &a) { return a.l * ceil_div(a.s, kEpiChunk); }
+
+struct FinArgs {
+    const double *part;
+    int64_t l, s;
+    double *mean, *stderr_, *rowsum;
+};
+inline int64_t blocks_of(const FinArgs &a) { return ceil_div(a.l, 256); }
+
+struct CoefArgs {
+    const double *grad_mean;
+    int64_t l, s;
+    double *coef;
+};
+inline int64_t blocks_of(const CoefArgs &a) { return ceil_div(a.l, 256); }
+
+struct WeightsArgs {
+    const float *phase;
+    const double *coef;
+    int64_t l, s, l_pad, s_pad;
+    int prec;
+    uint16_t *shi, *slo;
+    float *s32;
+};
+inline int64_t blocks_of(const WeightsArgs &a) { return (a.s_pad / 64) * (a.l_pad / 64); }
 
 // T = S B (observables x gates, K = samples) and the gradient partials
 // gpart[l_pad / (32 fm)][m_pad]; btbits / ctbits are the transposed tiled32
 // parities of the samples / observables against the generators.
-hipError_t launch_phase_bwd(const LaunchCtx &lc, int prec, int fm, int fn, const uint16_t *shi,
-                            const uint16_t *slo, const float *s32, const uint64_t *btbits,
-                            const uint64_t *ctbits, int64_t m_pad, int64_t l_pad, int64_t s_pad,
-                            float *gpart);
+struct BwdArgs {
+    const uint16_t *shi, *slo;
+    const float *s32;
+    const uint64_t *btbits, *ctbits;
+    int64_t m_pad, l_pad, s_pad;
+    float *gpart;
+};
+inline int64_t bwd_units(const BwdArgs &a, int fm, int fn) {
+    return ceil_div(a.m_pad / (32 * fn), 4) * (a.l_pad / (32 * fm));
+}
 
-hipError_t launch_grad_reduce(const LaunchCtx &lc, const float *gpart, int64_t n_parts,
-                              int64_t m, int64_t m_pad, double *grad);
+struct GradArgs {
+    const float *gpart;
+    int64_t n_parts, m, m_pad;
+    double *grad;
+};
+inline int64_t blocks_of(const GradArgs &a) { return ceil_div(a.m, 256); }
+
+// ---- launchers (iqp_kernels.hip); each returns hipGetLastError() ----
+hipError_t launch_theta_prep(const LaunchCtx &lc, const ThetaArgs &a);
+hipError_t launch_bitslice(const LaunchCtx &lc, const BitsliceArgs &a);
+hipError_t launch_support(const LaunchCtx &lc, const SupportArgs &a);
+hipError_t launch_parity_bs(const LaunchCtx &lc, int layout, const ParityArgs &a);
+hipError_t launch_phase_fwd(const LaunchCtx &lc, int prec, int fm, int fn, const FwdArgs &a);
+hipError_t launch_epilogue(const LaunchCtx &lc, const EpiArgs &a);
+hipError_t launch_finalize(const LaunchCtx &lc, const FinArgs &a);
+hipError_t launch_coef_plain(const LaunchCtx &lc, const CoefArgs &a);
+hipError_t launch_weights(const LaunchCtx &lc, const WeightsArgs &a);
+hipError_t launch_phase_bwd(const LaunchCtx &lc, int prec, int fm, int fn, const BwdArgs &a);
+hipError_t launch_grad_reduce(const LaunchCtx &lc, const GradArgs &a);
+
+// Batched launches: `args` is a device array of np argument structs of the
+// step's type and `off` a device array of np + 1 prefix sums of their block
+// counts (off[0] = 0, off[np] = total > 0).
+enum StepKind {
+    SK_THETA = 0, SK_BITSLICE, SK_PARITY0, SK_PARITY1, SK_PARITY2, SK_EPI, SK_FIN, SK_COEF,
+    SK_WEIGHTS, SK_GRAD, SK_SUPPORT, SK_COUNT
+};
+hipError_t launch_batched(const LaunchCtx &lc, int kind, const void *args, const int64_t *off,
+                          int np, int64_t total);
+
+// Persistent contractions over a work queue: `grid` workgroups take work
+// units 0 .. off[np]-1 in order from `counter` (which must read 0 at launch);
+// unit u belongs to problem p with off[p] <= u < off[p+1] and is that
+// problem's local unit u - off[p].
+hipError_t launch_phase_fwd_persistent(const LaunchCtx &lc, int prec, int fm, int fn,
+                                       const FwdArgs *args, const int64_t *off, int np,
+                                       unsigned long long *counter, int grid);
+hipError_t launch_phase_bwd_persistent(const LaunchCtx &lc, int prec, int fm, int fn,
+                                       const BwdArgs *args, const int64_t *off, int np,
+                                       unsigned long long *counter, int grid);
+// Workgroups of the persistent contraction that fit on the device at once.
+int persistent_grid(bool fwd, int prec, int fm, int fn);
+// Zero n work-queue counters (a kernel, so it can be captured in a graph).
+hipError_t launch_reset_counters(const LaunchCtx &lc, unsigned long long *c, int n);
 
 hipError_t launch_data_stats(const LaunchCtx &lc, const uint64_t *dbits, int64_t l, int64_t Nw,
                              int64_t N, double *pstat);

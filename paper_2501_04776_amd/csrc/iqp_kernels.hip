@@ -12,9 +12,14 @@
 //   finalize        mean and standard error per observable, fixed order
 //   weights         S_ki = (alpha_k + beta_k cos E_ki) sin E_ki, written in
 //                   the register image of the backward matrix-core operand
-//   phase_bwd       D[j][i] = sum_k c_kj S_ki on the matrix cores, epilogue
-//                   sum_i (-1)^{b_ij} D[j][i] per gate
-//   grad_reduce     dtheta_j = -2 sum over sample tiles, fixed order
+//   phase_bwd       T[k][j] = sum_i S_ki (-1)^{b_ij} on the matrix cores
+//                   (K = samples), epilogue sum_k c_kj T[k][j] per gate
+//   grad_reduce     dtheta_j = -2 sum over observable tiles, fixed order
+//
+// Every step is a body function over one problem and one block (or work
+// unit). A plain launch runs one problem; a batched launch runs many problems
+// of uneven size in one grid, and the two contractions also come as
+// persistent kernels that take work units from a queue.
 //   data_stats, mmd_loss, coef_*: the MMD^2 chain (eq. mmd_estimate)
 //
 // No float atomics anywhere: every reduction runs in a fixed order, so a call
@@ -30,6 +35,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 // 2 pi split for a two-step Cody-Waite reduction (Cody & Waite, 1980):
 // hi is the double nearest 2 pi, lo the double nearest 2 pi - hi.
@@ -60,38 +67,115 @@ __device__ __forceinline__ uint16_t f2bf_rne(float f) {
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// ---------------------------------------------------------------------------
-// theta_prep
-__global__ __launch_bounds__(256) void theta_prep_kernel(const double *__restrict__ theta,
-                                                         int64_t m, int64_t m_pad, int prec,
-                                                         uint16_t *__restrict__ hi,
-                                                         uint16_t *__restrict__ lo,
-                                                         float *__restrict__ t32) {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= m_pad) return;
-    double t = i < m ? theta[i] : 0.0;
-    double tr = t - IQP_PI * rint(t * IQP_INV_PI);
-    double two = 2.0 * tr;
-    if (prec == 1) {
-        uint16_t h = f2bf_rne((float)two);
-        double rem = two - (double)bf2f(h);
-        hi[i] = h;
-        lo[i] = f2bf_rne((float)rem);
-    } else {
-        // split by gate parity: lane half h of the 32x32x2 product reads gate 2t + h
-        t32[(i & 1) * (m_pad >> 1) + (i >> 1)] = (float)two;
+// A pointer read from an argument struct in memory is generic (flat) to the
+// compiler. The kernels hold such pointers in the global address space
+// (`glb<T>`), so every access through them is a global memory instruction,
+// which, unlike a flat one, never waits on LDS or scalar-memory counters.
+#define IQP_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+using glb = T IQP_GLOBAL *;
+template <typename T>
+__device__ __forceinline__ glb<T> gptr(T *p) {
+    return (glb<T>)p;
+}
+
+// A value that is the same in every lane, moved to a scalar register.
+__device__ __forceinline__ int64_t uniform64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Problem p of a batch owns blocks off[p] .. off[p+1]-1 (off[0] = 0, b <
+// off[np]); empty problems have off[p] = off[p+1] and are skipped.
+__device__ __forceinline__ int find_slot(const int64_t *__restrict__ off, int np, int64_t b) {
+    int lo = 0, hi = np;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename A, void (*F)(const A &, int64_t)>
+__global__ __launch_bounds__(256) void plain_kernel(A a) {
+    F(a, (int64_t)blockIdx.x);
+}
+
+template <typename A, void (*F)(const A &, int64_t)>
+__global__ __launch_bounds__(256) void batched_kernel(const A *__restrict__ args,
+                                                      const int64_t *__restrict__ off, int np) {
+    const int64_t b = (int64_t)blockIdx.x;
+    const int p = find_slot(off, np, b);
+    const A a = args[p];
+    F(a, b - off[p]);
+}
+
+// 256-thread blocks: a grid stays below 2^32 work-items.
+constexpr int64_t kMaxBlocks = ((int64_t)1 << 24) - 1;
+
+template <typename A, void (*F)(const A &, int64_t)>
+static hipError_t plain_launch(const LaunchCtx &lc, int family, const A &a, int64_t blocks) {
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
+    hipEvent_t ev;
+    timed_begin(lc, family, &ev);
+    hipLaunchKernelGGL((plain_kernel<A, F>), dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
+    hipError_t e = hipGetLastError();
+    timed_end(lc, family, ev);
+    return e;
+}
+
+// threadIdx.x, hidden from loop-invariant code motion: a persistent kernel
+// then recomputes lane-derived values per work unit instead of keeping them
+// live across units (the contraction bodies need every register).
+__device__ __forceinline__ int opaque_tid() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// Work-queue loop of the persistent kernels: the workgroup takes the next
+// unit from `counter` until the units run out. Every workgroup reaches the
+// exit, whatever the order in which units are taken.
+template <typename Body>
+__device__ __forceinline__ void persistent_loop(const int64_t *__restrict__ off, int np,
+                                                unsigned long long *counter, Body body) {
+    __shared__ unsigned long long slot;
+    const int64_t total = off[np];
+    for (;;) {
+        if (threadIdx.x == 0) slot = atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t u = uniform64(slot);
+        __syncthreads();
+        if (u >= total) break;
+        const int p = find_slot(off, np, u);
+        body(p, u - off[p]);
     }
 }
 
-hipError_t launch_theta_prep(const LaunchCtx &lc, const double *theta, int64_t m, int64_t m_pad,
-                             int prec, uint16_t *hi, uint16_t *lo, float *t32) {
-    hipEvent_t ev;
-    timed_begin(lc, KF_THETA, &ev);
-    hipLaunchKernelGGL(theta_prep_kernel, dim3((unsigned)ceil_div(m_pad, 256)), dim3(256), 0,
-                       lc.stream, theta, m, m_pad, prec, hi, lo, t32);
-    hipError_t e = hipGetLastError();
-    timed_end(lc, KF_THETA, ev);
-    return e;
+// ---------------------------------------------------------------------------
+// theta_prep
+__device__ __forceinline__ void theta_prep_body(const ThetaArgs &a, int64_t blk) {
+    const int64_t i = blk * 256 + threadIdx.x;
+    if (i >= a.m_pad) return;
+    const double t = i < a.m ? gptr(a.theta)[i] : 0.0;
+    const double tr = t - IQP_PI * rint(t * IQP_INV_PI);
+    const double two = 2.0 * tr;
+    if (a.prec == 1) {
+        const uint16_t h = f2bf_rne((float)two);
+        const double rem = two - (double)bf2f(h);
+        gptr(a.hi)[i] = h;
+        gptr(a.lo)[i] = f2bf_rne((float)rem);
+    } else {
+        // split by gate parity: lane half h of the 32x32x2 product reads gate 2t + h
+        gptr(a.t32)[(i & 1) * (a.m_pad >> 1) + (i >> 1)] = (float)two;
+    }
+}
+
+hipError_t launch_theta_prep(const LaunchCtx &lc, const ThetaArgs &a) {
+    return plain_launch<ThetaArgs, theta_prep_body>(lc, KF_THETA, a, blocks_of(a));
 }
 
 // ---------------------------------------------------------------------------
@@ -125,109 +209,184 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x, int lane) {
 }
 
 // Xt[q * ldx + rw]: bit r = qubit q of row 64 rw + r (rows >= R read as 0),
-// for q < 64 W and rw < ldx.
-__global__ __launch_bounds__(256) void bitslice_kernel(const uint64_t *__restrict__ rows,
-                                                       int64_t R, int W, int64_t ldx,
-                                                       uint64_t *__restrict__ Xt) {
+// for q < 64 W and rw < ldx; row q = 64 W is all zero (the parity kernel
+// reads it for absent support entries).
+__device__ __forceinline__ void bitslice_body(const BitsliceArgs &a, int64_t blk) {
     const int lane = threadIdx.x & 63;
-    const int64_t unit = (int64_t)blockIdx.x * 4 + wave_id();
-    if (unit >= ldx * W) return;
-    const int64_t w = unit / ldx, rw = unit - w * ldx;
+    const int64_t unit = blk * 4 + wave_id();
+    if (unit >= a.ldx * a.W) return;
+    const int64_t w = unit / a.ldx, rw = unit - w * a.ldx;
     const int64_t r = rw * 64 + lane;
-    const uint64_t x = r < R ? rows[r * W + w] : 0ull;
-    Xt[(w * 64 + lane) * ldx + rw] = transpose64(x, lane);
+    const uint64_t x = r < a.R ? gptr(a.rows)[r * a.W + w] : 0ull;
+    gptr(a.Xt)[(w * 64 + lane) * a.ldx + rw] = transpose64(x, lane);
+    if (unit == 0)
+        for (int64_t c = lane; c < a.ldx; c += 64) gptr(a.Xt)[(int64_t)64 * a.W * a.ldx + c] = 0ull;
 }
 
-// One wave: 64 generators (lane j) x kRowWords words of 64 rows.
+// Support lists, one lane per generator: the bit row is read once here, so
+// the parity kernel touches only the listed qubits.
+__device__ __forceinline__ void support_body(const SupportArgs &a, int64_t blk) {
+    const int64_t j = blk * 256 + threadIdx.x;
+    if (j >= a.rows) return;
+    int32_t s[kSupCap];
+#pragma unroll
+    for (int k = 0; k < kSupCap; ++k) s[k] = -1;
+    int cnt = 0;
+    if (j < a.m) {
+        for (int w = 0; w < a.W; ++w) {
+            uint64_t x = gptr(a.gens)[j * a.W + w];
+            while (x) {
+                const int32_t q = w * 64 + __builtin_ctzll(x);
+                x &= x - 1;
+#pragma unroll
+                for (int k = 0; k < kSupCap; ++k) s[k] = (cnt == k) ? q : s[k];
+                ++cnt;
+            }
+        }
+    }
+    if (cnt > kSupCap) {
+#pragma unroll
+        for (int k = 0; k < kSupCap; ++k) s[k] = -1;
+        s[0] = -2;
+    }
+    i32x4 IQP_GLOBAL *dst = reinterpret_cast<i32x4 IQP_GLOBAL *>(gptr(a.sup) + j * kSupCap);
+    dst[0] = (i32x4){s[0], s[1], s[2], s[3]};
+    dst[1] = (i32x4){s[4], s[5], s[6], s[7]};
+}
+
+// 64x64 bit transpose inside one lane: x[g] bit r -> x[r] bit g. At block
+// size k, rows i and i + k (i & k == 0) swap the off-diagonal k x k blocks of
+// their 2k x 2k block (mask m keeps the columns with bit k clear).
+__device__ __forceinline__ void transpose64_regs(uint64_t (&x)[64]) {
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int k = 32 >> st;
+        const uint64_t m = st == 0 ? 0x00000000FFFFFFFFull
+                         : st == 1 ? 0x0000FFFF0000FFFFull
+                         : st == 2 ? 0x00FF00FF00FF00FFull
+                         : st == 3 ? 0x0F0F0F0F0F0F0F0Full
+                         : st == 4 ? 0x3333333333333333ull
+                                   : 0x5555555555555555ull;
+#pragma unroll
+        for (int i = 0; i < 64; ++i) {
+            if (i & k) continue;
+            const uint64_t t = ((x[i] >> k) ^ x[i + k]) & m;
+            x[i + k] ^= t;
+            x[i] ^= t << k;
+        }
+    }
+}
+
+// One wave: 64 generators x 64 row words (lane rw). For generator j the
+// parities against 64 rows are the XOR of the bit-column words
+// Xt[q * ldx + rw] over q in supp(j): one coalesced 512-byte load per support
+// qubit. The wave reads its 64 support lists once (lane g holds generator
+// g's), and runs k-outer over the block's largest weight: entry k of every
+// generator is moved to a scalar register and its 64 loads are independent,
+// with absent entries reading the zero column. Generators heavier than the
+// list walk their bit row afterwards.
 //   LAYOUT 0: row-major    out[r * Gw + j/64], bit j%64
 //   LAYOUT 1: tiled32      out[((r/32) * Gw + j/64) * 32 + r%32], bit j%64
 //   LAYOUT 2: transposed tiled32 (rows = generators)
 //             out[((j/32) * Rw + r/64) * 32 + j%32], bit r%64
-// Layouts 0 and 1 transpose each 64x64 block in registers; layout 2 stores
-// the XOR words as they are. Generators j >= m, and rows beyond the bit
-// columns, give zero bits.
-constexpr int kRowWords = 4;
-
+// Layouts 0 and 1 transpose the lane's 64 x 64 block in registers; layout 2
+// stores the XOR words as they are. Generators j >= m give zero bits.
 template <int LAYOUT>
-__global__ __launch_bounds__(256) void parity_bs_kernel(const uint64_t *__restrict__ gens,
-                                                        int64_t m, int W,
-                                                        const uint64_t *__restrict__ Xt,
-                                                        int64_t Rw, int64_t ldx, int64_t R_out,
-                                                        int64_t Gw, uint64_t *__restrict__ out) {
+__device__ __forceinline__ void parity_bs_body(const ParityArgs &a, int64_t blk) {
+    const uint64_t IQP_GLOBAL *__restrict__ Xt = gptr(a.Xt);
+    uint64_t IQP_GLOBAL *__restrict__ out = gptr(a.out);
+    const int64_t Rw = a.Rw, ldx = a.ldx, R_out = a.R_out, Gw = a.Gw;
     const int lane = threadIdx.x & 63;
-    const int64_t n_rg = ceil_div(Rw, kRowWords);
-    const int64_t unit = (int64_t)blockIdx.x * 4 + wave_id();
-    if (unit >= Gw * n_rg) return;
-    const int64_t rg = unit / Gw, gb = unit - rg * Gw;
-    const int64_t j = gb * 64 + lane;
-    const int64_t rw0 = rg * kRowWords;
-    uint64_t acc[kRowWords];
+    const int64_t unit = blk * 4 + wave_id();
+    if (unit >= Gw * ceil_div(Rw, 64)) return;  // uniform over the wave
+    const int64_t rc = unit / Gw, gb = unit - rc * Gw;
+    const int64_t rw = rc * 64 + lane;
+    const bool live = rw < Rw;
+    const uint64_t IQP_GLOBAL *__restrict__ xcol = Xt + (live ? rw : 0);
+    const int32_t zrow = 64 * a.W;
+
+    const i32x4 IQP_GLOBAL *sp =
+        reinterpret_cast<const i32x4 IQP_GLOBAL *>(gptr(a.sup) + (gb * 64 + lane) * kSupCap);
+    const i32x4 s0 = sp[0], s1 = sp[1];
+    const int32_t sv[kSupCap] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+    const uint64_t heavy = __ballot(sv[0] == -2);
+    int32_t qv[kSupCap];
+    int kmax = 0;
 #pragma unroll
-    for (int t = 0; t < kRowWords; ++t) acc[t] = 0;
-    if (j < m) {
-        for (int w = 0; w < W; ++w) {
-            uint64_t x = gens[j * W + w];
-            while (x) {
-                const int64_t q = (int64_t)w * 64 + __builtin_ctzll(x);
-                x &= x - 1;
-                const uint64_t *xp = Xt + q * ldx + rw0;
+    for (int k = 0; k < kSupCap; ++k) {
+        qv[k] = sv[k] >= 0 ? sv[k] : zrow;
+        kmax += __ballot(sv[k] >= 0) != 0ull;  // lists fill from entry 0
+    }
+    uint64_t x[64];
 #pragma unroll
-                for (int t = 0; t < kRowWords; ++t) acc[t] ^= xp[t];
+    for (int g = 0; g < 64; ++g) x[g] = 0ull;
+#pragma unroll
+    for (int k = 0; k < kSupCap; ++k) {
+        if (k >= kmax) break;
+#pragma unroll
+        for (int g = 0; g < 64; ++g) {
+            const int32_t q = __builtin_amdgcn_readlane(qv[k], g);
+            x[g] ^= xcol[(int64_t)q * ldx];
+        }
+    }
+    if (heavy) {
+#pragma unroll
+        for (int g = 0; g < 64; ++g) {
+            if (!((heavy >> g) & 1ull)) continue;
+            const uint64_t IQP_GLOBAL *row = gptr(a.gens) + (gb * 64 + g) * a.W;
+            for (int w = 0; w < a.W; ++w) {
+                uint64_t bits = row[w];
+                while (bits) {
+                    const int64_t q = (int64_t)w * 64 + __builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    x[g] ^= xcol[q * ldx];
+                }
             }
         }
     }
+    if (!live) return;
+    if (LAYOUT == 2) {
 #pragma unroll
-    for (int t = 0; t < kRowWords; ++t) {
-        const int64_t rw = rw0 + t;
-        if (rw >= Rw) break;
-        if (LAYOUT == 2) {
-            out[((j >> 5) * Rw + rw) * 32 + (j & 31)] = acc[t];
-        } else {
-            const uint64_t y = transpose64(acc[t], lane);
-            const int64_t r = rw * 64 + lane;
-            if (r < R_out) {
-                if (LAYOUT == 1)
-                    out[((r >> 5) * Gw + gb) * 32 + (r & 31)] = y;
-                else
-                    out[r * Gw + gb] = y;
+        for (int hh = 0; hh < 2; ++hh) {
+            uint64_t IQP_GLOBAL *dst = out + ((gb * 2 + hh) * Rw + rw) * 32;
+#pragma unroll
+            for (int g = 0; g < 32; g += 2)
+                *reinterpret_cast<u64x2 IQP_GLOBAL *>(dst + g) = (u64x2){x[32 * hh + g], x[32 * hh + g + 1]};
+        }
+    } else {
+        transpose64_regs(x);
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            const int64_t r0 = rw * 64 + 32 * hh;
+            if (r0 >= R_out) break;  // R_out is a multiple of 32 in layout 1
+            if (LAYOUT == 1) {
+                uint64_t IQP_GLOBAL *dst = out + ((r0 >> 5) * Gw + gb) * 32;
+#pragma unroll
+                for (int b = 0; b < 32; b += 2)
+                    *reinterpret_cast<u64x2 IQP_GLOBAL *>(dst + b) = (u64x2){x[32 * hh + b], x[32 * hh + b + 1]};
+            } else {
+#pragma unroll
+                for (int b = 0; b < 32; ++b)
+                    if (r0 + b < R_out) out[(r0 + b) * Gw + gb] = x[32 * hh + b];
             }
         }
     }
 }
 
-hipError_t launch_bitslice(const LaunchCtx &lc, const uint64_t *rows, int64_t R, int W,
-                           int64_t ldx, uint64_t *Xt) {
-    const int64_t units = ldx * W;
-    if (units == 0) return hipSuccess;
-    hipEvent_t ev;
-    timed_begin(lc, KF_PARITY, &ev);
-    hipLaunchKernelGGL(bitslice_kernel, dim3((unsigned)ceil_div(units, 4)), dim3(256), 0,
-                       lc.stream, rows, R, W, ldx, Xt);
-    hipError_t e = hipGetLastError();
-    timed_end(lc, KF_PARITY, ev);
-    return e;
+hipError_t launch_bitslice(const LaunchCtx &lc, const BitsliceArgs &a) {
+    return plain_launch<BitsliceArgs, bitslice_body>(lc, KF_PARITY, a, blocks_of(a));
 }
 
-hipError_t launch_parity_bs(const LaunchCtx &lc, const uint64_t *gens, int64_t m, int W,
-                            const uint64_t *Xt, int64_t Rw, int64_t ldx, int64_t R_out,
-                            int64_t Gw, int layout, uint64_t *out) {
-    const int64_t units = Gw * ceil_div(Rw, kRowWords);
-    if (units == 0) return hipSuccess;
-    hipEvent_t ev;
-    timed_begin(lc, KF_PARITY, &ev);
-    dim3 grid((unsigned)ceil_div(units, 4));
-    if (layout == 0)
-        hipLaunchKernelGGL(parity_bs_kernel<0>, grid, dim3(256), 0, lc.stream, gens, m, W, Xt, Rw,
-                           ldx, R_out, Gw, out);
-    else if (layout == 1)
-        hipLaunchKernelGGL(parity_bs_kernel<1>, grid, dim3(256), 0, lc.stream, gens, m, W, Xt, Rw,
-                           ldx, R_out, Gw, out);
-    else
-        hipLaunchKernelGGL(parity_bs_kernel<2>, grid, dim3(256), 0, lc.stream, gens, m, W, Xt, Rw,
-                           ldx, R_out, Gw, out);
-    hipError_t e = hipGetLastError();
-    timed_end(lc, KF_PARITY, ev);
-    return e;
+hipError_t launch_support(const LaunchCtx &lc, const SupportArgs &a) {
+    return plain_launch<SupportArgs, support_body>(lc, KF_PARITY, a, blocks_of(a));
+}
+
+hipError_t launch_parity_bs(const LaunchCtx &lc, int layout, const ParityArgs &a) {
+    const int64_t nb = blocks_of(a);
+    if (layout == 0) return plain_launch<ParityArgs, parity_bs_body<0>>(lc, KF_PARITY, a, nb);
+    if (layout == 1) return plain_launch<ParityArgs, parity_bs_body<1>>(lc, KF_PARITY, a, nb);
+    if (layout == 2) return plain_launch<ParityArgs, parity_bs_body<2>>(lc, KF_PARITY, a, nb);
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
@@ -286,7 +445,7 @@ __device__ __forceinline__ bf16x8 expand_01(uint32_t x16) {
 // Direct global -> LDS copy of 16 bytes per lane: lane l's bytes land at
 // lds_block + 16 l. Completion is tracked by the vector-memory counter.
 typedef __attribute__((address_space(3))) void lds_void;
-__device__ __forceinline__ void dma16(const void *gsrc, void *lds_block) {
+__device__ __forceinline__ void dma16(const void IQP_GLOBAL *gsrc, void *lds_block) {
     __builtin_amdgcn_global_load_lds(gsrc, (lds_void *)lds_block, 16, 0, 0);
 }
 
@@ -425,7 +584,7 @@ __device__ __forceinline__ bool fwd_unit(FwdUnit &U, int64_t gu, int64_t n_ob, i
 }
 
 template <int FM, int FN>
-__device__ __forceinline__ void store_tile(const f32x16 (&acc)[FM][FN], float *Ep, int64_t ob,
+__device__ __forceinline__ void store_tile(const f32x16 (&acc)[FM][FN], float IQP_GLOBAL *Ep, int64_t ob,
                                            int64_t sb, int64_t s_pad, int h, int r) {
 #pragma unroll
     for (int f = 0; f < FM; ++f)
@@ -441,22 +600,24 @@ __device__ __forceinline__ void store_tile(const f32x16 (&acc)[FM][FN], float *E
 }
 
 template <int FM, int FN>
-__global__ __launch_bounds__(256, 1) void phase_fwd_bf16_kernel(
-    const uint64_t *__restrict__ cbits, const uint64_t *__restrict__ bbits,
-    const u32x4 *__restrict__ thh, const u32x4 *__restrict__ thl, int64_t mw, int64_t n_ob,
-    int64_t n_sb, int64_t wg_units, int64_t wps, float *__restrict__ E, int64_t l_pad,
-    int64_t s_pad) {
+__device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int tid) {
     // per word 8 units of 16 bytes: K-step t, half h at 2t + h
     __shared__ u32x4 lth[2][kChunkWords * 8], ltl[2][kChunkWords * 8];
-    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
-    if (gu >= wg_units) return;  // uniform over the workgroup
+    const uint64_t IQP_GLOBAL *__restrict__ cbits = gptr(a.cbits);
+    const uint64_t IQP_GLOBAL *__restrict__ bbits = gptr(a.bbits);
+    const u32x4 IQP_GLOBAL *__restrict__ thh = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.thh));
+    const u32x4 IQP_GLOBAL *__restrict__ thl = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.thl));
+    float IQP_GLOBAL *__restrict__ E = gptr(a.E);
+    const int64_t l_pad = a.l_pad, s_pad = a.s_pad, mw = a.m_pad / 64;
+    const int64_t n_ob = l_pad / (32 * FM), n_sb = s_pad / (32 * FN);
+    const int64_t wps = ceil_div(mw, a.splits);
     FwdUnit U;
     fwd_unit(U, gu, n_ob, n_sb, mw, wps);
-    const int lane = threadIdx.x & 63;
+    const int lane = tid & 63;
     const int h = lane >> 5, r = lane & 31;
     const uint32_t ones = in_vgpr(0x3F803F80u);
-    const uint64_t *cbase = cbits + U.ob * FM * mw * 32;
-    const uint64_t *bbase = bbits + (U.active ? U.sb : 0) * FN * mw * 32;
+    const uint64_t IQP_GLOBAL *cbase = cbits + U.ob * FM * mw * 32;
+    const uint64_t IQP_GLOBAL *bbase = bbits + (U.active ? U.sb : 0) * FN * mw * 32;
     const int64_t nwords = U.w1 > U.w0 ? U.w1 - U.w0 : 0;
     const int64_t nchunks = ceil_div(nwords, kChunkWords);
 
@@ -553,21 +714,23 @@ __device__ __forceinline__ void fwd32_group(const uint64_t (&cw)[FM], const uint
 }
 
 template <int FM, int FN>
-__global__ __launch_bounds__(256, 1) void phase_fwd_f32_kernel(
-    const uint64_t *__restrict__ cbits, const uint64_t *__restrict__ bbits,
-    const float *__restrict__ t32, int64_t m_pad, int64_t mw, int64_t n_ob, int64_t n_sb,
-    int64_t wg_units, int64_t wps, float *__restrict__ E, int64_t l_pad, int64_t s_pad) {
+__device__ __forceinline__ void fwd_f32_body(const FwdArgs &a, int64_t gu, int tid) {
     __shared__ float4 lt[2][kChunkWords * 16];
-    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
-    if (gu >= wg_units) return;
+    const uint64_t IQP_GLOBAL *__restrict__ cbits = gptr(a.cbits);
+    const uint64_t IQP_GLOBAL *__restrict__ bbits = gptr(a.bbits);
+    const float IQP_GLOBAL *__restrict__ t32 = gptr(a.t32);
+    float IQP_GLOBAL *__restrict__ E = gptr(a.E);
+    const int64_t l_pad = a.l_pad, s_pad = a.s_pad, m_pad = a.m_pad, mw = m_pad / 64;
+    const int64_t n_ob = l_pad / (32 * FM), n_sb = s_pad / (32 * FN);
+    const int64_t wps = ceil_div(mw, a.splits);
     FwdUnit U;
     fwd_unit(U, gu, n_ob, n_sb, mw, wps);
-    const int lane = threadIdx.x & 63;
+    const int lane = tid & 63;
     const int h = lane >> 5, r = lane & 31;
-    const float4 *tp4 = reinterpret_cast<const float4 *>(t32);
+    const float4 IQP_GLOBAL *tp4 = reinterpret_cast<const float4 IQP_GLOBAL *>(t32);
     const int64_t half4 = m_pad >> 3;  // float4 units per parity half
-    const uint64_t *cbase = cbits + U.ob * FM * mw * 32;
-    const uint64_t *bbase = bbits + (U.active ? U.sb : 0) * FN * mw * 32;
+    const uint64_t IQP_GLOBAL *cbase = cbits + U.ob * FM * mw * 32;
+    const uint64_t IQP_GLOBAL *bbase = bbits + (U.active ? U.sb : 0) * FN * mw * 32;
     const int64_t nwords = U.w1 > U.w0 ? U.w1 - U.w0 : 0;
     const int64_t nchunks = ceil_div(nwords, kChunkWords);
 
@@ -641,41 +804,86 @@ __global__ __launch_bounds__(256, 1) void phase_fwd_f32_kernel(
     if (U.active) store_tile<FM, FN>(acc, E + U.split * l_pad * s_pad, U.ob, U.sb, s_pad, h, r);
 }
 
+// Plain launch: one workgroup per unit, units spread over the XCDs in
+// contiguous ranges.
 template <int FM, int FN>
-static void fwd_dispatch(const LaunchCtx &lc, int prec, const uint64_t *cbits,
-                         const uint64_t *bbits, const uint16_t *thh, const uint16_t *thl,
-                         const float *t32, int64_t m_pad, int64_t l_pad, int64_t s_pad,
-                         int64_t splits, float *E) {
-    const int64_t mw = m_pad / 64;
-    const int64_t n_ob = l_pad / (32 * FM), n_sb = s_pad / (32 * FN);
-    const int64_t wps = ceil_div(mw, splits);
-    const int64_t wg_units = n_ob * ceil_div(n_sb, 4) * splits;
-    dim3 grid((unsigned)wg_units);
-    if (prec == 1)
-        hipLaunchKernelGGL((phase_fwd_bf16_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, cbits,
-                           bbits, reinterpret_cast<const u32x4 *>(thh),
-                           reinterpret_cast<const u32x4 *>(thl), mw, n_ob, n_sb, wg_units, wps, E,
-                           l_pad, s_pad);
-    else
-        hipLaunchKernelGGL((phase_fwd_f32_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, cbits,
-                           bbits, t32, m_pad, mw, n_ob, n_sb, wg_units, wps, E, l_pad, s_pad);
+__global__ __launch_bounds__(256, 1) void phase_fwd_bf16_kernel(FwdArgs a, int64_t units) {
+    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
+    if (gu >= units) return;  // uniform over the workgroup
+    fwd_bf16_body<FM, FN>(a, gu, (int)threadIdx.x);
 }
 
-hipError_t launch_phase_fwd(const LaunchCtx &lc, int prec, int fm, int fn, const uint64_t *cbits,
-                            const uint64_t *bbits, const uint16_t *thh, const uint16_t *thl,
-                            const float *t32, int64_t m_pad, int64_t l_pad, int64_t s_pad,
-                            int64_t splits, float *E) {
+template <int FM, int FN>
+__global__ __launch_bounds__(256, 1) void phase_fwd_f32_kernel(FwdArgs a, int64_t units) {
+    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
+    if (gu >= units) return;
+    fwd_f32_body<FM, FN>(a, gu, (int)threadIdx.x);
+}
+
+// Persistent launch over the units of a batch of problems.
+template <int FM, int FN>
+__global__ __launch_bounds__(256, 1) void phase_fwd_bf16_persistent(
+    const FwdArgs *__restrict__ args, const int64_t *__restrict__ off, int np,
+    unsigned long long *counter) {
+    persistent_loop(off, np, counter, [&](int p, int64_t u) { fwd_bf16_body<FM, FN>(args[p], u, opaque_tid()); });
+}
+
+template <int FM, int FN>
+__global__ __launch_bounds__(256, 1) void phase_fwd_f32_persistent(
+    const FwdArgs *__restrict__ args, const int64_t *__restrict__ off, int np,
+    unsigned long long *counter) {
+    persistent_loop(off, np, counter, [&](int p, int64_t u) { fwd_f32_body<FM, FN>(args[p], u, opaque_tid()); });
+}
+
+template <int FM, int FN>
+static hipError_t fwd_dispatch(const LaunchCtx &lc, int prec, const FwdArgs &a) {
+    const int64_t units = fwd_units(a, FM, FN);
+    if (units <= 0) return hipSuccess;
+    if (units > kMaxBlocks) return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)units);
+    if (prec == 1)
+        hipLaunchKernelGGL((phase_fwd_bf16_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a, units);
+    else
+        hipLaunchKernelGGL((phase_fwd_f32_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a, units);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_fwd(const LaunchCtx &lc, int prec, int fm, int fn, const FwdArgs &a) {
     hipEvent_t ev;
     timed_begin(lc, KF_FWD, &ev);
-    if (fm == 4 && fn == 4)
-        fwd_dispatch<4, 4>(lc, prec, cbits, bbits, thh, thl, t32, m_pad, l_pad, s_pad, splits, E);
-    else if (fm == 2 && fn == 2)
-        fwd_dispatch<2, 2>(lc, prec, cbits, bbits, thh, thl, t32, m_pad, l_pad, s_pad, splits, E);
-    else if (fm == 2 && fn == 4)
-        fwd_dispatch<2, 4>(lc, prec, cbits, bbits, thh, thl, t32, m_pad, l_pad, s_pad, splits, E);
+    hipError_t e;
+    if (fm == 4 && fn == 4) e = fwd_dispatch<4, 4>(lc, prec, a);
+    else if (fm == 2 && fn == 2) e = fwd_dispatch<2, 2>(lc, prec, a);
+    else if (fm == 2 && fn == 4) e = fwd_dispatch<2, 4>(lc, prec, a);
+    else e = hipErrorInvalidValue;
+    timed_end(lc, KF_FWD, ev);
+    return e;
+}
+
+template <int FM, int FN>
+static hipError_t fwd_persistent(const LaunchCtx &lc, int prec, const FwdArgs *args,
+                                 const int64_t *off, int np, unsigned long long *counter,
+                                 int grid) {
+    if (prec == 1)
+        hipLaunchKernelGGL((phase_fwd_bf16_persistent<FM, FN>), dim3(grid), dim3(256), 0,
+                           lc.stream, args, off, np, counter);
     else
-        return hipErrorInvalidValue;
-    hipError_t e = hipGetLastError();
+        hipLaunchKernelGGL((phase_fwd_f32_persistent<FM, FN>), dim3(grid), dim3(256), 0,
+                           lc.stream, args, off, np, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_fwd_persistent(const LaunchCtx &lc, int prec, int fm, int fn,
+                                       const FwdArgs *args, const int64_t *off, int np,
+                                       unsigned long long *counter, int grid) {
+    if (grid < 1 || np < 1) return hipErrorInvalidValue;
+    hipEvent_t ev;
+    timed_begin(lc, KF_FWD, &ev);
+    hipError_t e;
+    if (fm == 4 && fn == 4) e = fwd_persistent<4, 4>(lc, prec, args, off, np, counter, grid);
+    else if (fm == 2 && fn == 2) e = fwd_persistent<2, 2>(lc, prec, args, off, np, counter, grid);
+    else if (fm == 2 && fn == 4) e = fwd_persistent<2, 4>(lc, prec, args, off, np, counter, grid);
+    else e = hipErrorInvalidValue;
     timed_end(lc, KF_FWD, ev);
     return e;
 }
@@ -695,13 +903,13 @@ __device__ __forceinline__ double block_sum_256(double v, double *sh) {
     return r;
 }
 
-__global__ __launch_bounds__(256) void epilogue_kernel(const float *__restrict__ E, int64_t splits,
-                                                       int64_t l, int64_t s, int64_t l_pad,
-                                                       int64_t s_pad, int64_t nchunk,
-                                                       float *__restrict__ phase_out,
-                                                       double *__restrict__ part) {
+__device__ __forceinline__ void epilogue_body(const EpiArgs &a, int64_t blk) {
     __shared__ double sh[256];
-    const int64_t blk = blockIdx.x;
+    const float IQP_GLOBAL *__restrict__ E = gptr(a.E);
+    float IQP_GLOBAL *__restrict__ phase_out = gptr(a.phase_out);
+    double IQP_GLOBAL *__restrict__ part = gptr(a.part);
+    const int64_t splits = a.splits, s = a.s, l_pad = a.l_pad, s_pad = a.s_pad;
+    const int64_t nchunk = ceil_div(s, kEpiChunk);
     const int64_t k = blk / nchunk, ch = blk - k * nchunk;
     double sc = 0.0, sc2 = 0.0;
 #pragma unroll
@@ -728,26 +936,18 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const float *__restrict__
     }
 }
 
-hipError_t launch_epilogue(const LaunchCtx &lc, const float *E, int64_t splits, int64_t l,
-                           int64_t s, int64_t l_pad, int64_t s_pad, float *phase_out,
-                           double *part) {
-    const int64_t nchunk = ceil_div(s, kEpiChunk);
-    hipEvent_t ev;
-    timed_begin(lc, KF_EPI, &ev);
-    hipLaunchKernelGGL(epilogue_kernel, dim3((unsigned)(l * nchunk)), dim3(256), 0, lc.stream, E,
-                       splits, l, s, l_pad, s_pad, nchunk, phase_out, part);
-    hipError_t e = hipGetLastError();
-    timed_end(lc, KF_EPI, ev);
-    return e;
+hipError_t launch_epilogue(const LaunchCtx &lc, const EpiArgs &a) {
+    return plain_launch<EpiArgs, epilogue_body>(lc, KF_EPI, a, blocks_of(a));
 }
 
-__global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict__ part, int64_t l,
-                                                       int64_t nchunk, int64_t s,
-                                                       double *__restrict__ mean,
-                                                       double *__restrict__ stderr_,
-                                                       double *__restrict__ rowsum) {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= l) return;
+__device__ __forceinline__ void finalize_body(const FinArgs &a, int64_t blk) {
+    const double IQP_GLOBAL *__restrict__ part = gptr(a.part);
+    double IQP_GLOBAL *__restrict__ mean = gptr(a.mean);
+    double IQP_GLOBAL *__restrict__ stderr_ = gptr(a.stderr_);
+    double IQP_GLOBAL *__restrict__ rowsum = gptr(a.rowsum);
+    const int64_t s = a.s, nchunk = ceil_div(s, kEpiChunk);
+    const int64_t k = blk * 256 + threadIdx.x;
+    if (k >= a.l) return;
     double sc = 0.0, sc2 = 0.0;
     for (int64_t ch = 0; ch < nchunk; ++ch) {
         sc += part[(k * nchunk + ch) * 2 + 0];
@@ -764,39 +964,23 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double *__restrict_
     }
 }
 
-hipError_t launch_finalize(const LaunchCtx &lc, const double *part, int64_t l, int64_t s,
-                           double *mean, double *stderr_, double *rowsum) {
-    const int64_t nchunk = ceil_div(s, kEpiChunk);
-    hipEvent_t ev;
-    timed_begin(lc, KF_FIN, &ev);
-    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)ceil_div(l, 256)), dim3(256), 0,
-                       lc.stream, part, l, nchunk, s, mean, stderr_, rowsum);
-    hipError_t e = hipGetLastError();
-    timed_end(lc, KF_FIN, ev);
-    return e;
+hipError_t launch_finalize(const LaunchCtx &lc, const FinArgs &a) {
+    return plain_launch<FinArgs, finalize_body>(lc, KF_FIN, a, blocks_of(a));
 }
 
 // ---------------------------------------------------------------------------
 // Backward weights. coef[2k] = alpha_k, coef[2k+1] = beta_k give
 // dL/dc_ki = alpha_k + beta_k cos E_ki, and
 //   S_ki = (alpha_k + beta_k cos E_ki) sin E_ki.
-__global__ __launch_bounds__(256) void coef_plain_kernel(const double *__restrict__ u, int64_t l,
-                                                         int64_t s, double *__restrict__ coef) {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= l) return;
-    coef[2 * k] = u[k] / (double)s;
-    coef[2 * k + 1] = 0.0;
+__device__ __forceinline__ void coef_plain_body(const CoefArgs &a, int64_t blk) {
+    const int64_t k = blk * 256 + threadIdx.x;
+    if (k >= a.l) return;
+    gptr(a.coef)[2 * k] = gptr(a.grad_mean)[k] / (double)a.s;
+    gptr(a.coef)[2 * k + 1] = 0.0;
 }
 
-hipError_t launch_coef_plain(const LaunchCtx &lc, const double *grad_mean, int64_t l, int64_t s,
-                             double *coef) {
-    hipEvent_t ev;
-    timed_begin(lc, KF_WEIGHTS, &ev);
-    hipLaunchKernelGGL(coef_plain_kernel, dim3((unsigned)ceil_div(l, 256)), dim3(256), 0,
-                       lc.stream, grad_mean, l, s, coef);
-    hipError_t e = hipGetLastError();
-    timed_end(lc, KF_WEIGHTS, ev);
-    return e;
+hipError_t launch_coef_plain(const LaunchCtx &lc, const CoefArgs &a) {
+    return plain_launch<CoefArgs, coef_plain_body>(lc, KF_WEIGHTS, a, blocks_of(a));
 }
 
 // One block per 64 observables x 64 samples: S values are staged in LDS and
@@ -807,14 +991,19 @@ hipError_t launch_coef_plain(const LaunchCtx &lc, const double *grad_mean, int64
 //         in two arrays
 //   FP32: float (((k/32) * KT4s + i/8) * 64 + (i&1) * 32 + k%32) * 4 + (i/2)%4
 //         holds S[k][i] (KT4s = s_pad / 8): four K-steps per 16-byte load
-__global__ __launch_bounds__(256) void weights_kernel(const float *__restrict__ phase,
-                                                      const double *__restrict__ coef, int64_t l,
-                                                      int64_t s, int64_t s_pad, int prec,
-                                                      uint16_t *__restrict__ shi,
-                                                      uint16_t *__restrict__ slo,
-                                                      float *__restrict__ s32) {
+__device__ __forceinline__ void weights_body(const WeightsArgs &a, int64_t blk) {
     __shared__ float tile[64][65];  // [obs][sample]
-    const int64_t i0 = (int64_t)blockIdx.x * 64, k0 = (int64_t)blockIdx.y * 64;
+    const float IQP_GLOBAL *__restrict__ phase = gptr(a.phase);
+    const double IQP_GLOBAL *__restrict__ coef = gptr(a.coef);
+    uint16_t IQP_GLOBAL *__restrict__ shi = gptr(a.shi);
+    uint16_t IQP_GLOBAL *__restrict__ slo = gptr(a.slo);
+    float IQP_GLOBAL *__restrict__ s32 = gptr(a.s32);
+    const int64_t l = a.l, s = a.s, s_pad = a.s_pad;
+    const int prec = a.prec;
+    // blocks run sample tiles fastest
+    const int64_t nsx = s_pad / 64;
+    const int64_t by = blk / nsx;
+    const int64_t i0 = (blk - by * nsx) * 64, k0 = by * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -853,8 +1042,8 @@ __global__ __launch_bounds__(256) void weights_kernel(const float *__restrict__ 
                 dh[v] = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
                 dl[v] = (uint32_t)lv[0] | ((uint32_t)lv[1] << 16);
             }
-            reinterpret_cast<u32x4 *>(shi)[idx] = (u32x4){dh[0], dh[1], dh[2], dh[3]};
-            reinterpret_cast<u32x4 *>(slo)[idx] = (u32x4){dl[0], dl[1], dl[2], dl[3]};
+            reinterpret_cast<u32x4 IQP_GLOBAL *>(shi)[idx] = (u32x4){dh[0], dh[1], dh[2], dh[3]};
+            reinterpret_cast<u32x4 IQP_GLOBAL *>(slo)[idx] = (u32x4){dl[0], dl[1], dl[2], dl[3]};
         }
     } else {
         const int64_t KT4s = s_pad / 8;
@@ -869,17 +1058,8 @@ __global__ __launch_bounds__(256) void weights_kernel(const float *__restrict__ 
     }
 }
 
-hipError_t launch_weights(const LaunchCtx &lc, int prec, const float *phase, const double *coef,
-                          int64_t l, int64_t s, int64_t l_pad, int64_t s_pad, uint16_t *shi,
-                          uint16_t *slo, float *s32) {
-    hipEvent_t ev;
-    timed_begin(lc, KF_WEIGHTS, &ev);
-    dim3 grid((unsigned)(s_pad / 64), (unsigned)(l_pad / 64));
-    hipLaunchKernelGGL(weights_kernel, grid, dim3(256), 0, lc.stream, phase, coef, l, s, s_pad,
-                       prec, shi, slo, s32);
-    hipError_t e = hipGetLastError();
-    timed_end(lc, KF_WEIGHTS, ev);
-    return e;
+hipError_t launch_weights(const LaunchCtx &lc, const WeightsArgs &a) {
+    return plain_launch<WeightsArgs, weights_body>(lc, KF_WEIGHTS, a, blocks_of(a));
 }
 
 // ---------------------------------------------------------------------------
@@ -958,9 +1138,9 @@ __device__ __forceinline__ void bwd_region(const BwdOps<FM, FN> &cur, BwdOps<FM,
 // sum_k c_kj T[k][j] over this wave's observable rows, per gate column.
 template <int FM, int FN>
 __device__ __forceinline__ void bwd_epilogue(const f32x16 (&acc)[FM][FN],
-                                             const uint64_t *__restrict__ ctbits, int64_t ob,
+                                             const uint64_t IQP_GLOBAL *__restrict__ ctbits, int64_t ob,
                                              int64_t jb, int64_t lw, int h, int r, bool active,
-                                             float *__restrict__ gpart, int64_t m_pad) {
+                                             float IQP_GLOBAL *__restrict__ gpart, int64_t m_pad) {
 #pragma unroll
     for (int g = 0; g < FN; ++g) {
         const int64_t j = (jb * FN + g) * 32 + r;
@@ -980,30 +1160,32 @@ __device__ __forceinline__ void bwd_epilogue(const f32x16 (&acc)[FM][FN],
 }
 
 template <int FM, int FN>
-__global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(
-    const u32x4 *__restrict__ shi, const u32x4 *__restrict__ slo,
-    const uint64_t *__restrict__ btbits, const uint64_t *__restrict__ ctbits, int64_t sw,
-    int64_t lw, int64_t n_jb, int64_t wg_units, float *__restrict__ gpart, int64_t m_pad) {
+__device__ __forceinline__ void bwd_bf16_body(const BwdArgs &a, int64_t gu, int tid) {
     // one sample word: [limb][f][t][lane], 16 bytes each. The two buffers
     // are distinct objects selected at compile time (the word loop is
     // unrolled by two), so the compiler can tell that reads of one never
     // alias the global -> LDS copy in flight into the other.
     constexpr int kUnits = 2 * FM * 4 * 64;
     __shared__ u32x4 ls0[kUnits], ls1[kUnits];
-    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
-    if (gu >= wg_units) return;  // uniform over the workgroup
+    const u32x4 IQP_GLOBAL *__restrict__ shi = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.shi));
+    const u32x4 IQP_GLOBAL *__restrict__ slo = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.slo));
+    const uint64_t IQP_GLOBAL *__restrict__ btbits = gptr(a.btbits);
+    const uint64_t IQP_GLOBAL *__restrict__ ctbits = gptr(a.ctbits);
+    float IQP_GLOBAL *__restrict__ gpart = gptr(a.gpart);
+    const int64_t m_pad = a.m_pad, sw = a.s_pad / 64, lw = a.l_pad / 64;
+    const int64_t n_jb = m_pad / (32 * FN);
     const int64_t n_jbg = ceil_div(n_jb, 4);
     const int64_t ob = gu / n_jbg, jbg = gu - ob * n_jbg;
     const int64_t jb_raw = jbg * 4 + wave_id();
     const bool active = jb_raw < n_jb;
     const int64_t jb = active ? jb_raw : n_jb - 1;
-    const int lane = threadIdx.x & 63;
+    const int lane = tid & 63;
     const int h = lane >> 5, r = lane & 31;
     const uint32_t ones = in_vgpr(0x3F803F80u);
     const int64_t KTs = sw * 4;
-    const uint64_t *bbase = btbits + jb * FN * sw * 32;
-    const u32x4 *sbase_h = shi + ob * FM * KTs * 64;
-    const u32x4 *sbase_l = slo + ob * FM * KTs * 64;
+    const uint64_t IQP_GLOBAL *bbase = btbits + jb * FN * sw * 32;
+    const u32x4 IQP_GLOBAL *sbase_h = shi + ob * FM * KTs * 64;
+    const u32x4 IQP_GLOBAL *sbase_l = slo + ob * FM * KTs * 64;
 
     f32x16 acc[FM][FN];
 #pragma unroll
@@ -1068,24 +1250,25 @@ __global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(
 // FP32 form: A operand S[k][2t + h] from the float4 image (four K-steps per
 // lane and load), staged per sample word as [f][q][lane]; B operand +-1.0f.
 template <int FM, int FN>
-__global__ __launch_bounds__(256, 1) void phase_bwd_f32_kernel(
-    const float4 *__restrict__ s32, const uint64_t *__restrict__ btbits,
-    const uint64_t *__restrict__ ctbits, int64_t sw, int64_t lw, int64_t n_jb, int64_t wg_units,
-    float *__restrict__ gpart, int64_t m_pad) {
+__device__ __forceinline__ void bwd_f32_body(const BwdArgs &a, int64_t gu, int tid) {
     constexpr int kUnits = FM * 8 * 64;
     __shared__ float4 ls[2][kUnits];
-    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
-    if (gu >= wg_units) return;
+    const float4 IQP_GLOBAL *__restrict__ s32 = reinterpret_cast<const float4 IQP_GLOBAL *>(gptr(a.s32));
+    const uint64_t IQP_GLOBAL *__restrict__ btbits = gptr(a.btbits);
+    const uint64_t IQP_GLOBAL *__restrict__ ctbits = gptr(a.ctbits);
+    float IQP_GLOBAL *__restrict__ gpart = gptr(a.gpart);
+    const int64_t m_pad = a.m_pad, sw = a.s_pad / 64, lw = a.l_pad / 64;
+    const int64_t n_jb = m_pad / (32 * FN);
     const int64_t n_jbg = ceil_div(n_jb, 4);
     const int64_t ob = gu / n_jbg, jbg = gu - ob * n_jbg;
     const int64_t jb_raw = jbg * 4 + wave_id();
     const bool active = jb_raw < n_jb;
     const int64_t jb = active ? jb_raw : n_jb - 1;
-    const int lane = threadIdx.x & 63;
+    const int lane = tid & 63;
     const int h = lane >> 5, r = lane & 31;
     const int64_t KT4s = sw * 8;
-    const uint64_t *bbase = btbits + jb * FN * sw * 32;
-    const float4 *sbase = s32 + ob * FM * KT4s * 64;
+    const uint64_t IQP_GLOBAL *bbase = btbits + jb * FN * sw * 32;
+    const float4 IQP_GLOBAL *sbase = s32 + ob * FM * KT4s * 64;
 
     f32x16 acc[FM][FN];
 #pragma unroll
@@ -1149,62 +1332,176 @@ __global__ __launch_bounds__(256, 1) void phase_bwd_f32_kernel(
 }
 
 template <int FM, int FN>
-static void bwd_dispatch(const LaunchCtx &lc, int prec, const uint16_t *shi, const uint16_t *slo,
-                         const float *s32, const uint64_t *btbits, const uint64_t *ctbits,
-                         int64_t m_pad, int64_t l_pad, int64_t s_pad, float *gpart) {
-    const int64_t sw = s_pad / 64, lw = l_pad / 64;
-    const int64_t n_ob = l_pad / (32 * FM), n_jb = m_pad / (32 * FN);
-    const int64_t wg_units = ceil_div(n_jb, 4) * n_ob;
-    dim3 grid((unsigned)wg_units);
-    if (prec == 1)
-        hipLaunchKernelGGL((phase_bwd_bf16_kernel<FM, FN>), grid, dim3(256), 0, lc.stream,
-                           reinterpret_cast<const u32x4 *>(shi),
-                           reinterpret_cast<const u32x4 *>(slo), btbits, ctbits, sw, lw, n_jb,
-                           wg_units, gpart, m_pad);
-    else
-        hipLaunchKernelGGL((phase_bwd_f32_kernel<FM, FN>), grid, dim3(256), 0, lc.stream,
-                           reinterpret_cast<const float4 *>(s32), btbits, ctbits, sw, lw, n_jb,
-                           wg_units, gpart, m_pad);
+__global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(BwdArgs a, int64_t units) {
+    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
+    if (gu >= units) return;  // uniform over the workgroup
+    bwd_bf16_body<FM, FN>(a, gu, (int)threadIdx.x);
 }
 
-hipError_t launch_phase_bwd(const LaunchCtx &lc, int prec, int fm, int fn, const uint16_t *shi,
-                            const uint16_t *slo, const float *s32, const uint64_t *btbits,
-                            const uint64_t *ctbits, int64_t m_pad, int64_t l_pad, int64_t s_pad,
-                            float *gpart) {
+template <int FM, int FN>
+__global__ __launch_bounds__(256, 1) void phase_bwd_f32_kernel(BwdArgs a, int64_t units) {
+    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
+    if (gu >= units) return;
+    bwd_f32_body<FM, FN>(a, gu, (int)threadIdx.x);
+}
+
+template <int FM, int FN>
+__global__ __launch_bounds__(256, 1) void phase_bwd_bf16_persistent(
+    const BwdArgs *__restrict__ args, const int64_t *__restrict__ off, int np,
+    unsigned long long *counter) {
+    persistent_loop(off, np, counter, [&](int p, int64_t u) { bwd_bf16_body<FM, FN>(args[p], u, opaque_tid()); });
+}
+
+template <int FM, int FN>
+__global__ __launch_bounds__(256, 1) void phase_bwd_f32_persistent(
+    const BwdArgs *__restrict__ args, const int64_t *__restrict__ off, int np,
+    unsigned long long *counter) {
+    persistent_loop(off, np, counter, [&](int p, int64_t u) { bwd_f32_body<FM, FN>(args[p], u, opaque_tid()); });
+}
+
+template <int FM, int FN>
+static hipError_t bwd_dispatch(const LaunchCtx &lc, int prec, const BwdArgs &a) {
+    const int64_t units = bwd_units(a, FM, FN);
+    if (units <= 0) return hipSuccess;
+    if (units > kMaxBlocks) return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)units);
+    if (prec == 1)
+        hipLaunchKernelGGL((phase_bwd_bf16_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a, units);
+    else
+        hipLaunchKernelGGL((phase_bwd_f32_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a, units);
+    return hipGetLastError();
+}
+
+// (a 128x128 backward tile cannot hold the double-buffered pipeline in 512
+// registers without spilling, so it is not offered)
+hipError_t launch_phase_bwd(const LaunchCtx &lc, int prec, int fm, int fn, const BwdArgs &a) {
     hipEvent_t ev;
     timed_begin(lc, KF_BWD, &ev);
-    // (a 128x128 backward tile cannot hold the double-buffered pipeline in
-    // 512 registers without spilling, so it is not offered)
-    if (fm == 2 && fn == 2)
-        bwd_dispatch<2, 2>(lc, prec, shi, slo, s32, btbits, ctbits, m_pad, l_pad, s_pad, gpart);
-    else if (fm == 2 && fn == 4)
-        bwd_dispatch<2, 4>(lc, prec, shi, slo, s32, btbits, ctbits, m_pad, l_pad, s_pad, gpart);
-    else
-        return hipErrorInvalidValue;
-    hipError_t e = hipGetLastError();
+    hipError_t e;
+    if (fm == 2 && fn == 2) e = bwd_dispatch<2, 2>(lc, prec, a);
+    else if (fm == 2 && fn == 4) e = bwd_dispatch<2, 4>(lc, prec, a);
+    else e = hipErrorInvalidValue;
     timed_end(lc, KF_BWD, ev);
     return e;
 }
 
-__global__ __launch_bounds__(256) void grad_reduce_kernel(const float *__restrict__ gpart,
-                                                          int64_t n_parts, int64_t m,
-                                                          int64_t m_pad,
-                                                          double *__restrict__ grad) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= m) return;
-    double acc = 0.0;
-    for (int64_t p = 0; p < n_parts; ++p) acc += (double)gpart[p * m_pad + j];
-    grad[j] = -2.0 * acc;
+template <int FM, int FN>
+static hipError_t bwd_persistent(const LaunchCtx &lc, int prec, const BwdArgs *args,
+                                 const int64_t *off, int np, unsigned long long *counter,
+                                 int grid) {
+    if (prec == 1)
+        hipLaunchKernelGGL((phase_bwd_bf16_persistent<FM, FN>), dim3(grid), dim3(256), 0,
+                           lc.stream, args, off, np, counter);
+    else
+        hipLaunchKernelGGL((phase_bwd_f32_persistent<FM, FN>), dim3(grid), dim3(256), 0,
+                           lc.stream, args, off, np, counter);
+    return hipGetLastError();
 }
 
-hipError_t launch_grad_reduce(const LaunchCtx &lc, const float *gpart, int64_t n_parts,
-                              int64_t m, int64_t m_pad, double *grad) {
+hipError_t launch_phase_bwd_persistent(const LaunchCtx &lc, int prec, int fm, int fn,
+                                       const BwdArgs *args, const int64_t *off, int np,
+                                       unsigned long long *counter, int grid) {
+    if (grid < 1 || np < 1) return hipErrorInvalidValue;
     hipEvent_t ev;
-    timed_begin(lc, KF_GRAD, &ev);
-    hipLaunchKernelGGL(grad_reduce_kernel, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0,
-                       lc.stream, gpart, n_parts, m, m_pad, grad);
+    timed_begin(lc, KF_BWD, &ev);
+    hipError_t e;
+    if (fm == 2 && fn == 2) e = bwd_persistent<2, 2>(lc, prec, args, off, np, counter, grid);
+    else if (fm == 2 && fn == 4) e = bwd_persistent<2, 4>(lc, prec, args, off, np, counter, grid);
+    else e = hipErrorInvalidValue;
+    timed_end(lc, KF_BWD, ev);
+    return e;
+}
+
+// Resident workgroups of a kernel on the current device.
+template <typename K>
+static int resident_grid(K kernel) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess)
+        return 0;
+    return (per_cu > 0 ? per_cu : 1) * cus;
+}
+
+int persistent_grid(bool fwd, int prec, int fm, int fn) {
+    if (fwd) {
+        if (fm == 4 && fn == 4)
+            return prec == 1 ? resident_grid(phase_fwd_bf16_persistent<4, 4>)
+                             : resident_grid(phase_fwd_f32_persistent<4, 4>);
+        if (fm == 2 && fn == 2)
+            return prec == 1 ? resident_grid(phase_fwd_bf16_persistent<2, 2>)
+                             : resident_grid(phase_fwd_f32_persistent<2, 2>);
+        if (fm == 2 && fn == 4)
+            return prec == 1 ? resident_grid(phase_fwd_bf16_persistent<2, 4>)
+                             : resident_grid(phase_fwd_f32_persistent<2, 4>);
+        return 0;
+    }
+    if (fm == 2 && fn == 2)
+        return prec == 1 ? resident_grid(phase_bwd_bf16_persistent<2, 2>)
+                         : resident_grid(phase_bwd_f32_persistent<2, 2>);
+    if (fm == 2 && fn == 4)
+        return prec == 1 ? resident_grid(phase_bwd_bf16_persistent<2, 4>)
+                         : resident_grid(phase_bwd_f32_persistent<2, 4>);
+    return 0;
+}
+
+__global__ __launch_bounds__(64) void reset_counters_kernel(unsigned long long *c, int n) {
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
+}
+
+hipError_t launch_reset_counters(const LaunchCtx &lc, unsigned long long *c, int n) {
+    if (n < 1 || n > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, lc.stream, c, n);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ void grad_reduce_body(const GradArgs &a, int64_t blk) {
+    const int64_t j = blk * 256 + threadIdx.x;
+    if (j >= a.m) return;
+    double acc = 0.0;
+    for (int64_t p = 0; p < a.n_parts; ++p) acc += (double)gptr(a.gpart)[p * a.m_pad + j];
+    gptr(a.grad)[j] = -2.0 * acc;
+}
+
+hipError_t launch_grad_reduce(const LaunchCtx &lc, const GradArgs &a) {
+    return plain_launch<GradArgs, grad_reduce_body>(lc, KF_GRAD, a, blocks_of(a));
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches of the per-step bodies.
+template <typename A, void (*F)(const A &, int64_t)>
+static void batched(const LaunchCtx &lc, const void *args, const int64_t *off, int np,
+                    int64_t total) {
+    hipLaunchKernelGGL((batched_kernel<A, F>), dim3((unsigned)total), dim3(256), 0, lc.stream,
+                       static_cast<const A *>(args), off, np);
+}
+
+hipError_t launch_batched(const LaunchCtx &lc, int kind, const void *args, const int64_t *off,
+                          int np, int64_t total) {
+    if (total <= 0) return hipSuccess;
+    if (total > kMaxBlocks || np < 1) return hipErrorInvalidConfiguration;
+    static const int family[SK_COUNT] = {KF_THETA, KF_PARITY,  KF_PARITY,  KF_PARITY,
+                                         KF_PARITY, KF_EPI,    KF_FIN,     KF_WEIGHTS,
+                                         KF_WEIGHTS, KF_GRAD,  KF_PARITY};
+    if (kind < 0 || kind >= SK_COUNT) return hipErrorInvalidValue;
+    hipEvent_t ev;
+    timed_begin(lc, family[kind], &ev);
+    switch (kind) {
+        case SK_THETA: batched<ThetaArgs, theta_prep_body>(lc, args, off, np, total); break;
+        case SK_BITSLICE: batched<BitsliceArgs, bitslice_body>(lc, args, off, np, total); break;
+        case SK_PARITY0: batched<ParityArgs, parity_bs_body<0>>(lc, args, off, np, total); break;
+        case SK_PARITY1: batched<ParityArgs, parity_bs_body<1>>(lc, args, off, np, total); break;
+        case SK_PARITY2: batched<ParityArgs, parity_bs_body<2>>(lc, args, off, np, total); break;
+        case SK_EPI: batched<EpiArgs, epilogue_body>(lc, args, off, np, total); break;
+        case SK_FIN: batched<FinArgs, finalize_body>(lc, args, off, np, total); break;
+        case SK_COEF: batched<CoefArgs, coef_plain_body>(lc, args, off, np, total); break;
+        case SK_WEIGHTS: batched<WeightsArgs, weights_body>(lc, args, off, np, total); break;
+        case SK_GRAD: batched<GradArgs, grad_reduce_body>(lc, args, off, np, total); break;
+        case SK_SUPPORT: batched<SupportArgs, support_body>(lc, args, off, np, total); break;
+    }
     hipError_t e = hipGetLastError();
-    timed_end(lc, KF_GRAD, ev);
+    timed_end(lc, family[kind], ev);
     return e;
 }
 

@@ -31,6 +31,16 @@ class DevWorkload:
         self.ops01 = W.rows_to_dense(w.ops, w.n)
 
 
+def grad_bar(prec, w, ops01, u):
+    """Per-gate tolerance of dL/dtheta_j = sum_k u_k d_kj, where each
+    d_kj = -(2/s) sum_i sin(E_ki) (-1)^{b_ij} c_kj is an average of terms in
+    [-2, 2] and so carries twice the estimate tolerance; the independent
+    rounding errors of the observables with c_kj = 1 add in quadrature."""
+    import oracle
+    c = oracle.parity(w.n, ops01, w.gates).astype(np.float64)  # [l][m]
+    return TOL[prec] * np.maximum(1.0, 2.0 * np.sqrt((np.asarray(u) ** 2) @ c))
+
+
 def wrap(x):
     """Difference of angles mapped to [-pi, pi]."""
     return (x + np.pi) % (2 * np.pi) - np.pi

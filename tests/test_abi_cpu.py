@@ -116,8 +116,9 @@ def test_parity_validation_and_empty():
     # empty inputs are a no-op that never touches the device
     assert lib.iqp_parity(0, None, 3, None, 1, 0, None, None, 0, None) == L.IQP_OK
     assert lib.iqp_parity(3, None, 0, None, 1, 1, None, None, 0, None) == L.IQP_OK
-    assert lib.iqp_parity_workspace_bytes(100, 2, 1) > 0
-    assert lib.iqp_parity_workspace_bytes(100, 0, 1) == 0
+    assert lib.iqp_parity_workspace_bytes(100, 70, 2, 1) > lib.iqp_parity_workspace_bytes(100, 7, 2, 1) > 0
+    assert lib.iqp_parity_workspace_bytes(100, 70, 0, 1) == 0
+    assert lib.iqp_parity_workspace_bytes(100, -1, 2, 1) == 0
 
 
 def test_workspace_bytes_query():
@@ -132,6 +133,51 @@ def test_workspace_bytes_query():
     assert lib.iqp_workspace_bytes(L.IQP_CALL_MMD, ctypes.byref(c), 10, 10, 0, 1) == 0
     assert lib.iqp_workspace_bytes(9, ctypes.byref(c), 10, 10, 0, 1) == 0
     assert lib.iqp_workspace_bytes(0, None, 10, 10, 0, 1) == 0
+
+
+def _problems(shapes):
+    arr = (L.IqpProblem * len(shapes))()
+    for i, (n, m, l, s) in enumerate(shapes):
+        arr[i].circuit = L.IqpCircuit(n, (n + 63) // 64, m, FAKE.value, FAKE.value)
+        arr[i].n_ops, arr[i].ops = l, FAKE.value
+        arr[i].n_samples, arr[i].samples = s, FAKE.value
+    return arr
+
+
+@pytest.mark.parametrize("shapes,count,prec,flags,msg", [
+    ([(10, 5, 4, 8)], 0, 1, 0, "n_problems out of range"),
+    ([(10, 5, 4, 8)], 1, 3, 0, "precision"),
+    ([(10, 5, 4, 8)], 1, 1, 8, "unknown flags"),
+    ([(10, 5, 4, 8), (10, 5, 0, 8)], 2, 1, 0, "n_ops out of range [1, 2^24] (problem 1)"),
+    ([(10, 5, 4, 0)], 1, 1, 0, "n_samples out of range"),
+    ([(10, 0, 4, 8)], 1, 1, 0, "n_gates out of range"),
+])
+def test_batch_plan_rejects_invalid_shapes(shapes, count, prec, flags, msg):
+    plan = ctypes.c_void_p()
+    st = L.lib().iqp_batch_plan_create(count, _problems(shapes), prec, flags, ctypes.byref(plan))
+    assert st == L.IQP_ERR_INVALID_ARG
+    assert msg in L.last_error()
+    assert not plan.value
+
+
+def test_batch_plan_rejects_wrong_word_count_and_nulls():
+    lib = L.lib()
+    arr = _problems([(100, 5, 4, 8)])
+    arr[0].circuit.n_words = 1  # 100 qubits need 2 words
+    plan = ctypes.c_void_p()
+    assert lib.iqp_batch_plan_create(1, arr, 1, 0, ctypes.byref(plan)) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_batch_plan_create(1, None, 1, 0, ctypes.byref(plan)) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_batch_plan_create(1, _problems([(10, 5, 4, 8)]), 1, 0, None) == \
+        L.IQP_ERR_INVALID_ARG
+    # calls on a NULL plan are rejected without touching the device
+    assert lib.iqp_batch_expval(None, arr, FAKE, 1 << 40, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_batch_expval_grad(None, arr, FAKE, 1 << 40, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_batch_tune(None, arr, 1, FAKE, 1 << 40, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_batch_tune(None, arr, 0, FAKE, 1 << 40, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_batch_get_config(None, (ctypes.c_int32 * 6)()) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_batch_set_config(None, (ctypes.c_int32 * 5)()) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_batch_workspace_bytes(None) == 0
+    assert lib.iqp_batch_plan_destroy(None) == L.IQP_OK
 
 
 def test_profile_query_unknown_name():
