@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched workload: keep the default tiles instead of autotuning")
     ap.add_argument("--cpu-sample-ops", type=int, default=0,
                     help="observables in the oracle's timed sample (0 = choose)")
     ap.add_argument("--profile-pass", action="store_true",
@@ -293,6 +295,10 @@ def main_batch(args):
     def make_plan(prec):
         plan = api.BatchPlan([(api.Circuit(w.n, d.gens, d.theta), d.ops, d.samples)
                               for w, d in zip(ws, dws)], prec)
+        if args.no_tune:
+            log("%s: workspace %.2f GB, default tiles %s" % (prec, plan.ws_bytes / 1e9,
+                                                             plan.config()))
+            return plan
         t1 = time.time()
         plan.expval()
         cfg = plan.tune(us)

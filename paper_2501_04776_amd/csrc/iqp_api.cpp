@@ -137,6 +137,31 @@ int64_t choose_splits(int64_t tiles, int64_t mw) {
     return best;
 }
 
+// Sample-word splits of the backward contraction, chosen like the forward's:
+// the smallest count that keeps >= 95 % of the resident workgroups busy in
+// the last round (two resident per CU for the 64x64 wave tile, one for
+// 64x128, on 256 CUs), with >= 8 sample words per split. The count is then
+// trimmed so that no split is empty.
+int64_t choose_bsplits(int64_t units, int64_t sw, int bfn) {
+    const int64_t resident = (bfn == 2 ? 2 : 1) * 256;
+    int64_t best = 1;
+    double best_eff = -1.0;
+    for (int64_t ks = 1; ks <= 8; ++ks) {
+        if (ks > 1 && sw < 8 * ks) break;
+        const int64_t u = units * ks;
+        const double eff = (double)u / (double)(ceil_div(u, resident) * resident);
+        if (eff >= 0.95) {
+            best = ks;
+            break;
+        }
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            best = ks;
+        }
+    }
+    return ceil_div(sw, ceil_div(sw, best));
+}
+
 static size_t carve(size_t &cur, size_t bytes) {
     const size_t o = cur;
     cur += (bytes + 255) & ~(size_t)255;
@@ -144,8 +169,9 @@ static size_t carve(size_t &cur, size_t bytes) {
 }
 
 // Tile overrides for measurement sweeps: IQP_FWD_TILE = "FMxFN" (4x4, 2x4,
-// 2x2), IQP_BWD_TILE (2x4, 2x2) and
-// IQP_FWD_SPLITS = number of gate-word splits of the forward.
+// 2x2), IQP_BWD_TILE (2x4, 2x2), IQP_FWD_SPLITS = number of gate-word splits
+// of the forward, IQP_BWD_SPLITS = number of sample-word splits of the
+// backward.
 static void apply_env_tiles(TileCfg &tc) {
     const char *f = getenv("IQP_FWD_TILE");
     int a = 0, b = 0;
@@ -161,6 +187,8 @@ static void apply_env_tiles(TileCfg &tc) {
     }
     const char *sp = getenv("IQP_FWD_SPLITS");
     if (sp && atoi(sp) > 0) tc.splits = atoi(sp);
+    const char *bs = getenv("IQP_BWD_SPLITS");
+    if (bs && atoi(bs) > 0) tc.bsplits = atoi(bs);
 }
 
 void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l, int64_t s,
@@ -183,6 +211,11 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
     const int64_t tiles = (P.l_pad / (32 * P.tc.fm)) * (P.s_pad / (32 * P.tc.fn));
     if (P.tc.splits <= 0) P.tc.splits = choose_splits(tiles, P.mw);
     if (P.tc.splits > P.mw) P.tc.splits = P.mw;
+    const int64_t sw = P.s_pad / 64;
+    const int64_t bunits = ceil_div(P.m_pad / (32 * P.tc.bfn), 4) * (P.l_pad / (32 * P.tc.bfm));
+    if (P.tc.bsplits <= 0) P.tc.bsplits = choose_bsplits(bunits, sw, P.tc.bfn);
+    if (P.tc.bsplits > sw) P.tc.bsplits = sw;
+    P.tc.bsplits = ceil_div(sw, ceil_div(sw, P.tc.bsplits));
     P.fwd = parts.fwd;
     P.bwd = parts.bwd;
     P.phi = parts.phi;
@@ -220,7 +253,7 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
         } else {
             P.o_s32 = carve(cur, (size_t)P.s_pad * P.l_pad * 4);
         }
-        P.o_gpart = carve(cur, (size_t)(P.l_pad / (32 * P.tc.bfm)) * P.m_pad * 4);
+        P.o_gpart = carve(cur, (size_t)P.tc.bsplits * (P.l_pad / (32 * P.tc.bfm)) * P.m_pad * 4);
     }
     if (P.mmd) {
         P.o_xd = carve(cur, (size_t)(64 * P.W + 1) * P.ldd * 8);

@@ -535,6 +535,7 @@ int iqp_batch_plan_create(int32_t n_problems, const iqp_problem *probs, int prec
     TileCfg tc0;
     tc0.splits = 1;
     tc0.bfm = 2;
+    tc0.bsplits = 1;  // the work queue balances the backward
     bp->plans.resize(n_problems);
     for (int p = 0; p < n_problems; ++p) {
         const iqp_problem &q = probs[p];

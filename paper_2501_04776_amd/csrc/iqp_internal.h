@@ -26,6 +26,7 @@ struct TileCfg {
     int fm = 4, fn = 4;      // forward: observables x samples
     int bfm = 2, bfn = 2;    // backward: observables x gates
     int64_t splits = 0;      // forward split over gate words; 0 = choose
+    int64_t bsplits = 0;     // backward split over sample words; 0 = choose
 };
 
 // Kernel-family ids for the optional per-kernel timing.
@@ -148,18 +149,19 @@ struct WeightsArgs {
 };
 inline int64_t blocks_of(const WeightsArgs &a) { return (a.s_pad / 64) * (a.l_pad / 64); }
 
-// T = S B (observables x gates, K = samples) and the gradient partials
-// gpart[l_pad / (32 fm)][m_pad]; btbits / ctbits are the transposed tiled32
-// parities of the samples / observables against the generators.
+// T = S B (observables x gates, K = samples, split `ksplits` ways over the
+// sample words) and the gradient partials gpart[ksplits][l_pad / (32 fm)][m_pad];
+// btbits / ctbits are the transposed tiled32 parities of the samples /
+// observables against the generators. Every split must hold >= 1 sample word.
 struct BwdArgs {
     const uint16_t *shi, *slo;
     const float *s32;
     const uint64_t *btbits, *ctbits;
-    int64_t m_pad, l_pad, s_pad;
+    int64_t m_pad, l_pad, s_pad, ksplits;
     float *gpart;
 };
 inline int64_t bwd_units(const BwdArgs &a, int fm, int fn) {
-    return ceil_div(a.m_pad / (32 * fn), 4) * (a.l_pad / (32 * fm));
+    return ceil_div(a.m_pad / (32 * fn), 4) * (a.l_pad / (32 * fm)) * a.ksplits;
 }
 
 struct GradArgs {

@@ -1171,11 +1171,15 @@ __device__ __forceinline__ void bwd_bf16_body(const BwdArgs &a, int64_t gu, int 
     const u32x4 IQP_GLOBAL *__restrict__ slo = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.slo));
     const uint64_t IQP_GLOBAL *__restrict__ btbits = gptr(a.btbits);
     const uint64_t IQP_GLOBAL *__restrict__ ctbits = gptr(a.ctbits);
-    float IQP_GLOBAL *__restrict__ gpart = gptr(a.gpart);
     const int64_t m_pad = a.m_pad, sw = a.s_pad / 64, lw = a.l_pad / 64;
-    const int64_t n_jb = m_pad / (32 * FN);
+    const int64_t n_jb = m_pad / (32 * FN), n_ob = a.l_pad / (32 * FM);
     const int64_t n_jbg = ceil_div(n_jb, 4);
-    const int64_t ob = gu / n_jbg, jbg = gu - ob * n_jbg;
+    // unit = ((sample split) * n_ob + observable block) * n_jbg + gate-block group
+    const int64_t jbg = gu % n_jbg, t0 = gu / n_jbg;
+    const int64_t ob = t0 % n_ob, ks = t0 / n_ob;
+    const int64_t wps = ceil_div(sw, a.ksplits);
+    const int64_t w0 = ks * wps, w1 = (w0 + wps < sw) ? w0 + wps : sw;
+    float IQP_GLOBAL *__restrict__ gpart = gptr(a.gpart) + ks * n_ob * m_pad;
     const int64_t jb_raw = jbg * 4 + wave_id();
     const bool active = jb_raw < n_jb;
     const int64_t jb = active ? jb_raw : n_jb - 1;
@@ -1207,17 +1211,18 @@ __device__ __forceinline__ void bwd_bf16_body(const BwdArgs &a, int64_t gu, int 
             dma16((limb ? sbase_l : sbase_h) + src, &dst[b * 64]);
         }
     };
-    stage(0, ls0);
-    if (sw > 1) stage(1, ls1);
+    // every unit has w1 - w0 >= 1 sample words (the host picks the splits)
+    stage(w0, ls0);
+    if (w0 + 1 < w1) stage(w0 + 1, ls1);
     uint64_t nxt[FN], cur[FN];
 #pragma unroll
-    for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw) * 32)[r];
+    for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w0) * 32)[r];
     dma_wait_barrier();
 #pragma unroll
     for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> (8 * h);
-    if (sw > 1) {
+    if (w0 + 1 < w1) {
 #pragma unroll
-        for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + 1) * 32)[r];
+        for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w0 + 1) * 32)[r];
     }
     BwdOps<FM, FN> opA, opB;
     bwd_expand<FM, FN, 0>(opA, ls0, cur, lane, ones);
@@ -1230,19 +1235,19 @@ __device__ __forceinline__ void bwd_bf16_body(const BwdArgs &a, int64_t gu, int 
         bwd_region<FM, FN, 2>(opB, opA, mine, cur, lane, ones, acc);
         bwd_region<FM, FN, 3>(opA, opB, mine, cur, lane, ones, acc);
         dma_wait_barrier();
-        if (w + 2 < sw) stage(w + 2, mine);
+        if (w + 2 < w1) stage(w + 2, mine);
 #pragma unroll
         for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> (8 * h);
-        if (w + 2 < sw) {
+        if (w + 2 < w1) {
 #pragma unroll
             for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w + 2) * 32)[r];
         }
         // past the last word this expands a stale buffer and is never used
         bwd_region<FM, FN, 0>(opB, opA, other, cur, lane, ones, acc);
     };
-    for (int64_t w = 0; w < sw; w += 2) {
+    for (int64_t w = w0; w < w1; w += 2) {
         word(w, ls0, ls1);
-        if (w + 1 < sw) word(w + 1, ls1, ls0);
+        if (w + 1 < w1) word(w + 1, ls1, ls0);
     }
     bwd_epilogue<FM, FN>(acc, ctbits, ob, jb, lw, h, r, active, gpart, m_pad);
 }
@@ -1256,11 +1261,14 @@ __device__ __forceinline__ void bwd_f32_body(const BwdArgs &a, int64_t gu, int t
     const float4 IQP_GLOBAL *__restrict__ s32 = reinterpret_cast<const float4 IQP_GLOBAL *>(gptr(a.s32));
     const uint64_t IQP_GLOBAL *__restrict__ btbits = gptr(a.btbits);
     const uint64_t IQP_GLOBAL *__restrict__ ctbits = gptr(a.ctbits);
-    float IQP_GLOBAL *__restrict__ gpart = gptr(a.gpart);
     const int64_t m_pad = a.m_pad, sw = a.s_pad / 64, lw = a.l_pad / 64;
-    const int64_t n_jb = m_pad / (32 * FN);
+    const int64_t n_jb = m_pad / (32 * FN), n_ob = a.l_pad / (32 * FM);
     const int64_t n_jbg = ceil_div(n_jb, 4);
-    const int64_t ob = gu / n_jbg, jbg = gu - ob * n_jbg;
+    const int64_t jbg = gu % n_jbg, t0 = gu / n_jbg;
+    const int64_t ob = t0 % n_ob, ks = t0 / n_ob;
+    const int64_t wps = ceil_div(sw, a.ksplits);
+    const int64_t w0 = ks * wps, w1 = (w0 + wps < sw) ? w0 + wps : sw;
+    float IQP_GLOBAL *__restrict__ gpart = gptr(a.gpart) + ks * n_ob * m_pad;
     const int64_t jb_raw = jbg * 4 + wave_id();
     const bool active = jb_raw < n_jb;
     const int64_t jb = active ? jb_raw : n_jb - 1;
@@ -1288,14 +1296,14 @@ __device__ __forceinline__ void bwd_f32_body(const BwdArgs &a, int64_t gu, int t
             dma16(sbase + ((int64_t)f * KT4s + 8 * w + q) * 64 + lane, &ls[buf][b * 64]);
         }
     };
-    stage(0, 0);
+    stage(w0, 0);
     uint64_t nxt[FN], cur[FN];
 #pragma unroll
-    for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw) * 32)[r];
+    for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w0) * 32)[r];
     dma_wait_barrier();
-    for (int64_t w = 0; w < sw; ++w) {
-        const int buf = (int)(w & 1);
-        const bool more = w + 1 < sw;
+    for (int64_t w = w0; w < w1; ++w) {
+        const int buf = (int)((w - w0) & 1);
+        const bool more = w + 1 < w1;
         if (more) stage(w + 1, buf ^ 1);
 #pragma unroll
         for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> h;

@@ -64,6 +64,8 @@ struct PlanParts {
 
 // Gate-word splits of the forward that fill `kWaveSlots` wave slots.
 int64_t choose_splits(int64_t tiles, int64_t mw);
+// Sample-word splits of the backward for `units` workgroup units.
+int64_t choose_bsplits(int64_t units, int64_t sw, int bfn);
 
 // Lays out the buffers; tc.splits <= 0 picks the split count.
 void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l, int64_t s,
@@ -138,10 +140,11 @@ inline BwdArgs bwd_args(const Plan &P, void *ws) {
                    at<float>(ws, P.o_s32),       at<uint64_t>(ws, P.o_btbits),
                    at<uint64_t>(ws, P.o_ctbits), P.m_pad,
                    P.l_pad,                      P.s_pad,
-                   at<float>(ws, P.o_gpart)};
+                   P.tc.bsplits,                 at<float>(ws, P.o_gpart)};
 }
 inline GradArgs grad_args(const Plan &P, void *ws, int bfm, double *grad_theta) {
-    return GradArgs{at<float>(ws, P.o_gpart), P.l_pad / (32 * bfm), P.m, P.m_pad, grad_theta};
+    return GradArgs{at<float>(ws, P.o_gpart), P.tc.bsplits * (P.l_pad / (32 * bfm)), P.m, P.m_pad,
+                    grad_theta};
 }
 
 }  // namespace iqp

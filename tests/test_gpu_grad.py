@@ -154,3 +154,21 @@ def test_grad_deterministic_repeat():
         a = _grad(dw, u, prec, False)
         b = _grad(dw, u, prec, False)
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_grad_every_sample_split_matches_oracle(prec, monkeypatch):
+    # the backward contraction split over sample words (12 words here): one
+    # split, uneven splits, and one word per split give the same gradient
+    w = W.small_random(77, 70, 1500, 200, 700)
+    dw = DevWorkload(w)
+    u = np.random.default_rng(4).normal(size=w.l)
+    og = oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01, w.samples, u)
+    got = {}
+    for ks in (1, 2, 5, 12):
+        monkeypatch.setenv("IQP_BWD_SPLITS", str(ks))
+        got[ks] = _grad(dw, u, prec, True)
+        assert np.abs(got[ks] - og).max() < _gtol(prec, og), ks
+    monkeypatch.delenv("IQP_BWD_SPLITS")
+    for ks in (2, 5, 12):
+        assert np.abs(got[ks] - got[1]).max() < 1e-6 * max(1.0, np.abs(og).max())
