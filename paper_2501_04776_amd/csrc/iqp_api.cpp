@@ -206,7 +206,6 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
     P.s_pad = round_up(s, kPad);
     P.mw = P.m_pad / 64;
     P.lw = P.l_pad / 64;
-    P.Nw = ceil_div(N > 0 ? N : 1, 64);
     P.nchunk = ceil_div(s, kEpiChunk);
     const int64_t tiles = (P.l_pad / (32 * P.tc.fm)) * (P.s_pad / (32 * P.tc.fn));
     if (P.tc.splits <= 0) P.tc.splits = choose_splits(tiles, P.mw);
@@ -225,7 +224,6 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
     // for the bit-sliced parity
     P.ldz = round_up(P.s_pad / 64, 4);
     P.lda = round_up(P.l_pad / 64, 4);
-    P.ldd = round_up(P.Nw, 4);
     P.o_xz = carve(cur, (size_t)(64 * P.W + 1) * P.ldz * 8);
     P.o_xa = carve(cur, (size_t)(64 * P.W + 1) * P.lda * 8);
     P.o_sup = carve(cur, (size_t)P.m_pad * kSupCap * 4);
@@ -256,9 +254,6 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
         P.o_gpart = carve(cur, (size_t)P.tc.bsplits * (P.l_pad / (32 * P.tc.bfm)) * P.m_pad * 4);
     }
     if (P.mmd) {
-        P.o_xd = carve(cur, (size_t)(64 * P.W + 1) * P.ldd * 8);
-        P.o_dsup = carve(cur, (size_t)round_up(l, 64) * kSupCap * 4);
-        P.o_dbits = carve(cur, (size_t)round_up(l, 64) * P.Nw * 8);
         P.o_pstat = carve(cur, (size_t)l * 2 * 8);
     }
     P.total = cur;
@@ -496,18 +491,7 @@ int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
     float *phi = grad_theta ? at<float>(ws, P.o_phi) : nullptr;
     st = run_forward(P, c, ops, samples, ws, lc, phi, nullptr, nullptr, at<double>(ws, P.o_rowsum));
     if (st) return st;
-    IQP_TRY(launch_bitslice(lc, BitsliceArgs{data, N, (int)P.W, P.ldd, at<uint64_t>(ws, P.o_xd)}),
-            "bitslice(data)");
-    IQP_TRY(launch_support(lc, SupportArgs{ops, l, (int)P.W, round_up(l, 64),
-                                           at<int32_t>(ws, P.o_dsup)}),
-            "support(ops)");
-    IQP_TRY(launch_parity_bs(lc, IQP_BITS_TILED32_T,
-                             ParityArgs{ops, at<int32_t>(ws, P.o_dsup), l, (int)P.W,
-                                        at<uint64_t>(ws, P.o_xd), P.Nw, P.ldd, 0, ceil_div(l, 64),
-                                        at<uint64_t>(ws, P.o_dbits)}),
-            "parity(data)");
-    IQP_TRY(launch_data_stats(lc, at<uint64_t>(ws, P.o_dbits), l, P.Nw, N,
-                              at<double>(ws, P.o_pstat)),
+    IQP_TRY(launch_data_stats(lc, ops, l, data, N, (int)P.W, at<double>(ws, P.o_pstat)),
             "data_stats");
     IQP_TRY(launch_mmd_loss(lc, at<double>(ws, P.o_pstat), at<double>(ws, P.o_rowsum), op_weight,
                             l, s, N, unbiased, loss),

@@ -209,8 +209,10 @@ int persistent_grid(bool fwd, int prec, int fm, int fn);
 // Zero n work-queue counters (a kernel, so it can be captured in a graph).
 hipError_t launch_reset_counters(const LaunchCtx &lc, unsigned long long *c, int n);
 
-hipError_t launch_data_stats(const LaunchCtx &lc, const uint64_t *dbits, int64_t l, int64_t Nw,
-                             int64_t N, double *pstat);
+// pstat[2k] = sum_n (-1)^{a_k . x_n}, pstat[2k+1] = that sum / N, for the
+// observables ops [l][W] against the training strings data [N][W].
+hipError_t launch_data_stats(const LaunchCtx &lc, const uint64_t *ops, int64_t l,
+                             const uint64_t *data, int64_t N, int W, double *pstat);
 
 hipError_t launch_mmd_loss(const LaunchCtx &lc, const double *pstat, const double *rowsum,
                            const double *op_weight, int64_t l, int64_t s, int64_t N, int unbiased,

@@ -1514,28 +1514,68 @@ hipError_t launch_batched(const LaunchCtx &lc, int kind, const void *args, const
 }
 
 // ---------------------------------------------------------------------------
-// MMD^2 chain. data_stats: from the transposed tiled32 parity bits of the
-// observables against the N training strings (word ((k/32) Nw + w) 32 + k%32,
-// bit n%64 of word w = n/64) pstat[2k] = sum_n (-1)^{a_k . x_n} and
-// pstat[2k+1] = p_k = that sum / N.
-__global__ __launch_bounds__(256) void data_stats_kernel(const uint64_t *__restrict__ dbits,
-                                                         int64_t l, int64_t Nw, int64_t N,
+// MMD^2 chain. data_stats: pstat[2k] = sum_n (-1)^{a_k . x_n} and
+// pstat[2k+1] = p_k = that sum / N (eq. mmd_estimate's data term), counted
+// directly by AND + popcount: both operands may be dense (the observables of
+// a narrow kernel bandwidth, Bernoulli training strings), where bit columns
+// would not pay. A wave takes kStatOps observables, read as scalars; lane n
+// walks data rows n, n + 64, ...; the per-lane odd counts are summed across
+// the wave in a fixed butterfly order (integers: exact).
+constexpr int kStatOps = 8;
+
+__global__ __launch_bounds__(256) void data_stats_kernel(const uint64_t *__restrict__ ops,
+                                                         int64_t l,
+                                                         const uint64_t *__restrict__ data,
+                                                         int64_t N, int W,
                                                          double *__restrict__ pstat) {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= l) return;
-    int64_t odd = 0;
-    for (int64_t w = 0; w < Nw; ++w) odd += __popcll(dbits[((k >> 5) * Nw + w) * 32 + (k & 31)]);
-    const double sv = (double)(N - 2 * odd);
-    pstat[2 * k] = sv;
-    pstat[2 * k + 1] = sv / (double)N;
+    const int lane = threadIdx.x & 63;
+    const int64_t k0 = ((int64_t)blockIdx.x * 4 + wave_id()) * kStatOps;
+    if (k0 >= l) return;  // uniform over the wave
+    int cnt[kStatOps];
+#pragma unroll
+    for (int i = 0; i < kStatOps; ++i) cnt[i] = 0;
+    for (int64_t n0 = 0; n0 < N; n0 += 64) {
+        const int64_t n = n0 + lane;
+        const bool live = n < N;
+        uint32_t par[kStatOps];
+#pragma unroll
+        for (int i = 0; i < kStatOps; ++i) par[i] = 0;
+        for (int w = 0; w < W; ++w) {
+            const uint64_t x = live ? data[n * W + w] : 0ull;
+#pragma unroll
+            for (int i = 0; i < kStatOps; ++i) {
+                const uint64_t av = (k0 + i < l) ? ops[(k0 + i) * W + w] : 0ull;
+                par[i] ^= (uint32_t)__popcll(av & x);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kStatOps; ++i) cnt[i] += (int)(par[i] & 1u);
+    }
+#pragma unroll
+    for (int i = 0; i < kStatOps; ++i) {
+        int c = cnt[i];
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s, 64);
+        cnt[i] = c;
+    }
+#pragma unroll
+    for (int i = 0; i < kStatOps; ++i) {
+        if (lane == i && k0 + i < l) {
+            const double sv = (double)(N - 2 * (int64_t)cnt[i]);
+            pstat[2 * (k0 + i)] = sv;
+            pstat[2 * (k0 + i) + 1] = sv / (double)N;
+        }
+    }
 }
 
-hipError_t launch_data_stats(const LaunchCtx &lc, const uint64_t *dbits, int64_t l, int64_t Nw,
-                             int64_t N, double *pstat) {
+hipError_t launch_data_stats(const LaunchCtx &lc, const uint64_t *ops, int64_t l,
+                             const uint64_t *data, int64_t N, int W, double *pstat) {
+    const int64_t blocks = ceil_div(l, 4 * kStatOps);
+    if (blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
     hipEvent_t ev;
     timed_begin(lc, KF_MMD, &ev);
-    hipLaunchKernelGGL(data_stats_kernel, dim3((unsigned)ceil_div(l, 256)), dim3(256), 0,
-                       lc.stream, dbits, l, Nw, N, pstat);
+    hipLaunchKernelGGL(data_stats_kernel, dim3((unsigned)blocks), dim3(256), 0, lc.stream, ops,
+                       l, data, N, W, pstat);
     hipError_t e = hipGetLastError();
     timed_end(lc, KF_MMD, ev);
     return e;

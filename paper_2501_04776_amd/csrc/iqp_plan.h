@@ -40,17 +40,17 @@ int check_circuit(const iqp_circuit *c);
 struct Plan {
     int prec = 0;
     int64_t n = 0, W = 0, m = 0, l = 0, s = 0, N = 0;
-    int64_t m_pad = 0, l_pad = 0, s_pad = 0, mw = 0, lw = 0, Nw = 0;
+    int64_t m_pad = 0, l_pad = 0, s_pad = 0, mw = 0, lw = 0;
     TileCfg tc;
     int64_t nchunk = 0;
     bool fwd = false, phi = false, bwd = false, mmd = false;
     size_t o_thh = 0, o_thl = 0, o_t32 = 0, o_cbits = 0, o_bbits = 0, o_E = 0, o_part = 0;
     size_t o_rowsum = 0, o_phi = 0, o_coef = 0, o_ctbits = 0, o_shi = 0, o_slo = 0, o_s32 = 0;
-    size_t o_gpart = 0, o_dbits = 0, o_pstat = 0;
-    size_t o_xz = 0, o_xa = 0, o_xd = 0;  // bit columns of samples, ops, data
+    size_t o_gpart = 0, o_pstat = 0;
+    size_t o_xz = 0, o_xa = 0;            // bit columns of samples, ops
     size_t o_btbits = 0;                  // B^T: samples against generators, transposed
-    size_t o_sup = 0, o_dsup = 0;         // support lists of the generators / observables
-    int64_t ldz = 0, lda = 0, ldd = 0;
+    size_t o_sup = 0;                     // support lists of the generators
+    int64_t ldz = 0, lda = 0;
     size_t total = 0;
 };
 
@@ -59,7 +59,7 @@ struct PlanParts {
     bool fwd = true;   // forward buffers (theta limbs, C and B bits, E, sums)
     bool bwd = false;  // backward buffers (weights, B^T and C^T bits, partials)
     bool phi = false;  // a phase buffer of its own (backward without saved phases)
-    bool mmd = false;  // data parities and statistics
+    bool mmd = false;  // data statistics
 };
 
 // Gate-word splits of the forward that fill `kWaveSlots` wave slots.
