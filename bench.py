@@ -104,6 +104,7 @@ def main():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-bitflip", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched workload: keep the default tiles instead of autotuning")
     ap.add_argument("--cpu-sample-ops", type=int, default=0,
@@ -241,6 +242,44 @@ def main():
                         "ok": bool(em < TOL[prec] and es < TOL[prec] and eg < TOL[prec]),
                         "sampled_observables": int(pick.size)}
     result["parity"] = parity
+
+    # --- stochastic bitflip circuits (exact product form, FP64) --------------
+    if not mmd and not args.no_bitflip:
+        ub = torch.from_numpy(np.random.default_rng(9).normal(size=w.l)).cuda()
+
+        def bf_timed(grad, steps):
+            def one():
+                if grad:
+                    api.iqp_bitflip_expval_grad(circ, dw.ops, ub)
+                else:
+                    api.iqp_bitflip_expval(circ, dw.ops)
+            one()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                one()
+            b.record()
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / steps
+        bf_ms = bf_timed(False, max(3, args.steps // 2))
+        bfg_ms = bf_timed(True, max(3, args.steps // 2))
+        bmean = api.iqp_bitflip_expval(circ, dw.ops).cpu().numpy()[pick]
+        ubp = np.zeros(w.l)
+        ubp[pick] = np.random.default_rng(4).normal(size=pick.size)
+        bg = api.iqp_bitflip_expval_grad(circ, dw.ops, torch.from_numpy(ubp).cuda()).cpu().numpy()
+        obm = oracle.bitflip_expval(w.n, w.gates, w.theta, dw.ops01[pick])
+        obg = oracle.bitflip_grad(w.n, w.gates, w.theta, dw.ops01[pick], ubp[pick])
+        rel_m = float(np.max(np.abs(bmean - obm) / np.maximum(np.abs(obm), 1e-300)))
+        rel_g = float(np.abs(bg - obg).max() / max(1e-300, np.abs(obg).max()))
+        log("bitflip: expval %.3f ms, expval+grad %.3f ms" % (bf_ms, bfg_ms))
+        result["bitflip"] = {"expval_ms": bf_ms, "expval_grad_ms": bfg_ms,
+                             "entries_per_s": w.l * w.m / (bf_ms * 1e-3),
+                             "entries": "l*m entries of C*Theta per call",
+                             "max_rel_err_mean": rel_m, "max_rel_err_grad": rel_g,
+                             "ok": bool(rel_m < 1e-10 and rel_g < 1e-9),
+                             "sampled_observables": int(pick.size)}
 
     # --- oracle on the host cores -------------------------------------------
     # a bounded sample of the same workload: fwd + bwd for the first k

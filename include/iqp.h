@@ -76,11 +76,14 @@ enum {
     IQP_CALL_EXPVAL_GRAD = 1,      /* with phase_save supplied */
     IQP_CALL_EXPVAL_GRAD_RECOMPUTE = 2, /* phase_save == NULL */
     IQP_CALL_MMD = 3,
-    IQP_CALL_MMD_GRAD = 4
+    IQP_CALL_MMD_GRAD = 4,
+    IQP_CALL_BITFLIP = 5,
+    IQP_CALL_BITFLIP_GRAD = 6
 };
 
 /* Bytes of workspace the given call needs for these sizes (N is only read for
- * the MMD calls). Returns 0 for invalid sizes. */
+ * the MMD calls; s and precision are not read for the bitflip calls). Returns
+ * 0 for invalid sizes. */
 size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s, int64_t N,
                            int precision);
 
@@ -155,6 +158,25 @@ int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
                       const double *op_weight, int64_t s, const uint64_t *samples, int64_t N,
                       const uint64_t *data, int unbiased, int precision, double *loss,
                       double *grad_theta, void *ws, size_t ws_bytes, void *stream);
+
+/* Stochastic bitflip circuits (Sec. 2.5, Prop. 3): the incoherent version of
+ * the circuit, where gate j flips the bits of g_j with probability
+ * sin^2(theta_j). Its expectation values are exact and classical:
+ *     <Z_{a_k}> = prod_{j : a_k . g_j odd} cos(2 theta_j)   (eq. expval_bitflip)
+ * computed in FP64 from the C parity bits (a sum of log|cos| with a sign
+ * parity and a count of zero factors per observable).
+ *   ops        device [l][W], l >= 1
+ *   mean       device [l] the exact expectation values
+ *   grad_mean  device [l] u_k = dL/d<Z_{a_k}>
+ *   grad_theta device [m] dL/dtheta_j = -2 sin(2 theta_j) sum_k u_k c_kj
+ *              prod_{t in J_k, t != j} cos(2 theta_t), overwritten
+ *   ws         device workspace of >= iqp_workspace_bytes(IQP_CALL_BITFLIP[_GRAD], ...)
+ */
+int iqp_bitflip_expval(const iqp_circuit *c, int64_t l, const uint64_t *ops, double *mean,
+                       void *ws, size_t ws_bytes, void *stream);
+int iqp_bitflip_expval_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
+                            const double *grad_mean, double *grad_theta, void *ws,
+                            size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Batched form: many independent problems (circuit, observables, samples) of

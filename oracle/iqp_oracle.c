@@ -384,7 +384,7 @@ int orc_mmd_loss_grad(int64_t n, int64_t m, const int64_t *gptr, const int32_t *
 /* Exact values (pins only). */
 
 /* State-vector simulation (n <= 20): start in |0>, apply each gate through
- * exp(i theta X_g)|x> = cos(theta)|x> + i sin(theta)|x xor g> (Sec. 2.4),
+ * exp(i theta X_g)|x> = cos(theta)|x> + i sin(theta)|x xor g> (Sec. 2.5),
  * return the output probabilities |<x|U|0>|^2. Basis index bit q = qubit q. */
 int orc_statevector_probs(int64_t n, int64_t m, const int64_t *gptr, const int32_t *gidx,
                           const double *theta, double *probs)

@@ -6,14 +6,14 @@ include/iqp.h; this package only marshals arguments to it.
 """
 from . import packing
 from ._lib import IqpError
-from .api import (FP32, ROW_MAJOR, SPLIT_BF16, TILED32, TILED32_T, BatchPlan, Circuit, iqp_expval,
-                  iqp_expval_grad,
+from .api import (FP32, ROW_MAJOR, SPLIT_BF16, TILED32, TILED32_T, BatchPlan, Circuit,
+                  iqp_bitflip_expval, iqp_bitflip_expval_grad, iqp_expval, iqp_expval_grad,
                   iqp_mmd_loss_grad, iqp_parity, profile_enable, profile_query, profile_reset,
                   workspace_bytes)
-from .autograd import IQPExpval, IQPMMDLoss
+from .autograd import IQPBitflipExpval, IQPExpval, IQPMMDLoss
 
 __all__ = ["packing", "IqpError", "FP32", "SPLIT_BF16", "ROW_MAJOR", "TILED32", "TILED32_T", "BatchPlan",
-           "Circuit",
+           "Circuit", "iqp_bitflip_expval", "iqp_bitflip_expval_grad",
            "iqp_expval", "iqp_expval_grad", "iqp_mmd_loss_grad", "iqp_parity",
-           "profile_enable", "profile_query", "profile_reset", "workspace_bytes", "IQPExpval",
-           "IQPMMDLoss"]
+           "profile_enable", "profile_query", "profile_reset", "workspace_bytes",
+           "IQPBitflipExpval", "IQPExpval", "IQPMMDLoss"]

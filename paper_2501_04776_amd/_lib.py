@@ -26,6 +26,8 @@ IQP_CALL_EXPVAL_GRAD = 1
 IQP_CALL_EXPVAL_GRAD_RECOMPUTE = 2
 IQP_CALL_MMD = 3
 IQP_CALL_MMD_GRAD = 4
+IQP_CALL_BITFLIP = 5
+IQP_CALL_BITFLIP_GRAD = 6
 
 IQP_BITS_ROW_MAJOR = 0
 IQP_BITS_TILED32 = 1
@@ -33,7 +35,8 @@ IQP_BITS_TILED32_T = 2
 
 # every symbol include/iqp.h declares
 EXPORTED = ("iqp_workspace_bytes", "iqp_parity_workspace_bytes", "iqp_parity", "iqp_expval",
-            "iqp_expval_grad", "iqp_mmd_loss_grad", "iqp_batch_plan_create",
+            "iqp_expval_grad", "iqp_mmd_loss_grad", "iqp_bitflip_expval",
+            "iqp_bitflip_expval_grad", "iqp_batch_plan_create",
             "iqp_batch_plan_destroy", "iqp_batch_workspace_bytes", "iqp_batch_expval",
             "iqp_batch_expval_grad", "iqp_batch_tune", "iqp_batch_get_config",
             "iqp_batch_set_config", "iqp_strerror", "iqp_last_error", "iqp_profile_enable",
@@ -89,6 +92,10 @@ def lib():
     L.iqp_mmd_loss_grad.argtypes = [cp, i64, vp, vp, i64, vp, i64, vp, i32, i32, vp, vp, vp,
                                     sz, vp]
     L.iqp_mmd_loss_grad.restype = i32
+    L.iqp_bitflip_expval.argtypes = [cp, i64, vp, vp, vp, sz, vp]
+    L.iqp_bitflip_expval.restype = i32
+    L.iqp_bitflip_expval_grad.argtypes = [cp, i64, vp, vp, vp, vp, sz, vp]
+    L.iqp_bitflip_expval_grad.restype = i32
     pp = ctypes.POINTER(IqpProblem)
     L.iqp_batch_plan_create.argtypes = [ctypes.c_int32, pp, i32, i32, ctypes.POINTER(vp)]
     L.iqp_batch_plan_create.restype = i32

@@ -174,6 +174,36 @@ def iqp_mmd_loss_grad(circ: Circuit, ops: torch.Tensor, op_weight: torch.Tensor,
     return loss, g
 
 
+# --- stochastic bitflip circuits (exact product form) ------------------------
+def iqp_bitflip_expval(circ: Circuit, ops: torch.Tensor) -> torch.Tensor:
+    """Exact <Z_a> [l] of the bitflip version of the circuit."""
+    ops = _rows(ops, "ops", circ.W)
+    l = ops.shape[0]
+    mean = torch.empty(l, dtype=torch.float64, device=circ.device)
+    need = workspace_bytes(L.IQP_CALL_BITFLIP, circ.n, circ.m, l, 1)
+    ws, nb = workspace.get(circ.device, need)
+    c = circ.struct()
+    L.check(L.lib().iqp_bitflip_expval(ctypes.byref(c), l, _ptr(ops), _ptr(mean), _ptr(ws), nb,
+                                       _stream(ops)), "iqp_bitflip_expval")
+    return mean
+
+
+def iqp_bitflip_expval_grad(circ: Circuit, ops: torch.Tensor,
+                            grad_mean: torch.Tensor) -> torch.Tensor:
+    """dL/dtheta [m] of the bitflip expectation values for u = dL/d<Z>."""
+    ops = _rows(ops, "ops", circ.W)
+    l = ops.shape[0]
+    u = _vec(grad_mean, "grad_mean", l)
+    g = torch.empty(circ.m, dtype=torch.float64, device=circ.device)
+    need = workspace_bytes(L.IQP_CALL_BITFLIP_GRAD, circ.n, circ.m, l, 1)
+    ws, nb = workspace.get(circ.device, need)
+    c = circ.struct()
+    L.check(L.lib().iqp_bitflip_expval_grad(ctypes.byref(c), l, _ptr(ops), _ptr(u), _ptr(g),
+                                            _ptr(ws), nb, _stream(ops)),
+            "iqp_bitflip_expval_grad")
+    return g
+
+
 # --- batched form -------------------------------------------------------------
 class BatchPlan:
     """Many problems (circuit, observables, samples) of uneven size run as one

@@ -56,3 +56,24 @@ class IQPMMDLoss(torch.autograd.Function):
         (g,) = ctx.saved_tensors
         return ((g * grad_out).to(ctx.theta_dtype), None, None, None, None, None, None, None,
                 None)
+
+
+class IQPBitflipExpval(torch.autograd.Function):
+    """mean[l] = IQPBitflipExpval.apply(theta, gens, ops, n_qubits): the exact
+    expectation values of the stochastic bitflip version of the circuit
+    (Prop. 3), differentiable in theta."""
+
+    @staticmethod
+    def forward(ctx, theta, gens, ops, n_qubits):
+        circ = api.Circuit(n_qubits, gens, theta.detach())
+        mean = api.iqp_bitflip_expval(circ, ops)
+        ctx.save_for_backward(theta, gens, ops)
+        ctx.n_qubits = n_qubits
+        return mean
+
+    @staticmethod
+    def backward(ctx, grad_mean):
+        theta, gens, ops = ctx.saved_tensors
+        circ = api.Circuit(ctx.n_qubits, gens, theta.detach())
+        g = api.iqp_bitflip_expval_grad(circ, ops, grad_mean.to(torch.float64).contiguous())
+        return g.to(theta.dtype), None, None, None

@@ -259,6 +259,31 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
     P.total = cur;
 }
 
+// Plan of the bitflip-circuit calls: bit columns and support lists for the C
+// parity, C (tiled32), the encoded factors and per-observable sums, and C^T
+// for the gradient.
+static void make_bitflip_plan(Plan &P, bool grad, int64_t n, int64_t m, int64_t l) {
+    P = Plan();
+    P.n = n;
+    P.W = ceil_div(n, 64);
+    P.m = m;
+    P.l = l;
+    P.m_pad = round_up(m, kPad);
+    P.l_pad = round_up(l, kPad);
+    P.mw = P.m_pad / 64;
+    P.lw = P.l_pad / 64;
+    P.lda = round_up(P.l_pad / 64, 4);
+    size_t cur = 0;
+    P.o_xa = carve(cur, (size_t)(64 * P.W + 1) * P.lda * 8);
+    P.o_sup = carve(cur, (size_t)P.m_pad * kSupCap * 4);
+    P.o_cbits = carve(cur, (size_t)P.l_pad * P.mw * 8);
+    P.o_enc = carve(cur, (size_t)P.m_pad * 8);
+    P.o_stat = carve(cur, (size_t)P.l_pad * 2 * 8);
+    P.o_rowsum = carve(cur, (size_t)P.l_pad * 8);  // the product, when only the gradient is asked
+    if (grad) P.o_ctbits = carve(cur, (size_t)P.m_pad * P.lw * 8);
+    P.total = cur;
+}
+
 // Plan of a single-problem call: its parts, the default tiles and any
 // override from the environment.
 static void make_call_plan(Plan &P, int call, int64_t n, int64_t m, int64_t l, int64_t s,
@@ -362,7 +387,13 @@ extern "C" {
 
 size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s, int64_t N,
                            int precision) {
-    if (!c || c->n_qubits < 1 || c->n_gates < 1 || l < 1 || s < 1) return 0;
+    if (!c || c->n_qubits < 1 || c->n_gates < 1 || l < 1) return 0;
+    if (call == IQP_CALL_BITFLIP || call == IQP_CALL_BITFLIP_GRAD) {
+        Plan P;
+        make_bitflip_plan(P, call == IQP_CALL_BITFLIP_GRAD, c->n_qubits, c->n_gates, l);
+        return P.total;
+    }
+    if (s < 1) return 0;
     if (call < IQP_CALL_EXPVAL || call > IQP_CALL_MMD_GRAD) return 0;
     if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16) return 0;
     if ((call == IQP_CALL_MMD || call == IQP_CALL_MMD_GRAD) && N < 1) return 0;
@@ -501,6 +532,72 @@ int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
                             l, s, unbiased, at<double>(ws, P.o_coef)),
             "coef_mmd");
     return run_backward(P, c, ops, samples, phi, true, ws, lc, grad_theta);
+}
+
+// Forward of a bitflip circuit into the plan's buffers (mean may be the
+// workspace's own slot).
+static int run_bitflip_forward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
+                               void *ws, const LaunchCtx &lc, double *mean) {
+    IQP_TRY(launch_bitflip_prep(lc, BitflipPrepArgs{c->theta, P.m, at<double>(ws, P.o_enc)}),
+            "bitflip_prep");
+    IQP_TRY(launch_support(lc, support_args(P, c->gens, ws)), "support");
+    IQP_TRY(launch_bitslice(lc, BitsliceArgs{ops, P.l, (int)P.W, P.lda, at<uint64_t>(ws, P.o_xa)}),
+            "bitslice(A)");
+    IQP_TRY(launch_parity_bs(lc, IQP_BITS_TILED32,
+                             ParityArgs{c->gens, at<int32_t>(ws, P.o_sup), P.m, (int)P.W,
+                                        at<uint64_t>(ws, P.o_xa), P.l_pad / 64, P.lda, P.l_pad,
+                                        P.mw, at<uint64_t>(ws, P.o_cbits)}),
+            "parity(C)");
+    IQP_TRY(launch_bitflip_fwd(lc, BitflipFwdArgs{at<uint64_t>(ws, P.o_cbits),
+                                                   at<double>(ws, P.o_enc), P.l, P.mw, mean,
+                                                   nullptr, at<double>(ws, P.o_stat)}),
+            "bitflip_fwd");
+    return IQP_OK;
+}
+
+int iqp_bitflip_expval(const iqp_circuit *c, int64_t l, const uint64_t *ops, double *mean,
+                       void *ws, size_t ws_bytes, void *stream) {
+    g_last_error.clear();
+    int st = check_circuit(c);
+    if (st) return st;
+    if (l < 1 || l > kMaxRows) return fail(IQP_ERR_INVALID_ARG, "l out of range [1, 2^24]");
+    if (!ops) return fail(IQP_ERR_INVALID_ARG, "ops is NULL");
+    if (!mean) return fail(IQP_ERR_INVALID_ARG, "mean is NULL");
+    Plan P;
+    make_bitflip_plan(P, false, c->n_qubits, c->n_gates, l);
+    if ((st = check_ws(P, ws, ws_bytes))) return st;
+    if ((st = check_device())) return st;
+    return run_bitflip_forward(P, c, ops, ws, make_ctx(stream), mean);
+}
+
+int iqp_bitflip_expval_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
+                            const double *grad_mean, double *grad_theta, void *ws,
+                            size_t ws_bytes, void *stream) {
+    g_last_error.clear();
+    int st = check_circuit(c);
+    if (st) return st;
+    if (l < 1 || l > kMaxRows) return fail(IQP_ERR_INVALID_ARG, "l out of range [1, 2^24]");
+    if (!ops) return fail(IQP_ERR_INVALID_ARG, "ops is NULL");
+    if (!grad_mean) return fail(IQP_ERR_INVALID_ARG, "grad_mean is NULL");
+    if (!grad_theta) return fail(IQP_ERR_INVALID_ARG, "grad_theta is NULL");
+    Plan P;
+    make_bitflip_plan(P, true, c->n_qubits, c->n_gates, l);
+    if ((st = check_ws(P, ws, ws_bytes))) return st;
+    if ((st = check_device())) return st;
+    LaunchCtx lc = make_ctx(stream);
+    st = run_bitflip_forward(P, c, ops, ws, lc, at<double>(ws, P.o_rowsum));
+    if (st) return st;
+    IQP_TRY(launch_parity_bs(lc, IQP_BITS_TILED32_T,
+                             ParityArgs{c->gens, at<int32_t>(ws, P.o_sup), P.m, (int)P.W,
+                                        at<uint64_t>(ws, P.o_xa), P.lw, P.lda, 0, P.mw,
+                                        at<uint64_t>(ws, P.o_ctbits)}),
+            "parity(C^T)");
+    IQP_TRY(launch_bitflip_grad(lc, BitflipGradArgs{at<uint64_t>(ws, P.o_ctbits),
+                                                     at<double>(ws, P.o_enc), c->theta,
+                                                     at<double>(ws, P.o_stat), grad_mean, P.m,
+                                                     P.lw, grad_theta}),
+            "bitflip_grad");
+    return IQP_OK;
 }
 
 const char *iqp_strerror(int status) {

@@ -171,6 +171,31 @@ struct GradArgs {
 };
 inline int64_t blocks_of(const GradArgs &a) { return ceil_div(a.m, 256); }
 
+// Stochastic bitflip circuits (exact product form).
+struct BitflipPrepArgs {
+    const double *theta;
+    int64_t m;
+    double *enc;  // [m] copysign(-log|cos 2 theta|, cos 2 theta)
+};
+inline int64_t blocks_of(const BitflipPrepArgs &a) { return ceil_div(a.m, 256); }
+
+struct BitflipFwdArgs {
+    const uint64_t *cbits;  // tiled32 C bits, mw gate words per observable row
+    const double *enc;
+    int64_t l, mw;
+    double *mean, *stderr_;  // stderr_ may be NULL (written 0: the value is exact)
+    double *stat;            // [l][2]
+};
+inline int64_t blocks_of(const BitflipFwdArgs &a) { return ceil_div(a.l, 4); }
+
+struct BitflipGradArgs {
+    const uint64_t *ctbits;  // transposed tiled32 C^T bits, lw observable words per gate row
+    const double *enc, *theta, *stat, *grad_mean;
+    int64_t m, lw;
+    double *grad;
+};
+inline int64_t blocks_of(const BitflipGradArgs &a) { return ceil_div(a.m, 256); }
+
 // ---- launchers (iqp_kernels.hip); each returns hipGetLastError() ----
 hipError_t launch_theta_prep(const LaunchCtx &lc, const ThetaArgs &a);
 hipError_t launch_bitslice(const LaunchCtx &lc, const BitsliceArgs &a);
@@ -183,6 +208,9 @@ hipError_t launch_coef_plain(const LaunchCtx &lc, const CoefArgs &a);
 hipError_t launch_weights(const LaunchCtx &lc, const WeightsArgs &a);
 hipError_t launch_phase_bwd(const LaunchCtx &lc, int prec, int fm, int fn, const BwdArgs &a);
 hipError_t launch_grad_reduce(const LaunchCtx &lc, const GradArgs &a);
+hipError_t launch_bitflip_prep(const LaunchCtx &lc, const BitflipPrepArgs &a);
+hipError_t launch_bitflip_fwd(const LaunchCtx &lc, const BitflipFwdArgs &a);
+hipError_t launch_bitflip_grad(const LaunchCtx &lc, const BitflipGradArgs &a);
 
 // Batched launches: `args` is a device array of np argument structs of the
 // step's type and `off` a device array of np + 1 prefix sums of their block

@@ -1652,4 +1652,105 @@ hipError_t launch_coef_mmd(const LaunchCtx &lc, const double *pstat, const doubl
     return e;
 }
 
+// ---------------------------------------------------------------------------
+// Stochastic bitflip circuits (Prop. 3, eq. expval_bitflip): the exact
+// <Z_{a_k}> = prod_{j in J_k} cos(2 theta_j) over the generators that
+// anticommute with Z_{a_k}, all in FP64. The product is kept as a sum of
+// logarithms, a sign parity and a count of exact-zero factors, so that the
+// product leaving out any one factor (the gradient) needs no division.
+//   enc_j = copysign(-log|cos 2 theta_j|, cos 2 theta_j)  (+-inf for a zero)
+__device__ __forceinline__ void bitflip_prep_body(const BitflipPrepArgs &a, int64_t blk) {
+    const int64_t j = blk * 256 + threadIdx.x;
+    if (j >= a.m) return;
+    const double c = cos(2.0 * gptr(a.theta)[j]);
+    gptr(a.enc)[j] = copysign(c == 0.0 ? (double)INFINITY : -log(fabs(c)), c);
+}
+
+hipError_t launch_bitflip_prep(const LaunchCtx &lc, const BitflipPrepArgs &a) {
+    return plain_launch<BitflipPrepArgs, bitflip_prep_body>(lc, KF_THETA, a, blocks_of(a));
+}
+
+// One wave per observable k: lane v walks gate words v, v + 64, ... of the
+// tiled32 row of C and sums the encoded factors in gate order; the lanes'
+// (sum, sign parity, zero count) are then combined by a fixed butterfly.
+// stat[k] = (S_k = sum of log|c| over non-zero factors, sign of those
+// factors times 1 + min(zero factors, 2)); mean[k] = the product.
+__device__ __forceinline__ void bitflip_fwd_body(const BitflipFwdArgs &a, int64_t blk) {
+    const int64_t k = blk * 4 + wave_id();
+    if (k >= a.l) return;  // uniform over the wave
+    const int lane = threadIdx.x & 63;
+    const uint64_t IQP_GLOBAL *crow = gptr(a.cbits) + (k >> 5) * a.mw * 32 + (k & 31);
+    const double IQP_GLOBAL *enc = gptr(a.enc);
+    double S = 0.0;
+    int neg = 0, zeros = 0;
+    for (int64_t w = lane; w < a.mw; w += 64) {
+        uint64_t bits = crow[w * 32];
+        while (bits) {
+            const int64_t j = w * 64 + __builtin_ctzll(bits);
+            bits &= bits - 1;
+            const double e = enc[j];
+            if (isinf(e)) {
+                ++zeros;
+            } else {
+                S -= fabs(e);
+                neg ^= (int)signbit(e) & 1;
+            }
+        }
+    }
+#pragma unroll
+    for (int st = 32; st >= 1; st >>= 1) {
+        S += __shfl_xor(S, st, 64);
+        neg ^= __shfl_xor(neg, st, 64);
+        zeros += __shfl_xor(zeros, st, 64);
+    }
+    if (lane == 0) {
+        const double sgn = neg ? -1.0 : 1.0;
+        gptr(a.mean)[k] = zeros ? 0.0 : sgn * exp(S);
+        if (a.stderr_) gptr(a.stderr_)[k] = 0.0;
+        double IQP_GLOBAL *st = gptr(a.stat) + 2 * k;
+        st[0] = S;
+        st[1] = sgn * (double)(zeros < 2 ? 1 + zeros : 3);
+    }
+}
+
+hipError_t launch_bitflip_fwd(const LaunchCtx &lc, const BitflipFwdArgs &a) {
+    return plain_launch<BitflipFwdArgs, bitflip_fwd_body>(lc, KF_FWD, a, blocks_of(a));
+}
+
+// One lane per gate j: walks the transposed tiled32 row of C^T (observable
+// words) and sums u_k times the product over J_k without factor j:
+//   c_j = 0:  (zero count of k is 1) ? sign_k exp(S_k) : 0
+//   else:     (no zero factor in k) ? sign_k sgn(c_j) exp(S_k - log|c_j|) : 0
+// then dtheta_j = -2 sin(2 theta_j) times that sum.
+__device__ __forceinline__ void bitflip_grad_body(const BitflipGradArgs &a, int64_t blk) {
+    const int64_t j = blk * 256 + threadIdx.x;
+    if (j >= a.m) return;
+    const uint64_t IQP_GLOBAL *crow = gptr(a.ctbits) + (j >> 5) * a.lw * 32 + (j & 31);
+    const double IQP_GLOBAL *stat = gptr(a.stat);
+    const double IQP_GLOBAL *u = gptr(a.grad_mean);
+    const double e = gptr(a.enc)[j];
+    const bool jzero = isinf(e);
+    const double Lj = -fabs(e), sj = signbit(e) ? -1.0 : 1.0;
+    double acc = 0.0;
+    for (int64_t w = 0; w < a.lw; ++w) {
+        uint64_t bits = crow[w * 32];
+        while (bits) {
+            const int64_t k = w * 64 + __builtin_ctzll(bits);
+            bits &= bits - 1;
+            const double S = stat[2 * k], code = stat[2 * k + 1];
+            const double z = fabs(code) - 1.0;  // zero factors: 0, 1, or 2 for >= 2
+            const double sk = code < 0.0 ? -1.0 : 1.0;
+            double p = 0.0;
+            if (jzero) p = (z == 1.0) ? sk * exp(S) : 0.0;
+            else p = (z == 0.0) ? sk * sj * exp(S - Lj) : 0.0;
+            acc += u[k] * p;
+        }
+    }
+    gptr(a.grad)[j] = -2.0 * sin(2.0 * gptr(a.theta)[j]) * acc;
+}
+
+hipError_t launch_bitflip_grad(const LaunchCtx &lc, const BitflipGradArgs &a) {
+    return plain_launch<BitflipGradArgs, bitflip_grad_body>(lc, KF_BWD, a, blocks_of(a));
+}
+
 }  // namespace iqp

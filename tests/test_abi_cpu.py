@@ -133,6 +133,28 @@ def test_workspace_bytes_query():
     assert lib.iqp_workspace_bytes(L.IQP_CALL_MMD, ctypes.byref(c), 10, 10, 0, 1) == 0
     assert lib.iqp_workspace_bytes(9, ctypes.byref(c), 10, 10, 0, 1) == 0
     assert lib.iqp_workspace_bytes(0, None, 10, 10, 0, 1) == 0
+    # bitflip calls read neither s nor the precision
+    e = lib.iqp_workspace_bytes(L.IQP_CALL_BITFLIP, ctypes.byref(c), 1000, 0, 0, 9)
+    f = lib.iqp_workspace_bytes(L.IQP_CALL_BITFLIP_GRAD, ctypes.byref(c), 1000, 0, 0, 9)
+    assert 0 < e < f
+
+
+def test_bitflip_validation():
+    lib = L.lib()
+    c = _circ()
+    big = 1 << 40
+    st = lib.iqp_bitflip_expval(ctypes.byref(c), 0, FAKE, FAKE, FAKE, big, None)
+    assert st == L.IQP_ERR_INVALID_ARG and "l out of range" in L.last_error()
+    st = lib.iqp_bitflip_expval(ctypes.byref(c), 4, None, FAKE, FAKE, big, None)
+    assert st == L.IQP_ERR_INVALID_ARG and "ops is NULL" in L.last_error()
+    st = lib.iqp_bitflip_expval(ctypes.byref(c), 4, FAKE, None, FAKE, big, None)
+    assert st == L.IQP_ERR_INVALID_ARG and "mean is NULL" in L.last_error()
+    st = lib.iqp_bitflip_expval(ctypes.byref(c), 4, FAKE, FAKE, FAKE, 8, None)
+    assert st == L.IQP_ERR_WORKSPACE
+    st = lib.iqp_bitflip_expval_grad(ctypes.byref(c), 4, FAKE, None, FAKE, FAKE, big, None)
+    assert st == L.IQP_ERR_INVALID_ARG and "grad_mean" in L.last_error()
+    st = lib.iqp_bitflip_expval_grad(ctypes.byref(c), 4, FAKE, FAKE, None, FAKE, big, None)
+    assert st == L.IQP_ERR_INVALID_ARG and "grad_theta" in L.last_error()
 
 
 def _problems(shapes):

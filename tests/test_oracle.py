@@ -2,7 +2,7 @@
 
 Each test compares the oracle's Monte Carlo estimator, gradient or MMD^2 with
 a result computed another way: closed forms from the proof of Prop. 3, a
-state-vector simulation (Def. 2 and the gate action of Sec. 2.4), brute force
+state-vector simulation (Def. 2 and the gate action of Sec. 2.5), brute force
 over pairs, library matrix products, or statistics the paper states.
 """
 import math
