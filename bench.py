@@ -30,7 +30,7 @@ import numpy as np
 
 METRIC = "phase terms/s (ops×samples×gates), fwd & fwd+bwd, split-BF16 vs FP32 at tol"
 PEAK = {"split_bf16": (2.5e15, 4.0), "fp32": (157.3e12, 2.0)}  # (peak flop/s, MFMA flop/term)
-TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4, "sparse_fp32": 1e-5}
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -105,6 +105,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-bitflip", action="store_true")
+    ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched workload: keep the default tiles instead of autotuning")
     ap.add_argument("--cpu-sample-ops", type=int, default=0,
@@ -219,11 +220,28 @@ def main():
                           "fwd_ms": ms32f,
                           "mfma_frac_fwd": 2.0 * T / (ms32f * 1e-3) / PEAK["fp32"][0]}
 
-    # --- parity of the timed configuration against the oracle ---------------
+    # --- sparse-C form (FP32 on the vector units, non-zero entries of C only) -
     import oracle
     pick = np.random.default_rng(11).choice(w.l, size=min(8, w.l), replace=False)
+    if not args.no_sparse:
+        ms_sp = timed("sparse_fp32", steps=max(3, args.steps // 2), warmup=2)
+        ms_spf = timed("sparse_fp32", fwd_only=True, steps=max(3, args.steps // 2), warmup=1)
+        dens_pick = np.random.default_rng(12).choice(w.l, size=min(64, w.l), replace=False)
+        density = float(oracle.parity(w.n, dw.ops01[dens_pick], w.gates).mean())
+        log("sparse_fp32: fwd+bwd %.3f ms, fwd %.3f ms (C density %.4f)" % (ms_sp, ms_spf,
+                                                                           density))
+        result["sparse_fp32"] = {"fwd_bwd_terms_per_s": T / (ms_sp * 1e-3),
+                                 "fwd_terms_per_s": T / (ms_spf * 1e-3), "ms_per_step": ms_sp,
+                                 "fwd_ms": ms_spf, "c_density": density,
+                                 "nnz_terms_per_s_fwd": density * T / (ms_spf * 1e-3),
+                                 "terms": "dense-equivalent l*s*m; C density sampled on "
+                                          "%d observables" % dens_pick.size}
+
+    # --- parity of the timed configuration against the oracle ---------------
     parity = {}
-    for prec in (("split_bf16",) if args.no_fp32 else ("split_bf16", "fp32")):
+    precs = ["split_bf16"] + ([] if args.no_fp32 else ["fp32"]) + \
+        ([] if args.no_sparse else ["sparse_fp32"])
+    for prec in precs:
         if mmd:
             break
         mean, se = step(prec, fwd_only=True)

@@ -50,15 +50,22 @@ typedef enum {
 } iqp_status;
 
 /* Arithmetic of the phase contraction E = C Theta B^T.
- *   IQP_FP32:       2 theta_j in FP32, one FP32 matrix-core product per term.
- *   IQP_SPLIT_BF16: 2 theta_j = hi + lo with hi, lo BF16 (round to nearest
- *                   even), two BF16 matrix-core products per term (the +-1
- *                   and 0/1 parity operands are exact in BF16), FP32
- *                   accumulation.
+ *   IQP_FP32:        2 theta_j in FP32, one FP32 matrix-core product per term.
+ *   IQP_SPLIT_BF16:  2 theta_j = hi + lo with hi, lo BF16 (round to nearest
+ *                    even), two BF16 matrix-core products per term (the +-1
+ *                    and 0/1 parity operands are exact in BF16), FP32
+ *                    accumulation.
+ *   IQP_SPARSE_FP32: only the non-zero entries of C: for each observable the
+ *                    sum of +-2 theta_j over the generators that anticommute
+ *                    with it (FP32 on the vector units), so the work is the
+ *                    number of non-zero entries of C times s instead of
+ *                    l m s; faster when C is sparse (a few percent of
+ *                    entries). The gradient sums per-gate contributions in
+ *                    int64 fixed point, bitwise reproducible.
  * In both, theta is first reduced to [-pi/2, pi/2] by whole multiples of pi
  * (exp(i(theta + pi) X) = -exp(i theta X) is a global phase, Sec. 2.1), and
  * every phase is reduced modulo 2 pi in FP64 before its cos / sin. */
-typedef enum { IQP_FP32 = 0, IQP_SPLIT_BF16 = 1 } iqp_precision;
+typedef enum { IQP_FP32 = 0, IQP_SPLIT_BF16 = 1, IQP_SPARSE_FP32 = 2 } iqp_precision;
 
 /* A parameterized IQP circuit (Def. 1): generators g_j as bit rows and their
  * parameters theta_j. */

@@ -6,13 +6,14 @@ include/iqp.h; this package only marshals arguments to it.
 """
 from . import packing
 from ._lib import IqpError
-from .api import (FP32, ROW_MAJOR, SPLIT_BF16, TILED32, TILED32_T, BatchPlan, Circuit,
+from .api import (FP32, ROW_MAJOR, SPARSE_FP32, SPLIT_BF16, TILED32, TILED32_T, BatchPlan,
+                  Circuit,
                   iqp_bitflip_expval, iqp_bitflip_expval_grad, iqp_expval, iqp_expval_grad,
                   iqp_mmd_loss_grad, iqp_parity, profile_enable, profile_query, profile_reset,
                   workspace_bytes)
 from .autograd import IQPBitflipExpval, IQPExpval, IQPMMDLoss
 
-__all__ = ["packing", "IqpError", "FP32", "SPLIT_BF16", "ROW_MAJOR", "TILED32", "TILED32_T", "BatchPlan",
+__all__ = ["packing", "IqpError", "FP32", "SPLIT_BF16", "SPARSE_FP32", "ROW_MAJOR", "TILED32", "TILED32_T", "BatchPlan",
            "Circuit", "iqp_bitflip_expval", "iqp_bitflip_expval_grad",
            "iqp_expval", "iqp_expval_grad", "iqp_mmd_loss_grad", "iqp_parity",
            "profile_enable", "profile_query", "profile_reset", "workspace_bytes",

@@ -227,6 +227,26 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
     P.o_xz = carve(cur, (size_t)(64 * P.W + 1) * P.ldz * 8);
     P.o_xa = carve(cur, (size_t)(64 * P.W + 1) * P.lda * 8);
     P.o_sup = carve(cur, (size_t)P.m_pad * kSupCap * 4);
+    if (prec == IQP_SPARSE_FP32) {
+        // C row-major (observable rows) and B^T row-major (generator rows),
+        // read by both passes
+        P.o_cbits = carve(cur, (size_t)l * P.mw * 8);
+        P.o_btbits = carve(cur, (size_t)P.m_pad * (P.s_pad / 64) * 8);
+        if (P.fwd) {
+            P.o_t32 = carve(cur, (size_t)P.m_pad * 4);
+            P.o_part = carve(cur, (size_t)l * P.nchunk * 2 * 8);
+            P.o_rowsum = carve(cur, (size_t)l * 2 * 8);
+        }
+        if (P.phi) P.o_phi = carve(cur, (size_t)l * s * 4);
+        if (P.bwd) {
+            P.o_coef = carve(cur, (size_t)l * 2 * 8);
+            P.o_acc = carve(cur, (size_t)(P.m_pad + 1) * 8);  // int64 sums and a flag
+            P.o_scale = carve(cur, 8);
+        }
+        if (P.mmd) P.o_pstat = carve(cur, (size_t)l * 2 * 8);
+        P.total = cur;
+        return;
+    }
     if (P.fwd) {
         P.o_bbits = carve(cur, (size_t)P.s_pad * P.mw * 8);
         if (prec == IQP_SPLIT_BF16) {
@@ -319,8 +339,9 @@ static int check_common(const iqp_circuit *c, int64_t l, const uint64_t *ops, in
     if (s < 1 || s > kMaxRows) return fail(IQP_ERR_INVALID_ARG, "s out of range [1, 2^24]");
     if (!ops) return fail(IQP_ERR_INVALID_ARG, "ops is NULL");
     if (!samples) return fail(IQP_ERR_INVALID_ARG, "samples is NULL");
-    if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16)
-        return fail(IQP_ERR_INVALID_ARG, "precision must be IQP_FP32 or IQP_SPLIT_BF16");
+    if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16 && precision != IQP_SPARSE_FP32)
+        return fail(IQP_ERR_INVALID_ARG,
+                    "precision must be IQP_FP32, IQP_SPLIT_BF16 or IQP_SPARSE_FP32");
     return IQP_OK;
 }
 
@@ -333,9 +354,41 @@ static int check_ws(const Plan &P, void *ws, size_t ws_bytes) {
 }
 
 
+// Sparse form: the row-major C and B^T parities its kernels walk.
+static int run_sparse_parities(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
+                               const uint64_t *samples, void *ws, const LaunchCtx &lc) {
+    IQP_TRY(launch_support(lc, support_args(P, c->gens, ws)), "support");
+    IQP_TRY(launch_bitslice(lc, bitslice_ops_args(P, ops, ws)), "bitslice(A)");
+    IQP_TRY(launch_parity_bs(lc, IQP_BITS_ROW_MAJOR,
+                             ParityArgs{c->gens, at<int32_t>(ws, P.o_sup), P.m, (int)P.W,
+                                        at<uint64_t>(ws, P.o_xa), P.l_pad / 64, P.lda, P.l, P.mw,
+                                        at<uint64_t>(ws, P.o_cbits)}),
+            "parity(C, row-major)");
+    IQP_TRY(launch_bitslice(lc, bitslice_samples_args(P, samples, ws)), "bitslice(Z)");
+    IQP_TRY(launch_parity_bs(lc, 3,
+                             ParityArgs{c->gens, at<int32_t>(ws, P.o_sup), P.m, (int)P.W,
+                                        at<uint64_t>(ws, P.o_xz), P.s_pad / 64, P.ldz, 0, P.mw,
+                                        at<uint64_t>(ws, P.o_btbits)}),
+            "parity(B^T, row-major)");
+    return IQP_OK;
+}
+
 static int run_forward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
                        const uint64_t *samples, void *ws, const LaunchCtx &lc, float *phase_out,
                        double *mean, double *se, double *rowsum) {
+    if (P.prec == IQP_SPARSE_FP32) {
+        IQP_TRY(launch_theta_prep(lc, theta_args(P, c->theta, ws)), "theta_prep");
+        int st = run_sparse_parities(P, c, ops, samples, ws, lc);
+        if (st) return st;
+        IQP_TRY(launch_sparse_fwd(lc, SparseFwdArgs{at<uint64_t>(ws, P.o_cbits), P.mw,
+                                                    at<float>(ws, P.o_t32),
+                                                    at<uint64_t>(ws, P.o_btbits), P.s_pad / 64,
+                                                    P.l, P.s, phase_out,
+                                                    at<double>(ws, P.o_part)}),
+                "sparse_fwd");
+        IQP_TRY(launch_finalize(lc, fin_args(P, ws, mean, se, rowsum)), "finalize");
+        return IQP_OK;
+    }
     IQP_TRY(launch_theta_prep(lc, theta_args(P, c->theta, ws)), "theta_prep");
     IQP_TRY(launch_support(lc, support_args(P, c->gens, ws)), "support");
     IQP_TRY(launch_bitslice(lc, bitslice_ops_args(P, ops, ws)), "bitslice(A)");
@@ -355,6 +408,25 @@ static int run_forward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
 static int run_backward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
                         const uint64_t *samples, const float *phase, bool bitcols_ready, void *ws,
                         const LaunchCtx &lc, double *grad_theta) {
+    if (P.prec == IQP_SPARSE_FP32) {
+        long long *acc = at<long long>(ws, P.o_acc);
+        double *scale = at<double>(ws, P.o_scale);
+        IQP_TRY(launch_sparse_bound(lc, SparseBoundArgs{at<double>(ws, P.o_coef), P.l, P.s,
+                                                        P.m_pad, acc, scale}),
+                "sparse_bound");
+        if (!bitcols_ready) {
+            int st = run_sparse_parities(P, c, ops, samples, ws, lc);
+            if (st) return st;
+        }
+        IQP_TRY(launch_sparse_bwd(lc, SparseBwdArgs{at<uint64_t>(ws, P.o_cbits), P.mw,
+                                                    at<uint64_t>(ws, P.o_btbits), P.s_pad / 64,
+                                                    P.l, P.s, P.m_pad, phase,
+                                                    at<double>(ws, P.o_coef), scale, acc}),
+                "sparse_bwd");
+        IQP_TRY(launch_sparse_finish(lc, SparseFinishArgs{acc, scale, P.m, P.m_pad, grad_theta}),
+                "sparse_finish");
+        return IQP_OK;
+    }
     IQP_TRY(launch_weights(lc, weights_args(P, phase, ws)), "weights");
     if (!bitcols_ready) {
         IQP_TRY(launch_support(lc, support_args(P, c->gens, ws)), "support");
@@ -395,7 +467,8 @@ size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s,
     }
     if (s < 1) return 0;
     if (call < IQP_CALL_EXPVAL || call > IQP_CALL_MMD_GRAD) return 0;
-    if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16) return 0;
+    if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16 && precision != IQP_SPARSE_FP32)
+        return 0;
     if ((call == IQP_CALL_MMD || call == IQP_CALL_MMD_GRAD) && N < 1) return 0;
     Plan P;
     make_call_plan(P, call, c->n_qubits, c->n_gates, l, s, N, precision);

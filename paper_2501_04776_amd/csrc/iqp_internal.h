@@ -196,6 +196,56 @@ struct BitflipGradArgs {
 };
 inline int64_t blocks_of(const BitflipGradArgs &a) { return ceil_div(a.m, 256); }
 
+// Sparse-C contraction (FP32 on the vector units): the phases summed over
+// each observable's anticommuting generators only.
+//   crm   C row-major: Gw gate words per observable row
+//   btrm  B^T row-major: Rwb sample words per generator row
+//   t32   2 theta' per generator (plain FP32)
+struct SparseFwdArgs {
+    const uint64_t *crm;
+    int64_t Gw;
+    const float *t32;
+    const uint64_t *btrm;
+    int64_t Rwb, l, s;
+    float *phase_out;  // [l][s] or NULL
+    double *part;      // [l][ceil(s / kEpiChunk)][2] as the dense epilogue writes it
+};
+inline int64_t blocks_of(const SparseFwdArgs &a) {
+    return ceil_div(a.l * ceil_div(a.s, kEpiChunk), 4);
+}
+
+// acc[m_pad + 1] int64 (the last slot flags a non-finite contribution) and
+// *scale: the fixed-point scale of the gradient sums, from the bound
+// sum_k s (|alpha_k| + |beta_k|) on every partial sum.
+struct SparseBoundArgs {
+    const double *coef;
+    int64_t l, s, m_pad;
+    long long *acc;
+    double *scale;
+};
+inline int64_t blocks_of(const SparseBoundArgs &a) { return ceil_div(a.m_pad + 1, 256); }
+
+struct SparseBwdArgs {
+    const uint64_t *crm;
+    int64_t Gw;
+    const uint64_t *btrm;
+    int64_t Rwb, l, s, m_pad;  // j < m_pad; acc[m_pad] is the non-finite flag
+    const float *phase;
+    const double *coef, *scale;
+    long long *acc;
+};
+inline int64_t blocks_of(const SparseBwdArgs &a) {
+    return ceil_div(a.l * ceil_div(a.s, kEpiChunk), 4);
+}
+
+struct SparseFinishArgs {
+    const long long *acc;
+    const double *scale;
+    int64_t m, m_pad;
+    double *grad;
+};
+inline int64_t blocks_of(const SparseFinishArgs &a) { return ceil_div(a.m, 256); }
+
 // ---- launchers (iqp_kernels.hip); each returns hipGetLastError() ----
 hipError_t launch_theta_prep(const LaunchCtx &lc, const ThetaArgs &a);
 hipError_t launch_bitslice(const LaunchCtx &lc, const BitsliceArgs &a);
@@ -208,6 +258,10 @@ hipError_t launch_coef_plain(const LaunchCtx &lc, const CoefArgs &a);
 hipError_t launch_weights(const LaunchCtx &lc, const WeightsArgs &a);
 hipError_t launch_phase_bwd(const LaunchCtx &lc, int prec, int fm, int fn, const BwdArgs &a);
 hipError_t launch_grad_reduce(const LaunchCtx &lc, const GradArgs &a);
+hipError_t launch_sparse_fwd(const LaunchCtx &lc, const SparseFwdArgs &a);
+hipError_t launch_sparse_bound(const LaunchCtx &lc, const SparseBoundArgs &a);
+hipError_t launch_sparse_bwd(const LaunchCtx &lc, const SparseBwdArgs &a);
+hipError_t launch_sparse_finish(const LaunchCtx &lc, const SparseFinishArgs &a);
 hipError_t launch_bitflip_prep(const LaunchCtx &lc, const BitflipPrepArgs &a);
 hipError_t launch_bitflip_fwd(const LaunchCtx &lc, const BitflipFwdArgs &a);
 hipError_t launch_bitflip_grad(const LaunchCtx &lc, const BitflipGradArgs &a);

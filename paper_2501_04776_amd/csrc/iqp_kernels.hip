@@ -163,7 +163,9 @@ __device__ __forceinline__ void theta_prep_body(const ThetaArgs &a, int64_t blk)
     const double t = i < a.m ? gptr(a.theta)[i] : 0.0;
     const double tr = t - IQP_PI * rint(t * IQP_INV_PI);
     const double two = 2.0 * tr;
-    if (a.prec == 1) {
+    if (a.prec == 2) {
+        gptr(a.t32)[i] = (float)two;  // plain, for the sparse contraction
+    } else if (a.prec == 1) {
         const uint16_t h = f2bf_rne((float)two);
         const double rem = two - (double)bf2f(h);
         gptr(a.hi)[i] = h;
@@ -289,8 +291,9 @@ __device__ __forceinline__ void transpose64_regs(uint64_t (&x)[64]) {
 //   LAYOUT 1: tiled32      out[((r/32) * Gw + j/64) * 32 + r%32], bit j%64
 //   LAYOUT 2: transposed tiled32 (rows = generators)
 //             out[((j/32) * Rw + r/64) * 32 + j%32], bit r%64
-// Layouts 0 and 1 transpose the lane's 64 x 64 block in registers; layout 2
-// stores the XOR words as they are. Generators j >= m give zero bits.
+//   LAYOUT 3: transposed row-major (rows = generators) out[j * Rw + r/64], bit r%64
+// Layouts 0 and 1 transpose the lane's 64 x 64 block in registers; layouts 2
+// and 3 store the XOR words as they are. Generators j >= m give zero bits.
 template <int LAYOUT>
 __device__ __forceinline__ void parity_bs_body(const ParityArgs &a, int64_t blk) {
     const uint64_t IQP_GLOBAL *__restrict__ Xt = gptr(a.Xt);
@@ -345,7 +348,10 @@ __device__ __forceinline__ void parity_bs_body(const ParityArgs &a, int64_t blk)
         }
     }
     if (!live) return;
-    if (LAYOUT == 2) {
+    if (LAYOUT == 3) {
+#pragma unroll
+        for (int g = 0; g < 64; ++g) out[(gb * 64 + g) * Rw + rw] = x[g];
+    } else if (LAYOUT == 2) {
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
             uint64_t IQP_GLOBAL *dst = out + ((gb * 2 + hh) * Rw + rw) * 32;
@@ -386,6 +392,7 @@ hipError_t launch_parity_bs(const LaunchCtx &lc, int layout, const ParityArgs &a
     if (layout == 0) return plain_launch<ParityArgs, parity_bs_body<0>>(lc, KF_PARITY, a, nb);
     if (layout == 1) return plain_launch<ParityArgs, parity_bs_body<1>>(lc, KF_PARITY, a, nb);
     if (layout == 2) return plain_launch<ParityArgs, parity_bs_body<2>>(lc, KF_PARITY, a, nb);
+    if (layout == 3) return plain_launch<ParityArgs, parity_bs_body<3>>(lc, KF_PARITY, a, nb);
     return hipErrorInvalidValue;
 }
 
@@ -1751,6 +1758,176 @@ __device__ __forceinline__ void bitflip_grad_body(const BitflipGradArgs &a, int6
 
 hipError_t launch_bitflip_grad(const LaunchCtx &lc, const BitflipGradArgs &a) {
     return plain_launch<BitflipGradArgs, bitflip_grad_body>(lc, KF_BWD, a, blocks_of(a));
+}
+
+// ---------------------------------------------------------------------------
+// Sparse-C contraction: E_ki = sum_{j in J_k} t_j (-1)^{b_ij}, t_j = 2 theta'_j,
+// over the generators J_k that anticommute with observable k (the set bits of
+// row k of C), on the vector units in FP32 — the dense contraction's result
+// with |J_k| / m of its work. One wave per (observable k, chunk of kEpiChunk
+// samples); lane L holds samples 16 L .. 16 L + 15 of the chunk (bits
+// 16 (L % 4) + b of sample word 16 chunk + L / 4). The row of C is walked
+// with scalar loads in gate order; for each set bit the lane loads one word of
+// that generator's sample bits and adds t_j where a bit is set:
+//   E_ki = T_k - 2 sum_{j in J_k, b_ij = 1} t_j,  T_k = sum_{j in J_k} t_j (FP64).
+constexpr int kSpSamples = kEpiChunk / 64;
+
+__device__ __forceinline__ float masked(float t, uint32_t f, int b) {
+    // t where bit b of f is set, else 0: a signed one-bit field is 0 or -1
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)f, (unsigned)b, 1u);
+    return __uint_as_float(__float_as_uint(t) & m);
+}
+
+__device__ __forceinline__ void sparse_fwd_body(const SparseFwdArgs &a, int64_t blk) {
+    const int64_t nchunk = ceil_div(a.s, kEpiChunk);
+    const int64_t unit = blk * 4 + wave_id();
+    if (unit >= a.l * nchunk) return;  // uniform over the wave
+    const int64_t k = unit / nchunk, ch = unit - k * nchunk;
+    const int lane = threadIdx.x & 63;
+    const int64_t sw = ch * (kEpiChunk / 64) + (lane >> 2);
+    const int sh = 16 * (lane & 3);
+    const uint64_t IQP_GLOBAL *bcol = gptr(a.btrm) + (sw < a.Rwb ? sw : 0);
+    const uint64_t IQP_GLOBAL *crow = gptr(a.crm) + k * a.Gw;
+    const float IQP_GLOBAL *t32 = gptr(a.t32);
+    float acc[kSpSamples];
+#pragma unroll
+    for (int b = 0; b < kSpSamples; ++b) acc[b] = 0.0f;
+    double T = 0.0;
+    for (int64_t w = 0; w < a.Gw; ++w) {
+        uint64_t cw = crow[w];
+        while (cw) {
+            const int64_t j = w * 64 + __builtin_ctzll(cw);
+            cw &= cw - 1;
+            const float t = t32[j];
+            const uint32_t f = (uint32_t)(bcol[j * a.Rwb] >> sh);
+            T += (double)t;
+#pragma unroll
+            for (int b = 0; b < kSpSamples; ++b) acc[b] += masked(t, f, b);
+        }
+    }
+    double sc = 0.0, sc2 = 0.0;
+    const int64_t i0 = ch * kEpiChunk + lane * kSpSamples;
+    float IQP_GLOBAL *ph = a.phase_out ? gptr(a.phase_out) + k * a.s : nullptr;
+#pragma unroll
+    for (int b = 0; b < kSpSamples; ++b) {
+        const int64_t i = i0 + b;
+        if (i < a.s) {
+            const double e = T - 2.0 * (double)acc[b];
+            const double kk = rint(e * IQP_INV_TWO_PI);
+            double rr = fma(-kk, IQP_TWO_PI_HI, e);
+            rr = fma(-kk, IQP_TWO_PI_LO, rr);
+            const float rf = (float)rr;
+            const float c = cosf(rf);
+            if (ph) ph[i] = rf;
+            sc += (double)c;
+            sc2 += (double)c * (double)c;
+        }
+    }
+#pragma unroll
+    for (int st = 32; st >= 1; st >>= 1) {
+        sc += __shfl_xor(sc, st, 64);
+        sc2 += __shfl_xor(sc2, st, 64);
+    }
+    if (lane == 0) {
+        double IQP_GLOBAL *part = gptr(a.part) + (k * nchunk + ch) * 2;
+        part[0] = sc;
+        part[1] = sc2;
+    }
+}
+
+hipError_t launch_sparse_fwd(const LaunchCtx &lc, const SparseFwdArgs &a) {
+    return plain_launch<SparseFwdArgs, sparse_fwd_body>(lc, KF_FWD, a, blocks_of(a));
+}
+
+// Gradient of the sparse form: for every (k, j in J_k) the partial
+// T_kj = sum_i S_ki (-1)^{b_ij} of a sample chunk is summed across the wave
+// and added into an int64 fixed-point accumulator of gate j. Integer addition
+// is associative, so the result does not depend on the order in which the
+// waves add, and no per-pair storage is needed. The scale keeps every sum
+// below 2^62: |T_kj| <= s (|alpha_k| + |beta_k|) summed over k.
+__device__ __forceinline__ void sparse_bound_body(const SparseBoundArgs &a, int64_t blk) {
+    const int64_t j = blk * 256 + threadIdx.x;
+    if (j <= a.m_pad) gptr(a.acc)[j] = 0;
+    if (blk != 0) return;
+    __shared__ double sh[256];
+    double g = 0.0;
+    for (int64_t k = threadIdx.x; k < a.l; k += 256)
+        g += (double)a.s * (fabs(gptr(a.coef)[2 * k]) + fabs(gptr(a.coef)[2 * k + 1]));
+    g = block_sum_256(g, sh);
+    if (threadIdx.x == 0) {
+        const double G = (g > 0.0 && isfinite(g)) ? g : 1.0;
+        gptr(a.scale)[0] = ldexp(1.0, 61 - ilogb(G));
+    }
+}
+
+hipError_t launch_sparse_bound(const LaunchCtx &lc, const SparseBoundArgs &a) {
+    return plain_launch<SparseBoundArgs, sparse_bound_body>(lc, KF_WEIGHTS, a, blocks_of(a));
+}
+
+__device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t blk) {
+    const int64_t nchunk = ceil_div(a.s, kEpiChunk);
+    const int64_t unit = blk * 4 + wave_id();
+    if (unit >= a.l * nchunk) return;  // uniform over the wave
+    const int64_t k = unit / nchunk, ch = unit - k * nchunk;
+    const int lane = threadIdx.x & 63;
+    const int64_t sw = ch * (kEpiChunk / 64) + (lane >> 2);
+    const int sh = 16 * (lane & 3);
+    const uint64_t IQP_GLOBAL *bcol = gptr(a.btrm) + (sw < a.Rwb ? sw : 0);
+    const uint64_t IQP_GLOBAL *crow = gptr(a.crm) + k * a.Gw;
+    const double al = gptr(a.coef)[2 * k], be = gptr(a.coef)[2 * k + 1];
+    const double scale = gptr(a.scale)[0];
+    // S_ki = (alpha_k + beta_k cos E_ki) sin E_ki for the lane's samples
+    float S[kSpSamples];
+    float Ssum = 0.0f;
+    const int64_t i0 = ch * kEpiChunk + lane * kSpSamples;
+#pragma unroll
+    for (int b = 0; b < kSpSamples; ++b) {
+        const int64_t i = i0 + b;
+        float v = 0.0f;
+        if (i < a.s) {
+            float sn, cs;
+            sincosf(gptr(a.phase)[k * a.s + i], &sn, &cs);
+            v = (float)((al + be * (double)cs) * (double)sn);
+        }
+        S[b] = v;
+        Ssum += v;
+    }
+    for (int64_t w = 0; w < a.Gw; ++w) {
+        uint64_t cw = crow[w];
+        while (cw) {
+            const int64_t j = w * 64 + __builtin_ctzll(cw);
+            cw &= cw - 1;
+            const uint32_t f = (uint32_t)(bcol[j * a.Rwb] >> sh);
+            float p = 0.0f;
+#pragma unroll
+            for (int b = 0; b < kSpSamples; ++b) p += masked(S[b], f, b);
+            p = Ssum - 2.0f * p;
+#pragma unroll
+            for (int st = 32; st >= 1; st >>= 1) p += __shfl_xor(p, st, 64);
+            if (lane == 0) {
+                if (isfinite(p))
+                    atomicAdd((unsigned long long *)&gptr(a.acc)[j],
+                              (unsigned long long)llrint((double)p * scale));
+                else
+                    atomicOr((unsigned long long *)&gptr(a.acc)[a.m_pad], 1ull);
+            }
+        }
+    }
+}
+
+hipError_t launch_sparse_bwd(const LaunchCtx &lc, const SparseBwdArgs &a) {
+    return plain_launch<SparseBwdArgs, sparse_bwd_body>(lc, KF_BWD, a, blocks_of(a));
+}
+
+__device__ __forceinline__ void sparse_finish_body(const SparseFinishArgs &a, int64_t blk) {
+    const int64_t j = blk * 256 + threadIdx.x;
+    if (j >= a.m) return;
+    const bool bad = gptr(a.acc)[a.m_pad] != 0;
+    gptr(a.grad)[j] = bad ? (double)NAN : -2.0 * (double)gptr(a.acc)[j] / gptr(a.scale)[0];
+}
+
+hipError_t launch_sparse_finish(const LaunchCtx &lc, const SparseFinishArgs &a) {
+    return plain_launch<SparseFinishArgs, sparse_finish_body>(lc, KF_GRAD, a, blocks_of(a));
 }
 
 }  // namespace iqp

@@ -51,6 +51,7 @@ struct Plan {
     size_t o_btbits = 0;                  // B^T: samples against generators, transposed
     size_t o_sup = 0;                     // support lists of the generators
     size_t o_enc = 0, o_stat = 0;         // bitflip circuits: factors, per-observable sums
+    size_t o_acc = 0, o_scale = 0;        // sparse gradient: int64 sums (+ flag), scale
     int64_t ldz = 0, lda = 0;
     size_t total = 0;
 };

@@ -7,7 +7,7 @@ import workloads as W
 from paper_2501_04776_amd import packing
 
 # Absolute tolerances on floating results (means, standard errors, losses).
-TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4, "sparse_fp32": 1e-5}
 
 
 def dev_rows_from_index(rows, n):

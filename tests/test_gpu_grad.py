@@ -12,7 +12,7 @@ from tests.gpu_util import TOL, DevWorkload
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp32", "split_bf16"]
+PRECS = ["fp32", "split_bf16", "sparse_fp32"]
 
 
 def _grad(dw, u, prec, saved):
