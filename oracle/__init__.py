@@ -11,6 +11,7 @@ samples and training data as dense 0/1 uint8 matrices.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -39,6 +40,7 @@ def lib():
             build(force=True)
         L = ctypes.CDLL(_LIB)
         i64, i32, dp, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p
+        u64 = ctypes.c_uint64
         sigs = {
             "orc_num_threads": ([], i32),
             "orc_parity": ([i64, i64, vp, i64, vp, vp, vp], i32),
@@ -51,6 +53,9 @@ def lib():
             "orc_subset_expval": ([i64, i64, vp, vp, vp, i64, vp, vp], i32),
             "orc_bitflip_expval": ([i64, i64, vp, vp, vp, i64, vp, vp], i32),
             "orc_bitflip_grad": ([i64, i64, vp, vp, vp, i64, vp, vp, vp], i32),
+            "orc_philox4x64": ([vp, vp, vp], None),
+            "orc_sample_uniform": ([i64, i64, u64, u64, u64, u64, vp], i32),
+            "orc_sample_bernoulli": ([i64, i64, vp, u64, u64, u64, u64, vp], i32),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)
@@ -192,3 +197,113 @@ def bitflip_grad(n, gates, theta, ops01, grad_out):
     _check(lib().orc_bitflip_grad(n, gates.count, _p(gp), _p(gi), _p(theta), ops01.shape[0],
                                   _p(ops01), _p(u), _p(g)), "bitflip_grad")
     return g
+
+
+# ---------------------------------------------------------------------------
+# The training loop (Sec. 3.3 with the MMD^2 loss of Sec. 3.3.1): random
+# numbers, operators drawn from P_sigma, parameter sharing and fixed gates
+# (gates as tuples of generators, Sec. 3.1.1), and the optimizer update.
+
+def philox4x64(ctr, key):
+    """Philox4x64-10 of counter ctr[4] under key key[2] (Salmon et al. 2011)."""
+    c = _c(np.asarray(ctr, dtype=np.uint64), np.uint64)
+    k = _c(np.asarray(key, dtype=np.uint64), np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64(_p(c), _p(k), _p(out))
+    return out
+
+
+def sample_uniform(rows, n, seed, step, tag):
+    """uint8 [rows][n] uniform bits: qubit q of row r is bit q % 64 of output
+    r * ceil(n/64) + q / 64 of stream (seed, step, tag)."""
+    out = np.zeros((rows, n), dtype=np.uint8)
+    _check(lib().orc_sample_uniform(rows, n, int(seed[0]), int(seed[1]), int(step), int(tag),
+                                    _p(out)), "sample_uniform")
+    return out
+
+
+def bit_threshold(p):
+    """floor(p * 2^64) for a bit probability 0 <= p < 1 (exact: scaling by a
+    power of two and truncation)."""
+    if not (0.0 <= p < 1.0):
+        raise ValueError("bit probability must lie in [0, 1)")
+    return int(math.ldexp(float(p), 64))
+
+
+def sample_bernoulli(n, group_rows, group_prob, seed, step, tag):
+    """uint8 [sum(group_rows)][n]: qubit q of row r is 1 when output r * n + q
+    of stream (seed, step, tag) is below the threshold of r's group."""
+    thr = np.concatenate([np.full(int(r), bit_threshold(p), dtype=np.uint64)
+                          for r, p in zip(group_rows, group_prob)])
+    out = np.zeros((thr.size, n), dtype=np.uint8)
+    _check(lib().orc_sample_bernoulli(thr.size, n, _p(thr), int(seed[0]), int(seed[1]),
+                                      int(step), int(tag), _p(out)), "sample_bernoulli")
+    return out
+
+
+def gate_theta(param_index, params, fixed_theta):
+    """theta_j = params[param_index[j]], or fixed_theta[j] where the index is
+    -1 (a fixed gate): one parameter shared by all generators of a gate."""
+    idx = np.asarray(param_index)
+    theta = np.zeros(idx.size)
+    for j in range(idx.size):
+        theta[j] = params[idx[j]] if idx[j] >= 0 else fixed_theta[j]
+    return theta
+
+
+def param_grad(param_index, n_params, grad_theta):
+    """dL/dparam_p = sum of dL/dtheta_j over the generators j of parameter p
+    (chain rule through theta_j = params[param_index[j]])."""
+    g = np.zeros(n_params)
+    for j, p in enumerate(np.asarray(param_index)):
+        if p >= 0:
+            g[p] += grad_theta[j]
+    return g
+
+
+OPT_GD, OPT_ADAM = 0, 1
+
+
+def optimizer_update(opt, params, grad, m1, m2, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One update; t is the number of earlier updates. Gradient descent:
+    params - lr grad. Adam (Kingma and Ba 2015, Algorithm 1) with step count
+    t + 1: biased moments, their bias corrections, params - lr mhat /
+    (sqrt(vhat) + eps). Returns (params, m1, m2) as new arrays."""
+    params = np.array(params, dtype=np.float64)
+    grad = np.asarray(grad, dtype=np.float64)
+    m1 = np.array(m1, dtype=np.float64)
+    m2 = np.array(m2, dtype=np.float64)
+    if opt == OPT_GD:
+        return params - lr * grad, m1, m2
+    k = t + 1
+    m1 = beta1 * m1 + (1.0 - beta1) * grad
+    m2 = beta2 * m2 + (1.0 - beta2) * grad * grad
+    mhat = m1 / (1.0 - beta1 ** k)
+    vhat = m2 / (1.0 - beta2 ** k)
+    return params - lr * mhat / (np.sqrt(vhat) + eps), m1, m2
+
+
+def op_weights(group_rows):
+    """Each bandwidth group's weights sum to 1 / (number of groups)."""
+    G = len(group_rows)
+    return np.concatenate([np.full(int(r), 1.0 / (G * int(r))) for r in group_rows])
+
+
+TAG_SAMPLES, TAG_OPS = 0, 1
+
+
+def train_step(n, gates, param_index, fixed_theta, params, group_rows, group_prob, s, data01,
+               seed, step, opt, m1, m2, lr, beta1=0.9, beta2=0.999, eps=1e-8, unbiased=True):
+    """One training step at step count `step`: fresh samples and operators
+    from the two streams, the MMD^2 loss and gradient at the current
+    parameters, then the optimizer update. Returns a dict with loss, grad
+    (per parameter), params, m1, m2, samples, ops."""
+    z = sample_uniform(s, n, seed, step, TAG_SAMPLES)
+    ops = sample_bernoulli(n, group_rows, group_prob, seed, step, TAG_OPS)
+    theta = gate_theta(param_index, params, fixed_theta)
+    loss, gt = mmd_loss_grad(n, gates, theta, ops, op_weights(group_rows), z, data01,
+                             unbiased=unbiased)
+    gp = param_grad(param_index, len(params), gt)
+    new, m1, m2 = optimizer_update(opt, params, gp, m1, m2, step, lr, beta1, beta2, eps)
+    return {"loss": loss, "grad": gp, "params": new, "m1": m1, "m2": m2, "samples": z,
+            "ops": ops}

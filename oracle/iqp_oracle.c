@@ -5,7 +5,8 @@
  * estimator of Pauli-Z expectation values of parameterized IQP circuits
  * (arXiv 2501.04776), its gradient and the MMD^2 loss built on it, plus exact
  * values used only as pins (state-vector simulation, the subset expansion of
- * Prop. 3's proof, the product form). Only the test suite, the smoke check and
+ * Prop. 3's proof, the product form), and the random streams of the training
+ * loop (Philox4x64-10 and the bit samplers built on it). Only the test suite, the smoke check and
  * the benchmark's CPU-baseline leg may load this library; the product path
  * never links or calls it, and it shares no code with the HIP path.
  *
@@ -511,5 +512,79 @@ int orc_bitflip_grad(int64_t n, int64_t m, const int64_t *gptr, const int32_t *g
         }
     }
     free(J);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Random numbers for the training loop: Philox4x64-10, the counter-based
+ * generator of Salmon, Moraes, Dror and Shaw ("Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011), written from that definition. Ten rounds; each
+ * round multiplies counter words 0 and 2 by two fixed odd constants into
+ * 128-bit products, and the key is bumped by two Weyl constants between
+ * rounds.
+ */
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B97F4A7C15ull;
+            k1 += 0xBB67AE8584CAA73Bull;
+        }
+        const unsigned __int128 p0 = (unsigned __int128)0xD2E7470EE14C6C93ull * c0;
+        const unsigned __int128 p1 = (unsigned __int128)0xCA5A826395121157ull * c2;
+        const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* Output o of stream `tag` at training step `step`: word o % 4 of
+ * Philox(counter (o / 4, step, tag, 0), key (seed0, seed1)). */
+static uint64_t stream_word(uint64_t seed0, uint64_t seed1, uint64_t step, uint64_t tag,
+                            uint64_t o)
+{
+    const uint64_t ctr[4] = {o / 4, step, tag, 0};
+    const uint64_t key[2] = {seed0, seed1};
+    uint64_t out[4];
+    orc_philox4x64(ctr, key, out);
+    return out[o % 4];
+}
+
+/* Uniform bit strings (the samples z of eq. expvalsample, Prop. 1): qubit q
+ * of row r is bit q % 64 of output r * ceil(n / 64) + q / 64. */
+int orc_sample_uniform(int64_t rows, int64_t n, uint64_t seed0, uint64_t seed1, uint64_t step,
+                       uint64_t tag, uint8_t *out01)
+{
+    if (rows < 0 || n < 1 || !out01) return ORC_ERR_ARG;
+    const int64_t W = (n + 63) / 64;
+    for (int64_t r = 0; r < rows; ++r)
+        for (int64_t q = 0; q < n; ++q) {
+            const uint64_t word = stream_word(seed0, seed1, step, tag, (uint64_t)(r * W + q / 64));
+            out01[r * n + q] = (uint8_t)((word >> (q % 64)) & 1u);
+        }
+    return ORC_OK;
+}
+
+/* Independent Bernoulli bits (operators drawn from P_sigma, Sec. 3.3.1):
+ * qubit q of row r is 1 when output r * n + q is below the row's threshold
+ * (floor(p * 2^64) for bit probability p). */
+int orc_sample_bernoulli(int64_t rows, int64_t n, const uint64_t *row_threshold, uint64_t seed0,
+                         uint64_t seed1, uint64_t step, uint64_t tag, uint8_t *out01)
+{
+    if (rows < 0 || n < 1 || !row_threshold || !out01) return ORC_ERR_ARG;
+    for (int64_t r = 0; r < rows; ++r)
+        for (int64_t q = 0; q < n; ++q) {
+            const uint64_t v = stream_word(seed0, seed1, step, tag, (uint64_t)(r * n + q));
+            out01[r * n + q] = (uint8_t)(v < row_threshold[r]);
+        }
     return ORC_OK;
 }
