@@ -269,6 +269,130 @@ int iqp_batch_tune(iqp_batch_plan *plan, const iqp_problem *probs, int passes, v
 int iqp_batch_get_config(const iqp_batch_plan *plan, int32_t *cfg6);
 int iqp_batch_set_config(iqp_batch_plan *plan, const int32_t *cfg5);
 
+/* ---------------------------------------------------------------------------
+ * Training on the device: the optimisation loop of Sec. 3.3 run with the MMD^2
+ * loss of Sec. 3.3.1, where every step draws fresh samples z and fresh
+ * operators a ~ P_sigma, evaluates the loss and its gradient at the current
+ * parameters, and updates them. The pieces are separate calls; a training
+ * plan chains them into one HIP graph per step.
+ *
+ * Random numbers: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel
+ * random numbers: as easy as 1, 2, 3", SC 2011) under the key (seed0, seed1).
+ * Output o of stream `tag` at step t is word o % 4 of the block at counter
+ * (o / 4, t, tag, 0). The step t is read from device memory when the kernel
+ * runs, so a replayed graph draws new numbers after each update of t. The
+ * same key, step and tag give the same bits on every call.
+ */
+
+/* Uniform bit strings (the samples z of eq. expvalsample, Prop. 1):
+ *   out   device [rows][W], W = ceil(n_qubits / 64); word w of row r is
+ *         output r * W + w, with the bits past n_qubits cleared
+ *   step  device [1] int64 (read only)
+ * rows >= 0 (0: nothing to do), 1 <= n_qubits <= 2^20. */
+int iqp_sample_uniform(int64_t rows, int32_t n_qubits, uint64_t seed0, uint64_t seed1,
+                       const int64_t *step, uint64_t tag, uint64_t *out, void *stream);
+
+/* Independent Bernoulli bits in row groups (operators drawn from P_sigma,
+ * whose bit probability is (1 - exp(-1 / (2 sigma^2))) / 2 for a Gaussian
+ * kernel of bandwidth sigma, Sec. 3.3.1):
+ *   group_rows  host [n_groups] rows of each group (>= 0), in row order
+ *   group_prob  host [n_groups] bit probability p of each group, 0 <= p < 1
+ *   out         device [sum group_rows][W]; qubit q of row r is 1 when output
+ *               r * n_qubits + q is below floor(p * 2^64) of r's group
+ * 1 <= n_groups <= 16. */
+int iqp_sample_bernoulli(int32_t n_qubits, int32_t n_groups, const int64_t *group_rows,
+                         const double *group_prob, uint64_t seed0, uint64_t seed1,
+                         const int64_t *step, uint64_t tag, uint64_t *out, void *stream);
+
+/* Parameter sharing and fixed gates (gates given as tuples of generators
+ * share one parameter; initial gates keep fixed angles, Sec. 3.1.1):
+ *   theta[j] = params[param_index[j]], or fixed_theta[j] when
+ *   param_index[j] == -1.
+ *   param_index  device [n_gates] int32, each in [-1, n_params) (not checked
+ *                on the device: the training plan checks its host copy)
+ *   fixed_theta  device [n_gates] or NULL when no index is -1 */
+int iqp_gather_theta(int64_t n_gates, const int32_t *param_index, const double *params,
+                     const double *fixed_theta, double *theta, void *stream);
+
+/* Gradient of the parameters from that of the gates (chain rule of the
+ * gather above): grad_params[p] = sum of grad_theta[j] over the gates of p,
+ * added in the order listed, in FP64.
+ *   param_offsets  device [n_params + 1] int64, offsets into param_gates
+ *   param_gates    device int32 gate indices grouped by parameter */
+int iqp_reduce_grad(int64_t n_params, const int64_t *param_offsets, const int32_t *param_gates,
+                    const double *grad_theta, double *grad_params, void *stream);
+
+/* optimizers */
+enum {
+    IQP_OPT_GD = 0,  /* params -= lr * grad */
+    IQP_OPT_ADAM = 1 /* Adam (Kingma and Ba 2015): moments m1, m2 and bias
+                        correction with step count t + 1 */
+};
+
+/* One optimizer update of n_params parameters in place, in FP64, followed by
+ * step += 1 (step is device [1] int64: the number of earlier updates).
+ * m1, m2 device [n_params] moments (read and written by Adam; unused and may
+ * be NULL for gradient descent). lr > 0, 0 <= beta < 1, eps >= 0, finite. */
+int iqp_optimizer_update(int optimizer, int64_t n_params, double *params, const double *grad,
+                         double *m1, double *m2, int64_t *step, double lr, double beta1,
+                         double beta2, double eps, void *stream);
+
+/* A training plan: the circuit structure, the loss and the optimizer. */
+typedef struct {
+    int32_t n_qubits;
+    int32_t n_words;
+    int64_t n_gates;
+    const uint64_t *gens;        /* device [m][W] generators */
+    int64_t n_params;
+    const int32_t *param_index;  /* host [m]: parameter of gate j, or -1 (fixed gate) */
+    const double *fixed_theta;   /* device [m] angles of the fixed gates, or NULL */
+    int32_t n_groups;            /* operator groups (one per kernel bandwidth), 1..16 */
+    const int64_t *group_ops;    /* host [n_groups] operators per group per step */
+    const double *group_prob;    /* host [n_groups] bit probability of each group */
+    int64_t n_samples;           /* samples z per step */
+    int64_t n_data;
+    const uint64_t *data;        /* device [N][W] training bit strings */
+    int32_t unbiased;            /* MMD^2 estimator form, as iqp_mmd_loss_grad */
+    int32_t precision;           /* IQP_FP32, IQP_SPLIT_BF16 or IQP_SPARSE_FP32 */
+    int32_t optimizer;           /* IQP_OPT_GD or IQP_OPT_ADAM */
+    double lr, beta1, beta2, eps;
+    uint64_t seed0, seed1;       /* Philox key; samples use tag 0, operators tag 1 */
+} iqp_train_desc;
+
+typedef struct iqp_train_plan iqp_train_plan;
+
+/* flags of iqp_train_plan_create */
+enum {
+    IQP_TRAIN_NO_GRAPH = 1 /* launch the steps one by one instead of replaying a graph */
+};
+
+/* Creates a plan; reads the host arrays of `desc` (the pointers to device
+ * memory are kept and must stay valid). Each operator group's weights sum to
+ * 1 / n_groups. Host object, not thread-safe. */
+int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan **plan);
+int iqp_train_plan_destroy(iqp_train_plan *plan);
+size_t iqp_train_workspace_bytes(const iqp_train_plan *plan);
+
+/* Prepares a workspace: uploads the plan's tables (operator weights, the
+ * parameter index, the gates of each parameter), zeroes the moments and sets
+ * the step count to `step` (>= 0). Ordered on `stream`. */
+int iqp_train_init(iqp_train_plan *plan, int64_t step, void *ws, size_t ws_bytes, void *stream);
+
+/* n_steps >= 1 training steps. Step i draws z (s samples) and the operators
+ * at the current step count t, writes loss[i] (the MMD^2 at the parameters
+ * before its update), takes the gradient, updates params (device
+ * [n_params], in place) and sets t = t + 1. grad_params: device [n_params]
+ * gradient of the last step, or NULL. Without IQP_TRAIN_NO_GRAPH the steps
+ * are one captured graph (recaptured when ws, params, loss, grad_params or
+ * n_steps change) replayed on `stream`. */
+int iqp_train_step(iqp_train_plan *plan, int32_t n_steps, double *params, double *loss,
+                   double *grad_params, void *ws, size_t ws_bytes, void *stream);
+
+/* Device pointers into a workspace: the samples [s][W] and operators
+ * [l][W] of the last step, and the step count [1]. Any may be NULL. */
+int iqp_train_buffers(const iqp_train_plan *plan, void *ws, uint64_t **samples,
+                      uint64_t **ops, int64_t **step);
+
 /* Static text for a status code. */
 const char *iqp_strerror(int status);
 

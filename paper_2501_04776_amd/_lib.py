@@ -40,10 +40,16 @@ EXPORTED = ("iqp_workspace_bytes", "iqp_parity_workspace_bytes", "iqp_parity", "
             "iqp_bitflip_expval_grad", "iqp_batch_plan_create",
             "iqp_batch_plan_destroy", "iqp_batch_workspace_bytes", "iqp_batch_expval",
             "iqp_batch_expval_grad", "iqp_batch_tune", "iqp_batch_get_config",
-            "iqp_batch_set_config", "iqp_strerror", "iqp_last_error", "iqp_profile_enable",
+            "iqp_batch_set_config", "iqp_sample_uniform", "iqp_sample_bernoulli",
+            "iqp_gather_theta", "iqp_reduce_grad", "iqp_optimizer_update",
+            "iqp_train_plan_create", "iqp_train_plan_destroy", "iqp_train_workspace_bytes",
+            "iqp_train_init", "iqp_train_step", "iqp_train_buffers", "iqp_strerror", "iqp_last_error", "iqp_profile_enable",
             "iqp_profile_query", "iqp_profile_reset")
 
 IQP_BATCH_NO_GRAPH = 1
+IQP_TRAIN_NO_GRAPH = 1
+IQP_OPT_GD = 0
+IQP_OPT_ADAM = 1
 
 
 class IqpCircuit(ctypes.Structure):
@@ -58,6 +64,19 @@ class IqpProblem(ctypes.Structure):
                 ("mean", ctypes.c_void_p), ("stderr_", ctypes.c_void_p),
                 ("phase_save", ctypes.c_void_p), ("grad_mean", ctypes.c_void_p),
                 ("grad_theta", ctypes.c_void_p)]
+
+
+class IqpTrainDesc(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_words", ctypes.c_int32),
+                ("n_gates", ctypes.c_int64), ("gens", ctypes.c_void_p),
+                ("n_params", ctypes.c_int64), ("param_index", ctypes.c_void_p),
+                ("fixed_theta", ctypes.c_void_p), ("n_groups", ctypes.c_int32),
+                ("group_ops", ctypes.c_void_p), ("group_prob", ctypes.c_void_p),
+                ("n_samples", ctypes.c_int64), ("n_data", ctypes.c_int64),
+                ("data", ctypes.c_void_p), ("unbiased", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("optimizer", ctypes.c_int32),
+                ("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("seed0", ctypes.c_uint64), ("seed1", ctypes.c_uint64)]
 
 
 class IqpError(RuntimeError):
@@ -114,6 +133,31 @@ def lib():
     L.iqp_batch_get_config.restype = i32
     L.iqp_batch_set_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.iqp_batch_set_config.restype = i32
+    u64, dbl = ctypes.c_uint64, ctypes.c_double
+    L.iqp_sample_uniform.argtypes = [i64, ctypes.c_int32, u64, u64, vp, u64, vp, vp]
+    L.iqp_sample_uniform.restype = i32
+    L.iqp_sample_bernoulli.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, u64, u64, vp, u64,
+                                       vp, vp]
+    L.iqp_sample_bernoulli.restype = i32
+    L.iqp_gather_theta.argtypes = [i64, vp, vp, vp, vp, vp]
+    L.iqp_gather_theta.restype = i32
+    L.iqp_reduce_grad.argtypes = [i64, vp, vp, vp, vp, vp]
+    L.iqp_reduce_grad.restype = i32
+    L.iqp_optimizer_update.argtypes = [i32, i64, vp, vp, vp, vp, vp, dbl, dbl, dbl, dbl, vp]
+    L.iqp_optimizer_update.restype = i32
+    L.iqp_train_plan_create.argtypes = [ctypes.POINTER(IqpTrainDesc), i32, ctypes.POINTER(vp)]
+    L.iqp_train_plan_create.restype = i32
+    L.iqp_train_plan_destroy.argtypes = [vp]
+    L.iqp_train_plan_destroy.restype = i32
+    L.iqp_train_workspace_bytes.argtypes = [vp]
+    L.iqp_train_workspace_bytes.restype = sz
+    L.iqp_train_init.argtypes = [vp, i64, vp, sz, vp]
+    L.iqp_train_init.restype = i32
+    L.iqp_train_step.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, sz, vp]
+    L.iqp_train_step.restype = i32
+    L.iqp_train_buffers.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                    ctypes.POINTER(vp)]
+    L.iqp_train_buffers.restype = i32
     L.iqp_strerror.argtypes = [i32]
     L.iqp_strerror.restype = ctypes.c_char_p
     L.iqp_last_error.argtypes = []

@@ -318,6 +318,221 @@ class BatchPlan:
             pass
 
 
+# --- training on the device ---------------------------------------------------
+OPT_GD = L.IQP_OPT_GD
+OPT_ADAM = L.IQP_OPT_ADAM
+TAG_SAMPLES, TAG_OPS = 0, 1
+_OPTIMIZERS = {"gd": OPT_GD, "adam": OPT_ADAM, OPT_GD: OPT_GD, OPT_ADAM: OPT_ADAM}
+
+
+def _seed(seed):
+    s0, s1 = (int(seed[0]), int(seed[1]))
+    if not (0 <= s0 < 2**64 and 0 <= s1 < 2**64):
+        raise ValueError("seed words must lie in [0, 2^64)")
+    return s0, s1
+
+
+def _step_tensor(step: torch.Tensor) -> torch.Tensor:
+    if not step.is_cuda or step.dtype != torch.int64 or step.numel() != 1:
+        raise ValueError("step must be a CUDA int64 tensor with one element")
+    return step
+
+
+def sample_uniform(rows: int, n_qubits: int, seed, step: torch.Tensor, tag: int = TAG_SAMPLES,
+                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Uniform bit strings [rows][W] from the Philox stream (seed, *step, tag)."""
+    step = _step_tensor(step)
+    W = (int(n_qubits) + 63) // 64
+    if out is None:
+        out = torch.empty((rows, W), dtype=torch.int64, device=step.device)
+    out = _rows(out, "out", W)
+    s0, s1 = _seed(seed)
+    L.check(L.lib().iqp_sample_uniform(rows, n_qubits, s0, s1, _ptr(step), int(tag), _ptr(out),
+                                       _stream(step)), "iqp_sample_uniform")
+    return out
+
+
+def sample_bernoulli(n_qubits: int, group_rows, group_prob, seed, step: torch.Tensor,
+                     tag: int = TAG_OPS, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Bernoulli bit rows [sum(group_rows)][W]: the bits of group g are set
+    with probability group_prob[g] (Philox stream (seed, *step, tag))."""
+    step = _step_tensor(step)
+    rows = (ctypes.c_int64 * len(group_rows))(*[int(r) for r in group_rows])
+    probs = (ctypes.c_double * len(group_prob))(*[float(p) for p in group_prob])
+    if len(group_rows) != len(group_prob):
+        raise ValueError("one probability per group")
+    W = (int(n_qubits) + 63) // 64
+    if out is None:
+        out = torch.empty((sum(int(r) for r in group_rows), W), dtype=torch.int64,
+                          device=step.device)
+    out = _rows(out, "out", W)
+    s0, s1 = _seed(seed)
+    L.check(L.lib().iqp_sample_bernoulli(n_qubits, len(group_rows), rows, probs, s0, s1,
+                                         _ptr(step), int(tag), _ptr(out), _stream(step)),
+            "iqp_sample_bernoulli")
+    return out
+
+
+def gather_theta(param_index: torch.Tensor, params: torch.Tensor,
+                 fixed_theta: Optional[torch.Tensor] = None,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """theta[j] = params[param_index[j]], or fixed_theta[j] where the index is -1."""
+    m = param_index.numel()
+    idx = _vec(param_index, "param_index", m, torch.int32)
+    if out is None:
+        out = torch.empty(m, dtype=torch.float64, device=idx.device)
+    fixed = _vec(fixed_theta, "fixed_theta", m) if fixed_theta is not None else None
+    L.check(L.lib().iqp_gather_theta(m, _ptr(idx), _ptr(params.contiguous()), _ptr(fixed),
+                                     _ptr(out), _stream(idx)), "iqp_gather_theta")
+    return out
+
+
+def param_tables(param_index, n_params: int, device) -> Tuple[torch.Tensor, torch.Tensor]:
+    """(offsets [P+1] int64, gates int32) of each parameter's gates, in gate
+    order, from a host index array (host-side bookkeeping only)."""
+    import numpy as np
+    idx = np.asarray(param_index, dtype=np.int64)
+    order = np.argsort(np.where(idx >= 0, idx, n_params), kind="stable")
+    counts = np.bincount(idx[idx >= 0], minlength=n_params)
+    offs = np.zeros(n_params + 1, dtype=np.int64)
+    np.cumsum(counts, out=offs[1:])
+    gates = order[:int(offs[-1])].astype(np.int32)
+    return (torch.from_numpy(offs).to(device),
+            torch.from_numpy(gates if gates.size else np.zeros(1, np.int32)).to(device))
+
+
+def reduce_grad(offsets: torch.Tensor, gates: torch.Tensor, grad_theta: torch.Tensor,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dL/dparam_p = sum of dL/dtheta_j over the gates of p."""
+    P = offsets.numel() - 1
+    offs = _vec(offsets, "offsets", P + 1, torch.int64)
+    if out is None:
+        out = torch.empty(P, dtype=torch.float64, device=offs.device)
+    L.check(L.lib().iqp_reduce_grad(P, _ptr(offs), _ptr(gates.contiguous()),
+                                    _ptr(grad_theta.contiguous()), _ptr(out), _stream(offs)),
+            "iqp_reduce_grad")
+    return out
+
+
+def optimizer_update(optimizer, params: torch.Tensor, grad: torch.Tensor,
+                     m1: Optional[torch.Tensor], m2: Optional[torch.Tensor], step: torch.Tensor,
+                     lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                     eps: float = 1e-8) -> None:
+    """One update of params in place ('gd' or 'adam'), then step += 1."""
+    P = params.numel()
+    if not params.is_contiguous():
+        raise ValueError("params must be contiguous (updated in place)")
+    opt = _OPTIMIZERS[optimizer]
+    L.check(L.lib().iqp_optimizer_update(opt, P, _ptr(params), _ptr(_vec(grad, "grad", P)),
+                                         _ptr(m1), _ptr(m2), _ptr(_step_tensor(step)), lr, beta1,
+                                         beta2, eps, _stream(params)), "iqp_optimizer_update")
+
+
+class Trainer:
+    """MMD^2 training on the device (iqp_train_* of include/iqp.h): every
+    step draws fresh samples and operators (operator group g has
+    ``group_ops[g]`` rows with bit probability ``group_prob[g]``, e.g. one
+    group per Gaussian-kernel bandwidth), evaluates the loss and its gradient
+    at the current parameters and updates them in place. ``param_index`` (host,
+    one entry per generator) maps generators to parameters (shared
+    parameters), -1 marking fixed gates whose angles are ``fixed_theta``. The
+    trainer owns its workspace (optimizer moments and step count live there)."""
+
+    def __init__(self, n_qubits: int, gens: torch.Tensor, param_index, n_params: int,
+                 data: torch.Tensor, group_ops, group_prob, n_samples: int,
+                 fixed_theta: Optional[torch.Tensor] = None, unbiased: bool = True,
+                 precision=SPLIT_BF16, optimizer="adam", lr: float = 1e-3, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8, seed=(0, 0), graph: bool = True,
+                 step: int = 0):
+        import numpy as np
+        self.n = int(n_qubits)
+        self.W = (self.n + 63) // 64
+        self.gens = _rows(gens, "gens", self.W)
+        self.m = self.gens.shape[0]
+        self.P = int(n_params)
+        self.device = self.gens.device
+        self.data = _rows(data, "data", self.W)
+        idx = np.ascontiguousarray(param_index, dtype=np.int32)
+        if idx.size != self.m:
+            raise ValueError("param_index needs one entry per generator")
+        self.fixed = _vec(fixed_theta, "fixed_theta", self.m) if fixed_theta is not None else None
+        self.group_ops = np.ascontiguousarray(group_ops, dtype=np.int64)
+        self.group_prob = np.ascontiguousarray(group_prob, dtype=np.float64)
+        self.l = int(self.group_ops.sum())
+        self.s = int(n_samples)
+        s0, s1 = _seed(seed)
+        d = L.IqpTrainDesc()
+        d.n_qubits, d.n_words, d.n_gates, d.gens = self.n, self.W, self.m, self.gens.data_ptr()
+        d.n_params = self.P
+        d.param_index = idx.ctypes.data
+        d.fixed_theta = self.fixed.data_ptr() if self.fixed is not None else None
+        d.n_groups = self.group_ops.size
+        d.group_ops = self.group_ops.ctypes.data
+        d.group_prob = self.group_prob.ctypes.data
+        d.n_samples, d.n_data, d.data = self.s, self.data.shape[0], self.data.data_ptr()
+        d.unbiased, d.precision = int(bool(unbiased)), precision_id(precision)
+        d.optimizer = _OPTIMIZERS[optimizer]
+        d.lr, d.beta1, d.beta2, d.eps = lr, beta1, beta2, eps
+        d.seed0, d.seed1 = s0, s1
+        self._handle = ctypes.c_void_p()
+        flags = 0 if graph else L.IQP_TRAIN_NO_GRAPH
+        L.check(L.lib().iqp_train_plan_create(ctypes.byref(d), flags, ctypes.byref(self._handle)),
+                "iqp_train_plan_create")
+        self.ws_bytes = int(L.lib().iqp_train_workspace_bytes(self._handle))
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.grad = torch.zeros(self.P, dtype=torch.float64, device=self.device)
+        self._loss = {}
+        self.reset(step)
+
+    def reset(self, step: int = 0) -> None:
+        """Zero the optimizer moments and set the step count."""
+        L.check(L.lib().iqp_train_init(self._handle, int(step), _ptr(self.ws), self.ws_bytes,
+                                       _stream(self.ws)), "iqp_train_init")
+
+    def step(self, params: torch.Tensor, n_steps: int = 1) -> torch.Tensor:
+        """n_steps updates of params (in place); returns the loss of each step
+        (a device tensor, overwritten by the next call with the same n_steps)
+        and leaves the last step's parameter gradient in ``self.grad``."""
+        if not params.is_contiguous() or params.numel() != self.P or \
+                params.dtype != torch.float64 or not params.is_cuda:
+            raise ValueError("params must be a contiguous CUDA float64 tensor of %d" % self.P)
+        loss = self._loss.get(n_steps)
+        if loss is None:
+            loss = self._loss[n_steps] = torch.zeros(n_steps, dtype=torch.float64,
+                                                     device=self.device)
+        L.check(L.lib().iqp_train_step(self._handle, int(n_steps), _ptr(params), _ptr(loss),
+                                       _ptr(self.grad), _ptr(self.ws), self.ws_bytes,
+                                       _stream(params)), "iqp_train_step")
+        return loss
+
+    def buffers(self):
+        """(samples [s][W], ops [l][W], step [1]) views of the workspace: the
+        last step's draws and the step count."""
+        z, a, t = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        L.check(L.lib().iqp_train_buffers(self._handle, _ptr(self.ws), ctypes.byref(z),
+                                          ctypes.byref(a), ctypes.byref(t)), "iqp_train_buffers")
+        base = self.ws.data_ptr()
+        flat = self.ws.view(torch.int64)
+
+        def view(ptr, count):
+            off = (ptr - base) // 8
+            return flat[off:off + count]
+        return (view(z.value, self.s * self.W).view(self.s, self.W),
+                view(a.value, self.l * self.W).view(self.l, self.W), view(t.value, 1))
+
+    def close(self) -> None:
+        if self._handle:
+            torch.cuda.synchronize(self.device)
+            L.lib().iqp_train_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # --- per-kernel timing (measurement only) ----------------------------------
 def profile_enable(on: bool = True) -> None:
     L.check(L.lib().iqp_profile_enable(int(on)), "iqp_profile_enable")

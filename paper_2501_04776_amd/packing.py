@@ -41,5 +41,5 @@ def pack_index_rows(ptr: np.ndarray, idx: np.ndarray, n: int) -> np.ndarray:
 def unpack(words: np.ndarray, n: int) -> np.ndarray:
     """uint64 [count][W] -> 0/1 uint8 [count][n]."""
     words = np.ascontiguousarray(words, dtype=np.uint64)
-    by = words.view(np.uint8).reshape(words.shape[0], -1)
+    by = words.view(np.uint8).reshape(words.shape[0], 8 * words.shape[1])
     return np.unpackbits(by, axis=1, bitorder="little")[:, :n]

@@ -226,3 +226,83 @@ def test_packing_bit_order():
     w = packing.pack_index_rows(np.array([0, 3]), np.array([0, 63, 64]), 130)
     assert w[0, 0] == np.uint64(1) | (np.uint64(1) << np.uint64(63))
     assert w[0, 1] == np.uint64(1) and w[0, 2] == 0
+
+
+# --- training entry points ----------------------------------------------------
+def _groups(rows, probs):
+    return ((ctypes.c_int64 * len(rows))(*rows), (ctypes.c_double * len(probs))(*probs))
+
+
+def test_sampler_validation():
+    lib = L.lib()
+    assert lib.iqp_sample_uniform(-1, 10, 0, 0, FAKE, 0, FAKE, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_sample_uniform(4, 0, 0, 0, FAKE, 0, FAKE, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_sample_uniform(4, 10, 0, 0, None, 0, FAKE, None) == L.IQP_ERR_INVALID_ARG
+    assert "step" in L.last_error()
+    for rows, probs, msg in [([3], [1.0], "[0, 1)"), ([3], [-0.5], "[0, 1)"),
+                             ([-1], [0.3], "group_rows"), ([3] * 17, [0.3] * 17, "n_groups")]:
+        r, p = _groups(rows, probs)
+        st = lib.iqp_sample_bernoulli(10, len(rows), r, p, 0, 0, FAKE, 1, FAKE, None)
+        assert st == L.IQP_ERR_INVALID_ARG and msg in L.last_error(), (rows, probs)
+    r, p = _groups([3], [float("nan")])
+    assert lib.iqp_sample_bernoulli(10, 1, r, p, 0, 0, FAKE, 1, FAKE, None) == \
+        L.IQP_ERR_INVALID_ARG
+
+
+def test_optimizer_and_gather_validation():
+    lib = L.lib()
+    up = lib.iqp_optimizer_update
+    assert up(2, 4, FAKE, FAKE, FAKE, FAKE, FAKE, 0.1, 0.9, 0.99, 1e-8, None) == \
+        L.IQP_ERR_INVALID_ARG
+    assert up(1, 4, FAKE, FAKE, FAKE, FAKE, FAKE, -0.1, 0.9, 0.99, 1e-8, None) == \
+        L.IQP_ERR_INVALID_ARG
+    assert up(1, 4, FAKE, FAKE, FAKE, FAKE, FAKE, 0.1, 1.0, 0.99, 1e-8, None) == \
+        L.IQP_ERR_INVALID_ARG
+    assert up(1, 4, FAKE, FAKE, None, FAKE, FAKE, 0.1, 0.9, 0.99, 1e-8, None) == \
+        L.IQP_ERR_INVALID_ARG and "m1" in L.last_error()
+    assert up(0, 0, FAKE, FAKE, None, None, FAKE, 0.1, 0, 0, 0, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_gather_theta(0, FAKE, FAKE, None, FAKE, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_gather_theta(5, None, FAKE, None, FAKE, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_reduce_grad(3, FAKE, None, FAKE, FAKE, None) == L.IQP_ERR_INVALID_ARG
+
+
+def _desc(**kw):
+    idx = np.asarray(kw.pop("param_index", [0, 1, 1, -1]), dtype=np.int32)
+    gops = np.asarray(kw.pop("group_ops", [4, 4]), dtype=np.int64)
+    gprob = np.asarray(kw.pop("group_prob", [0.3, 0.1]), dtype=np.float64)
+    d = L.IqpTrainDesc()
+    d.n_qubits, d.n_words, d.n_gates, d.gens = 70, 2, idx.size, FAKE
+    d.n_params, d.param_index, d.fixed_theta = 2, idx.ctypes.data, FAKE
+    d.n_groups, d.group_ops, d.group_prob = gops.size, gops.ctypes.data, gprob.ctypes.data
+    d.n_samples, d.n_data, d.data = 16, 8, FAKE
+    d.unbiased, d.precision, d.optimizer = 1, 1, 1
+    d.lr, d.beta1, d.beta2, d.eps, d.seed0, d.seed1 = 0.01, 0.9, 0.999, 1e-8, 1, 2
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d, (idx, gops, gprob)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(n_words=1), "n_words"), (dict(n_params=0), "n_params"),
+    (dict(param_index=[0, 2, 1, -1]), "param_index[1]"),
+    (dict(param_index=[0, -2, 1, 1]), "param_index[1]"),
+    (dict(fixed_theta=None), "fixed_theta"), (dict(group_ops=[4, 0]), "group_ops"),
+    (dict(group_prob=[0.3, 1.5]), "[0, 1)"), (dict(n_samples=0), "n_samples"),
+    (dict(n_data=1), "unbiased"), (dict(precision=7), "precision"),
+    (dict(optimizer=5), "optimizer"), (dict(lr=0.0), "lr"), (dict(data=None), "data")])
+def test_train_plan_rejects_invalid_descriptions(kw, msg):
+    d, keep = _desc(**kw)
+    plan = ctypes.c_void_p()
+    st = L.lib().iqp_train_plan_create(ctypes.byref(d), 0, ctypes.byref(plan))
+    assert st == L.IQP_ERR_INVALID_ARG, kw
+    assert msg in L.last_error(), (kw, L.last_error())
+    assert not plan.value
+
+
+def test_train_calls_reject_null_plan():
+    lib = L.lib()
+    assert lib.iqp_train_step(None, 1, FAKE, FAKE, None, FAKE, 1 << 40, None) == \
+        L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_train_init(None, 0, FAKE, 1 << 40, None) == L.IQP_ERR_INVALID_ARG
+    assert lib.iqp_train_workspace_bytes(None) == 0
+    assert lib.iqp_train_buffers(None, FAKE, None, None, None) == L.IQP_ERR_INVALID_ARG

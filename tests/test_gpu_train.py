@@ -1,0 +1,233 @@
+"""GPU vs oracle for the on-device training step: the Philox bit samplers
+(bit-exact), the parameter gather and gradient reduction, the optimizer
+update, and whole steps of the training plan (fresh samples and operators
+from the device streams, MMD^2 loss and gradient, update) in every
+precision, replayed from a graph and launched step by step."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from paper_2501_04776_amd import api, packing
+from tests.gpu_util import TOL
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp32", "split_bf16", "sparse_fp32"]
+
+
+def step_t(v):
+    return torch.tensor([v], dtype=torch.int64, device="cuda")
+
+
+@pytest.mark.parametrize("rows,n", [(0, 5), (1, 1), (3, 63), (5, 64), (7, 65), (129, 300),
+                                    (1000, 2000)])
+@pytest.mark.parametrize("step,tag", [(0, 0), (5, 0), (2, 1)])
+def test_uniform_samples_bit_exact(rows, n, step, tag):
+    seed = (0x1234, 0xFEDCBA9876543210)
+    z = api.sample_uniform(rows, n, seed, step_t(step), tag)
+    torch.cuda.synchronize()
+    got = packing.unpack(z.cpu().numpy().view(np.uint64), n)
+    assert np.array_equal(got, oracle.sample_uniform(rows, n, seed, step, tag))
+    # the padding bits past n stay clear
+    if n % 64 and rows:
+        assert not (z.cpu().numpy().view(np.uint64)[:, -1] >> np.uint64(n % 64)).any()
+
+
+@pytest.mark.parametrize("n", [1, 37, 64, 300])
+@pytest.mark.parametrize("step", [0, 9])
+def test_bernoulli_operators_bit_exact(n, step):
+    seed = (77, 2**63 + 5)
+    rows, probs = [3, 0, 50, 4, 11], [0.3, 0.2, W.sigma_bit_probability(1.0), 0.0, 0.49]
+    a = api.sample_bernoulli(n, rows, probs, seed, step_t(step), 1)
+    torch.cuda.synchronize()
+    got = packing.unpack(a.cpu().numpy().view(np.uint64), n)
+    assert np.array_equal(got, oracle.sample_bernoulli(n, rows, probs, seed, step, 1))
+
+
+def test_gather_and_reduce_match_oracle():
+    rng = np.random.default_rng(3)
+    m, P = 5000, 700
+    idx = rng.integers(-1, P, size=m).astype(np.int32)
+    params = rng.normal(size=P)
+    fixed = rng.normal(size=m)
+    gt = rng.normal(size=m)
+    th = api.gather_theta(torch.from_numpy(idx).cuda(), torch.from_numpy(params).cuda(),
+                          torch.from_numpy(fixed).cuda())
+    offs, gates = api.param_tables(idx, P, "cuda")
+    gp = api.reduce_grad(offs, gates, torch.from_numpy(gt).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(th.cpu().numpy(), oracle.gate_theta(idx, params, fixed))
+    assert np.allclose(gp.cpu().numpy(), oracle.param_grad(idx, P, gt), rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("opt", ["gd", "adam"])
+def test_optimizer_update_matches_oracle(opt):
+    rng = np.random.default_rng(11)
+    P, lr, b1, b2, eps = 1000, 0.02, 0.8, 0.995, 1e-6
+    p = rng.normal(size=P)
+    m1, m2 = np.zeros(P), np.zeros(P)
+    dp = torch.from_numpy(p.copy()).cuda()
+    dm1, dm2 = torch.zeros(P, dtype=torch.float64, device="cuda"), \
+        torch.zeros(P, dtype=torch.float64, device="cuda")
+    st = step_t(0)
+    oid = oracle.OPT_GD if opt == "gd" else oracle.OPT_ADAM
+    for t in range(5):
+        g = rng.normal(size=P) * 10.0 ** rng.integers(-5, 2, size=P)
+        api.optimizer_update(opt, dp, torch.from_numpy(g).cuda(), dm1, dm2, st, lr, b1, b2, eps)
+        p, m1, m2 = oracle.optimizer_update(oid, p, g, m1, m2, t, lr, b1, b2, eps)
+        torch.cuda.synchronize()
+        assert st.item() == t + 1
+        assert np.allclose(dp.cpu().numpy(), p, rtol=1e-13, atol=1e-15), t
+        if opt == "adam":
+            assert np.allclose(dm1.cpu().numpy(), m1, rtol=1e-13, atol=1e-300)
+            assert np.allclose(dm2.cpu().numpy(), m2, rtol=1e-13, atol=1e-300)
+
+
+def train_problem(seed=5, n=40, P=300, s=500, N=64, ops=(30, 30)):
+    """n-qubit all-local circuit (n + n(n-1)/2 generators) whose generators
+    share P parameters (generator j -> j mod P) except every 7th, which is a
+    fixed gate; data Bernoulli(0.3); two operator groups (bandwidths 1, 5)."""
+    gates = W.local_gates(n)
+    m = gates.count
+    idx = (np.arange(m) % P).astype(np.int32)
+    idx[::7] = -1
+    rng = np.random.default_rng(seed)
+    fixed = np.where(idx < 0, rng.uniform(-np.pi, np.pi, size=m), 0.0)
+    data = (rng.random((N, n)) < 0.3).astype(np.uint8)
+    params = rng.normal(0.0, 0.3, size=P)
+    probs = [W.sigma_bit_probability(1.0), W.sigma_bit_probability(5.0)]
+    return dict(n=n, gates=gates, idx=idx, fixed=fixed, data=data, params=params,
+                group_rows=list(ops), group_prob=probs, s=s, P=P)
+
+
+def make_trainer(pb, prec, opt, lr, eps=1e-8, graph=True, seed=(3, 4)):
+    gens = torch.from_numpy(packing.pack_index_rows(pb["gates"].ptr, pb["gates"].idx,
+                                                    pb["n"]).view(np.int64)).cuda()
+    data = torch.from_numpy(packing.pack_dense(pb["data"]).view(np.int64)).cuda()
+    return api.Trainer(pb["n"], gens, pb["idx"], pb["P"], data, pb["group_rows"],
+                       pb["group_prob"], pb["s"], fixed_theta=torch.from_numpy(pb["fixed"]).cuda(),
+                       precision=prec, optimizer=opt, lr=lr, eps=eps, seed=seed, graph=graph)
+
+
+def gate_bar(prec, pb, og_gate):
+    # per-parameter bound: the gate gradients' bound of the MMD tests
+    # (tol * max(1, |g|inf)) times the number of gates summed into it
+    counts = np.bincount(pb["idx"][pb["idx"] >= 0], minlength=pb["P"])
+    return TOL[prec] * max(1.0, np.abs(og_gate).max()) * np.maximum(counts, 1)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_gd_steps_match_oracle(prec):
+    pb = train_problem()
+    lr = 0.05
+    tr = make_trainer(pb, prec, "gd", lr)
+    params = torch.from_numpy(pb["params"].copy()).cuda()
+    op = pb["params"].copy()
+    for t in range(3):
+        loss = tr.step(params)
+        torch.cuda.synchronize()
+        r = oracle.train_step(pb["n"], pb["gates"], pb["idx"], pb["fixed"], op, pb["group_rows"],
+                              pb["group_prob"], pb["s"], pb["data"], (3, 4), t, oracle.OPT_GD,
+                              np.zeros(pb["P"]), np.zeros(pb["P"]), lr)
+        z, a, st = tr.buffers()
+        assert st.item() == t + 1
+        assert np.array_equal(packing.unpack(z.cpu().numpy().view(np.uint64), pb["n"]),
+                              r["samples"])
+        assert np.array_equal(packing.unpack(a.cpu().numpy().view(np.uint64), pb["n"]), r["ops"])
+        th = oracle.gate_theta(pb["idx"], op, pb["fixed"])
+        _, og_gate = oracle.mmd_loss_grad(pb["n"], pb["gates"], th, r["ops"],
+                                          oracle.op_weights(pb["group_rows"]), r["samples"],
+                                          pb["data"])
+        bar = gate_bar(prec, pb, og_gate)
+        print("%s step %d: loss %.8g vs %.8g, grad max|d|/bar %.3g" %
+              (prec, t, loss[0].item(), r["loss"],
+               (np.abs(tr.grad.cpu().numpy() - r["grad"]) / bar).max()))
+        # the parameters differ by at most lr * bar per earlier step
+        drift = np.abs(params.cpu().numpy() - r["params"]).max()
+        assert abs(loss[0].item() - r["loss"]) < 4 * TOL[prec] + 10 * t * lr * bar.max()
+        assert np.all(np.abs(tr.grad.cpu().numpy() - r["grad"]) < bar * (1 + 10 * t))
+        assert drift < (t + 1) * lr * bar.max() * (1 + 10 * t)
+        op = r["params"]
+    tr.close()
+
+
+def test_adam_steps_match_oracle():
+    # a large eps makes the update Lipschitz in the gradient (lr / eps), so
+    # the parameters follow the oracle's to lr / eps times the gradient bound
+    pb = train_problem(seed=8)
+    lr, eps, prec = 0.02, 0.05, "split_bf16"
+    tr = make_trainer(pb, prec, "adam", lr, eps=eps)
+    params = torch.from_numpy(pb["params"].copy()).cuda()
+    op, m1, m2 = pb["params"].copy(), np.zeros(pb["P"]), np.zeros(pb["P"])
+    for t in range(3):
+        loss = tr.step(params)
+        torch.cuda.synchronize()
+        r = oracle.train_step(pb["n"], pb["gates"], pb["idx"], pb["fixed"], op, pb["group_rows"],
+                              pb["group_prob"], pb["s"], pb["data"], (3, 4), t, oracle.OPT_ADAM,
+                              m1, m2, lr, eps=eps)
+        bar = TOL[prec] * max(1.0, np.abs(r["grad"]).max()) * 50
+        assert abs(loss[0].item() - r["loss"]) < 4 * TOL[prec] + 10 * t * lr / eps * bar
+        assert np.abs(params.cpu().numpy() - r["params"]).max() < (t + 1) * 10 * lr / eps * bar
+        op, m1, m2 = r["params"], r["m1"], r["m2"]
+    tr.close()
+
+
+def test_graph_replay_equals_eager_and_multi_step_call():
+    pb = train_problem(seed=12, s=300)
+    outs = []
+    for graph, chunks in [(False, [1, 1, 1, 1]), (True, [1, 1, 1, 1]), (True, [4]),
+                          (True, [2, 2])]:
+        tr = make_trainer(pb, "split_bf16", "adam", 0.01, graph=graph)
+        params = torch.from_numpy(pb["params"].copy()).cuda()
+        losses = []
+        for c in chunks:
+            junk = torch.randn(1 << 18, device="cuda").sum()  # eager work between replays
+            losses.append(tr.step(params, n_steps=c).clone())
+            torch.cuda.synchronize()
+            assert torch.isfinite(junk)
+        outs.append((params.clone(), torch.cat(losses), tr.grad.clone(),
+                     tr.buffers()[2].item()))
+        tr.close()
+    for p, l, g, st in outs[1:]:
+        assert torch.equal(p, outs[0][0]) and torch.equal(l, outs[0][1])
+        assert torch.equal(g, outs[0][2]) and st == 4
+
+
+def test_reset_restarts_the_streams_and_moments():
+    pb = train_problem(seed=14, s=200)
+    tr = make_trainer(pb, "fp32", "adam", 0.01)
+    p1 = torch.from_numpy(pb["params"].copy()).cuda()
+    l1 = tr.step(p1, n_steps=2).clone()
+    tr.reset(0)
+    p2 = torch.from_numpy(pb["params"].copy()).cuda()
+    l2 = tr.step(p2, n_steps=2).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(l1, l2) and torch.equal(p1, p2)
+    tr.reset(7)  # a later step count draws the oracle's stream for that step
+    tr.step(p2)
+    torch.cuda.synchronize()
+    z, _, st = tr.buffers()
+    assert st.item() == 8
+    assert np.array_equal(packing.unpack(z.cpu().numpy().view(np.uint64), pb["n"]),
+                          oracle.sample_uniform(pb["s"], pb["n"], (3, 4), 7, 0))
+    tr.close()
+
+
+def test_training_reduces_the_loss():
+    # 30 Adam steps on a 12-qubit circuit whose target data came from the
+    # same family of circuits: the MMD^2 estimate falls
+    pb = train_problem(seed=21, n=12, P=78, s=2000, N=2000, ops=(200, 200))
+    rng = np.random.default_rng(21)
+    tgt = rng.normal(0.0, 0.6, size=pb["P"])
+    th = oracle.gate_theta(pb["idx"], tgt, pb["fixed"])
+    probs = oracle.statevector_probs(pb["n"], pb["gates"], th)
+    draws = rng.choice(probs.size, size=2000, p=probs / probs.sum())
+    pb["data"] = ((draws[:, None] >> np.arange(pb["n"])) & 1).astype(np.uint8)
+    tr = make_trainer(pb, "split_bf16", "adam", 0.05)
+    params = torch.zeros(pb["P"], dtype=torch.float64, device="cuda")
+    losses = tr.step(params, n_steps=30).cpu().numpy()
+    print("loss first 5 %s last 5 %s" % (losses[:5], losses[-5:]))
+    assert losses[-5:].mean() < 0.5 * losses[:5].mean()
+    tr.close()
