@@ -53,6 +53,9 @@ def lib():
             "orc_subset_expval": ([i64, i64, vp, vp, vp, i64, vp, vp], i32),
             "orc_bitflip_expval": ([i64, i64, vp, vp, vp, i64, vp, vp], i32),
             "orc_bitflip_grad": ([i64, i64, vp, vp, vp, i64, vp, vp, vp], i32),
+            "orc_expval_indep": ([i64, i64, vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, i32],
+                                 i32),
+            "orc_expval_indep_grad": ([i64, i64, vp, vp, vp, i64, vp, i64, vp, vp, vp, i32], i32),
             "orc_philox4x64": ([vp, vp, vp], None),
             "orc_sample_uniform": ([i64, i64, u64, u64, u64, u64, vp], i32),
             "orc_sample_bernoulli": ([i64, i64, vp, u64, u64, u64, u64, vp], i32),
@@ -122,6 +125,40 @@ def expval_grad(n, gates, theta, ops01, samples01, grad_mean, threads=0):
     _check(lib().orc_expval_grad(n, gates.count, _p(gp), _p(gi), _p(theta), ops01.shape[0],
                                  _p(ops01), samples01.shape[0], _p(samples01), _p(u), _p(g),
                                  threads), "expval_grad")
+    return g
+
+
+def expval_indep(n, gates, theta, ops01, samples01, phases=False, threads=0):
+    """Independent estimates: samples01 is [l][s][n], observable k averaging
+    over its own samples01[k] (the l x s x n option of Sec. 2.3)."""
+    gp, gi = _gates(gates)
+    theta = _c(theta, np.float64)
+    ops01 = _c(ops01, np.uint8)
+    samples01 = _c(samples01, np.uint8)
+    l, s = ops01.shape[0], samples01.shape[1]
+    if samples01.shape[0] != l or samples01.shape[2] != n:
+        raise ValueError("samples01 must be [l][s][n]")
+    mean = np.zeros(l)
+    se = np.zeros(l)
+    ph = np.zeros((l, s)) if phases else None
+    _check(lib().orc_expval_indep(n, gates.count, _p(gp), _p(gi), _p(theta), l, _p(ops01), s,
+                                  _p(samples01), _p(mean), _p(se), _p(ph), threads),
+           "expval_indep")
+    return (mean, se, ph) if phases else (mean, se)
+
+
+def expval_indep_grad(n, gates, theta, ops01, samples01, grad_mean, threads=0):
+    """dL/dtheta of the independent estimates for u = dL/dmean."""
+    gp, gi = _gates(gates)
+    theta = _c(theta, np.float64)
+    ops01 = _c(ops01, np.uint8)
+    samples01 = _c(samples01, np.uint8)
+    u = _c(grad_mean, np.float64)
+    g = np.zeros(gates.count)
+    _check(lib().orc_expval_indep_grad(n, gates.count, _p(gp), _p(gi), _p(theta),
+                                       ops01.shape[0], _p(ops01), samples01.shape[1],
+                                       _p(samples01), _p(u), _p(g), threads),
+           "expval_indep_grad")
     return g
 
 

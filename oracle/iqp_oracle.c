@@ -134,6 +134,10 @@ typedef struct {
     int unbiased;
     double *loss_part;      /* [nthreads] */
     double *phat, *qhat;    /* optional [l] diagnostics */
+    /* samples of observable k start at samples + k * zstride: 0 when all
+     * observables share one set, s * n for independent sets (the l x s x n
+     * option of Sec. 2.3) */
+    int64_t zstride;
     int status;
 } job_t;
 
@@ -153,11 +157,18 @@ static int64_t anticommuting(const job_t *jb, int64_t k, int64_t *J, double *Ckj
     return cnt;
 }
 
+/* Sample i of observable k. */
+static const uint8_t *sample_of(const job_t *jb, int64_t k, int64_t i)
+{
+    return jb->samples + k * jb->zstride + i * jb->n;
+}
+
 /* E_ki = sum_j B_ij C_kj theta_j (eq. Emat), summed over j in J_k ascending:
  * the terms with C_kj = 0 vanish exactly. */
-static double phase(const job_t *jb, int64_t i, const int64_t *J, const double *Ckj, int64_t nj)
+static double phase(const job_t *jb, int64_t k, int64_t i, const int64_t *J, const double *Ckj,
+                    int64_t nj)
 {
-    const uint8_t *z = jb->samples + i * jb->n;
+    const uint8_t *z = sample_of(jb, k, i);
     double e = 0.0;
     for (int64_t t = 0; t < nj; ++t) {
         int64_t j = J[t];
@@ -178,7 +189,7 @@ static void expval_range(range_t *rg)
         int64_t nj = anticommuting(jb, k, J, C);
         double sc = 0.0, sc2 = 0.0;
         for (int64_t i = 0; i < jb->s; ++i) {
-            double e = phase(jb, i, J, C, nj);
+            double e = phase(jb, k, i, J, C, nj);
             if (jb->phases) jb->phases[k * jb->s + i] = (float)e;
             if (jb->phases64) jb->phases64[k * jb->s + i] = e;
             double c = cos(e);
@@ -227,8 +238,8 @@ static void grad_range(range_t *rg)
         double u = jb->grad_mean[k];
         if (u == 0.0) continue;
         for (int64_t i = 0; i < jb->s; ++i) {
-            const uint8_t *z = jb->samples + i * jb->n;
-            double e = phase(jb, i, J, C, nj);
+            const uint8_t *z = sample_of(jb, k, i);
+            double e = phase(jb, k, i, J, C, nj);
             double w = -u * sin(e) / (double)jb->s;
             for (int64_t t = 0; t < nj; ++t)
                 g[J[t]] += w * sign_of(z, jb->gptr, jb->gidx, J[t]) * C[t];
@@ -260,6 +271,46 @@ int orc_expval_grad(int64_t n, int64_t m, const int64_t *gptr, const int32_t *gi
     jb.n = n; jb.m = m; jb.l = l; jb.s = s;
     jb.gptr = gptr; jb.gidx = gidx; jb.theta = theta;
     jb.ops = ops; jb.samples = samples; jb.grad_mean = grad_mean;
+    jb.grad_part = calloc((size_t)nthreads * (size_t)(m > 0 ? m : 1), sizeof(double));
+    if (!jb.grad_part) return ORC_ERR_MEM;
+    int st = run_ranges(l, nthreads, grad_range, &jb);
+    if (!st) st = jb.status;
+    if (!st) reduce_parts(jb.grad_part, nthreads, m, grad_theta);
+    free(jb.grad_part);
+    return st;
+}
+
+/* Independent estimates: observable k averages over its own s samples,
+ * samples[k][i][q] (the l x s x n sample tensor of Sec. 2.3), so that the
+ * estimates of different observables are uncorrelated. Same estimator and
+ * gradient as above otherwise. */
+int orc_expval_indep(int64_t n, int64_t m, const int64_t *gptr, const int32_t *gidx,
+                     const double *theta, int64_t l, const uint8_t *ops, int64_t s,
+                     const uint8_t *samples, double *mean, double *stderr_, double *phases,
+                     int nthreads)
+{
+    if (n < 1 || m < 0 || l < 0 || s < 1 || !mean) return ORC_ERR_ARG;
+    job_t jb = {0};
+    jb.n = n; jb.m = m; jb.l = l; jb.s = s;
+    jb.gptr = gptr; jb.gidx = gidx; jb.theta = theta;
+    jb.ops = ops; jb.samples = samples; jb.zstride = s * n;
+    jb.mean = mean; jb.stderr_ = stderr_; jb.phases64 = phases;
+    int st = run_ranges(l, nthreads, expval_range, &jb);
+    return st ? st : jb.status;
+}
+
+int orc_expval_indep_grad(int64_t n, int64_t m, const int64_t *gptr, const int32_t *gidx,
+                          const double *theta, int64_t l, const uint8_t *ops, int64_t s,
+                          const uint8_t *samples, const double *grad_mean, double *grad_theta,
+                          int nthreads)
+{
+    if (n < 1 || m < 0 || l < 0 || s < 1 || !grad_theta || !grad_mean) return ORC_ERR_ARG;
+    if (nthreads <= 0) nthreads = orc_num_threads();
+    if (nthreads > l) nthreads = l > 0 ? (int)l : 1;
+    job_t jb = {0};
+    jb.n = n; jb.m = m; jb.l = l; jb.s = s;
+    jb.gptr = gptr; jb.gidx = gidx; jb.theta = theta;
+    jb.ops = ops; jb.samples = samples; jb.zstride = s * n; jb.grad_mean = grad_mean;
     jb.grad_part = calloc((size_t)nthreads * (size_t)(m > 0 ? m : 1), sizeof(double));
     if (!jb.grad_part) return ORC_ERR_MEM;
     int st = run_ranges(l, nthreads, grad_range, &jb);
@@ -308,7 +359,7 @@ static void mmd_range(range_t *rg)
         int64_t nj = anticommuting(jb, k, J, C);
         double sc = 0.0, sc2 = 0.0;
         for (int64_t i = 0; i < jb->s; ++i) {
-            double e = phase(jb, i, J, C, nj);
+            double e = phase(jb, k, i, J, C, nj);
             cs[i] = cos(e);
             sn[i] = sin(e);
             sc += cs[i];
@@ -336,7 +387,7 @@ static void mmd_range(range_t *rg)
             else
                 dLdc = w * 2.0 * (q - p) / S;
             double f = -dLdc * sn[i];
-            const uint8_t *z = jb->samples + i * jb->n;
+            const uint8_t *z = sample_of(jb, k, i);
             for (int64_t t = 0; t < nj; ++t)
                 g[J[t]] += f * sign_of(z, jb->gptr, jb->gidx, J[t]) * C[t];
         }
