@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-bitflip", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
+    ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-indep", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="batched workload: keep the default tiles instead of autotuning")
     ap.add_argument("--cpu-sample-ops", type=int, default=0,
@@ -230,10 +232,25 @@ def main():
         density = float(oracle.parity(w.n, dw.ops01[dens_pick], w.gates).mean())
         log("sparse_fp32: fwd+bwd %.3f ms, fwd %.3f ms (C density %.4f)" % (ms_sp, ms_spf,
                                                                            density))
+        # the sparse contraction kernels alone, against 256 CUs x 64 lanes x
+        # 2.4 GHz of 32-bit lane ops: per non-zero term the forward issues 3
+        # (bit extract, mask, add), the backward 2 (add, select on the mask)
+        kb_sp = kernel_breakdown("sparse_fp32", 3)
+        nnz = density * T
+        valu_peak = 256 * 64 * 2.4e9
+        sp_roof = {}
+        for fam, ops in (("phase_fwd", 3.0), ("phase_bwd", 2.0)):
+            if fam in kb_sp:
+                rate = nnz / (kb_sp[fam]["avg_ms"] * 1e-3)
+                sp_roof[fam] = {"avg_ms": kb_sp[fam]["avg_ms"], "nnz_terms_per_s": rate,
+                                "valu_ops_per_term": ops, "valu_ops_per_s": ops * rate,
+                                "peak_valu_ops_per_s": valu_peak,
+                                "frac": ops * rate / valu_peak}
         result["sparse_fp32"] = {"fwd_bwd_terms_per_s": T / (ms_sp * 1e-3),
                                  "fwd_terms_per_s": T / (ms_spf * 1e-3), "ms_per_step": ms_sp,
                                  "fwd_ms": ms_spf, "c_density": density,
                                  "nnz_terms_per_s_fwd": density * T / (ms_spf * 1e-3),
+                                 "kernels": sp_roof, "bound": "alu",
                                  "terms": "dense-equivalent l*s*m; C density sampled on "
                                           "%d observables" % dens_pick.size}
 
@@ -299,6 +316,17 @@ def main():
                              "ok": bool(rel_m < 1e-10 and rel_g < 1e-9),
                              "sampled_observables": int(pick.size)}
 
+    # --- independent estimates: a sample set per observable ----------------
+    if not mmd and not args.no_indep:
+        result["indep"] = bench_indep(args, w, dw, circ, pick, T)
+
+    # --- on-device training step (MMD^2 workload shape) ---------------------
+    # n = 300 all-local circuit with one parameter per gate, 2000 Bernoulli(0.3)
+    # training strings, 2000 operators per bandwidth sigma in {1, 5, 17} and
+    # 10000 samples drawn on the device every step, Adam; K steps per graph
+    if not args.no_train:
+        result["train"] = bench_train(args, w if mmd else None)
+
     # --- oracle on the host cores -------------------------------------------
     # a bounded sample of the same workload: fwd + bwd for the first k
     # observables over all samples and gates, k sized for ~15 s of CPU time
@@ -329,6 +357,128 @@ def main():
                         "step": "iqp_mmd_loss_grad" if mmd else "iqp_expval + iqp_expval_grad",
                         "terms_per_step": T}
     print(json.dumps(result), flush=True)
+
+
+def bench_indep(args, w, dw, circ, pick, T):
+    """Independent estimates on the workload's circuit and observables, each
+    observable with its own s uniform samples (l s W words drawn on the host
+    from a seeded generator); fwd and fwd+bwd timed, 8 sampled observables
+    checked against the oracle with their own sample sets."""
+    import torch
+    import oracle
+    import workloads as W
+    from paper_2501_04776_amd import api
+
+    words = W.uniform_words(np.random.default_rng(2025), (w.l, w.s), w.n)
+    z = torch.from_numpy(words.view(np.int64)).cuda()
+    u = torch.from_numpy(np.random.default_rng(9).normal(size=w.l) / w.l).cuda()
+
+    def one(grad):
+        _, _, ph = api.iqp_expval_indep(circ, dw.ops, z, phase_save=grad)
+        if grad:
+            api.iqp_expval_indep_grad(circ, dw.ops, z, u, ph)
+
+    def timed(grad, steps):
+        one(grad)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            one(grad)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+    steps = max(3, args.steps // 2)
+    fwd_ms = timed(False, steps)
+    ms = timed(True, steps)
+    # parity on sampled observables, each with its own sample set
+    up = np.zeros(w.l)
+    up[pick] = np.random.default_rng(4).normal(size=pick.size)
+    mean, se, ph = api.iqp_expval_indep(circ, dw.ops, z, phase_save=True)
+    g = api.iqp_expval_indep_grad(circ, dw.ops, z, torch.from_numpy(up).cuda(), ph)
+    torch.cuda.synchronize()
+    z01 = np.stack([W.unpack_words(words[k], w.n) for k in pick])
+    om, ose = oracle.expval_indep(w.n, w.gates, w.theta, dw.ops01[pick], z01)
+    og = oracle.expval_indep_grad(w.n, w.gates, w.theta, dw.ops01[pick], z01, up[pick])
+    em = float(np.abs(mean.cpu().numpy()[pick] - om).max())
+    es = float(np.abs(se.cpu().numpy()[pick] - ose).max())
+    eg = float(np.abs(g.cpu().numpy() - og).max() / max(1.0, np.abs(og).max()))
+    tol = 1e-5
+    log("indep: fwd %.3f ms, fwd+bwd %.3f ms, mean err %.3g" % (fwd_ms, ms, em))
+    return {"fwd_ms": fwd_ms, "ms_per_step": ms, "fwd_terms_per_s": T / (fwd_ms * 1e-3),
+            "fwd_bwd_terms_per_s": T / (ms * 1e-3),
+            "terms": "dense-equivalent l*s*m with a separate sample set per observable",
+            "sample_words_bytes": int(words.nbytes),
+            "parity": {"max_abs_err_mean": em, "max_abs_err_stderr": es,
+                       "max_rel_err_grad": eg, "tol": tol,
+                       "ok": bool(em < tol and es < tol and eg < tol),
+                       "sampled_observables": int(pick.size)}}
+
+
+def bench_train(args, w=None):
+    import torch
+    import oracle
+    import workloads as W
+    from paper_2501_04776_amd import api, packing
+
+    n, s, N, sigmas, per = 300, 10000, 2000, (1.0, 5.0, 17.0), 2000
+    if w is None:
+        gates = W.local_gates(n)
+        theta = np.random.default_rng(404).normal(0.0, 0.1, size=gates.count)
+        data = W.bernoulli_rows(np.random.default_rng(405), N, n, 0.3)
+    else:
+        gates, theta, data = w.gates, w.theta, w.data
+    m = gates.count
+    probs = [W.sigma_bit_probability(sg) for sg in sigmas]
+    gens = torch.from_numpy(packing.pack_index_rows(gates.ptr, gates.idx, n).view(np.int64)).cuda()
+    ddata = torch.from_numpy(packing.pack_dense(data).view(np.int64)).cuda()
+    seed = (2025, 4776)
+    tr = api.Trainer(n, gens, np.arange(m, dtype=np.int32), m, ddata, [per] * 3, probs, s,
+                     precision="split_bf16", optimizer="adam", lr=1e-3, seed=seed)
+    params = torch.from_numpy(theta.copy()).cuda()
+    K = max(2, args.steps)
+    for _ in range(2):
+        tr.step(params, n_steps=K)  # warm-up (graph capture on the first call)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    loss = tr.step(params, n_steps=K)
+    b.record()
+    torch.cuda.synchronize()
+    step_ms = a.elapsed_time(b) / K
+    t_last = tr.buffers()[2].item() - 1
+    z, ops, _ = tr.buffers()
+    z01 = packing.unpack(z.cpu().numpy().view(np.uint64), n)
+    a01 = packing.unpack(ops.cpu().numpy().view(np.uint64), n)
+    exact = bool(np.array_equal(z01, oracle.sample_uniform(s, n, seed, t_last, 0)) and
+                 np.array_equal(a01, oracle.sample_bernoulli(n, [per] * 3, probs, seed, t_last,
+                                                             1)))
+    # the loss and gradient alone on the same draws, for the step's overhead
+    circ = api.Circuit(n, gens, params)
+    wts = torch.full((3 * per,), 1.0 / (3 * per), dtype=torch.float64, device="cuda")
+    zc, oc = z.clone(), ops.clone()
+    for _ in range(2):
+        api.iqp_mmd_loss_grad(circ, oc, wts, zc, ddata, True, True, "split_bf16")
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(K):
+        api.iqp_mmd_loss_grad(circ, oc, wts, zc, ddata, True, True, "split_bf16")
+    b.record()
+    torch.cuda.synchronize()
+    lg_ms = a.elapsed_time(b) / K
+    T = 3.0 * per * s * m
+    lo = loss.cpu().numpy()
+    log("train: %.3f ms/step (loss+grad alone %.3f ms), draws bit-exact %s, loss %.5g -> %.5g" %
+        (step_ms, lg_ms, exact, lo[0], lo[-1]))
+    tr.close()
+    return {"step_ms": step_ms, "steps_per_s": 1e3 / step_ms, "terms_per_s": T / (step_ms * 1e-3),
+            "loss_grad_ms": lg_ms, "overhead_ms": step_ms - lg_ms,
+            "draws_bit_exact_vs_oracle": exact, "steps_per_graph": K,
+            "loss_first_last": [float(lo[0]), float(lo[-1])],
+            "config": "n=300, m=45150 (one parameter per gate), 3 x 2000 operators ~ P_sigma, "
+                      "s=10000 drawn per step, N=2000, split_bf16, Adam lr 1e-3"}
 
 
 def main_batch(args):

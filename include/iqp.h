@@ -85,12 +85,16 @@ enum {
     IQP_CALL_MMD = 3,
     IQP_CALL_MMD_GRAD = 4,
     IQP_CALL_BITFLIP = 5,
-    IQP_CALL_BITFLIP_GRAD = 6
+    IQP_CALL_BITFLIP_GRAD = 6,
+    IQP_CALL_INDEP = 7,
+    IQP_CALL_INDEP_GRAD = 8,       /* with phase_save supplied */
+    IQP_CALL_INDEP_GRAD_RECOMPUTE = 9 /* phase_save == NULL */
 };
 
 /* Bytes of workspace the given call needs for these sizes (N is only read for
- * the MMD calls; s and precision are not read for the bitflip calls). Returns
- * 0 for invalid sizes. */
+ * the MMD calls; s and precision are not read for the bitflip calls,
+ * precision not for the independent-estimate calls). Returns 0 for invalid
+ * sizes. */
 size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s, int64_t N,
                            int precision);
 
@@ -165,6 +169,26 @@ int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
                       const double *op_weight, int64_t s, const uint64_t *samples, int64_t N,
                       const uint64_t *data, int unbiased, int precision, double *loss,
                       double *grad_theta, void *ws, size_t ws_bytes, void *stream);
+
+/* Independent estimates (the l x s x n sample tensor of Sec. 2.3): observable
+ * k averages over its own s samples, so estimates of different observables
+ * are uncorrelated (the shared-sample calls above correlate them). Same
+ * estimator, outputs and gradient as iqp_expval / iqp_expval_grad; computed
+ * in the sparse-C form (FP32 phases on the vector units, FP64 reduction), the
+ * parities of each observable's anticommuting generators taken against its
+ * own samples, at about the cost of the shared-sample sparse form.
+ *   samples    device [l][s][W]: sample i of observable k at (k s + i) W
+ *   l * s <= 2^32; precision is fixed (no precision argument)
+ *   ws         >= iqp_workspace_bytes(IQP_CALL_INDEP[_GRAD[_RECOMPUTE]], ...)
+ *              (about the size of the samples again, for their bit columns)
+ */
+int iqp_expval_indep(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+                     const uint64_t *samples, double *mean, double *stderr_, float *phase_save,
+                     void *ws, size_t ws_bytes, void *stream);
+int iqp_expval_indep_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+                          const uint64_t *samples, const double *grad_mean,
+                          const float *phase_save, double *grad_theta, void *ws,
+                          size_t ws_bytes, void *stream);
 
 /* Stochastic bitflip circuits (Sec. 2.5, Prop. 3): the incoherent version of
  * the circuit, where gate j flips the bits of g_j with probability

@@ -10,13 +10,15 @@ from .api import (FP32, OPT_ADAM, OPT_GD, ROW_MAJOR, SPARSE_FP32, SPLIT_BF16, TI
                   TILED32_T, BatchPlan, Circuit, Trainer, gather_theta, optimizer_update,
                   param_tables, reduce_grad, sample_bernoulli, sample_uniform,
                   iqp_bitflip_expval, iqp_bitflip_expval_grad, iqp_expval, iqp_expval_grad,
+                  iqp_expval_indep, iqp_expval_indep_grad,
                   iqp_mmd_loss_grad, iqp_parity, profile_enable, profile_query, profile_reset,
                   workspace_bytes)
 from .autograd import IQPBitflipExpval, IQPExpval, IQPMMDLoss
 
-__all__ = ["packing", "IqpError", "FP32", "SPLIT_BF16", "SPARSE_FP32", "ROW_MAJOR", "TILED32", "TILED32_T", "BatchPlan",
-           "Circuit", "Trainer", "OPT_GD", "OPT_ADAM", "gather_theta", "optimizer_update",
-           "param_tables", "reduce_grad", "sample_bernoulli", "sample_uniform", "iqp_bitflip_expval", "iqp_bitflip_expval_grad",
-           "iqp_expval", "iqp_expval_grad", "iqp_mmd_loss_grad", "iqp_parity",
-           "profile_enable", "profile_query", "profile_reset", "workspace_bytes",
+__all__ = ["packing", "IqpError", "FP32", "SPLIT_BF16", "SPARSE_FP32", "ROW_MAJOR", "TILED32",
+           "TILED32_T", "BatchPlan", "Circuit", "Trainer", "OPT_GD", "OPT_ADAM", "gather_theta",
+           "optimizer_update", "param_tables", "reduce_grad", "sample_bernoulli",
+           "sample_uniform", "iqp_bitflip_expval", "iqp_bitflip_expval_grad", "iqp_expval",
+           "iqp_expval_grad", "iqp_expval_indep", "iqp_expval_indep_grad", "iqp_mmd_loss_grad",
+           "iqp_parity", "profile_enable", "profile_query", "profile_reset", "workspace_bytes",
            "IQPBitflipExpval", "IQPExpval", "IQPMMDLoss"]

@@ -29,6 +29,9 @@ IQP_CALL_MMD = 3
 IQP_CALL_MMD_GRAD = 4
 IQP_CALL_BITFLIP = 5
 IQP_CALL_BITFLIP_GRAD = 6
+IQP_CALL_INDEP = 7
+IQP_CALL_INDEP_GRAD = 8
+IQP_CALL_INDEP_GRAD_RECOMPUTE = 9
 
 IQP_BITS_ROW_MAJOR = 0
 IQP_BITS_TILED32 = 1
@@ -36,7 +39,8 @@ IQP_BITS_TILED32_T = 2
 
 # every symbol include/iqp.h declares
 EXPORTED = ("iqp_workspace_bytes", "iqp_parity_workspace_bytes", "iqp_parity", "iqp_expval",
-            "iqp_expval_grad", "iqp_mmd_loss_grad", "iqp_bitflip_expval",
+            "iqp_expval_grad", "iqp_expval_indep", "iqp_expval_indep_grad",
+            "iqp_mmd_loss_grad", "iqp_bitflip_expval",
             "iqp_bitflip_expval_grad", "iqp_batch_plan_create",
             "iqp_batch_plan_destroy", "iqp_batch_workspace_bytes", "iqp_batch_expval",
             "iqp_batch_expval_grad", "iqp_batch_tune", "iqp_batch_get_config",
@@ -109,6 +113,10 @@ def lib():
     L.iqp_expval.restype = i32
     L.iqp_expval_grad.argtypes = [cp, i64, vp, i64, vp, i32, vp, vp, vp, vp, sz, vp]
     L.iqp_expval_grad.restype = i32
+    L.iqp_expval_indep.argtypes = [cp, i64, vp, i64, vp, vp, vp, vp, vp, sz, vp]
+    L.iqp_expval_indep.restype = i32
+    L.iqp_expval_indep_grad.argtypes = [cp, i64, vp, i64, vp, vp, vp, vp, vp, sz, vp]
+    L.iqp_expval_indep_grad.restype = i32
     L.iqp_mmd_loss_grad.argtypes = [cp, i64, vp, vp, i64, vp, i64, vp, i32, i32, vp, vp, vp,
                                     sz, vp]
     L.iqp_mmd_loss_grad.restype = i32

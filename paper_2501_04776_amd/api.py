@@ -155,6 +155,56 @@ def iqp_expval_grad(circ: Circuit, ops: torch.Tensor, samples: torch.Tensor,
     return g
 
 
+def _indep_samples(samples: torch.Tensor, l: int, W: int) -> torch.Tensor:
+    if not samples.is_cuda or samples.dtype != torch.int64 or samples.dim() != 3 or \
+            samples.shape[0] != l or samples.shape[2] != W:
+        raise ValueError("samples must be a CUDA int64 tensor of shape [%d, s, %d]" % (l, W))
+    return samples.contiguous()
+
+
+def iqp_expval_indep(circ: Circuit, ops: torch.Tensor, samples: torch.Tensor,
+                     stderr: bool = True, phase_save: bool = False):
+    """Independent estimates: samples [l][s][W], observable k averaging over
+    samples[k]. Returns (mean[l], stderr[l] or None, phase[l][s] or None)."""
+    ops = _rows(ops, "ops", circ.W)
+    l = ops.shape[0]
+    samples = _indep_samples(samples, l, circ.W)
+    s = samples.shape[1]
+    dev = circ.device
+    mean = torch.empty(l, dtype=torch.float64, device=dev)
+    se = torch.empty(l, dtype=torch.float64, device=dev) if stderr else None
+    ph = torch.empty((l, s), dtype=torch.float32, device=dev) if phase_save else None
+    need = workspace_bytes(L.IQP_CALL_INDEP, circ.n, circ.m, l, s)
+    ws, nb = workspace.get(dev, need)
+    c = circ.struct()
+    L.check(L.lib().iqp_expval_indep(ctypes.byref(c), l, _ptr(ops), s, _ptr(samples),
+                                     _ptr(mean), _ptr(se), _ptr(ph), _ptr(ws), nb, _stream(ops)),
+            "iqp_expval_indep")
+    return mean, se, ph
+
+
+def iqp_expval_indep_grad(circ: Circuit, ops: torch.Tensor, samples: torch.Tensor,
+                          grad_mean: torch.Tensor,
+                          phase_save: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dL/dtheta [m] of the independent estimates for u = dL/dmean."""
+    ops = _rows(ops, "ops", circ.W)
+    l = ops.shape[0]
+    samples = _indep_samples(samples, l, circ.W)
+    s = samples.shape[1]
+    u = _vec(grad_mean, "grad_mean", l)
+    if phase_save is not None:
+        phase_save = _vec(phase_save, "phase_save", l * s, torch.float32)
+    g = torch.empty(circ.m, dtype=torch.float64, device=circ.device)
+    call = L.IQP_CALL_INDEP_GRAD if phase_save is not None else L.IQP_CALL_INDEP_GRAD_RECOMPUTE
+    need = workspace_bytes(call, circ.n, circ.m, l, s)
+    ws, nb = workspace.get(circ.device, need)
+    c = circ.struct()
+    L.check(L.lib().iqp_expval_indep_grad(ctypes.byref(c), l, _ptr(ops), s, _ptr(samples),
+                                          _ptr(u), _ptr(phase_save), _ptr(g), _ptr(ws), nb,
+                                          _stream(ops)), "iqp_expval_indep_grad")
+    return g
+
+
 def iqp_mmd_loss_grad(circ: Circuit, ops: torch.Tensor, op_weight: torch.Tensor,
                       samples: torch.Tensor, data: torch.Tensor, unbiased: bool = True,
                       grad: bool = True, precision=SPLIT_BF16):

@@ -19,8 +19,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
-SOURCES = ["iqp_kernels.hip", "iqp_api.cpp", "iqp_batch.cpp", "iqp_train_kernels.hip",
-           "iqp_train.cpp"]
+SOURCES = ["iqp_kernels.hip", "iqp_sparse_kernels.hip", "iqp_api.cpp", "iqp_batch.cpp",
+           "iqp_train_kernels.hip", "iqp_train.cpp"]
 
 
 def build(verbose: bool = False) -> str:

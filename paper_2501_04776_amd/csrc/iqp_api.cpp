@@ -203,7 +203,8 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
     P.N = N;
     P.m_pad = round_up(m, kPad);
     P.l_pad = round_up(l, kPad);
-    P.s_pad = round_up(s, kPad);
+    // the sparse kernels read the sample parities of whole chunks
+    P.s_pad = round_up(s, prec == IQP_SPARSE_FP32 ? kEpiChunk : kPad);
     P.mw = P.m_pad / 64;
     P.lw = P.l_pad / 64;
     P.nchunk = ceil_div(s, kEpiChunk);
@@ -304,6 +305,48 @@ static void make_bitflip_plan(Plan &P, bool grad, int64_t n, int64_t m, int64_t 
     P.total = cur;
 }
 
+// Plan of the independent-estimate calls (the sparse form over one sample
+// set per observable): bit columns of A, support lists, C row-major,
+// 2 theta', the bit columns of every observable's sample set (ldz words per
+// column), the forward's sums, and the gradient's buffers.
+static void make_indep_plan(Plan &P, int call, int64_t n, int64_t m, int64_t l, int64_t s) {
+    P = Plan();
+    P.prec = IQP_SPARSE_FP32;
+    P.n = n;
+    P.W = ceil_div(n, 64);
+    P.m = m;
+    P.l = l;
+    P.s = s;
+    P.m_pad = round_up(m, kPad);
+    P.l_pad = round_up(l, kPad);
+    P.s_pad = round_up(s, kPad);
+    P.mw = P.m_pad / 64;
+    P.lw = P.l_pad / 64;
+    P.nchunk = ceil_div(s, kEpiChunk);
+    P.fwd = call != IQP_CALL_INDEP_GRAD;
+    P.bwd = call != IQP_CALL_INDEP;
+    P.phi = call == IQP_CALL_INDEP_GRAD_RECOMPUTE;
+    P.lda = round_up(P.l_pad / 64, 4);
+    P.ldz = round_up(ceil_div(s, 64), kEpiChunk / 64);  // whole chunks, zero past s
+    size_t cur = 0;
+    P.o_xa = carve(cur, (size_t)(64 * P.W + 1) * P.lda * 8);
+    P.o_sup = carve(cur, (size_t)P.m_pad * kSupCap * 4);
+    P.o_cbits = carve(cur, (size_t)l * P.mw * 8);
+    P.o_xz = carve(cur, (size_t)l * 64 * P.W * P.ldz * 8);
+    if (P.fwd) {
+        P.o_t32 = carve(cur, (size_t)P.m_pad * 4);
+        P.o_part = carve(cur, (size_t)l * P.nchunk * 2 * 8);
+        P.o_rowsum = carve(cur, (size_t)l * 2 * 8);
+    }
+    if (P.phi) P.o_phi = carve(cur, (size_t)l * s * 4);
+    if (P.bwd) {
+        P.o_coef = carve(cur, (size_t)l * 2 * 8);
+        P.o_acc = carve(cur, (size_t)(P.m_pad + 1) * 8);
+        P.o_scale = carve(cur, 8);
+    }
+    P.total = cur;
+}
+
 // Plan of a single-problem call: its parts, the default tiles and any
 // override from the environment.
 static void make_call_plan(Plan &P, int call, int64_t n, int64_t m, int64_t l, int64_t s,
@@ -354,6 +397,35 @@ static int check_ws(const Plan &P, void *ws, size_t ws_bytes) {
 }
 
 
+// The sparse kernels' sample parities: B^T row-major, shared by all observables.
+static SampleParity shared_parity(const Plan &P, void *ws) {
+    return SampleParity{at<uint64_t>(ws, P.o_btbits), nullptr, P.s_pad / 64, 0, nullptr, nullptr,
+                        (int)P.W};
+}
+
+// Independent estimates: the bit columns of each observable's own samples.
+static SampleParity indep_parity(const Plan &P, const iqp_circuit *c, void *ws) {
+    return SampleParity{nullptr,     at<uint64_t>(ws, P.o_xz), P.ldz,   64 * P.W * P.ldz,
+                        at<int32_t>(ws, P.o_sup), c->gens,     (int)P.W};
+}
+
+// C row-major and the per-observable sample bit columns of the independent
+// estimates.
+static int run_indep_parities(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
+                              const uint64_t *samples, void *ws, const LaunchCtx &lc) {
+    IQP_TRY(launch_support(lc, support_args(P, c->gens, ws)), "support");
+    IQP_TRY(launch_bitslice(lc, bitslice_ops_args(P, ops, ws)), "bitslice(A)");
+    IQP_TRY(launch_parity_bs(lc, IQP_BITS_ROW_MAJOR,
+                             ParityArgs{c->gens, at<int32_t>(ws, P.o_sup), P.m, (int)P.W,
+                                        at<uint64_t>(ws, P.o_xa), P.l_pad / 64, P.lda, P.l, P.mw,
+                                        at<uint64_t>(ws, P.o_cbits)}),
+            "parity(C, row-major)");
+    IQP_TRY(launch_indep_slice(lc, IndepSliceArgs{samples, P.l, P.s, (int)P.W, P.ldz,
+                                                  at<uint64_t>(ws, P.o_xz)}),
+            "bitslice(per-observable Z)");
+    return IQP_OK;
+}
+
 // Sparse form: the row-major C and B^T parities its kernels walk.
 static int run_sparse_parities(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
                                const uint64_t *samples, void *ws, const LaunchCtx &lc) {
@@ -381,8 +453,7 @@ static int run_forward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
         int st = run_sparse_parities(P, c, ops, samples, ws, lc);
         if (st) return st;
         IQP_TRY(launch_sparse_fwd(lc, SparseFwdArgs{at<uint64_t>(ws, P.o_cbits), P.mw,
-                                                    at<float>(ws, P.o_t32),
-                                                    at<uint64_t>(ws, P.o_btbits), P.s_pad / 64,
+                                                    at<float>(ws, P.o_t32), shared_parity(P, ws),
                                                     P.l, P.s, phase_out,
                                                     at<double>(ws, P.o_part)}),
                 "sparse_fwd");
@@ -419,9 +490,8 @@ static int run_backward(const Plan &P, const iqp_circuit *c, const uint64_t *ops
             if (st) return st;
         }
         IQP_TRY(launch_sparse_bwd(lc, SparseBwdArgs{at<uint64_t>(ws, P.o_cbits), P.mw,
-                                                    at<uint64_t>(ws, P.o_btbits), P.s_pad / 64,
-                                                    P.l, P.s, P.m_pad, phase,
-                                                    at<double>(ws, P.o_coef), scale, acc}),
+                                                    shared_parity(P, ws), P.l, P.s, P.m_pad,
+                                                    phase, at<double>(ws, P.o_coef), scale, acc}),
                 "sparse_bwd");
         IQP_TRY(launch_sparse_finish(lc, SparseFinishArgs{acc, scale, P.m, P.m_pad, grad_theta}),
                 "sparse_finish");
@@ -466,6 +536,12 @@ size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s,
         return P.total;
     }
     if (s < 1) return 0;
+    if (call >= IQP_CALL_INDEP && call <= IQP_CALL_INDEP_GRAD_RECOMPUTE) {
+        if (l * s > kMaxIndepRows) return 0;
+        Plan P;
+        make_indep_plan(P, call, c->n_qubits, c->n_gates, l, s);
+        return P.total;
+    }
     if (call < IQP_CALL_EXPVAL || call > IQP_CALL_MMD_GRAD) return 0;
     if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16 && precision != IQP_SPARSE_FP32)
         return 0;
@@ -571,6 +647,85 @@ int iqp_expval_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_
     }
     IQP_TRY(launch_coef_plain(lc, coef_args(P, grad_mean, ws)), "coef");
     return run_backward(P, c, ops, samples, phase, phase_save == nullptr, ws, lc, grad_theta);
+}
+
+// Forward of the independent estimates into the plan's buffers.
+static int run_indep_forward(const Plan &P, const iqp_circuit *c, const uint64_t *ops,
+                             const uint64_t *samples, void *ws, const LaunchCtx &lc,
+                             float *phase_out, double *mean, double *se) {
+    IQP_TRY(launch_theta_prep(lc, theta_args(P, c->theta, ws)), "theta_prep");
+    int st = run_indep_parities(P, c, ops, samples, ws, lc);
+    if (st) return st;
+    IQP_TRY(launch_sparse_fwd(lc, SparseFwdArgs{at<uint64_t>(ws, P.o_cbits), P.mw,
+                                                at<float>(ws, P.o_t32), indep_parity(P, c, ws),
+                                                P.l, P.s, phase_out, at<double>(ws, P.o_part)}),
+            "sparse_fwd(indep)");
+    IQP_TRY(launch_finalize(lc, fin_args(P, ws, mean, se, at<double>(ws, P.o_rowsum))),
+            "finalize");
+    return IQP_OK;
+}
+
+static int check_indep(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+                       const uint64_t *samples) {
+    int st = check_common(c, l, ops, s, samples, IQP_SPARSE_FP32);
+    if (st) return st;
+    if (l * s > kMaxIndepRows)
+        return fail(IQP_ERR_INVALID_ARG, "l * s above 2^32 sample rows");
+    return IQP_OK;
+}
+
+int iqp_expval_indep(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+                     const uint64_t *samples, double *mean, double *stderr_, float *phase_save,
+                     void *ws, size_t ws_bytes, void *stream) {
+    g_last_error.clear();
+    int st = check_indep(c, l, ops, s, samples);
+    if (st) return st;
+    if (!mean) return fail(IQP_ERR_INVALID_ARG, "mean is NULL");
+    Plan P;
+    make_indep_plan(P, IQP_CALL_INDEP, c->n_qubits, c->n_gates, l, s);
+    if ((st = check_ws(P, ws, ws_bytes))) return st;
+    if ((st = check_device())) return st;
+    return run_indep_forward(P, c, ops, samples, ws, make_ctx(stream), phase_save, mean,
+                             stderr_);
+}
+
+int iqp_expval_indep_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+                          const uint64_t *samples, const double *grad_mean,
+                          const float *phase_save, double *grad_theta, void *ws,
+                          size_t ws_bytes, void *stream) {
+    g_last_error.clear();
+    int st = check_indep(c, l, ops, s, samples);
+    if (st) return st;
+    if (!grad_mean) return fail(IQP_ERR_INVALID_ARG, "grad_mean is NULL");
+    if (!grad_theta) return fail(IQP_ERR_INVALID_ARG, "grad_theta is NULL");
+    Plan P;
+    make_indep_plan(P, phase_save ? IQP_CALL_INDEP_GRAD : IQP_CALL_INDEP_GRAD_RECOMPUTE,
+                    c->n_qubits, c->n_gates, l, s);
+    if ((st = check_ws(P, ws, ws_bytes))) return st;
+    if ((st = check_device())) return st;
+    LaunchCtx lc = make_ctx(stream);
+    const float *phase = phase_save;
+    if (!phase) {
+        if ((st = run_indep_forward(P, c, ops, samples, ws, lc, at<float>(ws, P.o_phi), nullptr,
+                                    nullptr)))
+            return st;
+        phase = at<float>(ws, P.o_phi);
+    } else if ((st = run_indep_parities(P, c, ops, samples, ws, lc))) {
+        return st;
+    }
+    IQP_TRY(launch_coef_plain(lc, coef_args(P, grad_mean, ws)), "coef");
+    long long *acc = at<long long>(ws, P.o_acc);
+    double *scale = at<double>(ws, P.o_scale);
+    IQP_TRY(launch_sparse_bound(lc, SparseBoundArgs{at<double>(ws, P.o_coef), P.l, P.s, P.m_pad,
+                                                    acc, scale}),
+            "sparse_bound");
+    IQP_TRY(launch_sparse_bwd(lc, SparseBwdArgs{at<uint64_t>(ws, P.o_cbits), P.mw,
+                                                indep_parity(P, c, ws), P.l, P.s, P.m_pad, phase,
+                                                at<double>(ws, P.o_coef), scale, acc}),
+            "sparse_bwd(indep)");
+    IQP_TRY(launch_sparse_finish(lc, SparseFinishArgs{acc, scale, P.m, P.m_pad, grad_theta}),
+            "sparse_finish");
+    return IQP_OK;
 }
 
 int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,

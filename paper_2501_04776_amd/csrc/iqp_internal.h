@@ -196,17 +196,32 @@ struct BitflipGradArgs {
 };
 inline int64_t blocks_of(const BitflipGradArgs &a) { return ceil_div(a.m, 256); }
 
+// Where the sparse kernels read the sample parities b_ij of generator j
+// (bit i % 64 of word i / 64):
+//   shared samples:       btrm, B^T row-major, Rwb sample words per generator
+//   independent samples:  xt, the bit columns of each observable's own
+//                         samples (xt + k * xstride, column q at q * Rwb),
+//                         combined over the support list sup (or the bit row
+//                         of gens for a generator heavier than kSupCap)
+struct SampleParity {
+    const uint64_t *btrm;
+    const uint64_t *xt;  // NULL for shared samples
+    int64_t Rwb, xstride;
+    const int32_t *sup;
+    const uint64_t *gens;
+    int W;
+};
+
 // Sparse-C contraction (FP32 on the vector units): the phases summed over
 // each observable's anticommuting generators only.
 //   crm   C row-major: Gw gate words per observable row
-//   btrm  B^T row-major: Rwb sample words per generator row
 //   t32   2 theta' per generator (plain FP32)
 struct SparseFwdArgs {
     const uint64_t *crm;
     int64_t Gw;
     const float *t32;
-    const uint64_t *btrm;
-    int64_t Rwb, l, s;
+    SampleParity bsrc;
+    int64_t l, s;
     float *phase_out;  // [l][s] or NULL
     double *part;      // [l][ceil(s / kEpiChunk)][2] as the dense epilogue writes it
 };
@@ -228,14 +243,29 @@ inline int64_t blocks_of(const SparseBoundArgs &a) { return ceil_div(a.m_pad + 1
 struct SparseBwdArgs {
     const uint64_t *crm;
     int64_t Gw;
-    const uint64_t *btrm;
-    int64_t Rwb, l, s, m_pad;  // j < m_pad; acc[m_pad] is the non-finite flag
+    SampleParity bsrc;
+    int64_t l, s, m_pad;  // j < m_pad; acc[m_pad] is the non-finite flag
     const float *phase;
     const double *coef, *scale;
     long long *acc;
 };
 inline int64_t blocks_of(const SparseBwdArgs &a) {
     return ceil_div(a.l * ceil_div(a.s, kEpiChunk), 4);
+}
+
+// Bit columns of l sample sets of s rows each ([l][s][W], row i of set k at
+// samples + (k s + i) W): xt[k * 64 W * ldx + q * ldx + rw], bit r = qubit q
+// of row 64 rw + r of set k (rows >= s read as 0), q < 64 W, rw < ldx.
+struct IndepSliceArgs {
+    const uint64_t *samples;
+    int64_t l, s;
+    int W;
+    int64_t ldx;
+    uint64_t *xt;
+};
+// one wave per (set, word, 8 row words)
+inline int64_t blocks_of(const IndepSliceArgs &a) {
+    return ceil_div(a.l * a.W * ceil_div(a.ldx, 8), 4);
 }
 
 struct SparseFinishArgs {
@@ -246,7 +276,8 @@ struct SparseFinishArgs {
 };
 inline int64_t blocks_of(const SparseFinishArgs &a) { return ceil_div(a.m, 256); }
 
-// ---- launchers (iqp_kernels.hip); each returns hipGetLastError() ----
+// ---- launchers (iqp_kernels.hip, iqp_sparse_kernels.hip); each returns
+// hipGetLastError() ----
 hipError_t launch_theta_prep(const LaunchCtx &lc, const ThetaArgs &a);
 hipError_t launch_bitslice(const LaunchCtx &lc, const BitsliceArgs &a);
 hipError_t launch_support(const LaunchCtx &lc, const SupportArgs &a);
@@ -262,6 +293,7 @@ hipError_t launch_sparse_fwd(const LaunchCtx &lc, const SparseFwdArgs &a);
 hipError_t launch_sparse_bound(const LaunchCtx &lc, const SparseBoundArgs &a);
 hipError_t launch_sparse_bwd(const LaunchCtx &lc, const SparseBwdArgs &a);
 hipError_t launch_sparse_finish(const LaunchCtx &lc, const SparseFinishArgs &a);
+hipError_t launch_indep_slice(const LaunchCtx &lc, const IndepSliceArgs &a);
 hipError_t launch_bitflip_prep(const LaunchCtx &lc, const BitflipPrepArgs &a);
 hipError_t launch_bitflip_fwd(const LaunchCtx &lc, const BitflipFwdArgs &a);
 hipError_t launch_bitflip_grad(const LaunchCtx &lc, const BitflipGradArgs &a);

@@ -24,136 +24,11 @@
 //
 // No float atomics anywhere: every reduction runs in a fixed order, so a call
 // is bitwise reproducible.
-#include "iqp_internal.h"
+#include "iqp_device.h"
 
 #include <math.h>
 
 namespace iqp {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-typedef short s16x2 __attribute__((ext_vector_type(2)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
-
-// 2 pi split for a two-step Cody-Waite reduction (Cody & Waite, 1980):
-// hi is the double nearest 2 pi, lo the double nearest 2 pi - hi.
-#define IQP_TWO_PI_HI 6.283185307179586
-#define IQP_TWO_PI_LO 2.4492935982947064e-16
-#define IQP_INV_TWO_PI 0.15915494309189535
-#define IQP_PI 3.141592653589793
-#define IQP_INV_PI 0.3183098861837907
-
-__device__ __forceinline__ int wave_id() {
-    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-}
-
-// Workgroups are handed to the 8 XCDs round-robin. Remap so that each XCD
-// owns a contiguous range of tile indices: neighbouring tiles share operand
-// strips, which then stay in that XCD's L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
-    int64_t q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
-    return x * q + (x < r ? x : r) + i;
-}
-
-__device__ __forceinline__ uint16_t f2bf_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// A pointer read from an argument struct in memory is generic (flat) to the
-// compiler. The kernels hold such pointers in the global address space
-// (`glb<T>`), so every access through them is a global memory instruction,
-// which, unlike a flat one, never waits on LDS or scalar-memory counters.
-#define IQP_GLOBAL __attribute__((address_space(1)))
-template <typename T>
-using glb = T IQP_GLOBAL *;
-template <typename T>
-__device__ __forceinline__ glb<T> gptr(T *p) {
-    return (glb<T>)p;
-}
-
-// A value that is the same in every lane, moved to a scalar register.
-__device__ __forceinline__ int64_t uniform64(uint64_t v) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// Problem p of a batch owns blocks off[p] .. off[p+1]-1 (off[0] = 0, b <
-// off[np]); empty problems have off[p] = off[p+1] and are skipped.
-__device__ __forceinline__ int find_slot(const int64_t *__restrict__ off, int np, int64_t b) {
-    int lo = 0, hi = np;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= b) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-template <typename A, void (*F)(const A &, int64_t)>
-__global__ __launch_bounds__(256) void plain_kernel(A a) {
-    F(a, (int64_t)blockIdx.x);
-}
-
-template <typename A, void (*F)(const A &, int64_t)>
-__global__ __launch_bounds__(256) void batched_kernel(const A *__restrict__ args,
-                                                      const int64_t *__restrict__ off, int np) {
-    const int64_t b = (int64_t)blockIdx.x;
-    const int p = find_slot(off, np, b);
-    const A a = args[p];
-    F(a, b - off[p]);
-}
-
-// 256-thread blocks: a grid stays below 2^32 work-items.
-constexpr int64_t kMaxBlocks = ((int64_t)1 << 24) - 1;
-
-template <typename A, void (*F)(const A &, int64_t)>
-static hipError_t plain_launch(const LaunchCtx &lc, int family, const A &a, int64_t blocks) {
-    if (blocks <= 0) return hipSuccess;
-    if (blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
-    hipEvent_t ev;
-    timed_begin(lc, family, &ev);
-    hipLaunchKernelGGL((plain_kernel<A, F>), dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
-    hipError_t e = hipGetLastError();
-    timed_end(lc, family, ev);
-    return e;
-}
-
-// threadIdx.x, hidden from loop-invariant code motion: a persistent kernel
-// then recomputes lane-derived values per work unit instead of keeping them
-// live across units (the contraction bodies need every register).
-__device__ __forceinline__ int opaque_tid() {
-    int t = (int)threadIdx.x;
-    asm volatile("" : "+v"(t));
-    return t;
-}
-
-// Work-queue loop of the persistent kernels: the workgroup takes the next
-// unit from `counter` until the units run out. Every workgroup reaches the
-// exit, whatever the order in which units are taken.
-template <typename Body>
-__device__ __forceinline__ void persistent_loop(const int64_t *__restrict__ off, int np,
-                                                unsigned long long *counter, Body body) {
-    __shared__ unsigned long long slot;
-    const int64_t total = off[np];
-    for (;;) {
-        if (threadIdx.x == 0) slot = atomicAdd(counter, 1ull);
-        __syncthreads();
-        const int64_t u = uniform64(slot);
-        __syncthreads();
-        if (u >= total) break;
-        const int p = find_slot(off, np, u);
-        body(p, u - off[p]);
-    }
-}
 
 // ---------------------------------------------------------------------------
 // theta_prep
@@ -187,29 +62,6 @@ hipError_t launch_theta_prep(const LaunchCtx &lc, const ThetaArgs &a) {
 // |g| words. Cost grows with the weight of g (1..4 in the circuits of the
 // paper), not with n.
 //
-// transpose64: lane r holds row r of a 64x64 bit matrix (bit c = column c)
-// and receives row r of its transpose. Six butterfly stages: at block size k
-// lanes r and r^k swap the off-diagonal k x k blocks of their 2k x 2k block.
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int k) {
-    const int lo = __shfl_xor((int)(uint32_t)x, k, 64);
-    const int hi = __shfl_xor((int)(uint32_t)(x >> 32), k, 64);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
-__device__ __forceinline__ uint64_t transpose64(uint64_t x, int lane) {
-    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull,
-                               0x00FF00FF00FF00FFull, 0x0F0F0F0F0F0F0F0Full,
-                               0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-    for (int st = 0; st < 6; ++st) {
-        const int k = 32 >> st;
-        const uint64_t m = masks[st];
-        const uint64_t p = shfl_xor_u64(x, k);
-        x = (lane & k) ? ((x & ~m) | ((p & ~m) >> k)) : ((x & m) | ((p & m) << k));
-    }
-    return x;
-}
-
 // Xt[q * ldx + rw]: bit r = qubit q of row 64 rw + r (rows >= R read as 0),
 // for q < 64 W and rw < ldx; row q = 64 W is all zero (the parity kernel
 // reads it for absent support entries).
@@ -897,18 +749,6 @@ hipError_t launch_phase_fwd_persistent(const LaunchCtx &lc, int prec, int fm, in
 
 // ---------------------------------------------------------------------------
 // epilogue: one block per (observable k, chunk of kEpiChunk samples).
-__device__ __forceinline__ double block_sum_256(double v, double *sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-#pragma unroll
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-        __syncthreads();
-    }
-    double r = sh[0];
-    __syncthreads();
-    return r;
-}
 
 __device__ __forceinline__ void epilogue_body(const EpiArgs &a, int64_t blk) {
     __shared__ double sh[256];
@@ -1758,176 +1598,6 @@ __device__ __forceinline__ void bitflip_grad_body(const BitflipGradArgs &a, int6
 
 hipError_t launch_bitflip_grad(const LaunchCtx &lc, const BitflipGradArgs &a) {
     return plain_launch<BitflipGradArgs, bitflip_grad_body>(lc, KF_BWD, a, blocks_of(a));
-}
-
-// ---------------------------------------------------------------------------
-// Sparse-C contraction: E_ki = sum_{j in J_k} t_j (-1)^{b_ij}, t_j = 2 theta'_j,
-// over the generators J_k that anticommute with observable k (the set bits of
-// row k of C), on the vector units in FP32 — the dense contraction's result
-// with |J_k| / m of its work. One wave per (observable k, chunk of kEpiChunk
-// samples); lane L holds samples 16 L .. 16 L + 15 of the chunk (bits
-// 16 (L % 4) + b of sample word 16 chunk + L / 4). The row of C is walked
-// with scalar loads in gate order; for each set bit the lane loads one word of
-// that generator's sample bits and adds t_j where a bit is set:
-//   E_ki = T_k - 2 sum_{j in J_k, b_ij = 1} t_j,  T_k = sum_{j in J_k} t_j (FP64).
-constexpr int kSpSamples = kEpiChunk / 64;
-
-__device__ __forceinline__ float masked(float t, uint32_t f, int b) {
-    // t where bit b of f is set, else 0: a signed one-bit field is 0 or -1
-    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)f, (unsigned)b, 1u);
-    return __uint_as_float(__float_as_uint(t) & m);
-}
-
-__device__ __forceinline__ void sparse_fwd_body(const SparseFwdArgs &a, int64_t blk) {
-    const int64_t nchunk = ceil_div(a.s, kEpiChunk);
-    const int64_t unit = blk * 4 + wave_id();
-    if (unit >= a.l * nchunk) return;  // uniform over the wave
-    const int64_t k = unit / nchunk, ch = unit - k * nchunk;
-    const int lane = threadIdx.x & 63;
-    const int64_t sw = ch * (kEpiChunk / 64) + (lane >> 2);
-    const int sh = 16 * (lane & 3);
-    const uint64_t IQP_GLOBAL *bcol = gptr(a.btrm) + (sw < a.Rwb ? sw : 0);
-    const uint64_t IQP_GLOBAL *crow = gptr(a.crm) + k * a.Gw;
-    const float IQP_GLOBAL *t32 = gptr(a.t32);
-    float acc[kSpSamples];
-#pragma unroll
-    for (int b = 0; b < kSpSamples; ++b) acc[b] = 0.0f;
-    double T = 0.0;
-    for (int64_t w = 0; w < a.Gw; ++w) {
-        uint64_t cw = crow[w];
-        while (cw) {
-            const int64_t j = w * 64 + __builtin_ctzll(cw);
-            cw &= cw - 1;
-            const float t = t32[j];
-            const uint32_t f = (uint32_t)(bcol[j * a.Rwb] >> sh);
-            T += (double)t;
-#pragma unroll
-            for (int b = 0; b < kSpSamples; ++b) acc[b] += masked(t, f, b);
-        }
-    }
-    double sc = 0.0, sc2 = 0.0;
-    const int64_t i0 = ch * kEpiChunk + lane * kSpSamples;
-    float IQP_GLOBAL *ph = a.phase_out ? gptr(a.phase_out) + k * a.s : nullptr;
-#pragma unroll
-    for (int b = 0; b < kSpSamples; ++b) {
-        const int64_t i = i0 + b;
-        if (i < a.s) {
-            const double e = T - 2.0 * (double)acc[b];
-            const double kk = rint(e * IQP_INV_TWO_PI);
-            double rr = fma(-kk, IQP_TWO_PI_HI, e);
-            rr = fma(-kk, IQP_TWO_PI_LO, rr);
-            const float rf = (float)rr;
-            const float c = cosf(rf);
-            if (ph) ph[i] = rf;
-            sc += (double)c;
-            sc2 += (double)c * (double)c;
-        }
-    }
-#pragma unroll
-    for (int st = 32; st >= 1; st >>= 1) {
-        sc += __shfl_xor(sc, st, 64);
-        sc2 += __shfl_xor(sc2, st, 64);
-    }
-    if (lane == 0) {
-        double IQP_GLOBAL *part = gptr(a.part) + (k * nchunk + ch) * 2;
-        part[0] = sc;
-        part[1] = sc2;
-    }
-}
-
-hipError_t launch_sparse_fwd(const LaunchCtx &lc, const SparseFwdArgs &a) {
-    return plain_launch<SparseFwdArgs, sparse_fwd_body>(lc, KF_FWD, a, blocks_of(a));
-}
-
-// Gradient of the sparse form: for every (k, j in J_k) the partial
-// T_kj = sum_i S_ki (-1)^{b_ij} of a sample chunk is summed across the wave
-// and added into an int64 fixed-point accumulator of gate j. Integer addition
-// is associative, so the result does not depend on the order in which the
-// waves add, and no per-pair storage is needed. The scale keeps every sum
-// below 2^62: |T_kj| <= s (|alpha_k| + |beta_k|) summed over k.
-__device__ __forceinline__ void sparse_bound_body(const SparseBoundArgs &a, int64_t blk) {
-    const int64_t j = blk * 256 + threadIdx.x;
-    if (j <= a.m_pad) gptr(a.acc)[j] = 0;
-    if (blk != 0) return;
-    __shared__ double sh[256];
-    double g = 0.0;
-    for (int64_t k = threadIdx.x; k < a.l; k += 256)
-        g += (double)a.s * (fabs(gptr(a.coef)[2 * k]) + fabs(gptr(a.coef)[2 * k + 1]));
-    g = block_sum_256(g, sh);
-    if (threadIdx.x == 0) {
-        const double G = (g > 0.0 && isfinite(g)) ? g : 1.0;
-        gptr(a.scale)[0] = ldexp(1.0, 61 - ilogb(G));
-    }
-}
-
-hipError_t launch_sparse_bound(const LaunchCtx &lc, const SparseBoundArgs &a) {
-    return plain_launch<SparseBoundArgs, sparse_bound_body>(lc, KF_WEIGHTS, a, blocks_of(a));
-}
-
-__device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t blk) {
-    const int64_t nchunk = ceil_div(a.s, kEpiChunk);
-    const int64_t unit = blk * 4 + wave_id();
-    if (unit >= a.l * nchunk) return;  // uniform over the wave
-    const int64_t k = unit / nchunk, ch = unit - k * nchunk;
-    const int lane = threadIdx.x & 63;
-    const int64_t sw = ch * (kEpiChunk / 64) + (lane >> 2);
-    const int sh = 16 * (lane & 3);
-    const uint64_t IQP_GLOBAL *bcol = gptr(a.btrm) + (sw < a.Rwb ? sw : 0);
-    const uint64_t IQP_GLOBAL *crow = gptr(a.crm) + k * a.Gw;
-    const double al = gptr(a.coef)[2 * k], be = gptr(a.coef)[2 * k + 1];
-    const double scale = gptr(a.scale)[0];
-    // S_ki = (alpha_k + beta_k cos E_ki) sin E_ki for the lane's samples
-    float S[kSpSamples];
-    float Ssum = 0.0f;
-    const int64_t i0 = ch * kEpiChunk + lane * kSpSamples;
-#pragma unroll
-    for (int b = 0; b < kSpSamples; ++b) {
-        const int64_t i = i0 + b;
-        float v = 0.0f;
-        if (i < a.s) {
-            float sn, cs;
-            sincosf(gptr(a.phase)[k * a.s + i], &sn, &cs);
-            v = (float)((al + be * (double)cs) * (double)sn);
-        }
-        S[b] = v;
-        Ssum += v;
-    }
-    for (int64_t w = 0; w < a.Gw; ++w) {
-        uint64_t cw = crow[w];
-        while (cw) {
-            const int64_t j = w * 64 + __builtin_ctzll(cw);
-            cw &= cw - 1;
-            const uint32_t f = (uint32_t)(bcol[j * a.Rwb] >> sh);
-            float p = 0.0f;
-#pragma unroll
-            for (int b = 0; b < kSpSamples; ++b) p += masked(S[b], f, b);
-            p = Ssum - 2.0f * p;
-#pragma unroll
-            for (int st = 32; st >= 1; st >>= 1) p += __shfl_xor(p, st, 64);
-            if (lane == 0) {
-                if (isfinite(p))
-                    atomicAdd((unsigned long long *)&gptr(a.acc)[j],
-                              (unsigned long long)llrint((double)p * scale));
-                else
-                    atomicOr((unsigned long long *)&gptr(a.acc)[a.m_pad], 1ull);
-            }
-        }
-    }
-}
-
-hipError_t launch_sparse_bwd(const LaunchCtx &lc, const SparseBwdArgs &a) {
-    return plain_launch<SparseBwdArgs, sparse_bwd_body>(lc, KF_BWD, a, blocks_of(a));
-}
-
-__device__ __forceinline__ void sparse_finish_body(const SparseFinishArgs &a, int64_t blk) {
-    const int64_t j = blk * 256 + threadIdx.x;
-    if (j >= a.m) return;
-    const bool bad = gptr(a.acc)[a.m_pad] != 0;
-    gptr(a.grad)[j] = bad ? (double)NAN : -2.0 * (double)gptr(a.acc)[j] / gptr(a.scale)[0];
-}
-
-hipError_t launch_sparse_finish(const LaunchCtx &lc, const SparseFinishArgs &a) {
-    return plain_launch<SparseFinishArgs, sparse_finish_body>(lc, KF_GRAD, a, blocks_of(a));
 }
 
 }  // namespace iqp

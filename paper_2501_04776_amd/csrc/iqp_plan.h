@@ -31,6 +31,8 @@ bool timing_enabled();
 
 // Size limits that keep every grid dimension and index in range.
 constexpr int64_t kMaxRows = (int64_t)1 << 24;
+// Sample rows l * s of the independent estimates.
+constexpr int64_t kMaxIndepRows = (int64_t)1 << 32;
 
 int check_circuit(const iqp_circuit *c);
 

@@ -1,0 +1,370 @@
+// gfx950 kernels of the sparse-C contraction and of independent estimates.
+//
+// Sparse-C: E_ki = sum_{j in J_k} t_j (-1)^{b_ij}, t_j = 2 theta'_j, over the
+// generators J_k that anticommute with observable k (the set bits of row k of
+// C), on the vector units in FP32: the dense contraction's result with
+// |J_k| / m of its work.
+//
+// Independent estimates (the l x s x n sample tensor of Sec. 2.3): observable
+// k averages over its own s samples, so its sample parities come from the bit
+// columns of its own sample set instead of one B^T shared by all observables.
+// Nothing else changes, so both forms run the same bodies over a different
+// source of sample-parity words.
+#include "iqp_device.h"
+
+namespace iqp {
+
+// Buffers a launch only reads (parity words, support lists, C rows, 2 theta'),
+// held in the constant address space: uniform loads through such pointers
+// are scalar loads even in kernels that also write memory (the backward's
+// atomics), since the compiler may assume they do not change in the launch.
+#define IQP_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const T IQP_CONST *cptr(const T *p) {
+    return (const T IQP_CONST *)p;
+}
+
+// ---------------------------------------------------------------------------
+// Sample-parity words: word w of generator j holds b_ij of samples 64 w ..
+// 64 w + 63 (bit i % 64). A wave covers one chunk of kSpWords words of one
+// observable. Two ways to read them:
+//   word(j)      the forward: each lane loads the word its 16 samples lie in
+//                (lane L: bits 16 (L % 4) .. 16 (L % 4) + 15 of word L / 4)
+//   words(j, m)  the backward: all kSpWords words of the chunk, the same in
+//                every lane (scalar loads), each used as a lane mask over the
+//                64 samples of one word (lane L: sample 64 r + L)
+// The sample-parity rows hold whole chunks (a multiple of kSpWords words,
+// the words of samples >= s being 0), so a wave reads all its words
+// unconditionally.
+constexpr int kSpWords = kEpiChunk / 64;
+
+// One B^T (row-major) for all observables.
+struct SharedWords {
+    const uint64_t IQP_CONST *row0;  // btrm + the wave's first sample word
+    int64_t Rwb;
+    const uint64_t IQP_GLOBAL *lane0;  // btrm + the lane's own word
+    __device__ __forceinline__ uint64_t word(int64_t j) const { return lane0[j * Rwb]; }
+    __device__ __forceinline__ void words(int64_t j, uint64_t (&m)[kSpWords]) const {
+        const uint64_t IQP_CONST *row = row0 + j * Rwb;
+#pragma unroll
+        for (int r = 0; r < kSpWords; ++r) m[r] = row[r];
+    }
+};
+
+// The bit columns of observable k's own samples: the parity of g_j is the
+// XOR of the columns of its qubits (its support list; a generator heavier
+// than kSupCap walks its bit row).
+struct IndepWords {
+    const uint64_t IQP_CONST *col0;  // xt + k * xstride + the wave's first sample word
+    int64_t ldx;
+    const int32_t IQP_CONST *sup;
+    const uint64_t IQP_CONST *gens;
+    int W;
+    const uint64_t IQP_GLOBAL *lane0;  // xt + k * xstride + the lane's own word
+    __device__ __forceinline__ uint64_t word(int64_t j) const {
+        const int32_t IQP_CONST *sj = sup + j * kSupCap;
+        uint64_t x = 0;
+        if (sj[0] == -2) {
+            for (int w = 0; w < W; ++w) {
+                uint64_t g = gens[j * W + w];
+                while (g) {
+                    x ^= lane0[(int64_t)(w * 64 + __builtin_ctzll(g)) * ldx];
+                    g &= g - 1;
+                }
+            }
+            return x;
+        }
+        for (int e = 0; e < kSupCap; ++e) {
+            const int32_t q = sj[e];
+            if (q < 0) break;
+            x ^= lane0[(int64_t)q * ldx];
+        }
+        return x;
+    }
+    __device__ __forceinline__ void add_column(int64_t q, uint64_t (&m)[kSpWords]) const {
+        const uint64_t IQP_CONST *c = col0 + q * ldx;
+#pragma unroll
+        for (int r = 0; r < kSpWords; ++r) m[r] ^= c[r];
+    }
+    __device__ __forceinline__ void words(int64_t j, uint64_t (&m)[kSpWords]) const {
+#pragma unroll
+        for (int r = 0; r < kSpWords; ++r) m[r] = 0ull;
+        const int32_t IQP_CONST *sj = sup + j * kSupCap;
+        if (sj[0] == -2) {
+            for (int w = 0; w < W; ++w) {
+                uint64_t g = gens[j * W + w];
+                while (g) {
+                    add_column(w * 64 + __builtin_ctzll(g), m);
+                    g &= g - 1;
+                }
+            }
+            return;
+        }
+        for (int e = 0; e < kSupCap; ++e) {
+            const int32_t q = sj[e];
+            if (q < 0) break;
+            add_column(q, m);
+        }
+    }
+};
+
+template <bool kIndep>
+struct WordsOf;
+template <>
+struct WordsOf<false> {
+    using T = SharedWords;
+    static __device__ __forceinline__ T make(const SampleParity &p, int64_t, int64_t sw0,
+                                             int64_t swl) {
+        return SharedWords{cptr(p.btrm) + sw0, p.Rwb, gptr(p.btrm) + swl};
+    }
+};
+template <>
+struct WordsOf<true> {
+    using T = IndepWords;
+    static __device__ __forceinline__ T make(const SampleParity &p, int64_t k, int64_t sw0,
+                                             int64_t swl) {
+        return IndepWords{cptr(p.xt) + k * p.xstride + sw0, p.Rwb, cptr(p.sup), cptr(p.gens),
+                          p.W, gptr(p.xt) + k * p.xstride + swl};
+    }
+};
+
+// Sum over the 64 lanes, complete in lane 63, by data-parallel-primitive
+// moves (no LDS round trips): within quads, then rows of 16 (rotations), then
+// row 0 into row 1, row 2 into row 3, and lane 31 into rows 2 and 3. A fixed
+// order, so the result is reproducible.
+__device__ __forceinline__ float dpp_add(float x, int ctrl, int row_mask) {
+    int y;
+    switch (ctrl) {  // the control word must be a constant
+    case 0xb1: y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xb1, 0xf, 0xf, false); break;
+    case 0x4e: y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4e, 0xf, 0xf, false); break;
+    case 0x124: y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xf, 0xf, false); break;
+    case 0x128: y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, false); break;
+    case 0x142: y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xa, 0xf, false); break;
+    default: y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xc, 0xf, false); break;
+    }
+    (void)row_mask;
+    return x + __int_as_float(y);
+}
+
+__device__ __forceinline__ float wave_sum_to_last(float x) {
+    x = dpp_add(x, 0xb1, 0xf);   // quad_perm [1, 0, 3, 2]
+    x = dpp_add(x, 0x4e, 0xf);   // quad_perm [2, 3, 0, 1]
+    x = dpp_add(x, 0x124, 0xf);  // row_ror 4
+    x = dpp_add(x, 0x128, 0xf);  // row_ror 8: every lane holds its row's sum
+    x = dpp_add(x, 0x142, 0xa);  // row_bcast 15 into rows 1 and 3
+    x = dpp_add(x, 0x143, 0xc);  // row_bcast 31 into rows 2 and 3
+    return x;
+}
+
+// x + y in the lanes whose bit of the uniform mask is set, x elsewhere: one
+// add and one select on the mask held in a scalar register pair.
+__device__ __forceinline__ float add_where(float x, float y, uint64_t mask) {
+    const float s = x + y;
+    return __builtin_amdgcn_inverse_ballot_w64(mask) ? s : x;
+}
+
+// ---------------------------------------------------------------------------
+// Forward. One wave per (observable k, chunk of kEpiChunk samples); lane L
+// holds 16 samples, bits 16 (L % 4) + b of the chunk's word L / 4. The row of
+// C is walked with scalar loads in gate order; for each set bit j the lane
+// loads its parity word and adds t_j to the samples whose bit is set (a
+// signed one-bit field extract gives 0 or -1, ANDed with t_j's bits):
+//   E_ki = T_k - 2 sum_{j in J_k, b_ij = 1} t_j,  T_k = sum_{j in J_k} t_j (FP64).
+// The wave then reduces each phase modulo 2 pi in FP64, takes the cosine and
+// writes the same per-chunk sums as the dense epilogue. (Here the per-lane
+// vector load of the word keeps more loads in flight than the backward's
+// scalar mask loads, which the forward's shorter loop body cannot hide.)
+constexpr int kSpSamples = kEpiChunk / 64;
+
+__device__ __forceinline__ float masked(float t, uint32_t f, int b) {
+    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)f, (unsigned)b, 1u);
+    return __uint_as_float(__float_as_uint(t) & m);
+}
+
+template <bool kIndep>
+__device__ __forceinline__ void sparse_fwd_body(const SparseFwdArgs &a, int64_t blk) {
+    const int64_t nchunk = ceil_div(a.s, kEpiChunk);
+    const int64_t unit = blk * 4 + wave_id();
+    if (unit >= a.l * nchunk) return;  // uniform over the wave
+    const int64_t k = unit / nchunk, ch = unit - k * nchunk;
+    const int lane = threadIdx.x & 63;
+    const int64_t sw0 = ch * kSpWords;
+    const int sh = 16 * (lane & 3);
+    const auto src = WordsOf<kIndep>::make(a.bsrc, k, sw0, sw0 + (lane >> 2));
+    const uint64_t IQP_CONST *crow = cptr(a.crm) + k * a.Gw;
+    const float IQP_CONST *t32 = cptr(a.t32);
+    float acc[kSpSamples];
+#pragma unroll
+    for (int b = 0; b < kSpSamples; ++b) acc[b] = 0.0f;
+    double T = 0.0;
+    for (int64_t w = 0; w < a.Gw; ++w) {
+        uint64_t cw = crow[w];
+        while (cw) {
+            const int64_t j = w * 64 + __builtin_ctzll(cw);
+            cw &= cw - 1;
+            const float t = t32[j];
+            const uint32_t f = (uint32_t)(src.word(j) >> sh);
+            T += (double)t;
+#pragma unroll
+            for (int b = 0; b < kSpSamples; ++b) acc[b] += masked(t, f, b);
+        }
+    }
+    double sc = 0.0, sc2 = 0.0;
+    const int64_t i0 = ch * kEpiChunk + lane * kSpSamples;
+    float IQP_GLOBAL *ph = a.phase_out ? gptr(a.phase_out) + k * a.s : nullptr;
+#pragma unroll
+    for (int b = 0; b < kSpSamples; ++b) {
+        const int64_t i = i0 + b;
+        if (i < a.s) {
+            const double e = T - 2.0 * (double)acc[b];
+            const double kk = rint(e * IQP_INV_TWO_PI);
+            double rr = fma(-kk, IQP_TWO_PI_HI, e);
+            rr = fma(-kk, IQP_TWO_PI_LO, rr);
+            const float rf = (float)rr;
+            const float c = cosf(rf);
+            if (ph) ph[i] = rf;
+            sc += (double)c;
+            sc2 += (double)c * (double)c;
+        }
+    }
+#pragma unroll
+    for (int st = 32; st >= 1; st >>= 1) {
+        sc += __shfl_xor(sc, st, 64);
+        sc2 += __shfl_xor(sc2, st, 64);
+    }
+    if (lane == 0) {
+        double IQP_GLOBAL *part = gptr(a.part) + (k * nchunk + ch) * 2;
+        part[0] = sc;
+        part[1] = sc2;
+    }
+}
+
+hipError_t launch_sparse_fwd(const LaunchCtx &lc, const SparseFwdArgs &a) {
+    if (a.bsrc.xt)
+        return plain_launch<SparseFwdArgs, sparse_fwd_body<true>>(lc, KF_FWD, a, blocks_of(a));
+    return plain_launch<SparseFwdArgs, sparse_fwd_body<false>>(lc, KF_FWD, a, blocks_of(a));
+}
+
+// ---------------------------------------------------------------------------
+// Gradient: for every (k, j in J_k) the partial T_kj = sum_i S_ki (-1)^{b_ij}
+// of a sample chunk is summed across the wave and added into an int64
+// fixed-point accumulator of gate j. Integer addition is associative, so the
+// result does not depend on the order in which the waves add, and no per-pair
+// storage is needed. The scale keeps every sum below 2^62: |T_kj| <= s
+// (|alpha_k| + |beta_k|) summed over k.
+__device__ __forceinline__ void sparse_bound_body(const SparseBoundArgs &a, int64_t blk) {
+    const int64_t j = blk * 256 + threadIdx.x;
+    if (j <= a.m_pad) gptr(a.acc)[j] = 0;
+    if (blk != 0) return;
+    __shared__ double sh[256];
+    double g = 0.0;
+    for (int64_t k = threadIdx.x; k < a.l; k += 256)
+        g += (double)a.s * (fabs(gptr(a.coef)[2 * k]) + fabs(gptr(a.coef)[2 * k + 1]));
+    g = block_sum_256(g, sh);
+    if (threadIdx.x == 0) {
+        const double G = (g > 0.0 && isfinite(g)) ? g : 1.0;
+        gptr(a.scale)[0] = ldexp(1.0, 61 - ilogb(G));
+    }
+}
+
+hipError_t launch_sparse_bound(const LaunchCtx &lc, const SparseBoundArgs &a) {
+    return plain_launch<SparseBoundArgs, sparse_bound_body>(lc, KF_WEIGHTS, a, blocks_of(a));
+}
+
+template <bool kIndep>
+__device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t blk) {
+    const int64_t nchunk = ceil_div(a.s, kEpiChunk);
+    const int64_t unit = blk * 4 + wave_id();
+    if (unit >= a.l * nchunk) return;  // uniform over the wave
+    const int64_t k = unit / nchunk, ch = unit - k * nchunk;
+    const int lane = threadIdx.x & 63;
+    const int64_t sw0 = ch * kSpWords;
+    const auto src = WordsOf<kIndep>::make(a.bsrc, k, sw0, sw0);
+    const uint64_t IQP_CONST *crow = cptr(a.crm) + k * a.Gw;
+    const double al = gptr(a.coef)[2 * k], be = gptr(a.coef)[2 * k + 1];
+    const double scale = gptr(a.scale)[0];
+    // S_ki = (alpha_k + beta_k cos E_ki) sin E_ki for the lane's samples
+    float S[kSpWords];
+    float Ssum = 0.0f;
+#pragma unroll
+    for (int r = 0; r < kSpWords; ++r) {
+        const int64_t i = (sw0 + r) * 64 + lane;
+        float v = 0.0f;
+        if (i < a.s) {
+            float sn, cs;
+            sincosf(gptr(a.phase)[k * a.s + i], &sn, &cs);
+            v = (float)((al + be * (double)cs) * (double)sn);
+        }
+        S[r] = v;
+        Ssum += v;
+    }
+    for (int64_t w = 0; w < a.Gw; ++w) {
+        uint64_t cw = crow[w];
+        while (cw) {
+            const int64_t j = w * 64 + __builtin_ctzll(cw);
+            cw &= cw - 1;
+            uint64_t m[kSpWords];
+            src.words(j, m);
+            float p = 0.0f;
+#pragma unroll
+            for (int r = 0; r < kSpWords; ++r) p = add_where(p, S[r], m[r]);
+            p = wave_sum_to_last(Ssum - 2.0f * p);
+            if (lane == 63) {
+                if (isfinite(p))
+                    atomicAdd((unsigned long long *)&gptr(a.acc)[j],
+                              (unsigned long long)llrint((double)p * scale));
+                else
+                    atomicOr((unsigned long long *)&gptr(a.acc)[a.m_pad], 1ull);
+            }
+        }
+    }
+}
+
+hipError_t launch_sparse_bwd(const LaunchCtx &lc, const SparseBwdArgs &a) {
+    if (a.bsrc.xt)
+        return plain_launch<SparseBwdArgs, sparse_bwd_body<true>>(lc, KF_BWD, a, blocks_of(a));
+    return plain_launch<SparseBwdArgs, sparse_bwd_body<false>>(lc, KF_BWD, a, blocks_of(a));
+}
+
+__device__ __forceinline__ void sparse_finish_body(const SparseFinishArgs &a, int64_t blk) {
+    const int64_t j = blk * 256 + threadIdx.x;
+    if (j >= a.m) return;
+    const bool bad = gptr(a.acc)[a.m_pad] != 0;
+    gptr(a.grad)[j] = bad ? (double)NAN : -2.0 * (double)gptr(a.acc)[j] / gptr(a.scale)[0];
+}
+
+hipError_t launch_sparse_finish(const LaunchCtx &lc, const SparseFinishArgs &a) {
+    return plain_launch<SparseFinishArgs, sparse_finish_body>(lc, KF_GRAD, a, blocks_of(a));
+}
+
+// ---------------------------------------------------------------------------
+// Bit columns of every observable's own sample set. One wave per (set k,
+// word w, 8 row words): each of the 8 64-row blocks is loaded (lane r reads
+// word w of row 64 rw + r) and transposed across the lanes, so lane q then
+// holds column 64 w + q of 8 consecutive row words and writes them as one
+// 64-byte run.
+__device__ __forceinline__ void indep_slice_body(const IndepSliceArgs &a, int64_t blk) {
+    const int64_t ngrp = ceil_div(a.ldx, (int64_t)8);
+    const int64_t unit = blk * 4 + wave_id();
+    if (unit >= a.l * a.W * ngrp) return;  // uniform over the wave
+    const int64_t k = unit / (a.W * ngrp);
+    const int64_t rem = unit - k * a.W * ngrp;
+    const int64_t w = rem / ngrp, g = rem - w * ngrp;
+    const int lane = threadIdx.x & 63;
+    const uint64_t IQP_GLOBAL *rows = gptr(a.samples) + k * a.s * a.W;
+    uint64_t IQP_GLOBAL *dst = gptr(a.xt) + k * 64 * a.W * a.ldx + (w * 64 + lane) * a.ldx;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int64_t rw = g * 8 + t;
+        if (rw >= a.ldx) break;  // uniform
+        const int64_t r = rw * 64 + lane;
+        const uint64_t x = r < a.s ? rows[r * a.W + w] : 0ull;
+        dst[rw] = transpose64(x, lane);
+    }
+}
+
+hipError_t launch_indep_slice(const LaunchCtx &lc, const IndepSliceArgs &a) {
+    return plain_launch<IndepSliceArgs, indep_slice_body>(lc, KF_PARITY, a, blocks_of(a));
+}
+
+}  // namespace iqp

@@ -131,12 +131,44 @@ def test_workspace_bytes_query():
     assert 0 < a < b < d
     assert lib.iqp_workspace_bytes(L.IQP_CALL_EXPVAL, ctypes.byref(c), 0, 10, 0, 1) == 0
     assert lib.iqp_workspace_bytes(L.IQP_CALL_MMD, ctypes.byref(c), 10, 10, 0, 1) == 0
-    assert lib.iqp_workspace_bytes(9, ctypes.byref(c), 10, 10, 0, 1) == 0
+    assert lib.iqp_workspace_bytes(10, ctypes.byref(c), 10, 10, 0, 1) == 0
     assert lib.iqp_workspace_bytes(0, None, 10, 10, 0, 1) == 0
     # bitflip calls read neither s nor the precision
     e = lib.iqp_workspace_bytes(L.IQP_CALL_BITFLIP, ctypes.byref(c), 1000, 0, 0, 9)
     f = lib.iqp_workspace_bytes(L.IQP_CALL_BITFLIP_GRAD, ctypes.byref(c), 1000, 0, 0, 9)
     assert 0 < e < f
+    # independent estimates: the per-observable sample bit columns dominate
+    # (l s W words), the precision is not read, l * s is capped at 2^32
+    g = lib.iqp_workspace_bytes(L.IQP_CALL_INDEP, ctypes.byref(c), 1000, 10000, 0, 9)
+    h = lib.iqp_workspace_bytes(L.IQP_CALL_INDEP_GRAD, ctypes.byref(c), 1000, 10000, 0, 9)
+    r = lib.iqp_workspace_bytes(L.IQP_CALL_INDEP_GRAD_RECOMPUTE, ctypes.byref(c), 1000, 10000,
+                                0, 9)
+    assert 1000 * 10000 * 5 * 8 < g and 0 < h < r and g < r
+    assert lib.iqp_workspace_bytes(L.IQP_CALL_INDEP, ctypes.byref(c), 1 << 17, 1 << 16, 0,
+                                   0) == 0
+
+
+def test_indep_validation():
+    lib = L.lib()
+    c = _circ()
+    big = 1 << 40
+    f = lib.iqp_expval_indep
+    assert f(ctypes.byref(c), 0, FAKE, 8, FAKE, FAKE, None, None, FAKE, big, None) == \
+        L.IQP_ERR_INVALID_ARG
+    assert f(ctypes.byref(c), 4, FAKE, 8, None, FAKE, None, None, FAKE, big, None) == \
+        L.IQP_ERR_INVALID_ARG
+    assert f(ctypes.byref(c), 4, FAKE, 8, FAKE, None, None, None, FAKE, big, None) == \
+        L.IQP_ERR_INVALID_ARG
+    assert f(ctypes.byref(c), 1 << 17, FAKE, 1 << 16, FAKE, FAKE, None, None, FAKE, big,
+             None) == L.IQP_ERR_INVALID_ARG
+    assert "2^32" in L.last_error()
+    assert f(ctypes.byref(c), 4, FAKE, 8, FAKE, FAKE, None, None, FAKE, 16, None) == \
+        L.IQP_ERR_WORKSPACE
+    g = lib.iqp_expval_indep_grad
+    assert g(ctypes.byref(c), 4, FAKE, 8, FAKE, None, None, FAKE, FAKE, big, None) == \
+        L.IQP_ERR_INVALID_ARG
+    assert g(ctypes.byref(c), 4, FAKE, 8, FAKE, FAKE, None, None, FAKE, big, None) == \
+        L.IQP_ERR_INVALID_ARG
 
 
 def test_bitflip_validation():

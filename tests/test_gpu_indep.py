@@ -1,0 +1,113 @@
+"""GPU vs oracle for independent estimates (a sample set per observable, the
+l x s x n option of Sec. 2.3): means, standard errors, phases and gradients
+through the C-ABI, on ragged shapes, heavy generators and the 300-qubit
+workload at full size on sampled observables."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from paper_2501_04776_amd import api
+from tests.gpu_util import TOL, DevWorkload, grad_bar, wrap
+
+pytestmark = pytest.mark.gpu
+
+T = TOL["sparse_fp32"]
+
+
+def indep_words(seed, l, s, n):
+    """Packed uniform sample sets [l][s][W] and the 0/1 rows of set k."""
+    words = W.uniform_words(np.random.default_rng(seed), (l, s), n)
+    return words, lambda k: W.unpack_words(words[k], n)
+
+
+def run(dw, z, u=None, saved=True):
+    circ = api.Circuit(dw.n, dw.gens, dw.theta)
+    mean, se, ph = api.iqp_expval_indep(circ, dw.ops, z, phase_save=True)
+    g = None
+    if u is not None:
+        g = api.iqp_expval_indep_grad(circ, dw.ops, z, torch.from_numpy(u).cuda(),
+                                      ph if saved else None)
+    torch.cuda.synchronize()
+    return (mean.cpu().numpy(), se.cpu().numpy(), ph.cpu().numpy(),
+            g.cpu().numpy() if g is not None else None)
+
+
+@pytest.mark.parametrize("shape", [(5, 40, 3, 70), (70, 1000, 300, 700), (130, 2100, 129, 1025),
+                                   (2000, 700, 64, 257), (64, 3000, 40, 64)])
+def test_indep_matches_oracle(shape):
+    n, m, l, s = shape
+    w = W.small_random(600 + sum(shape), n, m, l, 1)
+    dw = DevWorkload(w)
+    words, rows01 = indep_words(sum(shape), l, s, n)
+    z = torch.from_numpy(words.view(np.int64)).cuda()
+    z01 = np.stack([rows01(k) for k in range(l)])
+    u = np.random.default_rng(3).normal(size=l)
+    mean, se, ph, g = run(dw, z, u)
+    om, ose, oph = oracle.expval_indep(n, w.gates, w.theta, dw.ops01, z01, phases=True)
+    og = oracle.expval_indep_grad(n, w.gates, w.theta, dw.ops01, z01, u)
+    assert np.abs(mean - om).max() < T
+    assert np.abs(se - ose).max() < T
+    assert np.abs(wrap(ph - oph)).max() < 100 * T
+    bar = grad_bar("sparse_fp32", w, dw.ops01, u)
+    assert np.all(np.abs(g - og) < bar), np.abs(g - og).max()
+
+
+def test_heavy_generators_and_recompute():
+    # generators of weight up to 12 (beyond the 8-entry support lists) walk
+    # their bit rows; the gradient recomputing the phases equals the one
+    # reading the saved phases bitwise
+    n, m, l, s = 100, 400, 50, 300
+    w = W.small_random(31, n, m, l, 1, gate_w=(1, 12))
+    dw = DevWorkload(w)
+    words, rows01 = indep_words(32, l, s, n)
+    z = torch.from_numpy(words.view(np.int64)).cuda()
+    u = np.random.default_rng(4).normal(size=l)
+    mean, _, _, g = run(dw, z, u, saved=True)
+    _, _, _, g2 = run(dw, z, u, saved=False)
+    z01 = np.stack([rows01(k) for k in range(l)])
+    om, _ = oracle.expval_indep(n, w.gates, w.theta, dw.ops01, z01)
+    og = oracle.expval_indep_grad(n, w.gates, w.theta, dw.ops01, z01, u)
+    assert np.abs(mean - om).max() < T
+    assert np.all(np.abs(g - og) < grad_bar("sparse_fp32", w, dw.ops01, u))
+    assert np.array_equal(g, g2)
+
+
+def test_one_shared_set_equals_the_sparse_shared_path_bitwise():
+    # every observable given the same sample set: the same sums in the same
+    # order as the shared-sample sparse form
+    n, m, l, s = 90, 1500, 70, 900
+    w = W.small_random(41, n, m, l, s)
+    dw = DevWorkload(w)
+    z = dw.samples.unsqueeze(0).expand(l, -1, -1).contiguous()
+    u = torch.from_numpy(np.random.default_rng(5).normal(size=l)).cuda()
+    circ = api.Circuit(n, dw.gens, dw.theta)
+    mi, si, pi = api.iqp_expval_indep(circ, dw.ops, z, phase_save=True)
+    gi = api.iqp_expval_indep_grad(circ, dw.ops, z, u, pi)
+    ms, ss, ps = api.iqp_expval(circ, dw.ops, dw.samples, "sparse_fp32", phase_save=True)
+    gs = api.iqp_expval_grad(circ, dw.ops, dw.samples, u, ps, "sparse_fp32")
+    torch.cuda.synchronize()
+    assert torch.equal(mi, ms) and torch.equal(si, ss) and torch.equal(pi, ps)
+    assert torch.equal(gi, gs)
+
+
+def test_indep_full_size_sampled():
+    # the 300-qubit workload (45150 gates, 1000 observables, 10000 samples
+    # each: 400 MB of sample words); the oracle checks 6 sampled observables
+    # with their own sample sets, and the gradient of a loss on those
+    w = W.cfg2()
+    dw = DevWorkload(w)
+    words, rows01 = indep_words(2025, w.l, w.s, w.n)
+    z = torch.from_numpy(words.view(np.int64)).cuda()
+    pick = np.random.default_rng(0).choice(w.l, size=6, replace=False)
+    u = np.zeros(w.l)
+    u[pick] = np.random.default_rng(1).normal(size=pick.size)
+    mean, se, _, g = run(dw, z, u)
+    z01 = np.stack([rows01(k) for k in pick])
+    om, ose = oracle.expval_indep(w.n, w.gates, w.theta, dw.ops01[pick], z01)
+    og = oracle.expval_indep_grad(w.n, w.gates, w.theta, dw.ops01[pick], z01, u[pick])
+    print("indep n=300 sampled: max|d mean| %.3g" % np.abs(mean[pick] - om).max())
+    assert np.abs(mean[pick] - om).max() < T
+    assert np.abs(se[pick] - ose).max() < T
+    assert np.all(np.abs(g - og) < grad_bar("sparse_fp32", w, dw.ops01[pick], u[pick]))

@@ -146,6 +146,23 @@ def uniform_bits(rng: np.random.Generator, count: int, n: int) -> np.ndarray:
     return rng.integers(0, 2, size=(count, n), dtype=np.uint8)
 
 
+def uniform_words(rng: np.random.Generator, shape, n: int) -> np.ndarray:
+    """Uniform bit strings already packed: uint64 [*shape][ceil(n/64)], qubit
+    q in bit q % 64 of word q // 64, the bits past n clear."""
+    Wd = (n + 63) // 64
+    words = rng.integers(0, 2**64, size=tuple(shape) + (Wd,), dtype=np.uint64, endpoint=False)
+    if n % 64:
+        words[..., -1] &= np.uint64((1 << (n % 64)) - 1)
+    return words
+
+
+def unpack_words(words: np.ndarray, n: int) -> np.ndarray:
+    """0/1 uint8 rows [count][n] of packed words [count][W]."""
+    words = np.ascontiguousarray(words, dtype=np.uint64)
+    by = words.view(np.uint8).reshape(words.shape[0], 8 * words.shape[1])
+    return np.unpackbits(by, axis=1, bitorder="little")[:, :n]
+
+
 def all_bitstrings(n: int) -> np.ndarray:
     """All 2^n bitstrings; row x has qubit q equal to bit q of x."""
     x = np.arange(1 << n, dtype=np.int64)
