@@ -34,7 +34,17 @@ TOL = {"fp32": 1e-5, "split_bf16": 1e-4, "sparse_fp32": 1e-5}
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2501_04776_amd", "csrc", "iqp_kernels.hip")
+# the sources the dense contraction kernels are compiled from
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2501_04776_amd", "csrc", f)
+                  for f in ("iqp_kernels.hip", "iqp_device.h")]
+
+
+def kernel_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -46,7 +56,6 @@ def recorded_traffic(workload_name, kernel):
     summary of this workload (FETCH_SIZE and WRITE_SIZE, each scaled by what the
     counter reads for a plain device copy of known size), or None when there is
     none or the kernel source changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_%s.md" % workload_name)
     if not os.path.exists(path):
         return None
@@ -54,8 +63,8 @@ def recorded_traffic(workload_name, kernel):
     if "```json" not in text:
         return None
     rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if rec.get("kernel_source_sha256") != sha or kernel not in rec.get("kernels", {}):
+    if rec.get("kernel_source_sha256") != kernel_source_sha256() or \
+            kernel not in rec.get("kernels", {}):
         return None
     k = rec["kernels"][kernel]
     return k["fetch_bytes"] + k["write_bytes"]
