@@ -401,6 +401,19 @@ def bench_indep(args, w, dw, circ, pick, T):
     steps = max(3, args.steps // 2)
     fwd_ms = timed(False, steps)
     ms = timed(True, steps)
+    # kernel families: "parity" holds the per-observable bit transposes of the
+    # samples (and the C parities), "phase_fwd" / "phase_bwd" the sparse bodies
+    api.profile_reset()
+    api.profile_enable(True)
+    for _ in range(2):
+        one(True)
+    torch.cuda.synchronize()
+    kb = {}
+    for fam in ("parity", "phase_fwd", "phase_bwd"):
+        tot, n = api.profile_query(fam)
+        if n:
+            kb[fam] = {"ms_per_step": tot / 2, "launches_per_step": n / 2}
+    api.profile_enable(False)
     # parity on sampled observables, each with its own sample set
     up = np.zeros(w.l)
     up[pick] = np.random.default_rng(4).normal(size=pick.size)
@@ -418,7 +431,7 @@ def bench_indep(args, w, dw, circ, pick, T):
     return {"fwd_ms": fwd_ms, "ms_per_step": ms, "fwd_terms_per_s": T / (fwd_ms * 1e-3),
             "fwd_bwd_terms_per_s": T / (ms * 1e-3),
             "terms": "dense-equivalent l*s*m with a separate sample set per observable",
-            "sample_words_bytes": int(words.nbytes),
+            "sample_words_bytes": int(words.nbytes), "kernels": kb,
             "parity": {"max_abs_err_mean": em, "max_abs_err_stderr": es,
                        "max_rel_err_grad": eg, "tol": tol,
                        "ok": bool(em < tol and es < tol and eg < tol),

@@ -155,7 +155,13 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x, int lane) {
         const int k = 32 >> st;
         const uint64_t m = masks[st];
         const uint64_t p = shfl_xor_u64(x, k);
-        x = (lane & k) ? ((x & ~m) | ((p & ~m) >> k)) : ((x & m) | ((p & m) << k));
+        // without branches: sel is all ones in the lanes with bit k set,
+        // which keep their high blocks and take the partner's high blocks
+        // shifted down; the others keep their low blocks and take the
+        // partner's low blocks shifted up
+        const uint64_t sel = (uint64_t)0 - (uint64_t)((lane >> (5 - st)) & 1);
+        const uint64_t moved = (((p & ~m) >> k) & sel) | (((p & m) << k) & ~sel);
+        x = (x & (m ^ sel)) | moved;
     }
     return x;
 }

@@ -263,10 +263,8 @@ struct IndepSliceArgs {
     int64_t ldx;
     uint64_t *xt;
 };
-// one wave per (set, word, 8 row words)
-inline int64_t blocks_of(const IndepSliceArgs &a) {
-    return ceil_div(a.l * a.W * ceil_div(a.ldx, 8), 4);
-}
+// one wave per (set, 8 row words); ldx is a multiple of 8
+inline int64_t blocks_of(const IndepSliceArgs &a) { return ceil_div(a.l * (a.ldx / 8), 4); }
 
 struct SparseFinishArgs {
     const long long *acc;

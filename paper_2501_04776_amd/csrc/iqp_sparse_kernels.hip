@@ -128,6 +128,24 @@ struct WordsOf<true> {
     }
 };
 
+// The set bits of row k of C (the generators J_k), in gate order.
+struct GateWalk {
+    const uint64_t IQP_CONST *row;
+    int64_t Gw, w;
+    uint64_t cw;
+    __device__ __forceinline__ GateWalk(const uint64_t IQP_CONST *r, int64_t gw)
+        : row(r), Gw(gw), w(0), cw(r[0]) {}
+    __device__ __forceinline__ bool next(int64_t &j) {
+        while (cw == 0) {
+            if (++w >= Gw) return false;
+            cw = row[w];
+        }
+        j = w * 64 + __builtin_ctzll(cw);
+        cw &= cw - 1;
+        return true;
+    }
+};
+
 // Sum over the 64 lanes, complete in lane 63, by data-parallel-primitive
 // moves (no LDS round trips): within quads, then rows of 16 (rotations), then
 // row 0 into row 1, row 2 into row 3, and lane 31 into rows 2 and 3. A fixed
@@ -280,7 +298,7 @@ __device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t 
     const int lane = threadIdx.x & 63;
     const int64_t sw0 = ch * kSpWords;
     const auto src = WordsOf<kIndep>::make(a.bsrc, k, sw0, sw0);
-    const uint64_t IQP_CONST *crow = cptr(a.crm) + k * a.Gw;
+    GateWalk gates(cptr(a.crm) + k * a.Gw, a.Gw);
     const double al = gptr(a.coef)[2 * k], be = gptr(a.coef)[2 * k + 1];
     const double scale = gptr(a.scale)[0];
     // S_ki = (alpha_k + beta_k cos E_ki) sin E_ki for the lane's samples
@@ -298,24 +316,43 @@ __device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t 
         S[r] = v;
         Ssum += v;
     }
-    for (int64_t w = 0; w < a.Gw; ++w) {
-        uint64_t cw = crow[w];
-        while (cw) {
-            const int64_t j = w * 64 + __builtin_ctzll(cw);
-            cw &= cw - 1;
-            uint64_t m[kSpWords];
+    auto add_partial = [&](int64_t j, float p) {
+        p = wave_sum_to_last(Ssum - 2.0f * p);
+        if (lane == 63) {
+            if (isfinite(p))
+                atomicAdd((unsigned long long *)&gptr(a.acc)[j],
+                          (unsigned long long)llrint((double)p * scale));
+            else
+                atomicOr((unsigned long long *)&gptr(a.acc)[a.m_pad], 1ull);
+        }
+    };
+    int64_t j;
+    uint64_t m[kSpWords];
+    if constexpr (!kIndep) {
+        // the next generator's parity words are loaded once the current ones
+        // are consumed, so the load overlaps the current cross-lane sum and
+        // atomic (the independent form's support walk has no scalar
+        // registers to spare for this)
+        bool have = gates.next(j);
+        src.words(have ? j : 0, m);
+        while (have) {
+            float p = 0.0f;
+#pragma unroll
+            for (int r = 0; r < kSpWords; ++r) p = add_where(p, S[r], m[r]);
+            int64_t jn = j;
+            const bool more = gates.next(jn);
+            src.words(jn, m);
+            add_partial(j, p);
+            j = jn;
+            have = more;
+        }
+    } else {
+        while (gates.next(j)) {
             src.words(j, m);
             float p = 0.0f;
 #pragma unroll
             for (int r = 0; r < kSpWords; ++r) p = add_where(p, S[r], m[r]);
-            p = wave_sum_to_last(Ssum - 2.0f * p);
-            if (lane == 63) {
-                if (isfinite(p))
-                    atomicAdd((unsigned long long *)&gptr(a.acc)[j],
-                              (unsigned long long)llrint((double)p * scale));
-                else
-                    atomicOr((unsigned long long *)&gptr(a.acc)[a.m_pad], 1ull);
-            }
+            add_partial(j, p);
         }
     }
 }
@@ -339,27 +376,36 @@ hipError_t launch_sparse_finish(const LaunchCtx &lc, const SparseFinishArgs &a) 
 
 // ---------------------------------------------------------------------------
 // Bit columns of every observable's own sample set. One wave per (set k,
-// word w, 8 row words): each of the 8 64-row blocks is loaded (lane r reads
-// word w of row 64 rw + r) and transposed across the lanes, so lane q then
-// holds column 64 w + q of 8 consecutive row words and writes them as one
-// 64-byte run.
+// group of 8 row words; ldx is a multiple of 8): for each qubit word w the 8
+// 64-row blocks are loaded (lane r reads word w of row 64 rw + r; rows past s
+// read a valid row and are zeroed, so the 8 loads issue together) and
+// transposed across the lanes; lane q then holds column 64 w + q of the 8
+// row words and writes them as one 64-byte run. (Taking the words of one
+// block in turn instead reuses the rows' lines better but spreads each
+// column's run over the whole unit, which was slower.)
 __device__ __forceinline__ void indep_slice_body(const IndepSliceArgs &a, int64_t blk) {
-    const int64_t ngrp = ceil_div(a.ldx, (int64_t)8);
+    const int64_t ngrp = a.ldx / 8;
     const int64_t unit = blk * 4 + wave_id();
-    if (unit >= a.l * a.W * ngrp) return;  // uniform over the wave
-    const int64_t k = unit / (a.W * ngrp);
-    const int64_t rem = unit - k * a.W * ngrp;
-    const int64_t w = rem / ngrp, g = rem - w * ngrp;
+    if (unit >= a.l * ngrp) return;  // uniform over the wave
+    const int64_t k = unit / ngrp, g = unit - k * ngrp;
     const int lane = threadIdx.x & 63;
     const uint64_t IQP_GLOBAL *rows = gptr(a.samples) + k * a.s * a.W;
-    uint64_t IQP_GLOBAL *dst = gptr(a.xt) + k * 64 * a.W * a.ldx + (w * 64 + lane) * a.ldx;
+    uint64_t IQP_GLOBAL *set = gptr(a.xt) + k * 64 * a.W * a.ldx;
+    int64_t r[8];
+    bool in[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-        const int64_t rw = g * 8 + t;
-        if (rw >= a.ldx) break;  // uniform
-        const int64_t r = rw * 64 + lane;
-        const uint64_t x = r < a.s ? rows[r * a.W + w] : 0ull;
-        dst[rw] = transpose64(x, lane);
+        const int64_t row = (g * 8 + t) * 64 + lane;
+        in[t] = row < a.s;
+        r[t] = in[t] ? row : a.s - 1;
+    }
+    for (int w = 0; w < a.W; ++w) {
+        uint64_t x[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) x[t] = rows[r[t] * a.W + w];
+        uint64_t IQP_GLOBAL *dst = set + (int64_t)(w * 64 + lane) * a.ldx + g * 8;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) dst[t] = transpose64(in[t] ? x[t] : 0ull, lane);
     }
 }
 
