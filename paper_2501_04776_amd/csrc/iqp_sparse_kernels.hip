@@ -146,34 +146,6 @@ struct GateWalk {
     }
 };
 
-// Sum over the 64 lanes, complete in lane 63, by data-parallel-primitive
-// moves (no LDS round trips): within quads, then rows of 16 (rotations), then
-// row 0 into row 1, row 2 into row 3, and lane 31 into rows 2 and 3. A fixed
-// order, so the result is reproducible.
-__device__ __forceinline__ float dpp_add(float x, int ctrl, int row_mask) {
-    int y;
-    switch (ctrl) {  // the control word must be a constant
-    case 0xb1: y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xb1, 0xf, 0xf, false); break;
-    case 0x4e: y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4e, 0xf, 0xf, false); break;
-    case 0x124: y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xf, 0xf, false); break;
-    case 0x128: y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, false); break;
-    case 0x142: y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xa, 0xf, false); break;
-    default: y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xc, 0xf, false); break;
-    }
-    (void)row_mask;
-    return x + __int_as_float(y);
-}
-
-__device__ __forceinline__ float wave_sum_to_last(float x) {
-    x = dpp_add(x, 0xb1, 0xf);   // quad_perm [1, 0, 3, 2]
-    x = dpp_add(x, 0x4e, 0xf);   // quad_perm [2, 3, 0, 1]
-    x = dpp_add(x, 0x124, 0xf);  // row_ror 4
-    x = dpp_add(x, 0x128, 0xf);  // row_ror 8: every lane holds its row's sum
-    x = dpp_add(x, 0x142, 0xa);  // row_bcast 15 into rows 1 and 3
-    x = dpp_add(x, 0x143, 0xc);  // row_bcast 31 into rows 2 and 3
-    return x;
-}
-
 // x + y in the lanes whose bit of the uniform mask is set, x elsewhere: one
 // add and one select on the mask held in a scalar register pair.
 __device__ __forceinline__ float add_where(float x, float y, uint64_t mask) {
@@ -289,6 +261,11 @@ hipError_t launch_sparse_bound(const LaunchCtx &lc, const SparseBoundArgs &a) {
     return plain_launch<SparseBoundArgs, sparse_bound_body>(lc, KF_WEIGHTS, a, blocks_of(a));
 }
 
+// generators per reduction batch of the backward; LDS row stride in floats
+// (a multiple of 4 for 16-byte reads; 68 spreads the rows over the banks)
+constexpr int kRedBatch = 16;
+constexpr int kRedStride = 68;
+
 template <bool kIndep>
 __device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t blk) {
     const int64_t nchunk = ceil_div(a.s, kEpiChunk);
@@ -316,23 +293,52 @@ __device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t 
         S[r] = v;
         Ssum += v;
     }
-    auto add_partial = [&](int64_t j, float p) {
-        p = wave_sum_to_last(Ssum - 2.0f * p);
-        if (lane == 63) {
-            if (isfinite(p))
-                atomicAdd((unsigned long long *)&gptr(a.acc)[j],
-                          (unsigned long long)llrint((double)p * scale));
+    // The partials of kRedBatch generators are gathered in this wave's LDS
+    // rows (row e, lane L: lane L's partial for the e-th generator of the
+    // batch) and reduced together: lane L sums 16 lanes of row L % 16, two
+    // shuffles add the four quarters, and lanes 0..15 add their generator's
+    // total into its fixed-point accumulator. One LDS write per generator
+    // instead of a full cross-lane sum and an atomic per generator.
+    __shared__ __attribute__((aligned(16))) float red_all[4][kRedBatch * kRedStride];
+    float *red = red_all[wave_id()];
+    int nb = 0;
+    int32_t jv = 0;  // lane e < nb: the generator of batch row e
+    auto flush = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int e = lane & (kRedBatch - 1), q = lane >> 4;
+        const float4 *row = reinterpret_cast<const float4 *>(red + e * kRedStride + 16 * q);
+        const float4 v0 = row[0], v1 = row[1], v2 = row[2], v3 = row[3];
+        float tot = ((v0.x + v0.y) + (v0.z + v0.w)) + ((v1.x + v1.y) + (v1.z + v1.w)) +
+                    (((v2.x + v2.y) + (v2.z + v2.w)) + ((v3.x + v3.y) + (v3.z + v3.w)));
+        tot += __shfl_xor(tot, 16, 64);
+        tot += __shfl_xor(tot, 32, 64);
+        if (lane < nb) {
+            if (isfinite(tot))
+                atomicAdd((unsigned long long *)&gptr(a.acc)[jv],
+                          (unsigned long long)llrint((double)tot * scale));
             else
                 atomicOr((unsigned long long *)&gptr(a.acc)[a.m_pad], 1ull);
         }
+        // the rows are rewritten by the next batch only after every lane read
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        nb = 0;
+    };
+    auto add_partial = [&](int64_t j, float p) {
+        red[nb * kRedStride + lane] = Ssum - 2.0f * p;
+        jv = lane == nb ? (int32_t)j : jv;
+        if (++nb == kRedBatch) flush();
     };
     int64_t j;
     uint64_t m[kSpWords];
     if constexpr (!kIndep) {
         // the next generator's parity words are loaded once the current ones
-        // are consumed, so the load overlaps the current cross-lane sum and
-        // atomic (the independent form's support walk has no scalar
-        // registers to spare for this)
+        // are consumed, so the load overlaps the current partial's store (the
+        // independent form's support walk has no scalar registers to spare
+        // for this)
         bool have = gates.next(j);
         src.words(have ? j : 0, m);
         while (have) {
@@ -355,6 +361,7 @@ __device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t 
             add_partial(j, p);
         }
     }
+    if (nb > 0) flush();
 }
 
 hipError_t launch_sparse_bwd(const LaunchCtx &lc, const SparseBwdArgs &a) {

@@ -338,3 +338,13 @@ def test_train_calls_reject_null_plan():
     assert lib.iqp_train_init(None, 0, FAKE, 1 << 40, None) == L.IQP_ERR_INVALID_ARG
     assert lib.iqp_train_workspace_bytes(None) == 0
     assert lib.iqp_train_buffers(None, FAKE, None, None, None) == L.IQP_ERR_INVALID_ARG
+
+
+def test_param_tables_group_gates_by_parameter_in_gate_order():
+    from paper_2501_04776_amd import api
+    idx = np.array([2, -1, 0, 2, 2, 0, -1, 3], dtype=np.int32)
+    offs, gates = api.param_tables(idx, 5, "cpu")
+    offs, gates = offs.numpy(), gates.numpy()
+    assert list(offs) == [0, 2, 2, 5, 6, 6]  # parameter 1 and 4 have no gates
+    for p in range(5):
+        assert list(gates[offs[p]:offs[p + 1]]) == [j for j in range(idx.size) if idx[j] == p]
