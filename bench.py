@@ -51,6 +51,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def nnz_terms(oracle, w, ops01):
+    """Terms the oracle actually evaluates: it skips C_kj = 0, so
+    sum_k |J_k| * s."""
+    return float(oracle.parity(w.n, ops01, w.gates).sum()) * w.s
+
+
 def recorded_traffic(workload_name, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 byte-counter
     summary of this workload (FETCH_SIZE and WRITE_SIZE, each scaled by what the
@@ -358,8 +374,11 @@ def main():
         log("oracle: %d observables in %.2f s on %d threads" % (k, dt, nth))
         result["cpu_baseline"] = {"value": k * w.s * w.m / dt, "unit": "terms/s",
                                   "cores": min(nth, k), "kind": "oracle",
+                                  "nnz_terms_per_s": nnz_terms(oracle, w, dw.ops01[:k]) / dt,
+                                  "cpu_model": cpu_model(), "wall_s": dt,
                                   "sample": "fwd+bwd of the first %d of %d observables over all "
-                                            "%d samples and %d gates (%.1f s)" %
+                                            "%d samples and %d gates (%.1f s); value counts the "
+                                            "dense-equivalent l*s*m terms" %
                                             (k, w.l, w.s, w.m, dt)}
     result["config"] = {"workload": w.name, "n_qubits": w.n, "gates": w.m, "observables": w.l,
                         "samples": w.s, "precision": "split_bf16 (hi+lo BF16, FP32 accumulate)",
@@ -664,8 +683,11 @@ def main_batch(args):
         log("oracle: %d observables of circuit 0 in %.2f s on %d threads" % (k, dt, nth))
         result["cpu_baseline"] = {"value": k * w.s * w.m / dt, "unit": "terms/s",
                                   "cores": min(nth, k), "kind": "oracle",
+                                  "nnz_terms_per_s": nnz_terms(oracle, w, d.ops01[:k]) / dt,
+                                  "cpu_model": cpu_model(), "wall_s": dt,
                                   "sample": "fwd+bwd of the first %d of %d observables of circuit "
-                                            "0 (n=%d, m=%d) over its %d samples (%.1f s)" %
+                                            "0 (n=%d, m=%d) over its %d samples (%.1f s); value "
+                                            "counts the dense-equivalent l*s*m terms" %
                                             (k, w.l, w.n, w.m, w.s, dt)}
     result["config"] = {"workload": name, "circuits": 64, "samples": 4096,
                         "n_qubits": "U{50..2000}", "gates": "U{1e3..2e5}",
