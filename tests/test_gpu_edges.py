@@ -1,0 +1,99 @@
+"""GPU vs oracle on the edge cases of the method: the smallest sizes (one
+qubit, gate, observable or sample), generators of weight 0 and heavier than
+the 8-entry support lists, and the 1000-qubit workload at full size on
+sampled observables (means and gradient), in every precision."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from paper_2501_04776_amd import api
+from tests.gpu_util import TOL, DevWorkload, grad_bar
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp32", "split_bf16", "sparse_fp32"]
+
+
+def _fwd_grad(w, prec, u):
+    dw = DevWorkload(w)
+    circ = api.Circuit(w.n, dw.gens, dw.theta)
+    mean, se, ph = api.iqp_expval(circ, dw.ops, dw.samples, prec, phase_save=True)
+    g = api.iqp_expval_grad(circ, dw.ops, dw.samples, torch.from_numpy(u).cuda(), ph, prec)
+    g2 = api.iqp_expval_grad(circ, dw.ops, dw.samples, torch.from_numpy(u).cuda(), None, prec)
+    torch.cuda.synchronize()
+    return dw, mean.cpu().numpy(), se.cpu().numpy(), g.cpu().numpy(), g2.cpu().numpy()
+
+
+def _check(w, prec, u):
+    dw, mean, se, g, g2 = _fwd_grad(w, prec, u)
+    om, ose = oracle.expval(w.n, w.gates, w.theta, dw.ops01, w.samples)
+    og = oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01, w.samples, u)
+    assert np.abs(mean - om).max() < TOL[prec], np.abs(mean - om).max()
+    assert np.abs(se - ose).max() < TOL[prec]
+    bar = grad_bar(prec, w, dw.ops01, u)
+    assert np.all(np.abs(g - og) < bar), np.abs(g - og).max()
+    assert np.all(np.abs(g2 - og) < bar)
+    return mean, se
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape", [(1, 1, 1, 1), (1, 3, 2, 5), (7, 1, 4, 9), (9, 12, 1, 64),
+                                   (9, 12, 5, 1), (64, 1, 1, 1025), (65, 129, 1, 2)])
+def test_smallest_sizes(prec, shape):
+    n, m, l, s = shape
+    w = W.small_random(700 + sum(shape), n, m, l, s, theta_scale=np.pi)
+    u = np.random.default_rng(7).normal(size=l)
+    mean, se = _check(w, prec, u)
+    if s == 1:
+        assert np.all(se == 0.0)  # one sample: the population deviation is 0
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_zero_weight_and_heavy_generators(prec):
+    # generators of weight 0 (no effect), weight 9..20 (past the support
+    # lists: the parity step walks their bit rows), mixed with light ones;
+    # observables of weight 0 and of full weight
+    n = 130
+    rng = np.random.default_rng(11)
+    lists = [[]] * 3 + [sorted(rng.choice(n, size=int(k), replace=False).tolist())
+                        for k in rng.integers(9, 21, size=40)]
+    lists += [sorted(rng.choice(n, size=int(k), replace=False).tolist())
+              for k in rng.integers(1, 4, size=300)]
+    order = rng.permutation(len(lists))
+    gates = W.rows_from_lists([lists[i] for i in order])
+    theta = rng.uniform(-np.pi, np.pi, size=gates.count)
+    ops = W.rows_from_lists([[], list(range(n))] +
+                            [sorted(rng.choice(n, size=int(k), replace=False).tolist())
+                             for k in rng.integers(1, 6, size=60)])
+    z = W.uniform_bits(rng, 700, n)
+    w = W.Workload("heavy", n, gates, theta, ops, z)
+    u = rng.normal(size=ops.count)
+    mean, se = _check(w, prec, u)
+    assert mean[0] == 1.0 and se[0] == 0.0
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_cfg3_full_size_sampled(prec):
+    # the 1000-qubit workload (10^5 generators of weight 1..3, theta in
+    # (-pi, pi), 10^4 observables of weight 1..10, 10^4 samples) at full
+    # size; the oracle recomputes 12 sampled observables and the gradient of
+    # a loss on those
+    w = W.cfg3()
+    dw = DevWorkload(w)
+    circ = api.Circuit(w.n, dw.gens, dw.theta)
+    pick = np.random.default_rng(0).choice(w.l, size=12, replace=False)
+    u = np.zeros(w.l)
+    u[pick] = np.random.default_rng(1).normal(size=pick.size)
+    mean, se, ph = api.iqp_expval(circ, dw.ops, dw.samples, prec, phase_save=True)
+    g = api.iqp_expval_grad(circ, dw.ops, dw.samples, torch.from_numpy(u).cuda(), ph, prec)
+    torch.cuda.synchronize()
+    om, ose = oracle.expval(w.n, w.gates, w.theta, dw.ops01[pick], w.samples)
+    og = oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01[pick], w.samples, u[pick])
+    d = np.abs(mean.cpu().numpy()[pick] - om)
+    print("cfg3 %s: max|d mean| %.3g" % (prec, d.max()))
+    assert d.max() < TOL[prec]
+    assert np.abs(se.cpu().numpy()[pick] - ose).max() < TOL[prec]
+    bar = grad_bar(prec, w, dw.ops01[pick], u[pick])
+    assert np.all(np.abs(g.cpu().numpy() - og) < bar)
