@@ -11,12 +11,12 @@ Prints ONE JSON line. The metric is phase terms per second, T = l * s * m
 headline value is split-BF16 fwd+bwd. Results are checked against the FP64
 oracle on sampled observables before the number is printed.
 
-The batched workload (64 circuits of uneven size, --workload cfg5) runs as
+The batched workload (64 circuits of uneven size, --workload batch64) runs as
 one BatchPlan: a step is the forward and the backward pass over all circuits,
 each pass one graph replay with persistent contraction kernels, tiles from
 the autotuner.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2|cfg3|cfg4|cfg5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload n300|n1000|mmd_n300|batch64]
 """
 from __future__ import annotations
 
@@ -88,12 +88,12 @@ def recorded_traffic(workload_name, kernel):
 
 def make_workload(name):
     import workloads as W
-    if name == "cfg2":
-        return W.cfg2()
-    if name == "cfg3":
-        return W.cfg3()
-    if name == "cfg4":
-        return W.cfg4()
+    if name == "n300":
+        return W.local_n300()
+    if name == "n1000":
+        return W.random_n1000()
+    if name == "mmd_n300":
+        return W.mmd_n300()
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -126,7 +126,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="n300",
+                    choices=["n300", "n1000", "mmd_n300", "batch64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-bitflip", action="store_true")
@@ -146,7 +147,7 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "cfg5":
+    if args.workload == "batch64":
         return main_batch(args)
 
     import torch
@@ -157,7 +158,7 @@ def main():
     dw = DevWorkload(w)
     circ = api.Circuit(w.n, dw.gens, dw.theta)
     T = w.terms
-    mmd = args.workload == "cfg4"
+    mmd = args.workload == "mmd_n300"
     log("workload %s: n=%d m=%d l=%d s=%d T=%.4g (setup %.1fs)" % (w.name, w.n, w.m, w.l, w.s, T,
                                                                    time.time() - t0))
     u = torch.from_numpy(np.random.default_rng(7).normal(size=w.l) / w.l).cuda()
@@ -531,7 +532,7 @@ def main_batch(args):
     from paper_2501_04776_amd import api
 
     t0 = time.time()
-    ws = [W.cfg5_circuit(i) for i in range(64)]
+    ws = [W.batch64_circuit(i) for i in range(64)]
     dws = [DevWorkload(w) for w in ws]
     T = float(sum(w.terms for w in ws))
     name = "batch64_s4096_seed505"

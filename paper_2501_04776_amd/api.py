@@ -3,7 +3,8 @@
 Bit rows (generators, observables, samples, data) are torch int64 tensors on
 the GPU holding the uint64 words of ``packing``; theta and weights are
 float64. Every call runs on torch's current stream and returns without
-synchronising. The workspace is a cached device buffer per device.
+synchronising. The workspace is a cached device buffer per device and
+stream.
 """
 from __future__ import annotations
 
@@ -54,11 +55,15 @@ def _vec(t: torch.Tensor, name: str, size: int, dtype=torch.float64) -> torch.Te
 
 
 class _Workspace:
+    """One cached workspace per (device, stream): calls queued on one stream
+    reuse it in order; calls on different streams get different buffers, so
+    they never share scratch memory."""
+
     def __init__(self):
         self.buf = {}
 
     def get(self, device: torch.device, nbytes: int) -> Tuple[torch.Tensor, int]:
-        key = device.index
+        key = (device.index, torch.cuda.current_stream(device).cuda_stream)
         cur = self.buf.get(key)
         if cur is None or cur.numel() < nbytes:
             # drop the old buffer before allocating the larger one; work still

@@ -210,7 +210,7 @@ def test_batched_workload_full_size_sampled():
     # 8 sampled circuits one by one, and their gradient for a dL/dmean that
     # is non-zero only on those observables
     prec = "split_bf16"
-    ws = [W.cfg5_circuit(i) for i in range(64)]
+    ws = [W.batch64_circuit(i) for i in range(64)]
     dws = [DevWorkload(w) for w in ws]
     plan = _plan(dws, prec)
     plan.expval()

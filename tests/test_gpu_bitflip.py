@@ -43,7 +43,7 @@ def test_bitflip_all_local_circuit_weight_one_matches_quantum_product_form():
     # for all-1-and-2-qubit circuits the weight-1 observables have no
     # interference terms, so the bitflip value equals the quantum one
     # (eq. expval_intefere with an empty set): pinned by the state vector
-    w = W.cfg1(enumerate_samples=True)
+    w = W.local_n10(enumerate_samples=True)
     ops1 = np.eye(w.n, dtype=np.uint8)
     w1 = W.Workload("w1", w.n, w.gates, w.theta, W.dense_to_rows(ops1), w.samples)
     dw = DevWorkload(w1)
@@ -93,7 +93,7 @@ def test_bitflip_autograd():
 def test_bitflip_large_sampled():
     # the n = 1000, 100000-gate circuit with its 10000 observables; the oracle
     # checks 16 sampled observables and their gradient contributions
-    w = W.cfg3()
+    w = W.random_n1000()
     dw = DevWorkload(w)
     circ = api.Circuit(dw.n, dw.gens, dw.theta)
     mean = api.iqp_bitflip_expval(circ, dw.ops)

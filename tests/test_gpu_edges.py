@@ -75,12 +75,12 @@ def test_zero_weight_and_heavy_generators(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_cfg3_full_size_sampled(prec):
+def test_n1000_full_size_sampled(prec):
     # the 1000-qubit workload (10^5 generators of weight 1..3, theta in
     # (-pi, pi), 10^4 observables of weight 1..10, 10^4 samples) at full
     # size; the oracle recomputes 12 sampled observables and the gradient of
     # a loss on those
-    w = W.cfg3()
+    w = W.random_n1000()
     dw = DevWorkload(w)
     circ = api.Circuit(w.n, dw.gens, dw.theta)
     pick = np.random.default_rng(0).choice(w.l, size=12, replace=False)
@@ -92,8 +92,32 @@ def test_cfg3_full_size_sampled(prec):
     om, ose = oracle.expval(w.n, w.gates, w.theta, dw.ops01[pick], w.samples)
     og = oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01[pick], w.samples, u[pick])
     d = np.abs(mean.cpu().numpy()[pick] - om)
-    print("cfg3 %s: max|d mean| %.3g" % (prec, d.max()))
+    print("n=1000 %s: max|d mean| %.3g" % (prec, d.max()))
     assert d.max() < TOL[prec]
     assert np.abs(se.cpu().numpy()[pick] - ose).max() < TOL[prec]
     bar = grad_bar(prec, w, dw.ops01[pick], u[pick])
     assert np.all(np.abs(g.cpu().numpy() - og) < bar)
+
+
+def test_calls_on_two_streams_do_not_share_scratch():
+    # two different problems queued alternately on two streams: each stream
+    # has its own cached workspace, so both results equal their single-stream
+    # values
+    ws = [W.small_random(900 + i, 80, 2000, 300, 2000) for i in range(2)]
+    dws = [DevWorkload(w) for w in ws]
+    circs = [api.Circuit(w.n, d.gens, d.theta) for w, d in zip(ws, dws)]
+    want = []
+    for c, d in zip(circs, dws):
+        want.append(api.iqp_expval(c, d.ops, d.samples, "split_bf16")[0].clone())
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    got = [[], []]
+    for rep in range(4):
+        for i in range(2):
+            with torch.cuda.stream(streams[i]):
+                got[i].append(api.iqp_expval(circs[i], dws[i].ops, dws[i].samples,
+                                             "split_bf16")[0])
+    torch.cuda.synchronize()
+    for i in range(2):
+        for g in got[i]:
+            assert torch.equal(g, want[i])

@@ -49,7 +49,7 @@ def test_grad_matches_oracle(prec, saved, shape):
 @pytest.mark.parametrize("prec", PRECS)
 def test_grad_matches_central_differences_on_gpu(prec):
     # the n = 10 all-local circuit; finite differences of the GPU forward, eps = 1e-3
-    w = W.cfg1(enumerate_samples=False)
+    w = W.local_n10(enumerate_samples=False)
     dw = DevWorkload(w)
     u = np.random.default_rng(2).normal(size=w.l)
     g = _grad(dw, u, "fp32", True)
@@ -93,12 +93,12 @@ def test_mmd_loss_and_grad_match_oracle(prec, unbiased):
     assert np.abs(g.cpu().numpy() - og).max() < _gtol(prec, og)
 
 
-def test_mmd_cfg4_shape_sampled():
+def test_mmd_n300_shape_sampled():
     # the differentiation workload's circuit (n = 300, 45150 gates), data
     # (2000 Bernoulli(0.3) strings) and operator distribution (3 bandwidths),
     # with 200 observables per bandwidth and s = 1000 so that the oracle's
     # full loss and gradient stay within seconds
-    w = W.cfg4(ops_per_sigma=200, s=1000)
+    w = W.mmd_n300(ops_per_sigma=200, s=1000)
     dw = DevWorkload(w)
     circ = api.Circuit(w.n, dw.gens, dw.theta)
     for prec in PRECS:
@@ -108,7 +108,7 @@ def test_mmd_cfg4_shape_sampled():
         if prec == "fp32":
             ol, og = oracle.mmd_loss_grad(w.n, w.gates, w.theta, dw.ops01, w.op_weight,
                                           w.samples, w.data, True)
-        print("cfg4(200/sigma, s=1000) %s: loss %.8g vs %.8g, grad max|d| %.3g of %.3g" %
+        print("mmd n=300 (200/sigma, s=1000) %s: loss %.8g vs %.8g, grad max|d| %.3g of %.3g" %
               (prec, loss.item(), ol, np.abs(g.cpu().numpy() - og).max(), np.abs(og).max()))
         assert abs(loss.item() - ol) < TOL[prec]
         assert np.abs(g.cpu().numpy() - og).max() < _gtol(prec, og)
@@ -172,3 +172,42 @@ def test_grad_every_sample_split_matches_oracle(prec, monkeypatch):
     monkeypatch.delenv("IQP_BWD_SPLITS")
     for ks in (2, 5, 12):
         assert np.abs(got[ks] - got[1]).max() < 1e-6 * max(1.0, np.abs(og).max())
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mmd_full_size_consistency(prec):
+    # the MMD workload at full size (3 x 2000 operators, 10^4 samples, 2000
+    # training strings). The loss sums over every operator, so instead of
+    # sampled outputs it is checked against properties that hold at any
+    # size: (1) both estimator forms equal their formula rebuilt from
+    # iqp_expval's means and standard errors and the oracle's exact data
+    # terms; (2) the plug-in form's gradient equals iqp_expval_grad with
+    # u_k = 2 w_k (q_k - p_k).
+    w = W.mmd_n300()
+    dw = DevWorkload(w)
+    circ = api.Circuit(w.n, dw.gens, dw.theta)
+    N, s = w.data.shape[0], w.s
+    odd = oracle.parity(w.n, w.data, w.ops).sum(axis=0).astype(np.float64)
+    p = (N - 2.0 * odd) / N
+    mean, se, _ = api.iqp_expval(circ, dw.ops, dw.samples, prec)
+    torch.cuda.synchronize()
+    q, se = mean.cpu().numpy(), se.cpu().numpy()
+    sum_c = s * q
+    sum_c2 = s * (s * se * se + q * q)
+    wts = w.op_weight
+    want = {False: float(np.sum(wts * (p - q) ** 2)),
+            True: float(np.sum(wts * (((N * p) ** 2 - N) / (N * (N - 1)) - 2.0 * p * q +
+                                      (sum_c ** 2 - sum_c2) / (s * (s - 1)))))}
+    for unbiased in (False, True):
+        loss, g = api.iqp_mmd_loss_grad(circ, dw.ops, dw.op_weight, dw.samples, dw.data,
+                                        unbiased, True, prec)
+        torch.cuda.synchronize()
+        print("mmd full %s unbiased=%s: loss %.10g vs %.10g" % (prec, unbiased, loss.item(),
+                                                               want[unbiased]))
+        assert abs(loss.item() - want[unbiased]) < 1e-10 * max(1.0, abs(want[unbiased]))
+        if not unbiased:
+            u = torch.from_numpy(2.0 * wts * (q - p)).cuda()
+            gref = api.iqp_expval_grad(circ, dw.ops, dw.samples, u, None, prec)
+            torch.cuda.synchronize()
+            a, b = g.cpu().numpy(), gref.cpu().numpy()
+            assert np.abs(a - b).max() <= 1e-9 * max(1e-30, np.abs(b).max())

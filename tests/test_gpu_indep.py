@@ -96,7 +96,7 @@ def test_indep_full_size_sampled():
     # the 300-qubit workload (45150 gates, 1000 observables, 10000 samples
     # each: 400 MB of sample words); the oracle checks 6 sampled observables
     # with their own sample sets, and the gradient of a loss on those
-    w = W.cfg2()
+    w = W.local_n300()
     dw = DevWorkload(w)
     words, rows01 = indep_words(2025, w.l, w.s, w.n)
     z = torch.from_numpy(words.view(np.int64)).cuda()

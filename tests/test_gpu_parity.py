@@ -92,22 +92,22 @@ def _run(dw, prec, phase=False):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_cfg1_enumeration_matches_statevector(prec):
-    w = W.cfg1(enumerate_samples=True)
+def test_n10_enumeration_matches_statevector(prec):
+    w = W.local_n10(enumerate_samples=True)
     dw = DevWorkload(w)
     mean, se, _ = _run(dw, prec)
     exact = oracle.statevector_expval(w.n, w.gates, w.theta, dw.ops01)
     om, ose = oracle.expval(w.n, w.gates, w.theta, dw.ops01, w.samples)
     assert np.abs(om - exact).max() < 1e-12
     err = np.abs(mean - exact)
-    print("cfg1 enumeration %s: max|d mean| = %.3g" % (prec, err.max()))
+    print("n=10 enumeration %s: max|d mean| = %.3g" % (prec, err.max()))
     assert err.max() < TOL[prec]
     assert np.abs(se - ose).max() < TOL[prec]
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_cfg1_random_samples_match_oracle(prec):
-    w = W.cfg1(enumerate_samples=False)
+def test_n10_random_samples_match_oracle(prec):
+    w = W.local_n10(enumerate_samples=False)
     dw = DevWorkload(w)
     mean, se, ph = _run(dw, prec, phase=True)
     om, ose, oph = oracle.expval(w.n, w.gates, w.theta, dw.ops01, w.samples, phases=True)
@@ -172,16 +172,16 @@ def test_deterministic_repeat(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_cfg2_full_size_sampled_observables(prec):
+def test_n300_full_size_sampled_observables(prec):
     # the n = 300, 45150-gate, 1000 x 10000 workload at full size; the oracle
     # recomputes 24 sampled observables one by one on the same samples
-    w = W.cfg2()
+    w = W.local_n300()
     dw = DevWorkload(w)
     mean, se, _ = _run(dw, prec)
     pick = np.random.default_rng(0).choice(w.l, size=24, replace=False)
     om, ose = oracle.expval(w.n, w.gates, w.theta, dw.ops01[pick], w.samples)
     d = np.abs(mean[pick] - om)
-    print("cfg2 %s: max|d mean| = %.3g  max|d stderr| = %.3g" % (prec, d.max(),
+    print("n=300 %s: max|d mean| = %.3g  max|d stderr| = %.3g" % (prec, d.max(),
                                                                   np.abs(se[pick] - ose).max()))
     assert d.max() < TOL[prec]
     assert np.abs(se[pick] - ose).max() < TOL[prec]

@@ -194,7 +194,7 @@ def sigma_bit_probability(sigma: float) -> float:
 # The benchmark and parity workloads
 # ---------------------------------------------------------------------------
 
-def cfg1(enumerate_samples: bool = True, seed: int = 101) -> Workload:
+def local_n10(enumerate_samples: bool = True, seed: int = 101) -> Workload:
     """n = 10, all 55 one- and two-qubit gates, theta ~ U(-pi, pi), 100
     observables of weight U{1..3}; samples are all 1024 bitstrings or 1000
     uniform ones."""
@@ -208,7 +208,7 @@ def cfg1(enumerate_samples: bool = True, seed: int = 101) -> Workload:
                     samples, seed=seed)
 
 
-def cfg2(seed: int = 202, s: int = 10000, l: int = 1000) -> Workload:
+def local_n300(seed: int = 202, s: int = 10000, l: int = 1000) -> Workload:
     """n = 300, all 45150 one- and two-qubit gates, theta ~ N(0, 0.1^2),
     1000 weight-2 observables, 10000 uniform samples."""
     g, t, o, z, _ = streams(seed)
@@ -221,7 +221,7 @@ def cfg2(seed: int = 202, s: int = 10000, l: int = 1000) -> Workload:
                     seed=seed)
 
 
-def cfg3(seed: int = 303, m: int = 100000, l: int = 10000, s: int = 10000) -> Workload:
+def random_n1000(seed: int = 303, m: int = 100000, l: int = 10000, s: int = 10000) -> Workload:
     """n = 1000, 100000 generators of weight U{1..3}, theta ~ U(-pi, pi),
     10000 observables of weight U{1..10}, 10000 samples."""
     g, t, o, z, _ = streams(seed)
@@ -234,7 +234,7 @@ def cfg3(seed: int = 303, m: int = 100000, l: int = 10000, s: int = 10000) -> Wo
                     seed=seed)
 
 
-def cfg4(seed: int = 404, ops_per_sigma: int = 2000, s: int = 10000,
+def mmd_n300(seed: int = 404, ops_per_sigma: int = 2000, s: int = 10000,
          N: int = 2000, sigmas=(1.0, 5.0, 17.0)) -> Workload:
     """MMD form: the n = 300 all-local circuit, theta ~ N(0, 0.1^2); 2000
     Bernoulli(0.3) training bitstrings; per bandwidth sigma, 2000 observables
@@ -254,7 +254,7 @@ def cfg4(seed: int = 404, ops_per_sigma: int = 2000, s: int = 10000,
                     theta, ops, samples, data=data, op_weight=op_weight, seed=seed)
 
 
-def cfg5_shapes(seed: int = 505, count: int = 64):
+def batch64_shapes(seed: int = 505, count: int = 64):
     """(n, m, l) of the batched workload's circuits: n ~ U{50..2000},
     m ~ U{1e3..2e5}, l ~ U{100..5000}."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
@@ -264,11 +264,11 @@ def cfg5_shapes(seed: int = 505, count: int = 64):
     return [(int(a), int(b), int(c)) for a, b, c in zip(n, m, l)]
 
 
-def cfg5_circuit(index: int, seed: int = 505, s: int = 4096, scale: float = 1.0) -> Workload:
+def batch64_circuit(index: int, seed: int = 505, s: int = 4096, scale: float = 1.0) -> Workload:
     """Circuit ``index`` of the batched workload: generators of weight
     U{1..4}, theta ~ U(-pi, pi), observables of weight U{1..4}, s = 4096.
     ``scale`` < 1 shrinks m and l (for oracle-sized parity cases)."""
-    n, m, l = cfg5_shapes(seed)[index]
+    n, m, l = batch64_shapes(seed)[index]
     m = max(1, int(m * scale))
     l = max(1, int(l * scale))
     g, t, o, z, _ = streams(seed * 1000 + index)
