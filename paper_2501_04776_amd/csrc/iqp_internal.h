@@ -255,7 +255,8 @@ inline int64_t blocks_of(const SparseBwdArgs &a) {
 
 // Bit columns of l sample sets of s rows each ([l][s][W], row i of set k at
 // samples + (k s + i) W): xt[k * 64 W * ldx + q * ldx + rw], bit r = qubit q
-// of row 64 rw + r of set k (rows >= s read as 0), q < 64 W, rw < ldx.
+// of row 64 rw + r of set k (rows >= s read as 0), q < 64 W, rw < ldx (a
+// multiple of 16; one block per set and 16 row words).
 struct IndepSliceArgs {
     const uint64_t *samples;
     int64_t l, s;
@@ -263,8 +264,6 @@ struct IndepSliceArgs {
     int64_t ldx;
     uint64_t *xt;
 };
-// one wave per (set, 8 row words); ldx is a multiple of 8
-inline int64_t blocks_of(const IndepSliceArgs &a) { return ceil_div(a.l * (a.ldx / 8), 4); }
 
 struct SparseFinishArgs {
     const long long *acc;

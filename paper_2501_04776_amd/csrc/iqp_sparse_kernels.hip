@@ -382,42 +382,150 @@ hipError_t launch_sparse_finish(const LaunchCtx &lc, const SparseFinishArgs &a) 
 }
 
 // ---------------------------------------------------------------------------
-// Bit columns of every observable's own sample set. One wave per (set k,
-// group of 8 row words; ldx is a multiple of 8): for each qubit word w the 8
-// 64-row blocks are loaded (lane r reads word w of row 64 rw + r; rows past s
-// read a valid row and are zeroed, so the 8 loads issue together) and
-// transposed across the lanes; lane q then holds column 64 w + q of the 8
-// row words and writes them as one 64-byte run. (Taking the words of one
-// block in turn instead reuses the rows' lines better but spreads each
-// column's run over the whole unit, which was slower.)
-__device__ __forceinline__ void indep_slice_body(const IndepSliceArgs &a, int64_t blk) {
-    const int64_t ngrp = a.ldx / 8;
-    const int64_t unit = blk * 4 + wave_id();
-    if (unit >= a.l * ngrp) return;  // uniform over the wave
-    const int64_t k = unit / ngrp, g = unit - k * ngrp;
-    const int lane = threadIdx.x & 63;
-    const uint64_t IQP_GLOBAL *rows = gptr(a.samples) + k * a.s * a.W;
-    uint64_t IQP_GLOBAL *set = gptr(a.xt) + k * 64 * a.W * a.ldx;
-    int64_t r[8];
-    bool in[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const int64_t row = (g * 8 + t) * 64 + lane;
-        in[t] = row < a.s;
-        r[t] = in[t] ? row : a.s - 1;
+// Bit columns of every observable's own sample set. A step is (set k, group g
+// of 16 row words = 1024 rows, chunk c of 8 qubit words); ldx is a multiple
+// of 16. Persistent blocks (two per CU: LDS and registers allow two) take
+// steps b, b + grid, ...: the block reads words [8c, 8c + 8) of its 1024 rows
+// with coalesced loads (8 lanes cover one row's run) into registers, moves
+// them to LDS (row stride 9 words, so the column reads below hit distinct
+// banks) and issues the loads of its next step, which stay in flight while
+// wave v transposes words v and v + 4: for each of the 16 64-row blocks lane
+// r takes row r's word from LDS and the 64 x 64 bit transpose leaves lane q
+// with column 64 w + q, so lane q writes that column's 16 row words as one
+// 128-byte run, a whole cache line. Every sample word is read once and every
+// output line written by one lane. Rows past s read as 0.
+// The 64 x 64 bit transpose of transpose64 (same butterfly, same result)
+// with the lane exchanges done by gfx950's cross-lane moves rather than LDS
+// permutes: the 32- and 16-lane stages swap whole registers between the
+// wave's halves / alternate 16-lane rows; in the stages 8, 2 and 1 apart a
+// DPP move fetches the partner's dword, 4 apart a swizzle. There each lane
+// first rotates its dword by k (left by k where lane bit k is set), so the
+// partner's blocks arrive where they belong, and a bit-field insert keeps
+// its own blocks.
+template <int K>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+    if constexpr (K == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
+    if constexpr (K == 4) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
+    if constexpr (K == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    if constexpr (K == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    return v;
+}
+
+template <int K, int LOGK, uint32_t M>
+__device__ __forceinline__ void small_stage(uint32_t &lo, uint32_t &hi, int lane) {
+    const bool up = (lane >> LOGK) & 1;
+    const uint32_t keep = up ? ~M : M;
+    const uint32_t amt = up ? 32 - K : K;
+    const uint32_t rl = lane_xor<K>(__builtin_amdgcn_alignbit(lo, lo, amt));
+    const uint32_t rh = lane_xor<K>(__builtin_amdgcn_alignbit(hi, hi, amt));
+    lo = (lo & keep) | (rl & ~keep);
+    hi = (hi & keep) | (rh & ~keep);
+}
+
+__device__ __forceinline__ uint64_t transpose64_xlane(uint64_t x, int lane) {
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    {  // 32 apart: lanes 32..63 take the low dword of lanes 0..31 as their
+       // low dword, lanes 0..31 the high dword of lanes 32..63 as their high
+        const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+        lo = r[0];
+        hi = r[1];
     }
-    for (int w = 0; w < a.W; ++w) {
-        uint64_t x[8];
+    {  // 16 apart: gather the low and the high 16-bit halves of the two
+       // dwords, swap the odd rows of the first with the even rows of the
+       // second, spread them back
+        uint32_t a = (lo & 0xFFFFu) | (hi << 16), b = (lo >> 16) | (hi & 0xFFFF0000u);
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+        lo = (a & 0xFFFFu) | (b << 16);
+        hi = (a >> 16) | (b & 0xFFFF0000u);
+    }
+    small_stage<8, 3, 0x00FF00FFu>(lo, hi, lane);
+    small_stage<4, 2, 0x0F0F0F0Fu>(lo, hi, lane);
+    small_stage<2, 1, 0x33333333u>(lo, hi, lane);
+    small_stage<1, 0, 0x55555555u>(lo, hi, lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+constexpr int kSliceWords = 16;  // row words per step: 1024 rows
+constexpr int kSliceChunk = 8;   // qubit words per step
+constexpr int kSliceStride = kSliceChunk + 1;
+constexpr int64_t kSliceBlocks = 512;
+
+struct SliceStep {
+    int64_t k, g;
+    int w0, cw;
+};
+
+__device__ __forceinline__ SliceStep slice_step(const IndepSliceArgs &a, int64_t q) {
+    const int64_t ngrp = a.ldx / kSliceWords;
+    const int nch = (a.W + kSliceChunk - 1) / kSliceChunk;
+    const int64_t u = q / nch;
+    SliceStep st;
+    st.w0 = (int)(q - u * nch) * kSliceChunk;
+    st.cw = a.W - st.w0 < kSliceChunk ? a.W - st.w0 : kSliceChunk;
+    st.k = u / ngrp;
+    st.g = u - st.k * ngrp;
+    return st;
+}
+
+// this thread's 32 words of a step: word j of rows r0 + 32 it (rows past s
+// read row s - 1 here and are zeroed when stored to LDS, so that nothing
+// waits on these loads before then)
+__device__ __forceinline__ void slice_load(const IndepSliceArgs &a, const SliceStep &st, int j,
+                                           int r0, uint64_t (&v)[32]) {
+    if (j >= st.cw) return;
+    const uint64_t IQP_GLOBAL *rows = gptr(a.samples) + st.k * a.s * a.W + st.w0 + j;
+    const int64_t base = st.g * (kSliceWords * 64) + r0;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) x[t] = rows[r[t] * a.W + w];
-        uint64_t IQP_GLOBAL *dst = set + (int64_t)(w * 64 + lane) * a.ldx + g * 8;
+    for (int it = 0; it < 32; ++it) {
+        const int64_t row = base + 32 * it;
+        v[it] = rows[(row < a.s ? row : a.s - 1) * a.W];
+    }
+}
+
+__device__ __forceinline__ void indep_slice_body(const IndepSliceArgs &a, int64_t blk) {
+    __shared__ uint64_t stage[kSliceWords * 64 * kSliceStride];
+    const int64_t total = a.l * (a.ldx / kSliceWords) * ((a.W + kSliceChunk - 1) / kSliceChunk);
+    const int64_t grid = gridDim.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j = tid & (kSliceChunk - 1);  // word within the chunk this thread loads
+    const int r0 = tid / kSliceChunk;       // first of its rows; the rest step by 32
+    uint64_t v[32];
+    SliceStep st = slice_step(a, blk);
+    if (blk < total) slice_load(a, st, j, r0, v);
+    for (int64_t q = blk; q < total; q += grid) {
+        __syncthreads();  // the previous step's LDS reads are done
+        if (j < st.cw) {
+            const int64_t base = st.g * (kSliceWords * 64) + r0;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) dst[t] = transpose64(in[t] ? x[t] : 0ull, lane);
+            for (int it = 0; it < 32; ++it)
+                stage[(r0 + 32 * it) * kSliceStride + j] = base + 32 * it < a.s ? v[it] : 0ull;
+        }
+        __syncthreads();
+        const SliceStep cur = st;
+        if (q + grid < total) {
+            st = slice_step(a, q + grid);
+            slice_load(a, st, j, r0, v);
+        }
+        uint64_t IQP_GLOBAL *set = gptr(a.xt) + cur.k * 64 * a.W * a.ldx + cur.g * kSliceWords;
+        for (int jw = wave; jw < cur.cw; jw += 4) {
+            uint64_t y[kSliceWords];
+#pragma unroll
+            for (int t = 0; t < kSliceWords; ++t)
+                y[t] = transpose64_xlane(stage[(t * 64 + lane) * kSliceStride + jw], lane);
+            uint64_t IQP_GLOBAL *dst = set + (int64_t)((cur.w0 + jw) * 64 + lane) * a.ldx;
+#pragma unroll
+            for (int t = 0; t < kSliceWords; ++t) dst[t] = y[t];
+        }
     }
 }
 
 hipError_t launch_indep_slice(const LaunchCtx &lc, const IndepSliceArgs &a) {
-    return plain_launch<IndepSliceArgs, indep_slice_body>(lc, KF_PARITY, a, blocks_of(a));
+    if (a.ldx % kSliceWords != 0 || a.s < 1) return hipErrorInvalidValue;
+    const int64_t steps = a.l * (a.ldx / kSliceWords) * ((a.W + kSliceChunk - 1) / kSliceChunk);
+    return plain_launch<IndepSliceArgs, indep_slice_body>(lc, KF_PARITY, a,
+                                                          steps < kSliceBlocks ? steps : kSliceBlocks);
 }
 
 }  // namespace iqp
