@@ -61,20 +61,32 @@ struct IndepWords {
     const uint64_t IQP_CONST *gens;
     int W;
     const uint64_t IQP_GLOBAL *lane0;  // xt + k * xstride + the lane's own word
+    // The first four support entries come in one scalar load, so the
+    // column loads of a generator of weight <= 4 issue together.
     __device__ __forceinline__ uint64_t word(int64_t j) const {
         const int32_t IQP_CONST *sj = sup + j * kSupCap;
-        uint64_t x = 0;
-        if (sj[0] == -2) {
-            for (int w = 0; w < W; ++w) {
-                uint64_t g = gens[j * W + w];
-                while (g) {
-                    x ^= lane0[(int64_t)(w * 64 + __builtin_ctzll(g)) * ldx];
-                    g &= g - 1;
+        const int32_t q0 = sj[0], q1 = sj[1], q2 = sj[2], q3 = sj[3];
+        if (q0 < 0) {
+            uint64_t x = 0;
+            if (q0 == -2) {
+                for (int w = 0; w < W; ++w) {
+                    uint64_t g = gens[j * W + w];
+                    while (g) {
+                        x ^= lane0[(int64_t)(w * 64 + __builtin_ctzll(g)) * ldx];
+                        g &= g - 1;
+                    }
                 }
             }
             return x;
         }
-        for (int e = 0; e < kSupCap; ++e) {
+        uint64_t x = lane0[(int64_t)q0 * ldx];
+        if (q1 < 0) return x;
+        x ^= lane0[(int64_t)q1 * ldx];
+        if (q2 < 0) return x;
+        x ^= lane0[(int64_t)q2 * ldx];
+        if (q3 < 0) return x;
+        x ^= lane0[(int64_t)q3 * ldx];
+        for (int e = 4; e < kSupCap; ++e) {
             const int32_t q = sj[e];
             if (q < 0) break;
             x ^= lane0[(int64_t)q * ldx];
@@ -86,21 +98,36 @@ struct IndepWords {
 #pragma unroll
         for (int r = 0; r < kSpWords; ++r) m[r] ^= c[r];
     }
+    // The XORs run on the scalar unit, which bounds the backward: the first
+    // column is loaded into m rather than XORed into zeros, and the first
+    // four support entries come in one load.
     __device__ __forceinline__ void words(int64_t j, uint64_t (&m)[kSpWords]) const {
-#pragma unroll
-        for (int r = 0; r < kSpWords; ++r) m[r] = 0ull;
         const int32_t IQP_CONST *sj = sup + j * kSupCap;
-        if (sj[0] == -2) {
-            for (int w = 0; w < W; ++w) {
-                uint64_t g = gens[j * W + w];
-                while (g) {
-                    add_column(w * 64 + __builtin_ctzll(g), m);
-                    g &= g - 1;
+        const int32_t q0 = sj[0], q1 = sj[1], q2 = sj[2], q3 = sj[3];
+        if (q0 < 0) {
+#pragma unroll
+            for (int r = 0; r < kSpWords; ++r) m[r] = 0ull;
+            if (q0 == -2) {
+                for (int w = 0; w < W; ++w) {
+                    uint64_t g = gens[j * W + w];
+                    while (g) {
+                        add_column(w * 64 + __builtin_ctzll(g), m);
+                        g &= g - 1;
+                    }
                 }
             }
             return;
         }
-        for (int e = 0; e < kSupCap; ++e) {
+        const uint64_t IQP_CONST *c = col0 + (int64_t)q0 * ldx;
+#pragma unroll
+        for (int r = 0; r < kSpWords; ++r) m[r] = c[r];
+        if (q1 < 0) return;
+        add_column(q1, m);
+        if (q2 < 0) return;
+        add_column(q2, m);
+        if (q3 < 0) return;
+        add_column(q3, m);
+        for (int e = 4; e < kSupCap; ++e) {
             const int32_t q = sj[e];
             if (q < 0) break;
             add_column(q, m);
