@@ -34,8 +34,10 @@ def run(dw, z, u=None, saved=True):
             g.cpu().numpy() if g is not None else None)
 
 
+# n = 700 (11 qubit words) leaves a last bit-transpose chunk of 3 words;
+# n = 2000 (32 words) takes four full chunks
 @pytest.mark.parametrize("shape", [(5, 40, 3, 70), (70, 1000, 300, 700), (130, 2100, 129, 1025),
-                                   (2000, 700, 64, 257), (64, 3000, 40, 64)])
+                                   (2000, 700, 64, 257), (64, 3000, 40, 64), (700, 500, 40, 1500)])
 def test_indep_matches_oracle(shape):
     n, m, l, s = shape
     w = W.small_random(600 + sum(shape), n, m, l, 1)
