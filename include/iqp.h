@@ -46,7 +46,7 @@ typedef enum {
     IQP_ERR_INVALID_ARG = -1, /* a null pointer, a size out of range, n/W mismatch */
     IQP_ERR_WORKSPACE = -2,   /* ws_bytes smaller than iqp_workspace_bytes() */
     IQP_ERR_HIP = -3,         /* a HIP runtime call failed (see iqp_last_error) */
-    IQP_ERR_UNSUPPORTED = -4  /* an option this build does not implement */
+    IQP_ERR_UNSUPPORTED = -4  /* an option the library does not implement */
 } iqp_status;
 
 /* Arithmetic of the phase contraction E = C Theta B^T.
