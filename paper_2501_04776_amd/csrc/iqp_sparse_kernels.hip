@@ -426,9 +426,9 @@ hipError_t launch_sparse_finish(const LaunchCtx &lc, const SparseFinishArgs &a) 
 // permutes: the 32- and 16-lane stages swap whole registers between the
 // wave's halves / alternate 16-lane rows; in the stages 8, 2 and 1 apart a
 // DPP move fetches the partner's dword, 4 apart a swizzle. There each lane
-// first rotates its dword by k (left by k where lane bit k is set), so the
-// partner's blocks arrive where they belong, and a bit-field insert keeps
-// its own blocks.
+// first rotates its dword right by k (left by k where its lane index has the
+// bit of value k set), so the partner's blocks arrive where they belong, and
+// a bit-field insert keeps its own blocks.
 template <int K>
 __device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
     if constexpr (K == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
@@ -451,8 +451,8 @@ __device__ __forceinline__ void small_stage(uint32_t &lo, uint32_t &hi, int lane
 
 __device__ __forceinline__ uint64_t transpose64_xlane(uint64_t x, int lane) {
     uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-    {  // 32 apart: lanes 32..63 take the low dword of lanes 0..31 as their
-       // low dword, lanes 0..31 the high dword of lanes 32..63 as their high
+    {  // 32 apart: lanes 32..63 take the high dword of lanes 0..31 as their
+       // low dword, lanes 0..31 the low dword of lanes 32..63 as their high
         const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
         lo = r[0];
         hi = r[1];
