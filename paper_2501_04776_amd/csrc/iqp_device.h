@@ -136,34 +136,63 @@ __device__ __forceinline__ void persistent_loop(const int64_t *__restrict__ off,
 }
 
 
-// 64x64 bit transposes across the lanes of a wave.
+// 64x64 bit transpose across the lanes of a wave.
 // transpose64: lane r holds row r of a 64x64 bit matrix (bit c = column c)
 // and receives row r of its transpose. Six butterfly stages: at block size k
-// lanes r and r^k swap the off-diagonal k x k blocks of their 2k x 2k block.
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int k) {
-    const int lo = __shfl_xor((int)(uint32_t)x, k, 64);
-    const int hi = __shfl_xor((int)(uint32_t)(x >> 32), k, 64);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+// lanes r and r^k swap the off-diagonal k x k blocks of their 2k x 2k block
+// (the lane with bit k clear keeps its low blocks and takes the partner's
+// low blocks shifted up; the other keeps its high blocks and takes the
+// partner's high blocks shifted down). The lane exchanges use gfx950's
+// cross-lane moves rather than LDS permutes: the 32- and 16-lane stages swap
+// whole registers between the wave's halves / alternate 16-lane rows; in the
+// stages 8, 2 and 1 apart a DPP move fetches the partner's dword, 4 apart a
+// swizzle. There each lane first rotates its dword right by k (left by k
+// where its lane index has the bit of value k set), so the partner's blocks
+// arrive where they belong, and a bit-field insert keeps its own blocks.
+// 35 VALU instructions and 2 swizzles per transpose.
+template <int K>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+    if constexpr (K == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
+    if constexpr (K == 4) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
+    if constexpr (K == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    if constexpr (K == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    return v;
+}
+
+template <int K, int LOGK, uint32_t M>
+__device__ __forceinline__ void small_stage(uint32_t &lo, uint32_t &hi, int lane) {
+    const bool up = (lane >> LOGK) & 1;
+    const uint32_t keep = up ? ~M : M;
+    const uint32_t amt = up ? 32 - K : K;
+    const uint32_t rl = lane_xor<K>(__builtin_amdgcn_alignbit(lo, lo, amt));
+    const uint32_t rh = lane_xor<K>(__builtin_amdgcn_alignbit(hi, hi, amt));
+    lo = (lo & keep) | (rl & ~keep);
+    hi = (hi & keep) | (rh & ~keep);
 }
 
 __device__ __forceinline__ uint64_t transpose64(uint64_t x, int lane) {
-    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull,
-                               0x00FF00FF00FF00FFull, 0x0F0F0F0F0F0F0F0Full,
-                               0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-    for (int st = 0; st < 6; ++st) {
-        const int k = 32 >> st;
-        const uint64_t m = masks[st];
-        const uint64_t p = shfl_xor_u64(x, k);
-        // without branches: sel is all ones in the lanes with bit k set,
-        // which keep their high blocks and take the partner's high blocks
-        // shifted down; the others keep their low blocks and take the
-        // partner's low blocks shifted up
-        const uint64_t sel = (uint64_t)0 - (uint64_t)((lane >> (5 - st)) & 1);
-        const uint64_t moved = (((p & ~m) >> k) & sel) | (((p & m) << k) & ~sel);
-        x = (x & (m ^ sel)) | moved;
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    {  // 32 apart: lanes 32..63 take the high dword of lanes 0..31 as their
+       // low dword, lanes 0..31 the low dword of lanes 32..63 as their high
+        const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+        lo = r[0];
+        hi = r[1];
     }
-    return x;
+    {  // 16 apart: gather the low and the high 16-bit halves of the two
+       // dwords, swap the odd rows of the first with the even rows of the
+       // second, spread them back
+        uint32_t a = (lo & 0xFFFFu) | (hi << 16), b = (lo >> 16) | (hi & 0xFFFF0000u);
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+        lo = (a & 0xFFFFu) | (b << 16);
+        hi = (a >> 16) | (b & 0xFFFF0000u);
+    }
+    small_stage<8, 3, 0x00FF00FFu>(lo, hi, lane);
+    small_stage<4, 2, 0x0F0F0F0Fu>(lo, hi, lane);
+    small_stage<2, 1, 0x33333333u>(lo, hi, lane);
+    small_stage<1, 0, 0x55555555u>(lo, hi, lane);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Sum of one double per thread over a 256-thread block, in a fixed order.

@@ -421,59 +421,6 @@ hipError_t launch_sparse_finish(const LaunchCtx &lc, const SparseFinishArgs &a) 
 // with column 64 w + q, so lane q writes that column's 16 row words as one
 // 128-byte run, a whole cache line. Every sample word is read once and every
 // output line written by one lane. Rows past s read as 0.
-// The 64 x 64 bit transpose of transpose64 (same butterfly, same result)
-// with the lane exchanges done by gfx950's cross-lane moves rather than LDS
-// permutes: the 32- and 16-lane stages swap whole registers between the
-// wave's halves / alternate 16-lane rows; in the stages 8, 2 and 1 apart a
-// DPP move fetches the partner's dword, 4 apart a swizzle. There each lane
-// first rotates its dword right by k (left by k where its lane index has the
-// bit of value k set), so the partner's blocks arrive where they belong, and
-// a bit-field insert keeps its own blocks.
-template <int K>
-__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
-    if constexpr (K == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
-    if constexpr (K == 4) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
-    if constexpr (K == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
-    if constexpr (K == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
-    return v;
-}
-
-template <int K, int LOGK, uint32_t M>
-__device__ __forceinline__ void small_stage(uint32_t &lo, uint32_t &hi, int lane) {
-    const bool up = (lane >> LOGK) & 1;
-    const uint32_t keep = up ? ~M : M;
-    const uint32_t amt = up ? 32 - K : K;
-    const uint32_t rl = lane_xor<K>(__builtin_amdgcn_alignbit(lo, lo, amt));
-    const uint32_t rh = lane_xor<K>(__builtin_amdgcn_alignbit(hi, hi, amt));
-    lo = (lo & keep) | (rl & ~keep);
-    hi = (hi & keep) | (rh & ~keep);
-}
-
-__device__ __forceinline__ uint64_t transpose64_xlane(uint64_t x, int lane) {
-    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-    {  // 32 apart: lanes 32..63 take the high dword of lanes 0..31 as their
-       // low dword, lanes 0..31 the low dword of lanes 32..63 as their high
-        const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
-        lo = r[0];
-        hi = r[1];
-    }
-    {  // 16 apart: gather the low and the high 16-bit halves of the two
-       // dwords, swap the odd rows of the first with the even rows of the
-       // second, spread them back
-        uint32_t a = (lo & 0xFFFFu) | (hi << 16), b = (lo >> 16) | (hi & 0xFFFF0000u);
-        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
-        a = r[0];
-        b = r[1];
-        lo = (a & 0xFFFFu) | (b << 16);
-        hi = (a >> 16) | (b & 0xFFFF0000u);
-    }
-    small_stage<8, 3, 0x00FF00FFu>(lo, hi, lane);
-    small_stage<4, 2, 0x0F0F0F0Fu>(lo, hi, lane);
-    small_stage<2, 1, 0x33333333u>(lo, hi, lane);
-    small_stage<1, 0, 0x55555555u>(lo, hi, lane);
-    return ((uint64_t)hi << 32) | lo;
-}
-
 constexpr int kSliceWords = 16;  // row words per step: 1024 rows
 constexpr int kSliceChunk = 8;   // qubit words per step
 constexpr int kSliceStride = kSliceChunk + 1;
@@ -540,7 +487,7 @@ __device__ __forceinline__ void indep_slice_body(const IndepSliceArgs &a, int64_
             uint64_t y[kSliceWords];
 #pragma unroll
             for (int t = 0; t < kSliceWords; ++t)
-                y[t] = transpose64_xlane(stage[(t * 64 + lane) * kSliceStride + jw], lane);
+                y[t] = transpose64(stage[(t * 64 + lane) * kSliceStride + jw], lane);
             uint64_t IQP_GLOBAL *dst = set + (int64_t)((cur.w0 + jw) * 64 + lane) * a.ldx;
 #pragma unroll
             for (int t = 0; t < kSliceWords; ++t) dst[t] = y[t];
