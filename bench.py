@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="n300",
-                    choices=["n300", "n1000", "mmd_n300", "batch64"])
+                    choices=["n300", "n1000", "mmd_n300", "batch64", "paper_shapes"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-bitflip", action="store_true")
@@ -149,6 +149,8 @@ def main():
 
     if args.workload == "batch64":
         return main_batch(args)
+    if args.workload == "paper_shapes":
+        return main_paper_shapes(args)
 
     import torch
     from paper_2501_04776_amd import api
@@ -521,6 +523,82 @@ def bench_train(args, w=None):
             "loss_first_last": [float(lo[0]), float(lo[-1])],
             "config": "n=300, m=45150 (one parameter per gate), 3 x 2000 operators ~ P_sigma, "
                       "s=10000 drawn per step, N=2000, split_bf16, Adam lr 1e-3"}
+
+
+def main_paper_shapes(args):
+    """The benchmark shapes of Sec. 4.1 (context: the paper's timings are in a
+    figure): n in {100, 1000, 2000, 5000}, m in {1e3, 1e5}, l = s = 1e4,
+    generator and observable bits Bernoulli(3/n). Split-BF16 and the sparse
+    form, forward and forward + backward, each checked against the oracle on
+    4 sampled observables. The JSON value is the split-BF16 fwd+bwd rate over
+    all eight shapes together."""
+    import torch
+    import oracle
+    import workloads as W
+    from paper_2501_04776_amd import api
+
+    reps, warm = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
+
+    def median_ms(fn):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    rows, T_all, t_all = [], 0.0, 0.0
+    ok_all = True
+    for n in (100, 1000, 2000, 5000):
+        for m in (1000, 100000):
+            w = W.paper_shape(n, m)
+            dw = DevWorkload(w)
+            circ = api.Circuit(w.n, dw.gens, dw.theta)
+            u = torch.ones(w.l, dtype=torch.float64, device="cuda")
+            pick = np.random.default_rng(1).choice(w.l, size=4, replace=False)
+            om, _ = oracle.expval(w.n, w.gates, w.theta, dw.ops01[pick], w.samples)
+            row = {"n": n, "m": m, "l": w.l, "s": w.s, "terms": w.terms}
+            for prec, tol in (("split_bf16", 1e-4), ("sparse_fp32", 1e-5)):
+                out = {}
+
+                def fwd():
+                    out["m"] = api.iqp_expval(circ, dw.ops, dw.samples, prec, phase_save=True)[0]
+
+                def both():
+                    _, _, ph = api.iqp_expval(circ, dw.ops, dw.samples, prec, phase_save=True)
+                    api.iqp_expval_grad(circ, dw.ops, dw.samples, u, ph, prec)
+
+                tf, tb = median_ms(fwd), median_ms(both)
+                err = float(np.abs(out["m"].cpu().numpy()[pick] - om).max())
+                ok_all &= err < tol
+                row[prec] = {"fwd_ms": tf, "fwd_bwd_ms": tb, "max_abs_err_mean": err, "tol": tol}
+                if prec == "split_bf16":
+                    T_all += w.terms
+                    t_all += tb
+            log("n=%d m=%d: split_bf16 fwd %.3f / fwd+bwd %.3f ms, sparse fwd %.3f / %.3f ms, "
+                "errors %.1e / %.1e" % (n, m, row["split_bf16"]["fwd_ms"],
+                                       row["split_bf16"]["fwd_bwd_ms"], row["sparse_fp32"]["fwd_ms"],
+                                       row["sparse_fp32"]["fwd_bwd_ms"],
+                                       row["split_bf16"]["max_abs_err_mean"],
+                                       row["sparse_fp32"]["max_abs_err_mean"]))
+            rows.append(row)
+            del dw, circ, u
+            torch.cuda.empty_cache()
+    result = {"metric": METRIC, "value": T_all / (t_all * 1e-3), "unit": "terms/s", "n_gpus": 1,
+              "steps": reps, "warmup": warm, "ms_per_step": t_all, "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+              "parity_ok": bool(ok_all), "shapes": rows,
+              "config": {"workload": "paper_shapes_l10000_s10000",
+                         "shapes": "n in {100,1000,2000,5000} x m in {1e3,1e5}, Bernoulli(3/n) bits",
+                         "step": "the eight shapes' split-BF16 iqp_expval + iqp_expval_grad"}}
+    print(json.dumps(result), flush=True)
 
 
 def main_batch(args):

@@ -142,6 +142,21 @@ def bernoulli_rows(rng: np.random.Generator, count: int, n: int, p: float) -> np
     return (rng.random((count, n)) < p).astype(np.uint8)
 
 
+def bernoulli_index_rows(rng: np.random.Generator, count: int, n: int, p: float,
+                         chunk: int = 4096) -> IndexRows:
+    """``count`` rows whose n bits are i.i.d. Bernoulli(p), as index lists
+    (drawn ``chunk`` rows at a time; weight-0 rows occur)."""
+    ptr = np.zeros(count + 1, dtype=np.int64)
+    parts = []
+    for c0 in range(0, count, chunk):
+        c = min(chunk, count - c0)
+        r, q = np.nonzero(rng.random((c, n), dtype=np.float32) < p)
+        ptr[c0 + 1:c0 + c + 1] = ptr[c0] + np.cumsum(np.bincount(r, minlength=c))
+        parts.append(q.astype(np.int32))
+    idx = np.concatenate(parts) if parts else np.zeros(0, dtype=np.int32)
+    return IndexRows(ptr, idx)
+
+
 def uniform_bits(rng: np.random.Generator, count: int, n: int) -> np.ndarray:
     return rng.integers(0, 2, size=(count, n), dtype=np.uint8)
 
@@ -252,6 +267,19 @@ def mmd_n300(seed: int = 404, ops_per_sigma: int = 2000, s: int = 10000,
     data = bernoulli_rows(d, N, n, 0.3)
     return Workload("mmd_n300_m45150_l%d_s%d_N%d" % (ops.count, s, N), n, gates,
                     theta, ops, samples, data=data, op_weight=op_weight, seed=seed)
+
+
+def paper_shape(n: int, m: int, l: int = 10000, s: int = 10000, seed: int = 606) -> Workload:
+    """The benchmark shape of Sec. 4.1: m generators and l observables whose
+    bits are Bernoulli(3/n) (average weight 3), theta ~ U(-pi, pi), s uniform
+    samples."""
+    g, t, o, z, _ = streams(seed + 7 * n + m)
+    gates = bernoulli_index_rows(g, m, n, 3.0 / n)
+    theta = t.uniform(-math.pi, math.pi, size=m)
+    ops = bernoulli_index_rows(o, l, n, 3.0 / n)
+    samples = uniform_bits(z, s, n)
+    return Workload("paper_n%d_m%d_l%d_s%d" % (n, m, l, s), n, gates, theta, ops, samples,
+                    seed=seed)
 
 
 def batch64_shapes(seed: int = 505, count: int = 64):
