@@ -120,11 +120,17 @@ int check_device() {
 
 // ---------------------------------------------------------------------------
 // workspace plan
+// Each split adds an l x s partial E that the forward writes and the
+// epilogue reads back: per 128 x 128 tile about as long as 10 gate words of
+// matrix-core work, while a split raises the last round's fill by at most a
+// few percent. So a split is added only for every 128 gate words (m = 10^3
+// keeps one split: 0.84 -> 0.72 ms at l = s = 10^4; the 300-qubit workload
+// keeps three).
 int64_t choose_splits(int64_t tiles, int64_t mw) {
     int64_t best = 1;
     double best_eff = -1.0;
     for (int64_t sp = 1; sp <= 16; ++sp) {
-        if (sp > 1 && mw < 8 * sp) break;  // keep >= 8 gate words per split
+        if (sp > 1 && mw < 128 * (sp - 1)) break;
         const int64_t units = tiles * sp;
         const double eff =
             (double)units / (double)(ceil_div(units, kWaveSlots) * kWaveSlots);
