@@ -121,3 +121,25 @@ def test_calls_on_two_streams_do_not_share_scratch():
     for i in range(2):
         for g in got[i]:
             assert torch.equal(g, want[i])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_pi_shifted_angles_give_the_same_estimates(prec):
+    # exp(i(theta + k pi) X) = (-1)^k exp(i theta X) is a global phase, so every
+    # mean and every gradient is unchanged; the angles are reduced to
+    # [-pi/2, pi/2] in FP64 before anything is rounded to FP32 or BF16, so
+    # shifts by up to 10^4 pi (which cost ~1e-12 of FP64 precision in theta
+    # itself) leave the results within the estimate tolerance of the oracle
+    w = W.small_random(4242, 80, 700, 90, 1500, theta_scale=np.pi)
+    u = np.random.default_rng(6).normal(size=w.l)
+    k = np.random.default_rng(5).integers(-10 ** 4, 10 ** 4, size=w.m)
+    shifted = W.Workload(w.name, w.n, w.gates, w.theta + k * np.pi, w.ops, w.samples, seed=w.seed)
+    dw, m0, s0, g0, _ = _fwd_grad(w, prec, u)
+    _, m1, s1, g1, _ = _fwd_grad(shifted, prec, u)
+    om, ose = oracle.expval(w.n, w.gates, w.theta, dw.ops01, w.samples)
+    og = oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01, w.samples, u)
+    T = TOL[prec]
+    assert np.abs(m1 - om).max() < T and np.abs(s1 - ose).max() < T
+    assert np.abs(m1 - m0).max() < T
+    bar = grad_bar(prec, w, dw.ops01, u)
+    assert np.all(np.abs(g1 - og) < bar) and np.all(np.abs(g1 - g0) < bar)
