@@ -28,11 +28,13 @@ __device__ __forceinline__ const T IQP_CONST *cptr(const T *p) {
 // Sample-parity words: word w of generator j holds b_ij of samples 64 w ..
 // 64 w + 63 (bit i % 64). A wave covers one chunk of kSpWords words of one
 // observable. Two ways to read them:
-//   word(j)      the forward: each lane loads the word its 16 samples lie in
-//                (lane L: bits 16 (L % 4) .. 16 (L % 4) + 15 of word L / 4)
-//   words(j, m)  the backward: all kSpWords words of the chunk, the same in
-//                every lane (scalar loads), each used as a lane mask over the
-//                64 samples of one word (lane L: sample 64 r + L)
+//   word(j)      each lane loads the word its 16 samples lie in (lane L:
+//                bits 16 (L % 4) .. 16 (L % 4) + 15 of word L / 4); the
+//                forward, and the backward of independent sets
+//   words(j, m)  all kSpWords words of the chunk, the same in every lane
+//                (scalar loads), each used as a lane mask over the 64 samples
+//                of one word (lane L: sample 64 r + L); the backward of
+//                shared samples
 // The sample-parity rows hold whole chunks (a multiple of kSpWords words,
 // the words of samples >= s being 0), so a wave reads all its words
 // unconditionally.
@@ -55,7 +57,6 @@ struct SharedWords {
 // XOR of the columns of its qubits (its support list; a generator heavier
 // than kSupCap walks its bit row).
 struct IndepWords {
-    const uint64_t IQP_CONST *col0;  // xt + k * xstride + the wave's first sample word
     int64_t ldx;
     const int32_t IQP_CONST *sup;
     const uint64_t IQP_CONST *gens;
@@ -93,46 +94,6 @@ struct IndepWords {
         }
         return x;
     }
-    __device__ __forceinline__ void add_column(int64_t q, uint64_t (&m)[kSpWords]) const {
-        const uint64_t IQP_CONST *c = col0 + q * ldx;
-#pragma unroll
-        for (int r = 0; r < kSpWords; ++r) m[r] ^= c[r];
-    }
-    // The XORs run on the scalar unit, which bounds the backward: the first
-    // column is loaded into m rather than XORed into zeros, and the first
-    // four support entries come in one load.
-    __device__ __forceinline__ void words(int64_t j, uint64_t (&m)[kSpWords]) const {
-        const int32_t IQP_CONST *sj = sup + j * kSupCap;
-        const int32_t q0 = sj[0], q1 = sj[1], q2 = sj[2], q3 = sj[3];
-        if (q0 < 0) {
-#pragma unroll
-            for (int r = 0; r < kSpWords; ++r) m[r] = 0ull;
-            if (q0 == -2) {
-                for (int w = 0; w < W; ++w) {
-                    uint64_t g = gens[j * W + w];
-                    while (g) {
-                        add_column(w * 64 + __builtin_ctzll(g), m);
-                        g &= g - 1;
-                    }
-                }
-            }
-            return;
-        }
-        const uint64_t IQP_CONST *c = col0 + (int64_t)q0 * ldx;
-#pragma unroll
-        for (int r = 0; r < kSpWords; ++r) m[r] = c[r];
-        if (q1 < 0) return;
-        add_column(q1, m);
-        if (q2 < 0) return;
-        add_column(q2, m);
-        if (q3 < 0) return;
-        add_column(q3, m);
-        for (int e = 4; e < kSupCap; ++e) {
-            const int32_t q = sj[e];
-            if (q < 0) break;
-            add_column(q, m);
-        }
-    }
 };
 
 template <bool kIndep>
@@ -150,8 +111,7 @@ struct WordsOf<true> {
     using T = IndepWords;
     static __device__ __forceinline__ T make(const SampleParity &p, int64_t k, int64_t sw0,
                                              int64_t swl) {
-        return IndepWords{cptr(p.xt) + k * p.xstride + sw0, p.Rwb, cptr(p.sup), cptr(p.gens),
-                          p.W, gptr(p.xt) + k * p.xstride + swl};
+        return IndepWords{p.Rwb, cptr(p.sup), cptr(p.gens), p.W, gptr(p.xt) + k * p.xstride + swl};
     }
 };
 
@@ -301,7 +261,13 @@ __device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t 
     const int64_t k = unit / nchunk, ch = unit - k * nchunk;
     const int lane = threadIdx.x & 63;
     const int64_t sw0 = ch * kSpWords;
-    const auto src = WordsOf<kIndep>::make(a.bsrc, k, sw0, sw0);
+    // Lanes and samples: shared samples, lane L holds sample 64 r + L of
+    // each of the chunk's 16 words r (the parity words are uniform, scalar
+    // loads used as lane masks); independent sets, the forward's layout: lane
+    // L holds the 16 samples of bits 16 (L % 4) .. + 15 of the chunk's word
+    // L / 4 and loads its own parity word.
+    const int sh = 16 * (lane & 3);
+    const auto src = WordsOf<kIndep>::make(a.bsrc, k, sw0, kIndep ? sw0 + (lane >> 2) : sw0);
     GateWalk gates(cptr(a.crm) + k * a.Gw, a.Gw);
     const double al = gptr(a.coef)[2 * k], be = gptr(a.coef)[2 * k + 1];
     const double scale = gptr(a.scale)[0];
@@ -310,7 +276,7 @@ __device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t 
     float Ssum = 0.0f;
 #pragma unroll
     for (int r = 0; r < kSpWords; ++r) {
-        const int64_t i = (sw0 + r) * 64 + lane;
+        const int64_t i = kIndep ? (sw0 + (lane >> 2)) * 64 + sh + r : (sw0 + r) * 64 + lane;
         float v = 0.0f;
         if (i < a.s) {
             float sn, cs;
@@ -360,8 +326,8 @@ __device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t 
         if (++nb == kRedBatch) flush();
     };
     int64_t j;
-    uint64_t m[kSpWords];
     if constexpr (!kIndep) {
+        uint64_t m[kSpWords];
         // the next generator's parity words are loaded once the current ones
         // are consumed, so the load overlaps the current partial's store (the
         // independent form's support walk has no scalar registers to spare
@@ -380,11 +346,16 @@ __device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t 
             have = more;
         }
     } else {
+        // The parity word of generator j is the XOR of its support columns,
+        // here per lane with vector loads: as uniform scalar words the XORs
+        // ran on the scalar unit, which then bounded the kernel. Per sample a
+        // one-bit field extract masks S (3 lane ops per term, as in the
+        // forward).
         while (gates.next(j)) {
-            src.words(j, m);
+            const uint32_t f = (uint32_t)(src.word(j) >> sh);
             float p = 0.0f;
 #pragma unroll
-            for (int r = 0; r < kSpWords; ++r) p = add_where(p, S[r], m[r]);
+            for (int b = 0; b < kSpWords; ++b) p += masked(S[b], f, b);
             add_partial(j, p);
         }
     }

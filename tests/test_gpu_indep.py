@@ -76,14 +76,18 @@ def test_heavy_generators_and_recompute():
     assert np.array_equal(g, g2)
 
 
-def test_one_shared_set_equals_the_sparse_shared_path_bitwise():
-    # every observable given the same sample set: the same sums in the same
-    # order as the shared-sample sparse form
+def test_one_shared_set_equals_the_sparse_shared_path():
+    # every observable given the same sample set: the forward makes the same
+    # sums in the same order as the shared-sample sparse form (means,
+    # standard errors and phases bitwise); the backward sums each lane's
+    # samples in another order (16 consecutive samples per lane instead of
+    # one per word), so the gradients agree to rounding
     n, m, l, s = 90, 1500, 70, 900
     w = W.small_random(41, n, m, l, s)
     dw = DevWorkload(w)
     z = dw.samples.unsqueeze(0).expand(l, -1, -1).contiguous()
-    u = torch.from_numpy(np.random.default_rng(5).normal(size=l)).cuda()
+    un = np.random.default_rng(5).normal(size=l)
+    u = torch.from_numpy(un).cuda()
     circ = api.Circuit(n, dw.gens, dw.theta)
     mi, si, pi = api.iqp_expval_indep(circ, dw.ops, z, phase_save=True)
     gi = api.iqp_expval_indep_grad(circ, dw.ops, z, u, pi)
@@ -91,7 +95,8 @@ def test_one_shared_set_equals_the_sparse_shared_path_bitwise():
     gs = api.iqp_expval_grad(circ, dw.ops, dw.samples, u, ps, "sparse_fp32")
     torch.cuda.synchronize()
     assert torch.equal(mi, ms) and torch.equal(si, ss) and torch.equal(pi, ps)
-    assert torch.equal(gi, gs)
+    bar = grad_bar("sparse_fp32", w, dw.ops01, un)
+    assert np.all(np.abs(gi.cpu().numpy() - gs.cpu().numpy()) < bar)
 
 
 def test_indep_full_size_sampled():
