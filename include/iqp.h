@@ -176,7 +176,8 @@ int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
  * estimator, outputs and gradient as iqp_expval / iqp_expval_grad; computed
  * in the sparse-C form (FP32 phases on the vector units, FP64 reduction), the
  * parities of each observable's anticommuting generators taken against its
- * own samples, at about the cost of the shared-sample sparse form.
+ * own samples (whose bit columns are built first), at about twice the cost of
+ * the shared-sample sparse form.
  *   samples    device [l][s][W]: sample i of observable k at (k s + i) W
  *   l * s <= 2^32; precision is fixed (no precision argument)
  *   ws         >= iqp_workspace_bytes(IQP_CALL_INDEP[_GRAD[_RECOMPUTE]], ...)
