@@ -517,9 +517,41 @@ def bench_train(args, w=None):
     log("train: %.3f ms/step (loss+grad alone %.3f ms), draws bit-exact %s, loss %.5g -> %.5g" %
         (step_ms, lg_ms, exact, lo[0], lo[-1]))
     tr.close()
+    # the same steps with one loss call per bandwidth group: split-BF16 for
+    # sigma = 1 (operators of weight ~60, a third of C non-zero), the sparse
+    # form for sigma = 5 and 17 (weight ~3 and mostly the identity)
+    gp = ["split_bf16", "sparse_fp32", "sparse_fp32"]
+    tg = api.Trainer(n, gens, np.arange(m, dtype=np.int32), m, ddata, [per] * 3, probs, s,
+                     precision="split_bf16", optimizer="adam", lr=1e-3, seed=seed,
+                     group_precision=gp)
+    pg = torch.from_numpy(theta.copy()).cuda()
+    for _ in range(2):
+        tg.step(pg, n_steps=K)
+    torch.cuda.synchronize()
+    pg.copy_(torch.from_numpy(theta.copy()))
+    tg.reset(0)
+    a.record()
+    lg = tg.step(pg, n_steps=K)
+    b.record()
+    torch.cuda.synchronize()
+    group_ms = a.elapsed_time(b) / K
+    # the first step's loss and draws are those of the split-BF16 trainer's first step after reset
+    tr2 = api.Trainer(n, gens, np.arange(m, dtype=np.int32), m, ddata, [per] * 3, probs, s,
+                      precision="split_bf16", optimizer="adam", lr=1e-3, seed=seed)
+    p2 = torch.from_numpy(theta.copy()).cuda()
+    l2 = tr2.step(p2, n_steps=1)
+    torch.cuda.synchronize()
+    dl = abs(float(lg[0].item()) - float(l2[0].item()))
+    tr2.close()
+    tg.close()
+    log("train, per-group precision %s: %.3f ms/step (%.2fx), first loss vs split-BF16 %.2g" %
+        (gp, group_ms, step_ms / group_ms, dl))
     return {"step_ms": step_ms, "steps_per_s": 1e3 / step_ms, "terms_per_s": T / (step_ms * 1e-3),
             "loss_grad_ms": lg_ms, "overhead_ms": step_ms - lg_ms,
             "draws_bit_exact_vs_oracle": exact, "steps_per_graph": K,
+            "group_precision": {"precisions": gp, "step_ms": group_ms,
+                                "steps_per_s": 1e3 / group_ms,
+                                "first_loss_abs_diff_vs_split_bf16": dl},
             "loss_first_last": [float(lo[0]), float(lo[-1])],
             "config": "n=300, m=45150 (one parameter per gate), 3 x 2000 operators ~ P_sigma, "
                       "s=10000 drawn per step, N=2000, split_bf16, Adam lr 1e-3"}

@@ -382,6 +382,8 @@ typedef struct {
     int32_t optimizer;           /* IQP_OPT_GD or IQP_OPT_ADAM */
     double lr, beta1, beta2, eps;
     uint64_t seed0, seed1;       /* Philox key; samples use tag 0, operators tag 1 */
+    const int32_t *group_precision; /* host [n_groups] precision of each group, or
+                                       NULL: every group takes `precision` */
 } iqp_train_desc;
 
 typedef struct iqp_train_plan iqp_train_plan;
@@ -393,7 +395,12 @@ enum {
 
 /* Creates a plan; reads the host arrays of `desc` (the pointers to device
  * memory are kept and must stay valid). Each operator group's weights sum to
- * 1 / n_groups. Host object, not thread-safe. */
+ * 1 / n_groups. With group_precision, the loss and gradient of each group are
+ * one iqp_mmd_loss_grad call of its own in its own precision (MMD^2 and its
+ * gradient are sums over the operators, Sec. 3.3.1), summed in group order:
+ * for groups whose operators anticommute with few generators (the narrow
+ * kernels' sparse operators) IQP_SPARSE_FP32 does a small fraction of the
+ * dense work. Host object, not thread-safe. */
 int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan **plan);
 int iqp_train_plan_destroy(iqp_train_plan *plan);
 size_t iqp_train_workspace_bytes(const iqp_train_plan *plan);

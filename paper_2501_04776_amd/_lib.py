@@ -80,7 +80,8 @@ class IqpTrainDesc(ctypes.Structure):
                 ("data", ctypes.c_void_p), ("unbiased", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("optimizer", ctypes.c_int32),
                 ("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
-                ("eps", ctypes.c_double), ("seed0", ctypes.c_uint64), ("seed1", ctypes.c_uint64)]
+                ("eps", ctypes.c_double), ("seed0", ctypes.c_uint64), ("seed1", ctypes.c_uint64),
+                ("group_precision", ctypes.c_void_p)]
 
 
 class IqpError(RuntimeError):

@@ -490,15 +490,18 @@ class Trainer:
     group per Gaussian-kernel bandwidth), evaluates the loss and its gradient
     at the current parameters and updates them in place. ``param_index`` (host,
     one entry per generator) maps generators to parameters (shared
-    parameters), -1 marking fixed gates whose angles are ``fixed_theta``. The
-    trainer owns its workspace (optimizer moments and step count live there)."""
+    parameters), -1 marking fixed gates whose angles are ``fixed_theta``.
+    ``group_precision`` (one precision per group, or None for ``precision``
+    everywhere) computes each group's loss and gradient by a call of its own,
+    e.g. the sparse form for groups of low-weight operators. The trainer owns
+    its workspace (optimizer moments and step count live there)."""
 
     def __init__(self, n_qubits: int, gens: torch.Tensor, param_index, n_params: int,
                  data: torch.Tensor, group_ops, group_prob, n_samples: int,
                  fixed_theta: Optional[torch.Tensor] = None, unbiased: bool = True,
                  precision=SPLIT_BF16, optimizer="adam", lr: float = 1e-3, beta1: float = 0.9,
                  beta2: float = 0.999, eps: float = 1e-8, seed=(0, 0), graph: bool = True,
-                 step: int = 0):
+                 step: int = 0, group_precision=None):
         import numpy as np
         self.n = int(n_qubits)
         self.W = (self.n + 63) // 64
@@ -529,6 +532,12 @@ class Trainer:
         d.optimizer = _OPTIMIZERS[optimizer]
         d.lr, d.beta1, d.beta2, d.eps = lr, beta1, beta2, eps
         d.seed0, d.seed1 = s0, s1
+        self.group_prec = None
+        if group_precision is not None:
+            if len(group_precision) != self.group_ops.size:
+                raise ValueError("group_precision needs one entry per group")
+            self.group_prec = np.array([precision_id(p) for p in group_precision], dtype=np.int32)
+            d.group_precision = self.group_prec.ctypes.data
         self._handle = ctypes.c_void_p()
         flags = 0 if graph else L.IQP_TRAIN_NO_GRAPH
         L.check(L.lib().iqp_train_plan_create(ctypes.byref(d), flags, ctypes.byref(self._handle)),

@@ -93,11 +93,19 @@ struct iqp_train_plan {
     int flags = 0;
     std::vector<int64_t> group_ops;
     std::vector<double> group_prob;
+    // loss calls: consecutive groups of one precision share a call (their
+    // operators and weights are contiguous); empty: one call in `precision`
+    struct LossCall {
+        int64_t first_op = 0, n_ops = 0;
+        int32_t precision = 0;
+    };
+    std::vector<LossCall> calls;
     int64_t l = 0, s = 0, W = 0, m = 0, P = 0;
     bool has_fixed = false;
     // workspace layout
     size_t o_z = 0, o_ops = 0, o_theta = 0, o_gtheta = 0, o_gpar = 0, o_m1 = 0, o_m2 = 0;
     size_t o_step = 0, o_tab = 0, tab_bytes = 0, o_mmd = 0, mmd_bytes = 0, total = 0;
+    size_t o_lparts = 0, o_gparts = 0;  // per-group losses and gradients
     // offsets inside the table region (operator weights, parameter index,
     // gates of each parameter): the same bytes as the pinned staging copy
     size_t t_w = 0, t_index = 0, t_offs = 0, t_gates = 0;
@@ -158,10 +166,29 @@ int enqueue_step(const iqp_train_plan *tp, void *ws, double *params, double *los
                                 params, d.fixed_theta, theta),
             "gather_theta");
     const iqp_circuit c{d.n_qubits, d.n_words, d.n_gates, d.gens, theta};
-    int rc = iqp_mmd_loss_grad(&c, tp->l, ops, reinterpret_cast<const double *>(tab + tp->t_w),
-                               tp->s, z, d.n_data, d.data, d.unbiased, d.precision, loss_i,
-                               gtheta, ws_at<char>(ws, tp->o_mmd), tp->mmd_bytes, st);
-    if (rc) return rc;
+    const double *w = reinterpret_cast<const double *>(tab + tp->t_w);
+    if (tp->calls.empty()) {
+        const int rc = iqp_mmd_loss_grad(&c, tp->l, ops, w, tp->s, z, d.n_data, d.data,
+                                         d.unbiased, d.precision, loss_i, gtheta,
+                                         ws_at<char>(ws, tp->o_mmd), tp->mmd_bytes, st);
+        if (rc) return rc;
+    } else {
+        // one call per run of groups in one precision, each into its own
+        // loss and gradient slot, then summed in call order
+        double *lparts = ws_at<double>(ws, tp->o_lparts);
+        double *gparts = ws_at<double>(ws, tp->o_gparts);
+        const int nc = (int)tp->calls.size();
+        for (int i = 0; i < nc; ++i) {
+            const auto &cl = tp->calls[i];
+            const int rc = iqp_mmd_loss_grad(&c, cl.n_ops, ops + cl.first_op * tp->W,
+                                             w + cl.first_op, tp->s, z, d.n_data, d.data,
+                                             d.unbiased, cl.precision, lparts + i,
+                                             gparts + i * tp->m, ws_at<char>(ws, tp->o_mmd),
+                                             tp->mmd_bytes, st);
+            if (rc) return rc;
+        }
+        IQP_TRY(launch_sum_groups(st, nc, tp->m, lparts, gparts, loss_i, gtheta), "sum_groups");
+    }
     IQP_TRY(launch_reduce_grad(st, tp->P, reinterpret_cast<const int64_t *>(tab + tp->t_offs),
                                reinterpret_cast<const int32_t *>(tab + tp->t_gates), gtheta, gpar),
             "reduce_grad");
@@ -331,6 +358,14 @@ int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan 
         return fail(IQP_ERR_INVALID_ARG,
                     "precision must be IQP_FP32, IQP_SPLIT_BF16 or IQP_SPARSE_FP32");
     if ((st = check_optimizer(d.optimizer, d.lr, d.beta1, d.beta2, d.eps))) return st;
+    if (d.group_precision)
+        for (int g = 0; g < d.n_groups; ++g) {
+            const int32_t p = d.group_precision[g];
+            if (p != IQP_FP32 && p != IQP_SPLIT_BF16 && p != IQP_SPARSE_FP32)
+                return fail(IQP_ERR_INVALID_ARG, "group_precision[" + std::to_string(g) +
+                                                     "] must be IQP_FP32, IQP_SPLIT_BF16 or "
+                                                     "IQP_SPARSE_FP32");
+        }
     // gates of each parameter, in gate order
     std::vector<int64_t> offs(d.n_params + 1, 0);
     bool has_fixed = false;
@@ -358,9 +393,20 @@ int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan 
     tp->flags = flags;
     tp->group_ops.assign(d.group_ops, d.group_ops + d.n_groups);
     tp->group_prob.assign(d.group_prob, d.group_prob + d.n_groups);
+    if (d.group_precision) {
+        int64_t off = 0;
+        for (int g = 0; g < d.n_groups; ++g) {
+            if (g > 0 && d.group_precision[g] == d.group_precision[g - 1])
+                tp->calls.back().n_ops += tp->group_ops[g];
+            else
+                tp->calls.push_back({off, tp->group_ops[g], d.group_precision[g]});
+            off += tp->group_ops[g];
+        }
+    }
     tp->d.group_ops = nullptr;  // host arrays are the plan's copies from here on
     tp->d.group_prob = nullptr;
     tp->d.param_index = nullptr;
+    tp->d.group_precision = nullptr;
     tp->l = l;
     tp->s = d.n_samples;
     tp->W = d.n_words;
@@ -395,8 +441,23 @@ int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan 
     tp->tab_bytes = tcur;
     tp->o_tab = carve(tp->tab_bytes);
     const iqp_circuit c{d.n_qubits, d.n_words, d.n_gates, d.gens, nullptr};
-    tp->mmd_bytes = iqp_workspace_bytes(IQP_CALL_MMD_GRAD, &c, tp->l, tp->s, d.n_data,
-                                        d.precision);
+    if (tp->calls.empty()) {
+        tp->mmd_bytes = iqp_workspace_bytes(IQP_CALL_MMD_GRAD, &c, tp->l, tp->s, d.n_data,
+                                            d.precision);
+    } else {
+        // the loss calls run one after another on the stream and share it
+        for (const auto &cl : tp->calls) {
+            const size_t b = iqp_workspace_bytes(IQP_CALL_MMD_GRAD, &c, cl.n_ops, tp->s,
+                                                 d.n_data, cl.precision);
+            if (b == 0) {
+                tp->mmd_bytes = 0;
+                break;
+            }
+            tp->mmd_bytes = std::max(tp->mmd_bytes, b);
+        }
+        tp->o_lparts = carve(tp->calls.size() * 8);
+        tp->o_gparts = carve(tp->calls.size() * tp->m * 8);
+    }
     if (tp->mmd_bytes == 0) {
         destroy(tp);
         return fail(IQP_ERR_INVALID_ARG, "loss workspace size query failed");

@@ -47,6 +47,9 @@ hipError_t launch_reduce_grad(hipStream_t st, int64_t P, const int64_t *offsets,
                               const int32_t *gates, const double *grad_theta,
                               double *grad_params);
 // the update, then step += 1
+hipError_t launch_sum_groups(hipStream_t st, int32_t n_groups, int64_t m,
+                             const double *loss_parts, const double *grad_parts, double *loss,
+                             double *grad_theta);
 hipError_t launch_optimizer(hipStream_t st, const OptimizerArgs &a);
 hipError_t launch_fill_f64(hipStream_t st, double *x, int64_t count, double v);
 hipError_t launch_set_step(hipStream_t st, int64_t *step, int64_t v);

@@ -108,6 +108,24 @@ __global__ void __launch_bounds__(256) reduce_grad_kernel(int64_t P, const int64
     grad_params[p] = acc;
 }
 
+// The loss and gradient of the operator groups, summed in group order: one
+// thread per gate; thread 0 also sums the losses.
+__global__ void __launch_bounds__(256) sum_groups_kernel(int32_t n_groups, int64_t m,
+                                                         const double *loss_parts,
+                                                         const double *grad_parts, double *loss,
+                                                         double *grad_theta) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j == 0) {
+        double l = 0.0;
+        for (int g = 0; g < n_groups; ++g) l += loss_parts[g];
+        *loss = l;
+    }
+    if (j >= m) return;
+    double acc = 0.0;
+    for (int g = 0; g < n_groups; ++g) acc += grad_parts[(int64_t)g * m + j];
+    grad_theta[j] = acc;
+}
+
 // Gradient descent or Adam (Kingma and Ba 2015, Algorithm 1) at step count
 // t + 1, t = *step, one thread per parameter. The step count is advanced by
 // a separate launch, after every thread has read it.
@@ -172,6 +190,14 @@ hipError_t launch_reduce_grad(hipStream_t st, int64_t P, const int64_t *offsets,
                               double *grad_params) {
     hipLaunchKernelGGL(reduce_grad_kernel, dim3(grid_of(P)), dim3(256), 0, st, P, offsets, gates,
                        grad_theta, grad_params);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_groups(hipStream_t st, int32_t n_groups, int64_t m,
+                             const double *loss_parts, const double *grad_parts, double *loss,
+                             double *grad_theta) {
+    hipLaunchKernelGGL(sum_groups_kernel, dim3(grid_of(m)), dim3(256), 0, st, n_groups, m,
+                       loss_parts, grad_parts, loss, grad_theta);
     return hipGetLastError();
 }
 

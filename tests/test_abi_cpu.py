@@ -302,6 +302,8 @@ def _desc(**kw):
     idx = np.asarray(kw.pop("param_index", [0, 1, 1, -1]), dtype=np.int32)
     gops = np.asarray(kw.pop("group_ops", [4, 4]), dtype=np.int64)
     gprob = np.asarray(kw.pop("group_prob", [0.3, 0.1]), dtype=np.float64)
+    gprec = kw.pop("group_precision", None)
+    gprec = None if gprec is None else np.asarray(gprec, dtype=np.int32)
     d = L.IqpTrainDesc()
     d.n_qubits, d.n_words, d.n_gates, d.gens = 70, 2, idx.size, FAKE
     d.n_params, d.param_index, d.fixed_theta = 2, idx.ctypes.data, FAKE
@@ -309,9 +311,10 @@ def _desc(**kw):
     d.n_samples, d.n_data, d.data = 16, 8, FAKE
     d.unbiased, d.precision, d.optimizer = 1, 1, 1
     d.lr, d.beta1, d.beta2, d.eps, d.seed0, d.seed1 = 0.01, 0.9, 0.999, 1e-8, 1, 2
+    d.group_precision = None if gprec is None else gprec.ctypes.data
     for k, v in kw.items():
         setattr(d, k, v)
-    return d, (idx, gops, gprob)
+    return d, (idx, gops, gprob, gprec)
 
 
 @pytest.mark.parametrize("kw,msg", [
@@ -321,7 +324,9 @@ def _desc(**kw):
     (dict(fixed_theta=None), "fixed_theta"), (dict(group_ops=[4, 0]), "group_ops"),
     (dict(group_prob=[0.3, 1.5]), "[0, 1)"), (dict(n_samples=0), "n_samples"),
     (dict(n_data=1), "unbiased"), (dict(precision=7), "precision"),
-    (dict(optimizer=5), "optimizer"), (dict(lr=0.0), "lr"), (dict(data=None), "data")])
+    (dict(optimizer=5), "optimizer"), (dict(lr=0.0), "lr"), (dict(data=None), "data"),
+    (dict(group_precision=[1, 7]), "group_precision[1]"),
+    (dict(group_precision=[-1, 2]), "group_precision[0]")])
 def test_train_plan_rejects_invalid_descriptions(kw, msg):
     d, keep = _desc(**kw)
     plan = ctypes.c_void_p()

@@ -102,13 +102,14 @@ def train_problem(seed=5, n=40, P=300, s=500, N=64, ops=(30, 30)):
                 group_rows=list(ops), group_prob=probs, s=s, P=P)
 
 
-def make_trainer(pb, prec, opt, lr, eps=1e-8, graph=True, seed=(3, 4)):
+def make_trainer(pb, prec, opt, lr, eps=1e-8, graph=True, seed=(3, 4), group_precision=None):
     gens = torch.from_numpy(packing.pack_index_rows(pb["gates"].ptr, pb["gates"].idx,
                                                     pb["n"]).view(np.int64)).cuda()
     data = torch.from_numpy(packing.pack_dense(pb["data"]).view(np.int64)).cuda()
     return api.Trainer(pb["n"], gens, pb["idx"], pb["P"], data, pb["group_rows"],
                        pb["group_prob"], pb["s"], fixed_theta=torch.from_numpy(pb["fixed"]).cuda(),
-                       precision=prec, optimizer=opt, lr=lr, eps=eps, seed=seed, graph=graph)
+                       precision=prec, optimizer=opt, lr=lr, eps=eps, seed=seed, graph=graph,
+                       group_precision=group_precision)
 
 
 def gate_bar(prec, pb, og_gate):
@@ -118,11 +119,17 @@ def gate_bar(prec, pb, og_gate):
     return TOL[prec] * max(1.0, np.abs(og_gate).max()) * np.maximum(counts, 1)
 
 
-@pytest.mark.parametrize("prec", PRECS)
+# "groups": one loss call per operator group, split-BF16 for the bandwidth-1
+# group and the sparse form for the bandwidth-5 group, summed on the device
+@pytest.mark.parametrize("prec", PRECS + ["groups"])
 def test_gd_steps_match_oracle(prec):
     pb = train_problem()
     lr = 0.05
-    tr = make_trainer(pb, prec, "gd", lr)
+    if prec == "groups":
+        tr = make_trainer(pb, "fp32", "gd", lr, group_precision=["split_bf16", "sparse_fp32"])
+        prec = "split_bf16"  # the looser of the two tolerances
+    else:
+        tr = make_trainer(pb, prec, "gd", lr)
     params = torch.from_numpy(pb["params"].copy()).cuda()
     op = pb["params"].copy()
     for t in range(3):
@@ -231,3 +238,19 @@ def test_training_reduces_the_loss():
     print("loss first 5 %s last 5 %s" % (losses[:5], losses[-5:]))
     assert losses[-5:].mean() < 0.5 * losses[:5].mean()
     tr.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "sparse_fp32"])
+def test_groups_of_one_precision_share_one_call(prec):
+    # consecutive groups in one precision are one loss call over their
+    # contiguous operators: the single call's loss, gradient and update, bitwise
+    pb = train_problem(seed=11)
+    one = make_trainer(pb, prec, "gd", 0.05)
+    per = make_trainer(pb, prec, "gd", 0.05, group_precision=[prec, prec])
+    p1 = torch.from_numpy(pb["params"].copy()).cuda()
+    p2 = p1.clone()
+    l1, l2 = one.step(p1, n_steps=2), per.step(p2, n_steps=2)
+    torch.cuda.synchronize()
+    assert torch.equal(l1, l2) and torch.equal(one.grad, per.grad) and torch.equal(p1, p2)
+    one.close()
+    per.close()
