@@ -395,9 +395,9 @@ enum {
 
 /* Creates a plan; reads the host arrays of `desc` (the pointers to device
  * memory are kept and must stay valid). Each operator group's weights sum to
- * 1 / n_groups. With group_precision, the loss and gradient of each group are
- * one iqp_mmd_loss_grad call of its own in its own precision (MMD^2 and its
- * gradient are sums over the operators, Sec. 3.3.1), summed in group order:
+ * 1 / n_groups. With group_precision, the loss and gradient are one
+ * iqp_mmd_loss_grad call per run of consecutive groups in one precision (MMD^2
+ * and its gradient are sums over the operators, Sec. 3.3.1), summed in order:
  * for groups whose operators anticommute with few generators (the narrow
  * kernels' sparse operators) IQP_SPARSE_FP32 does a small fraction of the
  * dense work. Host object, not thread-safe. */
