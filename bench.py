@@ -11,12 +11,20 @@ Prints ONE JSON line. The metric is phase terms per second, T = l * s * m
 headline value is split-BF16 fwd+bwd. Results are checked against the FP64
 oracle on sampled observables before the number is printed.
 
+Besides the headline, the default run reports the FP32 path, the sparse-C
+form, bitflip circuits, independent sample sets per observable, and the
+on-device training step (split-BF16, and with a precision per operator
+group), each checked against the oracle, plus the oracle's own rate on the
+host cores.
+
 The batched workload (64 circuits of uneven size, --workload batch64) runs as
 one BatchPlan: a step is the forward and the backward pass over all circuits,
 each pass one graph replay with persistent contraction kernels, tiles from
-the autotuner.
+the autotuner. --workload paper_shapes times the paper's benchmark shapes
+(context).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload n300|n1000|mmd_n300|batch64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload n300|n1000|mmd_n300|batch64|paper_shapes]
 """
 from __future__ import annotations
 
