@@ -14,8 +14,9 @@ oracle on sampled observables before the number is printed.
 Besides the headline, the default run reports the FP32 path, the sparse-C
 form, bitflip circuits, independent sample sets per observable, and the
 on-device training step (split-BF16, and with a precision per operator
-group), each checked against the oracle, plus the oracle's own rate on the
-host cores.
+group), each checked against the oracle (the per-group training step
+against the split-BF16 step's loss), plus the oracle's own rate on the host
+cores.
 
 The batched workload (64 circuits of uneven size, --workload batch64) runs as
 one BatchPlan: a step is the forward and the backward pass over all circuits,
