@@ -85,10 +85,10 @@ def test_optimizer_update_matches_oracle(opt):
             assert np.allclose(dm2.cpu().numpy(), m2, rtol=1e-13, atol=1e-300)
 
 
-def train_problem(seed=5, n=40, P=300, s=500, N=64, ops=(30, 30)):
+def train_problem(seed=5, n=40, P=300, s=500, N=64, ops=(30, 30), sigmas=(1.0, 5.0)):
     """n-qubit all-local circuit (n + n(n-1)/2 generators) whose generators
     share P parameters (generator j -> j mod P) except every 7th, which is a
-    fixed gate; data Bernoulli(0.3); two operator groups (bandwidths 1, 5)."""
+    fixed gate; data Bernoulli(0.3); one operator group per bandwidth."""
     gates = W.local_gates(n)
     m = gates.count
     idx = (np.arange(m) % P).astype(np.int32)
@@ -97,7 +97,7 @@ def train_problem(seed=5, n=40, P=300, s=500, N=64, ops=(30, 30)):
     fixed = np.where(idx < 0, rng.uniform(-np.pi, np.pi, size=m), 0.0)
     data = (rng.random((N, n)) < 0.3).astype(np.uint8)
     params = rng.normal(0.0, 0.3, size=P)
-    probs = [W.sigma_bit_probability(1.0), W.sigma_bit_probability(5.0)]
+    probs = [W.sigma_bit_probability(sg) for sg in sigmas]
     return dict(n=n, gates=gates, idx=idx, fixed=fixed, data=data, params=params,
                 group_rows=list(ops), group_prob=probs, s=s, P=P)
 
@@ -254,3 +254,27 @@ def test_groups_of_one_precision_share_one_call(prec):
     assert torch.equal(l1, l2) and torch.equal(one.grad, per.grad) and torch.equal(p1, p2)
     one.close()
     per.close()
+
+
+def test_three_groups_one_merged_run_match_oracle():
+    # bandwidths 1, 5, 17 in split-BF16, sparse, sparse: one dense call and
+    # one sparse call over the last two (contiguous) groups, summed
+    pb = train_problem(seed=13, ops=(30, 20, 25), sigmas=(1.0, 5.0, 17.0))
+    lr, prec = 0.05, "split_bf16"
+    tr = make_trainer(pb, prec, "gd", lr,
+                      group_precision=["split_bf16", "sparse_fp32", "sparse_fp32"])
+    params = torch.from_numpy(pb["params"].copy()).cuda()
+    loss = tr.step(params)
+    torch.cuda.synchronize()
+    r = oracle.train_step(pb["n"], pb["gates"], pb["idx"], pb["fixed"], pb["params"],
+                          pb["group_rows"], pb["group_prob"], pb["s"], pb["data"], (3, 4), 0,
+                          oracle.OPT_GD, np.zeros(pb["P"]), np.zeros(pb["P"]), lr)
+    th = oracle.gate_theta(pb["idx"], pb["params"], pb["fixed"])
+    _, og_gate = oracle.mmd_loss_grad(pb["n"], pb["gates"], th, r["ops"],
+                                      oracle.op_weights(pb["group_rows"]), r["samples"],
+                                      pb["data"])
+    bar = gate_bar(prec, pb, og_gate)
+    assert abs(loss[0].item() - r["loss"]) < 4 * TOL[prec]
+    assert np.all(np.abs(tr.grad.cpu().numpy() - r["grad"]) < bar)
+    assert np.abs(params.cpu().numpy() - r["params"]).max() < lr * bar.max()
+    tr.close()
