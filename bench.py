@@ -526,13 +526,14 @@ def bench_train(args, w=None):
     log("train: %.3f ms/step (loss+grad alone %.3f ms), draws bit-exact %s, loss %.5g -> %.5g" %
         (step_ms, lg_ms, exact, lo[0], lo[-1]))
     tr.close()
-    # the same steps with one loss call per bandwidth group: split-BF16 for
-    # sigma = 1 (operators of weight ~60, a third of C non-zero), the sparse
-    # form for sigma = 5 and 17 (weight ~3 and mostly the identity)
-    gp = ["split_bf16", "sparse_fp32", "sparse_fp32"]
+    # the same steps with the precision of each bandwidth group chosen by the
+    # plan from the expected density of C: split-BF16 for sigma = 1
+    # (operators of weight ~60, a third of C non-zero), the sparse form for
+    # sigma = 5 and 17 (weight ~3, and mostly the identity)
     tg = api.Trainer(n, gens, np.arange(m, dtype=np.int32), m, ddata, [per] * 3, probs, s,
                      precision="split_bf16", optimizer="adam", lr=1e-3, seed=seed,
-                     group_precision=gp)
+                     group_precision="auto")
+    gp = tg.group_precisions()
     pg = torch.from_numpy(theta.copy()).cuda()
     for _ in range(2):
         tg.step(pg, n_steps=K)
@@ -558,7 +559,7 @@ def bench_train(args, w=None):
     return {"step_ms": step_ms, "steps_per_s": 1e3 / step_ms, "terms_per_s": T / (step_ms * 1e-3),
             "loss_grad_ms": lg_ms, "overhead_ms": step_ms - lg_ms,
             "draws_bit_exact_vs_oracle": exact, "steps_per_graph": K,
-            "group_precision": {"precisions": gp, "step_ms": group_ms,
+            "group_precision": {"mode": "auto", "precisions": gp, "step_ms": group_ms,
                                 "steps_per_s": 1e3 / group_ms,
                                 "first_loss_abs_diff_vs_split_bf16": dl},
             "loss_first_last": [float(lo[0]), float(lo[-1])],

@@ -390,7 +390,9 @@ typedef struct iqp_train_plan iqp_train_plan;
 
 /* flags of iqp_train_plan_create */
 enum {
-    IQP_TRAIN_NO_GRAPH = 1 /* launch the steps one by one instead of replaying a graph */
+    IQP_TRAIN_NO_GRAPH = 1,      /* launch the steps one by one instead of replaying a graph */
+    IQP_TRAIN_AUTO_PRECISION = 2 /* choose each group's precision (group_precision must be
+                                    NULL): see iqp_train_plan_create */
 };
 
 /* Creates a plan; reads the host arrays of `desc` (the pointers to device
@@ -400,7 +402,12 @@ enum {
  * and its gradient are sums over the operators, Sec. 3.3.1), summed in order:
  * for groups whose operators anticommute with few generators (the narrow
  * kernels' sparse operators) IQP_SPARSE_FP32 does a small fraction of the
- * dense work. Host object, not thread-safe. */
+ * dense work. With IQP_TRAIN_AUTO_PRECISION the plan copies the generators to
+ * the host once (a synchronous copy) and runs group g in IQP_SPARSE_FP32 when
+ * its expected density of C, the mean over generators j of
+ * (1 - (1 - 2 p_g)^{|g_j|}) / 2 (the probability that a string with
+ * Bernoulli(p_g) bits overlaps g_j in an odd number of qubits), is below
+ * 4 %, and in `precision` otherwise. Host object, not thread-safe. */
 int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan **plan);
 int iqp_train_plan_destroy(iqp_train_plan *plan);
 size_t iqp_train_workspace_bytes(const iqp_train_plan *plan);
@@ -419,6 +426,10 @@ int iqp_train_init(iqp_train_plan *plan, int64_t step, void *ws, size_t ws_bytes
  * n_steps change) replayed on `stream`. */
 int iqp_train_step(iqp_train_plan *plan, int32_t n_steps, double *params, double *loss,
                    double *grad_params, void *ws, size_t ws_bytes, void *stream);
+
+/* The precision each operator group's loss and gradient run in (host
+ * [n_groups], written). */
+int iqp_train_group_precision(const iqp_train_plan *plan, int32_t *out);
 
 /* Device pointers into a workspace: the samples [s][W] and operators
  * [l][W] of the last step, and the step count [1]. Any may be NULL. */

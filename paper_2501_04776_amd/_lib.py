@@ -47,11 +47,12 @@ EXPORTED = ("iqp_workspace_bytes", "iqp_parity_workspace_bytes", "iqp_parity", "
             "iqp_batch_set_config", "iqp_sample_uniform", "iqp_sample_bernoulli",
             "iqp_gather_theta", "iqp_reduce_grad", "iqp_optimizer_update",
             "iqp_train_plan_create", "iqp_train_plan_destroy", "iqp_train_workspace_bytes",
-            "iqp_train_init", "iqp_train_step", "iqp_train_buffers", "iqp_strerror", "iqp_last_error", "iqp_profile_enable",
+            "iqp_train_init", "iqp_train_step", "iqp_train_buffers", "iqp_train_group_precision", "iqp_strerror", "iqp_last_error", "iqp_profile_enable",
             "iqp_profile_query", "iqp_profile_reset")
 
 IQP_BATCH_NO_GRAPH = 1
 IQP_TRAIN_NO_GRAPH = 1
+IQP_TRAIN_AUTO_PRECISION = 2
 IQP_OPT_GD = 0
 IQP_OPT_ADAM = 1
 
@@ -167,6 +168,8 @@ def lib():
     L.iqp_train_buffers.argtypes = [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                     ctypes.POINTER(vp)]
     L.iqp_train_buffers.restype = i32
+    L.iqp_train_group_precision.argtypes = [vp, vp]
+    L.iqp_train_group_precision.restype = i32
     L.iqp_strerror.argtypes = [i32]
     L.iqp_strerror.restype = ctypes.c_char_p
     L.iqp_last_error.argtypes = []

@@ -492,9 +492,11 @@ class Trainer:
     one entry per generator) maps generators to parameters (shared
     parameters), -1 marking fixed gates whose angles are ``fixed_theta``.
     ``group_precision`` (one precision per group, or None for ``precision``
-    everywhere) computes each group's loss and gradient by a call of its own,
-    e.g. the sparse form for groups of low-weight operators. The trainer owns
-    its workspace (optimizer moments and step count live there)."""
+    everywhere, or "auto" to let the plan pick the sparse form for groups
+    whose expected density of C is low) computes each group's loss and
+    gradient by a call of its own, e.g. the sparse form for groups of
+    low-weight operators. The trainer owns its workspace (optimizer moments
+    and step count live there)."""
 
     def __init__(self, n_qubits: int, gens: torch.Tensor, param_index, n_params: int,
                  data: torch.Tensor, group_ops, group_prob, n_samples: int,
@@ -533,13 +535,14 @@ class Trainer:
         d.lr, d.beta1, d.beta2, d.eps = lr, beta1, beta2, eps
         d.seed0, d.seed1 = s0, s1
         self.group_prec = None
-        if group_precision is not None:
+        auto = isinstance(group_precision, str) and group_precision == "auto"
+        if group_precision is not None and not auto:
             if len(group_precision) != self.group_ops.size:
                 raise ValueError("group_precision needs one entry per group")
             self.group_prec = np.array([precision_id(p) for p in group_precision], dtype=np.int32)
             d.group_precision = self.group_prec.ctypes.data
         self._handle = ctypes.c_void_p()
-        flags = 0 if graph else L.IQP_TRAIN_NO_GRAPH
+        flags = (0 if graph else L.IQP_TRAIN_NO_GRAPH) | (L.IQP_TRAIN_AUTO_PRECISION if auto else 0)
         L.check(L.lib().iqp_train_plan_create(ctypes.byref(d), flags, ctypes.byref(self._handle)),
                 "iqp_train_plan_create")
         self.ws_bytes = int(L.lib().iqp_train_workspace_bytes(self._handle))
@@ -547,6 +550,15 @@ class Trainer:
         self.grad = torch.zeros(self.P, dtype=torch.float64, device=self.device)
         self._loss = {}
         self.reset(step)
+
+    def group_precisions(self):
+        """The precision name each operator group runs in."""
+        import numpy as np
+        out = np.zeros(self.group_ops.size, dtype=np.int32)
+        L.check(L.lib().iqp_train_group_precision(self._handle, out.ctypes.data),
+                "iqp_train_group_precision")
+        names = {v: k for k, v in _PRECISIONS.items() if isinstance(k, str)}
+        return [names[int(p)] for p in out]
 
     def reset(self, step: int = 0) -> None:
         """Zero the optimizer moments and set the step count."""

@@ -16,6 +16,11 @@ using namespace iqp;
 namespace {
 
 constexpr int32_t kMaxQubits = 1 << 20;
+// Expected density of C below which a group runs in the sparse form: the
+// sparse form's time grows with the non-zeros of C, the dense forms' does
+// not, and on MI355X they cross at a few percent (4 % leaves margin on the
+// dense side; the MMD workload's groups sit at ~30 %, ~2 % and ~0.2 %).
+constexpr double kSparseDensity = 0.04;
 
 int check_seed_step(const int64_t *step, const uint64_t *out, int64_t rows) {
     if (!step) return fail(IQP_ERR_INVALID_ARG, "step is NULL");
@@ -100,6 +105,7 @@ struct iqp_train_plan {
         int32_t precision = 0;
     };
     std::vector<LossCall> calls;
+    std::vector<int32_t> group_prec;  // the precision of each group
     int64_t l = 0, s = 0, W = 0, m = 0, P = 0;
     bool has_fixed = false;
     // workspace layout
@@ -330,7 +336,10 @@ int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan 
     *plan = nullptr;
     if (!desc) return fail(IQP_ERR_INVALID_ARG, "desc is NULL");
     const iqp_train_desc &d = *desc;
-    if (flags & ~(int)IQP_TRAIN_NO_GRAPH) return fail(IQP_ERR_INVALID_ARG, "unknown flags");
+    if (flags & ~(int)(IQP_TRAIN_NO_GRAPH | IQP_TRAIN_AUTO_PRECISION))
+        return fail(IQP_ERR_INVALID_ARG, "unknown flags");
+    if ((flags & IQP_TRAIN_AUTO_PRECISION) && d.group_precision)
+        return fail(IQP_ERR_INVALID_ARG, "IQP_TRAIN_AUTO_PRECISION needs group_precision NULL");
     if (d.n_qubits < 1 || d.n_qubits > kMaxQubits)
         return fail(IQP_ERR_INVALID_ARG, "n_qubits out of range [1, 2^20]");
     if (d.n_words != (int32_t)ceil_div(d.n_qubits, 64))
@@ -393,13 +402,39 @@ int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan 
     tp->flags = flags;
     tp->group_ops.assign(d.group_ops, d.group_ops + d.n_groups);
     tp->group_prob.assign(d.group_prob, d.group_prob + d.n_groups);
-    if (d.group_precision) {
+    std::vector<int32_t> prec(d.n_groups, d.precision);
+    if (d.group_precision) prec.assign(d.group_precision, d.group_precision + d.n_groups);
+    if (flags & IQP_TRAIN_AUTO_PRECISION) {
+        // expected density of C per group from the generators' weights
+        std::vector<uint64_t> g((size_t)d.n_gates * d.n_words);
+        const hipError_t e = hipMemcpy(g.data(), d.gens, g.size() * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            destroy(tp);
+            return hip_fail(e, "copy of the generators");
+        }
+        std::vector<int64_t> count(d.n_qubits + 1, 0);  // generators per weight
+        for (int64_t j = 0; j < d.n_gates; ++j) {
+            int w = 0;
+            for (int32_t k = 0; k < d.n_words; ++k) w += __builtin_popcountll(g[j * d.n_words + k]);
+            ++count[w];
+        }
+        for (int gi = 0; gi < d.n_groups; ++gi) {
+            const double q = 1.0 - 2.0 * tp->group_prob[gi];
+            double dens = 0.0;
+            for (int w = 0; w <= d.n_qubits; ++w)
+                if (count[w]) dens += (double)count[w] * 0.5 * (1.0 - std::pow(q, w));
+            dens /= (double)d.n_gates;
+            prec[gi] = dens < kSparseDensity ? IQP_SPARSE_FP32 : d.precision;
+        }
+    }
+    tp->group_prec = prec;
+    if (d.group_precision || (flags & IQP_TRAIN_AUTO_PRECISION)) {
         int64_t off = 0;
         for (int g = 0; g < d.n_groups; ++g) {
-            if (g > 0 && d.group_precision[g] == d.group_precision[g - 1])
+            if (g > 0 && prec[g] == prec[g - 1])
                 tp->calls.back().n_ops += tp->group_ops[g];
             else
-                tp->calls.push_back({off, tp->group_ops[g], d.group_precision[g]});
+                tp->calls.push_back({off, tp->group_ops[g], prec[g]});
             off += tp->group_ops[g];
         }
     }
@@ -526,6 +561,14 @@ int iqp_train_step(iqp_train_plan *plan, int32_t n_steps, double *params, double
     hipGraphExec_t exec = nullptr;
     if ((st = step_graph(plan, n_steps, params, loss, grad_params, ws, &exec))) return st;
     IQP_TRY(hipGraphLaunch(exec, s), "hipGraphLaunch");
+    return IQP_OK;
+}
+
+int iqp_train_group_precision(const iqp_train_plan *plan, int32_t *out) {
+    clear_error();
+    if (!plan) return fail(IQP_ERR_INVALID_ARG, "plan is NULL");
+    if (!out) return fail(IQP_ERR_INVALID_ARG, "out is NULL");
+    std::copy(plan->group_prec.begin(), plan->group_prec.end(), out);
     return IQP_OK;
 }
 

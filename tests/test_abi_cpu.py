@@ -336,8 +336,22 @@ def test_train_plan_rejects_invalid_descriptions(kw, msg):
     assert not plan.value
 
 
+def test_train_plan_flags():
+    d, keep = _desc()
+    plan = ctypes.c_void_p()
+    lib = L.lib()
+    assert lib.iqp_train_plan_create(ctypes.byref(d), 4, ctypes.byref(plan)) == \
+        L.IQP_ERR_INVALID_ARG and "flags" in L.last_error()
+    d, keep = _desc(group_precision=[1, 2])
+    assert lib.iqp_train_plan_create(ctypes.byref(d), L.IQP_TRAIN_AUTO_PRECISION,
+                                     ctypes.byref(plan)) == L.IQP_ERR_INVALID_ARG
+    assert "AUTO_PRECISION" in L.last_error() and not plan.value
+
+
 def test_train_calls_reject_null_plan():
     lib = L.lib()
+    out = np.zeros(2, dtype=np.int32)
+    assert lib.iqp_train_group_precision(None, out.ctypes.data) == L.IQP_ERR_INVALID_ARG
     assert lib.iqp_train_step(None, 1, FAKE, FAKE, None, FAKE, 1 << 40, None) == \
         L.IQP_ERR_INVALID_ARG
     assert lib.iqp_train_init(None, 0, FAKE, 1 << 40, None) == L.IQP_ERR_INVALID_ARG

@@ -278,3 +278,25 @@ def test_three_groups_one_merged_run_match_oracle():
     assert np.all(np.abs(tr.grad.cpu().numpy() - r["grad"]) < bar)
     assert np.abs(params.cpu().numpy() - r["params"]).max() < lr * bar.max()
     tr.close()
+
+
+def test_auto_group_precision_picks_the_sparse_form_for_narrow_bandwidths():
+    # the expected density of C per group (generators of weight 1 and 2 here):
+    # sigma = 1 about 30 %, sigma = 5 about 2 %, sigma = 17 about 0.2 %; the
+    # plan picks split-BF16, sparse, sparse and then runs exactly the explicit
+    # assignment
+    pb = train_problem(seed=17, ops=(30, 20, 25), sigmas=(1.0, 5.0, 17.0))
+    auto = make_trainer(pb, "split_bf16", "gd", 0.05, group_precision="auto")
+    assert auto.group_precisions() == ["split_bf16", "sparse_fp32", "sparse_fp32"]
+    expl = make_trainer(pb, "split_bf16", "gd", 0.05,
+                        group_precision=["split_bf16", "sparse_fp32", "sparse_fp32"])
+    assert expl.group_precisions() == ["split_bf16", "sparse_fp32", "sparse_fp32"]
+    plain = make_trainer(pb, "fp32", "gd", 0.05)
+    assert plain.group_precisions() == ["fp32"] * 3
+    p1 = torch.from_numpy(pb["params"].copy()).cuda()
+    p2 = p1.clone()
+    l1, l2 = auto.step(p1, n_steps=2), expl.step(p2, n_steps=2)
+    torch.cuda.synchronize()
+    assert torch.equal(l1, l2) and torch.equal(auto.grad, expl.grad) and torch.equal(p1, p2)
+    for tr in (auto, expl, plain):
+        tr.close()
