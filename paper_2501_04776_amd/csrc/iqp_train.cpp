@@ -412,10 +412,19 @@ int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan 
             destroy(tp);
             return hip_fail(e, "copy of the generators");
         }
-        std::vector<int64_t> count(d.n_qubits + 1, 0);  // generators per weight
+        // generators per weight; pad bits past n_qubits are masked off (they
+        // must be zero, but they are not checked, and must not index past
+        // the table)
+        std::vector<int64_t> count(d.n_qubits + 1, 0);
+        const int tail = d.n_qubits & 63;
+        const uint64_t last_mask = tail ? ((1ull << tail) - 1) : ~0ull;
         for (int64_t j = 0; j < d.n_gates; ++j) {
             int w = 0;
-            for (int32_t k = 0; k < d.n_words; ++k) w += __builtin_popcountll(g[j * d.n_words + k]);
+            for (int32_t k = 0; k < d.n_words; ++k) {
+                uint64_t x = g[j * d.n_words + k];
+                if (k == d.n_words - 1) x &= last_mask;
+                w += __builtin_popcountll(x);
+            }
             ++count[w];
         }
         for (int gi = 0; gi < d.n_groups; ++gi) {
