@@ -9,7 +9,7 @@ import torch
 import oracle
 import workloads as W
 from paper_2501_04776_amd import api
-from tests.gpu_util import TOL, DevWorkload, grad_bar, wrap
+from tests.gpu_util import TOL, DevWorkload, check_grad, wrap
 
 pytestmark = pytest.mark.gpu
 
@@ -45,10 +45,7 @@ def _check_forward(plan, ws, dws, prec, phases=True):
 def _check_backward(plan, ws, dws, us, prec):
     torch.cuda.synchronize()
     for i, (w, d) in enumerate(zip(ws, dws)):
-        og = oracle.expval_grad(w.n, w.gates, w.theta, d.ops01, w.samples, us[i])
-        g = plan.grads[i].cpu().numpy()
-        bar = grad_bar(prec, w, d.ops01, us[i])
-        assert np.all(np.abs(g - og) < bar), (i, np.abs(g - og).max(), bar.min())
+        check_grad(prec, plan.grads[i].cpu().numpy(), w, d.ops01, us[i], where="problem %d" % i)
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -237,9 +234,9 @@ def test_batched_workload_full_size_sampled():
         assert np.abs(mean - om).max() < TOL[prec]
         assert np.abs(se - ose).max() < TOL[prec]
         uk = us_full[i].cpu().numpy()[k]
-        og = oracle.expval_grad(w.n, w.gates, w.theta, d.ops01[k], w.samples, uk)
-        g = plan.grads[i].cpu().numpy()
-        assert np.all(np.abs(g - og) < grad_bar(prec, w, d.ops01[k], uk))
+        err, rep = check_grad(prec, plan.grads[i].cpu().numpy(), w, d.ops01[k], uk,
+                              where="circuit %d" % i)
+        print("circuit %d: max|d grad| = %.3g (representation %.3g)" % (i, err, rep))
     for i in range(64):
         if i not in picks:
             assert not plan.grads[i].abs().max().item()  # dL/dmean = 0 gives dtheta = 0

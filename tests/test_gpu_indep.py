@@ -9,7 +9,7 @@ import torch
 import oracle
 import workloads as W
 from paper_2501_04776_amd import api
-from tests.gpu_util import TOL, DevWorkload, grad_bar, wrap
+from tests.gpu_util import TOL, DevWorkload, grad_tol, wrap
 
 pytestmark = pytest.mark.gpu
 
@@ -52,8 +52,7 @@ def test_indep_matches_oracle(shape):
     assert np.abs(mean - om).max() < T
     assert np.abs(se - ose).max() < T
     assert np.abs(wrap(ph - oph)).max() < 100 * T
-    bar = grad_bar("sparse_fp32", w, dw.ops01, u)
-    assert np.all(np.abs(g - og) < bar), np.abs(g - og).max()
+    assert np.abs(g - og).max() < grad_tol("sparse_fp32", og), np.abs(g - og).max()
 
 
 def test_heavy_generators_and_recompute():
@@ -72,7 +71,7 @@ def test_heavy_generators_and_recompute():
     om, _ = oracle.expval_indep(n, w.gates, w.theta, dw.ops01, z01)
     og = oracle.expval_indep_grad(n, w.gates, w.theta, dw.ops01, z01, u)
     assert np.abs(mean - om).max() < T
-    assert np.all(np.abs(g - og) < grad_bar("sparse_fp32", w, dw.ops01, u))
+    assert np.abs(g - og).max() < grad_tol("sparse_fp32", og)
     assert np.array_equal(g, g2)
 
 
@@ -95,8 +94,8 @@ def test_one_shared_set_equals_the_sparse_shared_path():
     gs = api.iqp_expval_grad(circ, dw.ops, dw.samples, u, ps, "sparse_fp32")
     torch.cuda.synchronize()
     assert torch.equal(mi, ms) and torch.equal(si, ss) and torch.equal(pi, ps)
-    bar = grad_bar("sparse_fp32", w, dw.ops01, un)
-    assert np.all(np.abs(gi.cpu().numpy() - gs.cpu().numpy()) < bar)
+    gsn = gs.cpu().numpy()
+    assert np.abs(gi.cpu().numpy() - gsn).max() < grad_tol("sparse_fp32", gsn)
 
 
 def test_indep_full_size_sampled():
@@ -117,4 +116,4 @@ def test_indep_full_size_sampled():
     print("indep n=300 sampled: max|d mean| %.3g" % np.abs(mean[pick] - om).max())
     assert np.abs(mean[pick] - om).max() < T
     assert np.abs(se[pick] - ose).max() < T
-    assert np.all(np.abs(g - og) < grad_bar("sparse_fp32", w, dw.ops01[pick], u[pick]))
+    assert np.abs(g - og).max() < grad_tol("sparse_fp32", og)

@@ -1,0 +1,94 @@
+"""CPU: the precision forms' operand rounding, emulated through the oracle.
+
+Pins the host model of tests/precision_model.py (BF16 rounding against
+torch's conversion, the emulated gradient without rounding against the
+oracle's own gradient), then ties each form's gradient tolerance to its
+arithmetic on the shape where two BF16 limbs of theta are not enough:
+n = 64, m = 5000, l = 900, s = 513 (weight-1..4 generators, theta uniform on
+[-pi, pi], every observable weighted). The bar is the survey's
+tol * max(1, |g|_inf) with tol 1e-5 (FP32) and 1e-4 (split BF16)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests import precision_model as PM
+
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4, "split3_bf16": 1e-4}
+
+
+def test_bf16_rne_matches_torch_conversion():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.normal(size=20000) * 10.0 ** rng.integers(-8, 8, 20000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3.140625, -2.0 ** -130]])
+    x32 = x.astype(np.float32)
+    ref = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(PM.bf16_rne(x32), ref)
+
+
+def test_limbs_shrink_the_residual():
+    t = PM.two_theta_reduced(np.random.default_rng(1).uniform(-40, 40, 5000))
+    assert np.all(np.abs(t) <= np.pi + 1e-12)
+    # each limb keeps 8 significant bits of what is left: half an ulp of the
+    # binade of |t| is 2^-8 |t| at most, and so on
+    for k, bound in ((1, 2.0 ** -8), (2, 2.0 ** -16), (3, 2.0 ** -24)):
+        r = np.abs(PM.bf16_limbs(t, k) - t)
+        assert np.all(r <= bound * np.abs(t) + 1e-300), (k, (r / np.abs(t)).max())
+
+
+@pytest.fixture(scope="module")
+def hard_case():
+    w = W.small_random(6569, 64, 5000, 900, 513)
+    ops01 = W.rows_to_dense(w.ops, w.n)
+    u = np.random.default_rng(9).normal(size=w.l)
+    og = oracle.expval_grad(w.n, w.gates, w.theta, ops01, w.samples, u)
+    return w, ops01, u, og
+
+
+def test_emulation_without_rounding_is_the_oracle(hard_case):
+    w, ops01, u, og = hard_case
+    g = PM.grad_emulated(w.n, w.gates, w.theta, ops01, w.samples, u)
+    assert np.abs(g - og).max() < 1e-12 * max(1.0, np.abs(og).max())
+
+
+def test_each_form_against_its_bar(hard_case):
+    w, ops01, u, og = hard_case
+    errs = {}
+    for prec in ("fp32", "split_bf16", "split3_bf16"):
+        g = PM.grad_emulated(w.n, w.gates, w.theta, ops01, w.samples, u, prec)
+        errs[prec] = np.abs(g - og).max() / (TOL[prec] * max(1.0, np.abs(og).max()))
+    print("emulated gradient error / bar:", errs)
+    # FP32 operands and the three-limb form meet their bars with a wide margin
+    assert errs["fp32"] < 0.3
+    assert errs["split3_bf16"] < 0.3
+    # two BF16 limbs of theta (16 significant bits) do not, by their own
+    # arithmetic: the residual of every gate repeats in all samples' phases
+    assert 0.8 < errs["split_bf16"] < 1.6
+
+
+def test_two_limb_theta_is_the_dominant_term(hard_case):
+    """The split-BF16 miss comes from theta, not from the backward weights:
+    exact weights with two-limb theta give the same error, two-limb weights
+    with exact theta a small fraction of it."""
+    w, ops01, u, og = hard_case
+    bar = 1e-4 * max(1.0, np.abs(og).max())
+    th2 = PM.theta_represented("split_bf16", w.theta)
+    g_theta = PM.grad_emulated(w.n, w.gates, th2, ops01, w.samples, u)
+    _, _, ph = oracle.expval(w.n, w.gates, w.theta, ops01, w.samples, phases=True)
+    S = PM.weights_represented("split_bf16", (u[:, None] / w.s) * np.sin(ph), np.abs(u) / w.s)
+    C = oracle.parity(w.n, ops01, w.gates).astype(np.float64)
+    B = 1.0 - 2.0 * oracle.parity(w.n, w.samples, w.gates).astype(np.float64)
+    g_s = -2.0 * (C * (S @ B)).sum(axis=0)
+    e_theta = np.abs(g_theta - og).max() / bar
+    e_s = np.abs(g_s - og).max() / bar
+    assert e_theta > 0.8 and e_s < 0.1, (e_theta, e_s)
+
+
+def test_means_of_every_form_within_tolerance(hard_case):
+    w, ops01, _, _ = hard_case
+    m0, _ = oracle.expval(w.n, w.gates, w.theta, ops01, w.samples)
+    for prec in ("fp32", "split_bf16", "split3_bf16"):
+        th = PM.theta_represented(prec, w.theta)
+        m, _ = oracle.expval(w.n, w.gates, th, ops01, w.samples)
+        assert np.abs(m - m0).max() < 0.25 * TOL[prec], prec
