@@ -41,9 +41,12 @@ METRIC = "phase terms/s (ops×samples×gates), fwd & fwd+bwd, split-BF16 vs FP32
 # (dense peak of the kernel's dtype in flop/s, matrix-core flops the form issues
 # per phase term). The algorithmic work is one multiply-add, 2 flops, per term
 # in every form; split-BF16 issues two BF16 products (hi and lo limb) per term.
-PEAK = {"split_bf16": (2.5e15, 4.0), "fp32": (157.3e12, 2.0)}
+PEAK = {"split_bf16": (2.5e15, 4.0), "fp32": (157.3e12, 2.0),
+        # three BF16 limbs of theta in the forward; two INT8 limbs of the
+        # backward weights against the dense INT8 peak (5.0 POP/s)
+        "split3_bf16_fwd": (2.5e15, 6.0), "split3_bf16_bwd": (5.0e15, 4.0)}
 ALGO_FLOPS_PER_TERM = 2.0
-TOL = {"fp32": 1e-5, "split_bf16": 1e-4, "sparse_fp32": 1e-5}
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4, "split3_bf16": 1e-4, "sparse_fp32": 1e-5}
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -108,8 +111,9 @@ def roofline(T, avg_ms, kernel, traffic, prec="split_bf16"):
     peak, issued = PEAK[prec]
     t = avg_ms * 1e-3
     achieved = ALGO_FLOPS_PER_TERM * T / t
+    unit = "TOP/s" if prec == "split3_bf16_bwd" else "TFLOP/s"  # INT8 products
     return {"bound": "mfma", "kernel": kernel, "achieved": achieved / 1e12,
-            "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+            "peak": peak / 1e12, "unit": unit, "frac": achieved / peak,
             "traffic": traffic, "traffic_unit": "bytes per launch (HBM read + write)",
             "flops_per_launch": ALGO_FLOPS_PER_TERM * T,
             "flops_per_term": ALGO_FLOPS_PER_TERM,
@@ -161,6 +165,10 @@ def main():
                     choices=["n300", "n1000", "mmd_n300", "batch64", "paper_shapes"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-split3", action="store_true")
+    ap.add_argument("--profile-precision", default="split_bf16",
+                    choices=["split_bf16", "split3_bf16", "fp32"],
+                    help="precision of the --profile-pass steps")
     ap.add_argument("--no-bitflip", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-train", action="store_true")
@@ -660,7 +668,9 @@ def main_paper_shapes(args):
 
 def main_batch(args):
     """The 64-circuit batched workload: n ~ U{50..2000}, m ~ U{1e3..2e5},
-    l ~ U{100..5000}, s = 4096, all circuits in one pass per direction."""
+    l ~ U{100..5000}, s = 4096, all circuits in one pass per direction. The
+    headline is split-BF16; the three-limb form (split3_bf16) and the FP32
+    path run the same step beside it."""
     import torch
     import oracle
     import workloads as W
@@ -707,8 +717,70 @@ def main_batch(args):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / steps
 
+    def kernel_times(plan, nprof):
+        # with timing on, a pass runs its launches one by one, each bracketed
+        # by events on its stream
+        api.profile_reset()
+        api.profile_enable(True)
+        for _ in range(nprof):
+            plan.expval()
+            plan.expval_grad(us)
+        torch.cuda.synchronize()
+        kb = {}
+        for k in ("parity", "theta_prep", "phase_fwd", "phase_epilogue", "finalize", "weights",
+                  "phase_bwd", "grad_reduce"):
+            tot, n = api.profile_query(k)
+            if n:
+                kb[k] = {"avg_ms": tot / n, "launches": n, "ms_per_step": tot / nprof}
+        api.profile_enable(False)
+        return kb
+
+    # parity: 3 sampled observables of 8 sampled circuits, means and the
+    # gradient of a loss that weights only those observables
+    pick_c = np.random.default_rng(0).choice(64, size=8, replace=False)
+    prng = np.random.default_rng(1)
+    sel, upick = {}, []
+    for i, w in enumerate(ws):
+        u = np.zeros(w.l)
+        if i in pick_c:
+            sel[i] = prng.choice(w.l, size=3, replace=False)
+            u[sel[i]] = prng.normal(size=3)
+        upick.append(torch.from_numpy(u).cuda())
+    ref = {}
+    for i, k in sel.items():
+        w, d = ws[i], dws[i]
+        om, ose = oracle.expval(w.n, w.gates, w.theta, d.ops01[k], w.samples)
+        og = oracle.expval_grad(w.n, w.gates, w.theta, d.ops01[k], w.samples,
+                                upick[i].cpu().numpy()[k])
+        ref[i] = (om, ose, og)
+
+    def parity(plan, prec):
+        plan.expval()
+        plan.expval_grad(upick)
+        torch.cuda.synchronize()
+        e = {"max_abs_err_mean": 0.0, "max_abs_err_stderr": 0.0, "max_abs_err_grad": 0.0,
+             "max_rel_err_grad": 0.0}
+        for i, k in sel.items():
+            om, ose, og = ref[i]
+            dg = float(np.abs(plan.grads[i].cpu().numpy() - og).max())
+            e["max_abs_err_mean"] = max(e["max_abs_err_mean"],
+                                        float(np.abs(plan.means[i].cpu().numpy()[k] - om).max()))
+            e["max_abs_err_stderr"] = max(e["max_abs_err_stderr"], float(
+                np.abs(plan.stderrs[i].cpu().numpy()[k] - ose).max()))
+            e["max_abs_err_grad"] = max(e["max_abs_err_grad"], dg)
+            e["max_rel_err_grad"] = max(e["max_rel_err_grad"], dg / max(1.0, np.abs(og).max()))
+        tol = TOL[prec]
+        ok = (e["max_abs_err_mean"] < tol and e["max_abs_err_stderr"] < tol and
+              e["max_rel_err_grad"] < tol)
+        return dict(e, tol=tol, ok=bool(ok), sampled="3 observables of 8 circuits",
+                    grad_bar="tol * max(1, |g|_inf)")
+
     plan = make_plan("split_bf16")
     if args.profile_pass:
+        prec = args.profile_precision
+        if prec != "split_bf16":
+            plan.close()
+            plan = make_plan(prec)
         for _ in range(args.steps):
             plan.expval()
             plan.expval_grad(us)
@@ -717,7 +789,8 @@ def main_batch(args):
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        log("profile pass done: %d steps, copy of %d bytes" % (args.steps, src.numel() * 4))
+        log("profile pass done: %d %s steps, copy of %d bytes" % (args.steps, prec,
+                                                                  src.numel() * 4))
         return
 
     result = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -729,27 +802,33 @@ def main_batch(args):
     result.update({"value": T / (ms * 1e-3), "unit": "terms/s", "ms_per_step": ms,
                    "fwd_terms_per_s": T / (ms_fwd * 1e-3), "fwd_ms": ms_fwd,
                    "tiles": plan.config()})
-
-    # per-kernel times: with timing on, a pass runs its launches one by one,
-    # each bracketed by events on its stream
-    api.profile_reset()
-    api.profile_enable(True)
-    nprof = max(2, min(args.steps, 4))
-    for _ in range(nprof):
-        plan.expval()
-        plan.expval_grad(us)
-    torch.cuda.synchronize()
-    kb = {}
-    for k in ("parity", "theta_prep", "phase_fwd", "phase_epilogue", "finalize", "weights",
-              "phase_bwd", "grad_reduce"):
-        tot, n = api.profile_query(k)
-        if n:
-            kb[k] = {"avg_ms": tot / n, "launches": n, "ms_per_step": tot / nprof}
-    api.profile_enable(False)
+    kb = kernel_times(plan, max(2, min(args.steps, 4)))
     result["kernels"] = kb
     dom = max(("phase_fwd", "phase_bwd"), key=lambda k: kb[k]["avg_ms"])
     result["roofline"] = roofline(T, kb[dom]["avg_ms"], dom + " (persistent, all 64 circuits)",
                                   recorded_traffic(name, dom))
+    par = {"split_bf16": parity(plan, "split_bf16")}
+    plan.close()
+    del plan
+
+    # three BF16 limbs of theta, fixed-point weights on the INT8 matrix cores
+    if not args.no_split3:
+        p3 = make_plan("split3_bf16")
+        ms3 = timed(p3)
+        ms3f = timed(p3, fwd_only=True)
+        log("split3_bf16 batched: fwd+bwd %.3f ms, fwd %.3f ms" % (ms3, ms3f))
+        kb3 = kernel_times(p3, max(2, min(args.steps, 4)))
+        fwd3 = roofline(T, kb3["phase_fwd"]["avg_ms"], "phase_fwd (persistent, 3 BF16 limbs)",
+                        None, "split3_bf16_fwd")
+        bwd3 = roofline(T, kb3["phase_bwd"]["avg_ms"], "phase_bwd (persistent, INT8 limbs)",
+                        None, "split3_bf16_bwd")
+        result["split3_bf16"] = {"fwd_bwd_terms_per_s": T / (ms3 * 1e-3),
+                                 "fwd_terms_per_s": T / (ms3f * 1e-3), "ms_per_step": ms3,
+                                 "fwd_ms": ms3f, "tiles": p3.config(), "kernels": kb3,
+                                 "roofline_fwd": fwd3, "roofline_bwd": bwd3}
+        par["split3_bf16"] = parity(p3, "split3_bf16")
+        p3.close()
+        del p3
 
     if not args.no_fp32:
         plan32 = make_plan("fp32")
@@ -760,39 +839,10 @@ def main_batch(args):
                           "fwd_terms_per_s": T / (ms32f * 1e-3), "ms_per_step": ms32,
                           "fwd_ms": ms32f, "tiles": plan32.config(),
                           "mfma_frac_fwd": 2.0 * T / (ms32f * 1e-3) / PEAK["fp32"][0]}
+        par["fp32"] = parity(plan32, "fp32")
         plan32.close()
         del plan32
-
-    # parity: 3 sampled observables of 8 sampled circuits, means and the
-    # gradient of a loss that weights only those observables
-    pick_c = np.random.default_rng(0).choice(64, size=8, replace=False)
-    errs = {"max_abs_err_mean": 0.0, "max_abs_err_stderr": 0.0, "max_rel_err_grad": 0.0}
-    prng = np.random.default_rng(1)
-    sel, upick = {}, []
-    for i, w in enumerate(ws):
-        u = np.zeros(w.l)
-        if i in pick_c:
-            sel[i] = prng.choice(w.l, size=3, replace=False)
-            u[sel[i]] = prng.normal(size=3)
-        upick.append(torch.from_numpy(u).cuda())
-    plan.expval()
-    plan.expval_grad(upick)
-    torch.cuda.synchronize()
-    for i, k in sel.items():
-        w, d = ws[i], dws[i]
-        om, ose = oracle.expval(w.n, w.gates, w.theta, d.ops01[k], w.samples)
-        og = oracle.expval_grad(w.n, w.gates, w.theta, d.ops01[k], w.samples,
-                                upick[i].cpu().numpy()[k])
-        errs["max_abs_err_mean"] = max(errs["max_abs_err_mean"],
-                                       float(np.abs(plan.means[i].cpu().numpy()[k] - om).max()))
-        errs["max_abs_err_stderr"] = max(errs["max_abs_err_stderr"],
-                                         float(np.abs(plan.stderrs[i].cpu().numpy()[k] - ose).max()))
-        errs["max_rel_err_grad"] = max(errs["max_rel_err_grad"],
-                                       float(np.abs(plan.grads[i].cpu().numpy() - og).max() /
-                                             max(1.0, np.abs(og).max())))
-    tol = TOL["split_bf16"]
-    result["parity"] = {"split_bf16": dict(errs, tol=tol, ok=bool(max(errs.values()) < tol),
-                                           sampled="3 observables of 8 circuits")}
+    result["parity"] = par
 
     if not args.no_cpu_baseline:
         # the oracle on a bounded sample: fwd + bwd of the first k observables
@@ -826,7 +876,6 @@ def main_batch(args):
                         "precision": "split_bf16 (hi+lo BF16, FP32 accumulate)",
                         "step": "BatchPlan.expval + BatchPlan.expval_grad (graph replays)",
                         "terms_per_step": T}
-    plan.close()
     print(json.dumps(result), flush=True)
 
 

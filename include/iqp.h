@@ -54,7 +54,22 @@ typedef enum {
  *   IQP_SPLIT_BF16:  2 theta_j = hi + lo with hi, lo BF16 (round to nearest
  *                    even), two BF16 matrix-core products per term (the +-1
  *                    and 0/1 parity operands are exact in BF16), FP32
- *                    accumulation.
+ *                    accumulation. 2 theta_j keeps 16 significant bits: the
+ *                    means meet 1e-4, but each gate's residual (up to
+ *                    2^-16 |2 theta_j|) repeats in every sample's phase, so
+ *                    with many anticommuting gates and many weighted
+ *                    observables the gradient can exceed 1e-4 * max(1, |g|).
+ *                    The backward weights S (below) are hi + lo BF16 too.
+ *   IQP_SPLIT3_BF16: 2 theta_j = hi + mid + lo, three BF16 limbs (24
+ *                    significant bits, the precision of FP32), three BF16
+ *                    products per term in the forward, FP32 accumulation.
+ *                    The backward weights S_ki = dL/dcos(E_ki) sin(E_ki) are
+ *                    held in 16-bit fixed point per observable,
+ *                    S_ki ~ q_k (256 d1_ki + d0_ki) with signed 8-bit limbs,
+ *                    q_k = bound_k / 32639, and contracted on the INT8
+ *                    matrix cores with exact INT32 sums: two INT8 products
+ *                    per term, the matrix-core time of one BF16 product. The
+ *                    gradient meets 1e-4 * max(1, |g|).
  *   IQP_SPARSE_FP32: only the non-zero entries of C: for each observable the
  *                    sum of +-2 theta_j over the generators that anticommute
  *                    with it (FP32 on the vector units), so the work is the
@@ -62,10 +77,15 @@ typedef enum {
  *                    l m s; faster when C is sparse (a few percent of
  *                    entries). The gradient sums per-gate contributions in
  *                    int64 fixed point, bitwise reproducible.
- * In both, theta is first reduced to [-pi/2, pi/2] by whole multiples of pi
+ * In all, theta is first reduced to [-pi/2, pi/2] by whole multiples of pi
  * (exp(i(theta + pi) X) = -exp(i theta X) is a global phase, Sec. 2.1), and
  * every phase is reduced modulo 2 pi in FP64 before its cos / sin. */
-typedef enum { IQP_FP32 = 0, IQP_SPLIT_BF16 = 1, IQP_SPARSE_FP32 = 2 } iqp_precision;
+typedef enum {
+    IQP_FP32 = 0,
+    IQP_SPLIT_BF16 = 1,
+    IQP_SPARSE_FP32 = 2,
+    IQP_SPLIT3_BF16 = 3
+} iqp_precision;
 
 /* A parameterized IQP circuit (Def. 1): generators g_j as bit rows and their
  * parameters theta_j. */
@@ -258,7 +278,8 @@ enum {
  * (host array) are read: n_qubits, n_words, n_gates, n_ops, n_samples. The
  * tile configuration is the one recorded for these shapes by iqp_batch_tune
  * in this process (or in the file named by the environment variable
- * IQP_TUNE_CACHE), else a default. The current device must be gfx950. */
+ * IQP_TUNE_CACHE), else a default. The current device must be gfx950.
+ * precision: IQP_FP32, IQP_SPLIT_BF16 or IQP_SPLIT3_BF16 (the dense forms). */
 int iqp_batch_plan_create(int32_t n_problems, const iqp_problem *probs, int precision,
                           int flags, iqp_batch_plan **plan);
 int iqp_batch_plan_destroy(iqp_batch_plan *plan);
@@ -378,7 +399,7 @@ typedef struct {
     int64_t n_data;
     const uint64_t *data;        /* device [N][W] training bit strings */
     int32_t unbiased;            /* MMD^2 estimator form, as iqp_mmd_loss_grad */
-    int32_t precision;           /* IQP_FP32, IQP_SPLIT_BF16 or IQP_SPARSE_FP32 */
+    int32_t precision;           /* any iqp_precision */
     int32_t optimizer;           /* IQP_OPT_GD or IQP_OPT_ADAM */
     double lr, beta1, beta2, eps;
     uint64_t seed0, seed1;       /* Philox key; samples use tag 0, operators tag 1 */

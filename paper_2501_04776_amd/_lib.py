@@ -21,6 +21,7 @@ IQP_ERR_UNSUPPORTED = -4
 IQP_FP32 = 0
 IQP_SPLIT_BF16 = 1
 IQP_SPARSE_FP32 = 2
+IQP_SPLIT3_BF16 = 3
 
 IQP_CALL_EXPVAL = 0
 IQP_CALL_EXPVAL_GRAD = 1

@@ -220,6 +220,11 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
     const int64_t sw = P.s_pad / 64;
     const int64_t bunits = ceil_div(P.m_pad / (32 * P.tc.bfn), 4) * (P.l_pad / (32 * P.tc.bfm));
     if (P.tc.bsplits <= 0) P.tc.bsplits = choose_bsplits(bunits, sw, P.tc.bfn);
+    if (prec == IQP_SPLIT3_BF16) {
+        // the INT32 sums of the fixed-point weights stay exact per unit
+        const int64_t min_ks = ceil_div(sw * 64, kI8MaxSamplesPerUnit);
+        if (P.tc.bsplits < min_ks) P.tc.bsplits = min_ks;
+    }
     if (P.tc.bsplits > sw) P.tc.bsplits = sw;
     P.tc.bsplits = ceil_div(sw, ceil_div(sw, P.tc.bsplits));
     P.fwd = parts.fwd;
@@ -256,9 +261,10 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
     }
     if (P.fwd) {
         P.o_bbits = carve(cur, (size_t)P.s_pad * P.mw * 8);
-        if (prec == IQP_SPLIT_BF16) {
+        if (prec == IQP_SPLIT_BF16 || prec == IQP_SPLIT3_BF16) {
             P.o_thh = carve(cur, (size_t)P.m_pad * 2);
             P.o_thl = carve(cur, (size_t)P.m_pad * 2);
+            if (prec == IQP_SPLIT3_BF16) P.o_thm = carve(cur, (size_t)P.m_pad * 2);
         } else {
             P.o_t32 = carve(cur, (size_t)P.m_pad * 4);
         }
@@ -275,6 +281,12 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
         if (prec == IQP_SPLIT_BF16) {
             P.o_shi = carve(cur, (size_t)P.s_pad * P.l_pad * 2);
             P.o_slo = carve(cur, (size_t)P.s_pad * P.l_pad * 2);
+        } else if (prec == IQP_SPLIT3_BF16) {
+            // signed 8-bit limbs, row scales and non-finite flags
+            P.o_shi = carve(cur, (size_t)P.s_pad * P.l_pad);
+            P.o_slo = carve(cur, (size_t)P.s_pad * P.l_pad);
+            P.o_sq = carve(cur, (size_t)P.l_pad * 8);
+            P.o_nf = carve(cur, (size_t)P.l_pad * 4);
         } else {
             P.o_s32 = carve(cur, (size_t)P.s_pad * P.l_pad * 4);
         }
@@ -388,9 +400,9 @@ static int check_common(const iqp_circuit *c, int64_t l, const uint64_t *ops, in
     if (s < 1 || s > kMaxRows) return fail(IQP_ERR_INVALID_ARG, "s out of range [1, 2^24]");
     if (!ops) return fail(IQP_ERR_INVALID_ARG, "ops is NULL");
     if (!samples) return fail(IQP_ERR_INVALID_ARG, "samples is NULL");
-    if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16 && precision != IQP_SPARSE_FP32)
-        return fail(IQP_ERR_INVALID_ARG,
-                    "precision must be IQP_FP32, IQP_SPLIT_BF16 or IQP_SPARSE_FP32");
+    if (!valid_precision(precision))
+        return fail(IQP_ERR_INVALID_ARG, "precision must be IQP_FP32, IQP_SPLIT_BF16, "
+                                         "IQP_SPARSE_FP32 or IQP_SPLIT3_BF16");
     return IQP_OK;
 }
 
@@ -549,8 +561,7 @@ size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s,
         return P.total;
     }
     if (call < IQP_CALL_EXPVAL || call > IQP_CALL_MMD_GRAD) return 0;
-    if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16 && precision != IQP_SPARSE_FP32)
-        return 0;
+    if (!valid_precision(precision)) return 0;
     if ((call == IQP_CALL_MMD || call == IQP_CALL_MMD_GRAD) && N < 1) return 0;
     Plan P;
     make_call_plan(P, call, c->n_qubits, c->n_gates, l, s, N, precision);
@@ -762,8 +773,9 @@ int iqp_mmd_loss_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops,
                             l, s, N, unbiased, loss),
             "mmd_loss");
     if (!grad_theta) return IQP_OK;
+    const CoefArgs ca = coef_args(P, nullptr, ws);
     IQP_TRY(launch_coef_mmd(lc, at<double>(ws, P.o_pstat), at<double>(ws, P.o_rowsum), op_weight,
-                            l, s, unbiased, at<double>(ws, P.o_coef)),
+                            l, s, unbiased, ca.coef, ca.sq, ca.nf),
             "coef_mmd");
     return run_backward(P, c, ops, samples, phi, true, ws, lc, grad_theta);
 }

@@ -501,8 +501,9 @@ int iqp_batch_plan_create(int32_t n_problems, const iqp_problem *probs, int prec
     if (n_problems < 1 || n_problems > kMaxProblems)
         return fail(IQP_ERR_INVALID_ARG, "n_problems out of range [1, 65536]");
     if (!probs) return fail(IQP_ERR_INVALID_ARG, "probs is NULL");
-    if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16)
-        return fail(IQP_ERR_INVALID_ARG, "precision must be IQP_FP32 or IQP_SPLIT_BF16");
+    if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16 && precision != IQP_SPLIT3_BF16)
+        return fail(IQP_ERR_INVALID_ARG,
+                    "precision must be IQP_FP32, IQP_SPLIT_BF16 or IQP_SPLIT3_BF16");
     if (flags & ~(int)IQP_BATCH_NO_GRAPH) return fail(IQP_ERR_INVALID_ARG, "unknown flags");
     int st;
     for (int p = 0; p < n_problems; ++p)

@@ -44,6 +44,14 @@ struct LaunchCtx {
 void timed_begin(const LaunchCtx &lc, int family, hipEvent_t *ev);
 void timed_end(const LaunchCtx &lc, int family, hipEvent_t ev);
 
+// Fixed-point backward weights (IQP_SPLIT3_BF16): |S_ki| <= sigma_k maps to
+// integers N with |N| <= kI8Max = 127 * 256 + 127, the largest magnitude two
+// signed 8-bit limbs hold as N = 256 hi + lo with hi = floor((N + 128) / 256)
+// in [-127, 127] and lo in [-128, 127]. An INT32 accumulator of such limbs
+// stays exact (|sum| <= 2^30) over up to 2^23 samples per work unit.
+constexpr double kI8Max = 32639.0;
+constexpr int64_t kI8MaxSamplesPerUnit = (int64_t)1 << 23;
+
 // Support-list capacity: the qubits of a generator of weight <= kSupCap are
 // listed; heavier generators are read from their bit rows.
 constexpr int kSupCap = 8;
@@ -55,11 +63,13 @@ constexpr int kSupCap = 8;
 // its flat block index to (problem, local block) through a prefix sum of the
 // per-problem block counts.
 
+// prec: IQP_FP32 (t32 split by gate parity), IQP_SPLIT_BF16 (hi, lo),
+// IQP_SPARSE_FP32 (t32 plain), IQP_SPLIT3_BF16 (hi, mid, lo).
 struct ThetaArgs {
     const double *theta;
     int64_t m, m_pad;
     int prec;
-    uint16_t *hi, *lo;
+    uint16_t *hi, *lo, *mid;
     float *t32;
 };
 inline int64_t blocks_of(const ThetaArgs &a) { return ceil_div(a.m_pad, 256); }
@@ -108,7 +118,7 @@ inline int64_t blocks_of(const ParityArgs &a) { return ceil_div(a.Gw * ceil_div(
 // `splits` ways (partials E[split][l_pad][s_pad]).
 struct FwdArgs {
     const uint64_t *cbits, *bbits;
-    const uint16_t *thh, *thl;
+    const uint16_t *thh, *thl, *thm;  // thm: third limb (IQP_SPLIT3_BF16 only)
     const float *t32;
     int64_t m_pad, l_pad, s_pad, splits;
     float *E;
@@ -132,13 +142,22 @@ struct FinArgs {
 };
 inline int64_t blocks_of(const FinArgs &a) { return ceil_div(a.l, 256); }
 
+// coef[2k], coef[2k+1] = alpha_k, beta_k of the backward weights. For the
+// fixed-point weights (IQP_SPLIT3_BF16) also the row scale
+// sq[k] = (|alpha_k| + |beta_k|) / kI8Max and a zeroed non-finite flag nf[k];
+// both pointers are NULL for the other forms.
 struct CoefArgs {
     const double *grad_mean;
     int64_t l, s;
     double *coef;
+    double *sq;
+    int32_t *nf;
 };
 inline int64_t blocks_of(const CoefArgs &a) { return ceil_div(a.l, 256); }
 
+// IQP_SPLIT3_BF16: shi / slo hold the high / low signed 8-bit limbs of
+// N_ki = rint(S_ki / sq[k]) (|N| <= kI8Max), and nf[k] is set to 1 where a
+// weight of row k is not finite.
 struct WeightsArgs {
     const float *phase;
     const double *coef;
@@ -146,6 +165,7 @@ struct WeightsArgs {
     int prec;
     uint16_t *shi, *slo;
     float *s32;
+    int32_t *nf;
 };
 inline int64_t blocks_of(const WeightsArgs &a) { return (a.s_pad / 64) * (a.l_pad / 64); }
 
@@ -159,6 +179,8 @@ struct BwdArgs {
     const uint64_t *btbits, *ctbits;
     int64_t m_pad, l_pad, s_pad, ksplits;
     float *gpart;
+    const double *sq;   // IQP_SPLIT3_BF16: row scales and non-finite flags
+    const int32_t *nf;
 };
 inline int64_t bwd_units(const BwdArgs &a, int fm, int fn) {
     return ceil_div(a.m_pad / (32 * fn), 4) * (a.l_pad / (32 * fm)) * a.ksplits;
@@ -331,6 +353,6 @@ hipError_t launch_mmd_loss(const LaunchCtx &lc, const double *pstat, const doubl
 
 hipError_t launch_coef_mmd(const LaunchCtx &lc, const double *pstat, const double *rowsum,
                            const double *op_weight, int64_t l, int64_t s, int unbiased,
-                           double *coef);
+                           double *coef, double *sq, int32_t *nf);
 
 }  // namespace iqp

@@ -1,7 +1,8 @@
 // gfx950 kernels of the IQP Monte Carlo expectation-value path.
 //
 //   theta_prep      theta -> 2 theta' (theta' = theta reduced to [-pi/2, pi/2]
-//                   by whole multiples of pi), as FP32 or BF16 hi + lo
+//                   by whole multiples of pi), as FP32 or two / three BF16
+//                   limbs
 //   bitslice,       bit-exact popcount(row AND col) mod 2 matrices (the
 //   parity_bs       exponents of B and C, Sec. 2.2) as XORs of per-qubit bit
 //                   columns, with in-register 64x64 bit transposes
@@ -40,11 +41,18 @@ __device__ __forceinline__ void theta_prep_body(const ThetaArgs &a, int64_t blk)
     const double two = 2.0 * tr;
     if (a.prec == 2) {
         gptr(a.t32)[i] = (float)two;  // plain, for the sparse contraction
-    } else if (a.prec == 1) {
+    } else if (a.prec == 1 || a.prec == 3) {
+        // each limb is the BF16 rounding of what the previous ones leave
         const uint16_t h = f2bf_rne((float)two);
         const double rem = two - (double)bf2f(h);
+        const uint16_t l = f2bf_rne((float)rem);
         gptr(a.hi)[i] = h;
-        gptr(a.lo)[i] = f2bf_rne((float)rem);
+        if (a.prec == 1) {
+            gptr(a.lo)[i] = l;
+        } else {
+            gptr(a.mid)[i] = l;
+            gptr(a.lo)[i] = f2bf_rne((float)(rem - (double)bf2f(l)));
+        }
     } else {
         // split by gate parity: lane half h of the 32x32x2 product reads gate 2t + h
         gptr(a.t32)[(i & 1) * (a.m_pad >> 1) + (i >> 1)] = (float)two;
@@ -270,22 +278,23 @@ __device__ __forceinline__ bf16x8 expand_pm1(uint32_t x16, uint32_t ones) {
     return __builtin_bit_cast(bf16x8, d);
 }
 
-// C_kj theta_j / 2 = bit ? 2 theta'_j : 0 for both limbs; the sign bit is
-// spread over its half by an arithmetic shift to make the mask.
-__device__ __forceinline__ void expand_masked(uint32_t x16, const u32x4 &th, const u32x4 &tl,
-                                              bf16x8 &ah, bf16x8 &al) {
+// C_kj theta_j / 2 = bit ? 2 theta'_j : 0 for each of the NL limbs; the sign
+// bit is spread over its half by an arithmetic shift to make the mask.
+template <int NL>
+__device__ __forceinline__ void expand_masked(uint32_t x16, const u32x4 (&th)[NL],
+                                              bf16x8 (&out)[NL]) {
     const u16x2 xv = {(unsigned short)x16, (unsigned short)x16};
-    uint32_t dh[4], dl[4];
+    uint32_t d[NL][4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const u16x2 sh = {(unsigned short)(15 - 2 * v), (unsigned short)(14 - 2 * v)};
         const s16x2 sg = __builtin_bit_cast(s16x2, (u16x2)(xv << sh)) >> (s16x2){15, 15};
         const uint32_t msk = __builtin_bit_cast(uint32_t, sg);
-        dh[v] = th[v] & msk;
-        dl[v] = tl[v] & msk;
+#pragma unroll
+        for (int L = 0; L < NL; ++L) d[L][v] = th[L][v] & msk;
     }
-    ah = __builtin_bit_cast(bf16x8, dh);
-    al = __builtin_bit_cast(bf16x8, dl);
+#pragma unroll
+    for (int L = 0; L < NL; ++L) out[L] = __builtin_bit_cast(bf16x8, d[L]);
 }
 
 // c_kj in {0, 1}: 1.0 = 0x3F80.
@@ -362,15 +371,15 @@ __device__ __forceinline__ void interleave_half() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
-// Operands of one K-step: the +-1 B fragments and the masked hi / lo theta
-// A fragments.
-template <int FM, int FN>
+// Operands of one K-step: the +-1 B fragments and the masked theta limb A
+// fragments (limb 0 = hi, then lo, or mid and lo with three limbs).
+template <int FM, int FN, int NL>
 struct FwdOps {
-    bf16x8 bv[FN], ah[FM], al[FM];
+    bf16x8 bv[FN], a[NL][FM];
 };
 
-template <int FM, int FN, int T>
-__device__ __forceinline__ void fwd_expand_b(FwdOps<FM, FN> &o, const uint64_t (&bw)[FN],
+template <int FM, int FN, int NL, int T>
+__device__ __forceinline__ void fwd_expand_b(FwdOps<FM, FN, NL> &o, const uint64_t (&bw)[FN],
                                              uint32_t ones) {
 #pragma unroll
     for (int g = 0; g < FN; ++g) {
@@ -379,47 +388,67 @@ __device__ __forceinline__ void fwd_expand_b(FwdOps<FM, FN> &o, const uint64_t (
     }
 }
 
-template <int FM, int FN, int T>
-__device__ __forceinline__ void fwd_expand_a(FwdOps<FM, FN> &o, const uint64_t (&cw)[FM],
-                                             const u32x4 &th, const u32x4 &tl) {
+template <int FM, int FN, int NL, int T>
+__device__ __forceinline__ void fwd_expand_a(FwdOps<FM, FN, NL> &o, const uint64_t (&cw)[FM],
+                                             const u32x4 (&th)[NL]) {
 #pragma unroll
     for (int f = 0; f < FM; ++f) {
         const uint32_t d = (uint32_t)(cw[f] >> (32 * (T >> 1)));
-        expand_masked((T & 1) ? (d >> 16) : d, th, tl, o.ah[f], o.al[f]);
+        bf16x8 x[NL];
+        expand_masked<NL>((T & 1) ? (d >> 16) : d, th, x);
+#pragma unroll
+        for (int L = 0; L < NL; ++L) o.a[L][f] = x[L];
     }
 }
 
-template <int FM, int FN, int T>
-__device__ __forceinline__ void fwd_expand(FwdOps<FM, FN> &o, const uint64_t (&cw)[FM],
-                                           const uint64_t (&bw)[FN], const u32x4 &th,
-                                           const u32x4 &tl, uint32_t ones) {
-    fwd_expand_b<FM, FN, T>(o, bw, ones);
-    fwd_expand_a<FM, FN, T>(o, cw, th, tl);
+template <int FM, int FN, int NL, int T>
+__device__ __forceinline__ void fwd_expand(FwdOps<FM, FN, NL> &o, const uint64_t (&cw)[FM],
+                                           const uint64_t (&bw)[FN], const u32x4 (&th)[NL],
+                                           uint32_t ones) {
+    fwd_expand_b<FM, FN, NL, T>(o, bw, ones);
+    fwd_expand_a<FM, FN, NL, T>(o, cw, th);
 }
 
-template <int FM, int FN, int LIMB>
-__device__ __forceinline__ void fwd_mfma_half(const FwdOps<FM, FN> &o, f32x16 (&acc)[FM][FN]) {
+template <int FM, int FN, int NL, int LIMB>
+__device__ __forceinline__ void fwd_mfma_limb(const FwdOps<FM, FN, NL> &o,
+                                              f32x16 (&acc)[FM][FN]) {
 #pragma unroll
     for (int f = 0; f < FM; ++f)
 #pragma unroll
         for (int g = 0; g < FN; ++g)
-            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(LIMB ? o.al[f] : o.ah[f], o.bv[g],
-                                                                acc[f][g], 0, 0, 0);
+            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.a[LIMB][f], o.bv[g], acc[f][g],
+                                                                0, 0, 0);
+}
+
+// The theta limbs of one K-step from LDS: limb L at Tp[L][off].
+template <int NL>
+__device__ __forceinline__ void fwd_theta(u32x4 (&th)[NL], const u32x4 *const (&Tp)[NL], int off) {
+#pragma unroll
+    for (int L = 0; L < NL; ++L) th[L] = Tp[L][off];
 }
 
 // One pipeline region: the products of K-step t (operands `cur`) while the
-// operands of K-step T1 are expanded into `nxt` (theta limbs th, tl).
-template <int FM, int FN, int T1>
-__device__ __forceinline__ void fwd_region(const FwdOps<FM, FN> &cur, FwdOps<FM, FN> &nxt,
+// operands of K-step T1 (theta limbs at offset `off`) are expanded into `nxt`.
+// The products of each limb run as one pass over all accumulators, so two
+// products into the same accumulator are always a full pass apart.
+template <int FM, int FN, int NL, int T1>
+__device__ __forceinline__ void fwd_region(const FwdOps<FM, FN, NL> &cur, FwdOps<FM, FN, NL> &nxt,
                                            const uint64_t (&cw)[FM], const uint64_t (&bw)[FN],
-                                           const u32x4 &th, const u32x4 &tl, uint32_t ones,
+                                           const u32x4 *const (&Tp)[NL], int off, uint32_t ones,
                                            f32x16 (&acc)[FM][FN]) {
-    fwd_expand_b<FM, FN, T1>(nxt, bw, ones);
-    fwd_mfma_half<FM, FN, 0>(cur, acc);
-    interleave_half<2, FM * FN, 8 * FN + 4>();
-    fwd_expand_a<FM, FN, T1>(nxt, cw, th, tl);
-    fwd_mfma_half<FM, FN, 1>(cur, acc);
-    interleave_half<0, FM * FN, 16 * FM + 4>();
+    u32x4 th[NL];
+    fwd_theta<NL>(th, Tp, off);
+    fwd_expand_b<FM, FN, NL, T1>(nxt, bw, ones);
+    fwd_mfma_limb<FM, FN, NL, 0>(cur, acc);
+    interleave_half<NL, FM * FN, 8 * FN + 4>();
+    fwd_expand_a<FM, FN, NL, T1>(nxt, cw, th);
+    fwd_mfma_limb<FM, FN, NL, 1>(cur, acc);
+    if constexpr (NL == 3) {
+        fwd_mfma_limb<FM, FN, NL, 2>(cur, acc);
+        interleave_half<0, 2 * FM * FN, 20 * FM + 4>();
+    } else {
+        interleave_half<0, FM * FN, 16 * FM + 4>();
+    }
 }
 
 // Decomposition shared by both forward kernels.
@@ -458,14 +487,17 @@ __device__ __forceinline__ void store_tile(const f32x16 (&acc)[FM][FN], float IQ
         }
 }
 
-template <int FM, int FN>
+// NL = 2 (IQP_SPLIT_BF16: hi, lo) or 3 (IQP_SPLIT3_BF16: hi, mid, lo).
+template <int FM, int FN, int NL>
 __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int tid) {
-    // per word 8 units of 16 bytes: K-step t, half h at 2t + h
-    __shared__ u32x4 lth[2][kChunkWords * 8], ltl[2][kChunkWords * 8];
+    // per word 8 units of 16 bytes per limb: K-step t, half h at 2t + h
+    __shared__ u32x4 lt[NL][2][kChunkWords * 8];
     const uint64_t IQP_GLOBAL *__restrict__ cbits = gptr(a.cbits);
     const uint64_t IQP_GLOBAL *__restrict__ bbits = gptr(a.bbits);
-    const u32x4 IQP_GLOBAL *__restrict__ thh = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.thh));
-    const u32x4 IQP_GLOBAL *__restrict__ thl = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.thl));
+    const u32x4 IQP_GLOBAL *thp[NL];
+    thp[0] = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.thh));
+    thp[NL - 1] = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.thl));
+    if constexpr (NL == 3) thp[1] = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.thm));
     float IQP_GLOBAL *__restrict__ E = gptr(a.E);
     const int64_t l_pad = a.l_pad, s_pad = a.s_pad, mw = a.m_pad / 64;
     const int64_t n_ob = l_pad / (32 * FM), n_sb = s_pad / (32 * FN);
@@ -488,13 +520,13 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int 
 #pragma unroll
             for (int a = 0; a < 16; ++a) acc[f][g][a] = 0.0f;
 
-    // stage a chunk: wave v copies units [64 v, 64 v + 64) of both limbs
+    // stage a chunk: wave v copies units [64 v, 64 v + 64) of every limb
     const int wv = wave_id();
     auto stage = [&](int64_t cw0, int buf) {
         const int64_t src = cw0 * 8 + wv * 64 + lane;
         if (src < U.w1 * 8) {
-            dma16(thh + src, &lth[buf][wv * 64]);
-            dma16(thl + src, &ltl[buf][wv * 64]);
+#pragma unroll
+            for (int L = 0; L < NL; ++L) dma16(thp[L] + src, &lt[L][buf][wv * 64]);
         }
     };
     if (nchunks > 0) stage(U.w0, 0);
@@ -506,19 +538,25 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int 
         for (int g = 0; g < FN; ++g) nxt_b[g] = (bbase + (g * mw + U.w0) * 32)[r];
     }
     dma_wait_barrier();
-    FwdOps<FM, FN> opA, opB;
+    FwdOps<FM, FN, NL> opA, opB;
     for (int64_t c = 0; c < nchunks; ++c) {
         const int buf = (int)(c & 1);
         const int64_t cw0 = U.w0 + c * kChunkWords;
         const int64_t cw1 = (cw0 + kChunkWords < U.w1) ? cw0 + kChunkWords : U.w1;
         if (c + 1 < nchunks) stage(cw1, buf ^ 1);
-        const u32x4 *Th = lth[buf] + h, *Tl = ltl[buf] + h;
+        const u32x4 *Tp[NL];
+#pragma unroll
+        for (int L = 0; L < NL; ++L) Tp[L] = lt[L][buf] + h;
         // K-step 0 of the chunk's first word
 #pragma unroll
         for (int f = 0; f < FM; ++f) cur_c[f] = nxt_c[f] >> (8 * h);
 #pragma unroll
         for (int g = 0; g < FN; ++g) cur_b[g] = nxt_b[g] >> (8 * h);
-        fwd_expand<FM, FN, 0>(opA, cur_c, cur_b, Th[0], Tl[0], ones);
+        {
+            u32x4 th[NL];
+            fwd_theta<NL>(th, Tp, 0);
+            fwd_expand<FM, FN, NL, 0>(opA, cur_c, cur_b, th, ones);
+        }
         for (int64_t w = cw0; w < cw1; ++w) {
             const int o = (int)(w - cw0) * 8;
             if (w + 1 < U.w1) {
@@ -528,9 +566,9 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int 
                 for (int g = 0; g < FN; ++g) nxt_b[g] = (bbase + (g * mw + w + 1) * 32)[r];
             }
             // region t: products of K-step t, expansion of K-step t+1
-            fwd_region<FM, FN, 1>(opA, opB, cur_c, cur_b, Th[o + 2], Tl[o + 2], ones, acc);
-            fwd_region<FM, FN, 2>(opB, opA, cur_c, cur_b, Th[o + 4], Tl[o + 4], ones, acc);
-            fwd_region<FM, FN, 3>(opA, opB, cur_c, cur_b, Th[o + 6], Tl[o + 6], ones, acc);
+            fwd_region<FM, FN, NL, 1>(opA, opB, cur_c, cur_b, Tp, o + 2, ones, acc);
+            fwd_region<FM, FN, NL, 2>(opB, opA, cur_c, cur_b, Tp, o + 4, ones, acc);
+            fwd_region<FM, FN, NL, 3>(opA, opB, cur_c, cur_b, Tp, o + 6, ones, acc);
             // K-step 0 of word w+1, unconditionally so that it interleaves with
             // the products below: past the chunk's last word it reads inside
             // the chunk's buffer and is recomputed after the barrier
@@ -539,7 +577,7 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int 
             for (int f = 0; f < FM; ++f) cur_c[f] = nxt_c[f] >> (8 * h);
 #pragma unroll
             for (int g = 0; g < FN; ++g) cur_b[g] = nxt_b[g] >> (8 * h);
-            fwd_region<FM, FN, 0>(opB, opA, cur_c, cur_b, Th[on], Tl[on], ones, acc);
+            fwd_region<FM, FN, NL, 0>(opB, opA, cur_c, cur_b, Tp, on, ones, acc);
         }
         dma_wait_barrier();
     }
@@ -665,11 +703,11 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs &a, int64_t gu, int t
 
 // Plain launch: one workgroup per unit, units spread over the XCDs in
 // contiguous ranges.
-template <int FM, int FN>
+template <int FM, int FN, int NL>
 __global__ __launch_bounds__(256, 1) void phase_fwd_bf16_kernel(FwdArgs a, int64_t units) {
     const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
     if (gu >= units) return;  // uniform over the workgroup
-    fwd_bf16_body<FM, FN>(a, gu, (int)threadIdx.x);
+    fwd_bf16_body<FM, FN, NL>(a, gu, (int)threadIdx.x);
 }
 
 template <int FM, int FN>
@@ -680,11 +718,12 @@ __global__ __launch_bounds__(256, 1) void phase_fwd_f32_kernel(FwdArgs a, int64_
 }
 
 // Persistent launch over the units of a batch of problems.
-template <int FM, int FN>
+template <int FM, int FN, int NL>
 __global__ __launch_bounds__(256, 1) void phase_fwd_bf16_persistent(
     const FwdArgs *__restrict__ args, const int64_t *__restrict__ off, int np,
     unsigned long long *counter) {
-    persistent_loop(off, np, counter, [&](int p, int64_t u) { fwd_bf16_body<FM, FN>(args[p], u, opaque_tid()); });
+    persistent_loop(off, np, counter,
+                    [&](int p, int64_t u) { fwd_bf16_body<FM, FN, NL>(args[p], u, opaque_tid()); });
 }
 
 template <int FM, int FN>
@@ -701,7 +740,11 @@ static hipError_t fwd_dispatch(const LaunchCtx &lc, int prec, const FwdArgs &a) 
     if (units > kMaxBlocks) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)units);
     if (prec == 1)
-        hipLaunchKernelGGL((phase_fwd_bf16_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a, units);
+        hipLaunchKernelGGL((phase_fwd_bf16_kernel<FM, FN, 2>), grid, dim3(256), 0, lc.stream, a,
+                           units);
+    else if (prec == 3)
+        hipLaunchKernelGGL((phase_fwd_bf16_kernel<FM, FN, 3>), grid, dim3(256), 0, lc.stream, a,
+                           units);
     else
         hipLaunchKernelGGL((phase_fwd_f32_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a, units);
     return hipGetLastError();
@@ -724,7 +767,10 @@ static hipError_t fwd_persistent(const LaunchCtx &lc, int prec, const FwdArgs *a
                                  const int64_t *off, int np, unsigned long long *counter,
                                  int grid) {
     if (prec == 1)
-        hipLaunchKernelGGL((phase_fwd_bf16_persistent<FM, FN>), dim3(grid), dim3(256), 0,
+        hipLaunchKernelGGL((phase_fwd_bf16_persistent<FM, FN, 2>), dim3(grid), dim3(256), 0,
+                           lc.stream, args, off, np, counter);
+    else if (prec == 3)
+        hipLaunchKernelGGL((phase_fwd_bf16_persistent<FM, FN, 3>), dim3(grid), dim3(256), 0,
                            lc.stream, args, off, np, counter);
     else
         hipLaunchKernelGGL((phase_fwd_f32_persistent<FM, FN>), dim3(grid), dim3(256), 0,
@@ -819,11 +865,23 @@ hipError_t launch_finalize(const LaunchCtx &lc, const FinArgs &a) {
 // Backward weights. coef[2k] = alpha_k, coef[2k+1] = beta_k give
 // dL/dc_ki = alpha_k + beta_k cos E_ki, and
 //   S_ki = (alpha_k + beta_k cos E_ki) sin E_ki.
+// Row scale of the fixed-point weights: |S_ki| <= |alpha_k| + |beta_k| since
+// |cos|, |sin| <= 1.
+__device__ __forceinline__ void coef_rowscale(double *sq, int32_t *nf, int64_t k, double al,
+                                              double be) {
+    if (sq) {
+        gptr(sq)[k] = (fabs(al) + fabs(be)) / kI8Max;
+        gptr(nf)[k] = 0;
+    }
+}
+
 __device__ __forceinline__ void coef_plain_body(const CoefArgs &a, int64_t blk) {
     const int64_t k = blk * 256 + threadIdx.x;
     if (k >= a.l) return;
-    gptr(a.coef)[2 * k] = gptr(a.grad_mean)[k] / (double)a.s;
+    const double al = gptr(a.grad_mean)[k] / (double)a.s;
+    gptr(a.coef)[2 * k] = al;
     gptr(a.coef)[2 * k + 1] = 0.0;
+    coef_rowscale(a.sq, a.nf, k, al, 0.0);
 }
 
 hipError_t launch_coef_plain(const LaunchCtx &lc, const CoefArgs &a) {
@@ -867,7 +925,43 @@ __device__ __forceinline__ void weights_body(const WeightsArgs &a, int64_t blk) 
         tile[kr][tx] = v;
     }
     __syncthreads();
-    if (prec == 1) {
+    if (prec == 3) {
+        // 16-bit fixed point per observable row: N = rint(S / q_k), split into
+        // signed 8-bit limbs N = 256 hi + lo; 64 observables x 4 groups of 16
+        // samples, one 16-byte unit of each limb per thread, at
+        // ((k/32) * KTs + i/32) * 64 + ((i/16)&1) * 32 + k%32, KTs = s_pad / 32
+        const int64_t KTs = s_pad / 32;
+        const int kl = threadIdx.x & 63, sg = threadIdx.x >> 6;
+        const int64_t k = k0 + kl, i = i0 + 16 * sg;
+        double inv = 0.0;
+        if (k < l) {
+            const double sig = fabs(coef[2 * k]) + fabs(coef[2 * k + 1]);
+            inv = sig > 0.0 ? kI8Max / sig : 0.0;
+        }
+        bool bad = false;
+        uint32_t dh[4], dl[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            uint32_t ph = 0, pl = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float x = tile[kl][16 * sg + 4 * v + e];
+                bad |= !isfinite(x);
+                double nv = rint((double)x * inv);
+                nv = nv > kI8Max ? kI8Max : (nv < -kI8Max - 1.0 ? -kI8Max - 1.0 : nv);
+                const int32_t N = isfinite(nv) ? (int32_t)nv : 0;
+                const int32_t hi = (N + 128) >> 8, lo = N - 256 * hi;
+                ph |= ((uint32_t)hi & 0xFFu) << (8 * e);
+                pl |= ((uint32_t)lo & 0xFFu) << (8 * e);
+            }
+            dh[v] = ph;
+            dl[v] = pl;
+        }
+        const int64_t idx = ((k >> 5) * KTs + (i >> 5)) * 64 + ((i >> 4) & 1) * 32 + (k & 31);
+        reinterpret_cast<u32x4 IQP_GLOBAL *>(shi)[idx] = (u32x4){dh[0], dh[1], dh[2], dh[3]};
+        reinterpret_cast<u32x4 IQP_GLOBAL *>(slo)[idx] = (u32x4){dl[0], dl[1], dl[2], dl[3]};
+        if (bad && k < l) gptr(a.nf)[k] = 1;  // every writer stores the same value
+    } else if (prec == 1) {
         const int64_t KTs = s_pad / 16;
         // 64 observables x 8 groups of 8 samples = 512 units, 2 per thread
 #pragma unroll
@@ -1186,6 +1280,234 @@ __device__ __forceinline__ void bwd_f32_body(const BwdArgs &a, int64_t gu, int t
     bwd_epilogue<FM, FN>(acc, ctbits, ob, jb, lw, h, r, active, gpart, m_pad);
 }
 
+// ---------------------------------------------------------------------------
+// INT8 form of the backward (IQP_SPLIT3_BF16). S is held per observable row in
+// 16-bit fixed point, S_ki ~ q_k (256 hi_ki + lo_ki) with signed 8-bit limbs,
+// written by weights_kernel as the A-operand image of a 32x32x32 INT8 product
+// (lane l: row l % 32, K values 16 (l / 32) .. + 15). Each K-step (32
+// samples) takes two INT8 products per 32x32 block, one per limb, into
+// separate INT32 accumulators, so the sums are exact; the epilogue forms
+// q_k (256 T_hi + T_lo) in FP64 per row before the masked sum over rows.
+// Same work units, staging and pipeline as the BF16 form, with two K-steps
+// per 64-sample word instead of four.
+typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
+
+// B_ij = (-1)^{bit} as signed bytes (+1 = 0x01, -1 = 0xFF) for the 16 K values
+// of the lane (bits 0..15 of x16). For dword v (bits 4v .. 4v+3), packed
+// 16-bit shifts move bits 4v, 4v+1 to positions 15, 31 of one dword and bits
+// 4v+2, 4v+3 to positions 15, 31 of another; the byte permute's
+// sign-replicating selectors 8..11 turn those four sign positions into
+// 0x00 / 0xFF bytes in order.
+__device__ __forceinline__ i32x4 expand_pm1_i8(uint32_t x16) {
+    const u16x2 xv = {(unsigned short)x16, (unsigned short)x16};
+    uint32_t d[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const u16x2 sh1 = {(unsigned short)(15 - 4 * v), (unsigned short)(14 - 4 * v)};
+        const u16x2 sh0 = {(unsigned short)(13 - 4 * v), (unsigned short)(12 - 4 * v)};
+        const uint32_t s1 = __builtin_bit_cast(uint32_t, (u16x2)(xv << sh1));
+        const uint32_t s0 = __builtin_bit_cast(uint32_t, (u16x2)(xv << sh0));
+        d[v] = __builtin_amdgcn_perm(s0, s1, 0x0B0A0908u) | 0x01010101u;
+    }
+    return (i32x4){(int32_t)d[0], (int32_t)d[1], (int32_t)d[2], (int32_t)d[3]};
+}
+
+template <int FM, int FN>
+struct BwdOpsI8 {
+    i32x4 a[2][FM], bv[FN];
+};
+
+template <int FM, int FN, int T>
+__device__ __forceinline__ void bwdi8_expand_a(BwdOpsI8<FM, FN> &o, const u32x4 *ls, int lane) {
+#pragma unroll
+    for (int L = 0; L < 2; ++L)
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+            o.a[L][f] = __builtin_bit_cast(i32x4, ls[((L * FM + f) * 2 + T) * 64 + lane]);
+}
+
+template <int FM, int FN, int T, int G0, int G1>
+__device__ __forceinline__ void bwdi8_expand_b(BwdOpsI8<FM, FN> &o, const uint64_t (&bw)[FN]) {
+#pragma unroll
+    for (int g = G0; g < G1; ++g) o.bv[g] = expand_pm1_i8((uint32_t)(bw[g] >> (32 * T)));
+}
+
+template <int FM, int FN, int L>
+__device__ __forceinline__ void bwdi8_mfma_limb(const BwdOpsI8<FM, FN> &o,
+                                                i32x16 (&acc)[2][FM][FN]) {
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int g = 0; g < FN; ++g)
+            acc[L][f][g] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.a[L][f], o.bv[g], acc[L][f][g],
+                                                                 0, 0, 0);
+}
+
+// One pipeline region: the products of K-step t (operands `cur`) while the
+// operands of K-step T1 are read from `lsn` and expanded into `nxt`.
+template <int FM, int FN, int T1>
+__device__ __forceinline__ void bwdi8_region(const BwdOpsI8<FM, FN> &cur, BwdOpsI8<FM, FN> &nxt,
+                                             const u32x4 *lsn, const uint64_t (&bw)[FN], int lane,
+                                             i32x16 (&acc)[2][FM][FN]) {
+    bwdi8_expand_a<FM, FN, T1>(nxt, lsn, lane);
+    bwdi8_expand_b<FM, FN, T1, 0, FN / 2>(nxt, bw);
+    bwdi8_mfma_limb<FM, FN, 0>(cur, acc);
+    interleave_half<2 * FM, FM * FN, 9 * FN + 2>();
+    bwdi8_expand_b<FM, FN, T1, FN / 2, FN>(nxt, bw);
+    bwdi8_mfma_limb<FM, FN, 1>(cur, acc);
+    interleave_half<0, FM * FN, 9 * FN + 2>();
+}
+
+// sum_k c_kj q_k (256 T_hi + T_lo)[k][j] over this wave's observable rows, per
+// gate column; a row whose weights were not finite contributes NaN.
+template <int FM, int FN>
+__device__ __forceinline__ void bwdi8_epilogue(const i32x16 (&acc)[2][FM][FN],
+                                               const uint64_t IQP_GLOBAL *__restrict__ ctbits,
+                                               const double IQP_GLOBAL *__restrict__ sq,
+                                               const int32_t IQP_GLOBAL *__restrict__ nf,
+                                               int64_t ob, int64_t jb, int64_t lw, int h, int r,
+                                               bool active, float IQP_GLOBAL *__restrict__ gpart,
+                                               int64_t m_pad) {
+    double gs[FN];
+#pragma unroll
+    for (int g = 0; g < FN; ++g) gs[g] = 0.0;
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+        const int64_t k0 = (ob * FM + f) * 32;
+        double q[16];
+#pragma unroll
+        for (int a = 0; a < 16; ++a) {
+            const int64_t k = k0 + acc_row(a, h);
+            q[a] = nf[k] ? (double)NAN : sq[k];
+        }
+#pragma unroll
+        for (int g = 0; g < FN; ++g) {
+            const int64_t j = (jb * FN + g) * 32 + r;
+            const uint64_t cw = ctbits[((j >> 5) * lw + (k0 >> 6)) * 32 + (j & 31)];
+            const uint32_t c32 = (uint32_t)(cw >> (k0 & 63)) >> (4 * h);
+#pragma unroll
+            for (int a = 0; a < 16; ++a) {
+                const double t = 256.0 * (double)acc[1][f][g][a] + (double)acc[0][f][g][a];
+                gs[g] += ((c32 >> (8 * (a >> 2) + (a & 3))) & 1u) ? q[a] * t : 0.0;
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < FN; ++g) {
+        const int64_t j = (jb * FN + g) * 32 + r;
+        const double v = gs[g] + __shfl_xor(gs[g], 32, 64);
+        if (active && h == 0) gpart[ob * m_pad + j] = (float)v;
+    }
+}
+
+template <int FM, int FN>
+__device__ __forceinline__ void bwd_i8_body(const BwdArgs &a, int64_t gu, int tid) {
+    // one sample word: [limb][f][t][lane], 16 bytes each, two buffers
+    constexpr int kUnits = 2 * FM * 2 * 64;
+    __shared__ u32x4 ls0[kUnits], ls1[kUnits];
+    const u32x4 IQP_GLOBAL *__restrict__ shi = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.shi));
+    const u32x4 IQP_GLOBAL *__restrict__ slo = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.slo));
+    const uint64_t IQP_GLOBAL *__restrict__ btbits = gptr(a.btbits);
+    const uint64_t IQP_GLOBAL *__restrict__ ctbits = gptr(a.ctbits);
+    const int64_t m_pad = a.m_pad, sw = a.s_pad / 64, lw = a.l_pad / 64;
+    const int64_t n_jb = m_pad / (32 * FN), n_ob = a.l_pad / (32 * FM);
+    const int64_t n_jbg = ceil_div(n_jb, 4);
+    // unit = ((sample split) * n_ob + observable block) * n_jbg + gate-block group
+    const int64_t jbg = gu % n_jbg, t0 = gu / n_jbg;
+    const int64_t ob = t0 % n_ob, ks = t0 / n_ob;
+    const int64_t wps = ceil_div(sw, a.ksplits);
+    const int64_t w0 = ks * wps, w1 = (w0 + wps < sw) ? w0 + wps : sw;
+    float IQP_GLOBAL *__restrict__ gpart = gptr(a.gpart) + ks * n_ob * m_pad;
+    const int64_t jb_raw = jbg * 4 + wave_id();
+    const bool active = jb_raw < n_jb;
+    const int64_t jb = active ? jb_raw : n_jb - 1;
+    const int lane = tid & 63;
+    const int h = lane >> 5, r = lane & 31;
+    const int64_t KTs = sw * 2;
+    const uint64_t IQP_GLOBAL *bbase = btbits + jb * FN * sw * 32;
+    const u32x4 IQP_GLOBAL *sbase_h = shi + ob * FM * KTs * 64;
+    const u32x4 IQP_GLOBAL *sbase_l = slo + ob * FM * KTs * 64;
+
+    i32x16 acc[2][FM][FN];
+#pragma unroll
+    for (int L = 0; L < 2; ++L)
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int g = 0; g < FN; ++g)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[L][f][g][e] = 0;
+
+    // staging block b = (limb * FM + f) * 2 + t (64 units of 16 bytes)
+    //   <- S(limb)[(f * KTs + 2 w + t) * 64 + ln]; limb 0 = lo, 1 = hi;
+    // wave v copies blocks v, v+4, ...
+    const int wv = wave_id();
+    auto stage = [&](int64_t w, u32x4 *dst) {
+#pragma unroll
+        for (int k = 0; k < kUnits / 256; ++k) {
+            const int b = wv + 4 * k;
+            const int t = b & 1, f = (b >> 1) % FM, limb = b / (2 * FM);
+            const int64_t src = ((int64_t)f * KTs + 2 * w + t) * 64 + lane;
+            dma16((limb ? sbase_h : sbase_l) + src, &dst[b * 64]);
+        }
+    };
+    // every unit has w1 - w0 >= 1 sample words (the host picks the splits)
+    stage(w0, ls0);
+    if (w0 + 1 < w1) stage(w0 + 1, ls1);
+    uint64_t nxt[FN], cur[FN];
+#pragma unroll
+    for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w0) * 32)[r];
+    dma_wait_barrier();
+    // K-step t of a word uses bits 32 t + 16 h .. + 15 of the lane's word
+#pragma unroll
+    for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> (16 * h);
+    if (w0 + 1 < w1) {
+#pragma unroll
+        for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w0 + 1) * 32)[r];
+    }
+    BwdOpsI8<FM, FN> opA, opB;
+    bwdi8_expand_a<FM, FN, 0>(opA, ls0, lane);
+    bwdi8_expand_b<FM, FN, 0, 0, FN>(opA, cur);
+    // Word w reads `mine`; its second region runs after a barrier that makes
+    // word w+1's buffer `other` valid, so that region already expands word
+    // w+1's first K-step; the copy of word w+2 into `mine` is issued right
+    // after that barrier.
+    auto word = [&](int64_t w, u32x4 *mine, const u32x4 *other) {
+        bwdi8_region<FM, FN, 1>(opA, opB, mine, cur, lane, acc);
+        dma_wait_barrier();
+        if (w + 2 < w1) stage(w + 2, mine);
+#pragma unroll
+        for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> (16 * h);
+        if (w + 2 < w1) {
+#pragma unroll
+            for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w + 2) * 32)[r];
+        }
+        // past the last word this expands a stale buffer and is never used
+        bwdi8_region<FM, FN, 0>(opB, opA, other, cur, lane, acc);
+    };
+    for (int64_t w = w0; w < w1; w += 2) {
+        word(w, ls0, ls1);
+        if (w + 1 < w1) word(w + 1, ls1, ls0);
+    }
+    bwdi8_epilogue<FM, FN>(acc, ctbits, gptr(a.sq), gptr(a.nf), ob, jb, lw, h, r, active, gpart,
+                           m_pad);
+}
+
+template <int FM, int FN>
+__global__ __launch_bounds__(256, 1) void phase_bwd_i8_kernel(BwdArgs a, int64_t units) {
+    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
+    if (gu >= units) return;  // uniform over the workgroup
+    bwd_i8_body<FM, FN>(a, gu, (int)threadIdx.x);
+}
+
+template <int FM, int FN>
+__global__ __launch_bounds__(256, 1) void phase_bwd_i8_persistent(
+    const BwdArgs *__restrict__ args, const int64_t *__restrict__ off, int np,
+    unsigned long long *counter) {
+    persistent_loop(off, np, counter,
+                    [&](int p, int64_t u) { bwd_i8_body<FM, FN>(args[p], u, opaque_tid()); });
+}
+
 template <int FM, int FN>
 __global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(BwdArgs a, int64_t units) {
     const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
@@ -1222,6 +1544,8 @@ static hipError_t bwd_dispatch(const LaunchCtx &lc, int prec, const BwdArgs &a) 
     dim3 grid((unsigned)units);
     if (prec == 1)
         hipLaunchKernelGGL((phase_bwd_bf16_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a, units);
+    else if (prec == 3)
+        hipLaunchKernelGGL((phase_bwd_i8_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a, units);
     else
         hipLaunchKernelGGL((phase_bwd_f32_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a, units);
     return hipGetLastError();
@@ -1246,6 +1570,9 @@ static hipError_t bwd_persistent(const LaunchCtx &lc, int prec, const BwdArgs *a
                                  int grid) {
     if (prec == 1)
         hipLaunchKernelGGL((phase_bwd_bf16_persistent<FM, FN>), dim3(grid), dim3(256), 0,
+                           lc.stream, args, off, np, counter);
+    else if (prec == 3)
+        hipLaunchKernelGGL((phase_bwd_i8_persistent<FM, FN>), dim3(grid), dim3(256), 0,
                            lc.stream, args, off, np, counter);
     else
         hipLaunchKernelGGL((phase_bwd_f32_persistent<FM, FN>), dim3(grid), dim3(256), 0,
@@ -1280,24 +1607,27 @@ static int resident_grid(K kernel) {
 }
 
 int persistent_grid(bool fwd, int prec, int fm, int fn) {
+#define IQP_GRID3(K2, K3, KF) \
+    (prec == 1 ? resident_grid(K2) : prec == 3 ? resident_grid(K3) : resident_grid(KF))
     if (fwd) {
         if (fm == 4 && fn == 4)
-            return prec == 1 ? resident_grid(phase_fwd_bf16_persistent<4, 4>)
-                             : resident_grid(phase_fwd_f32_persistent<4, 4>);
+            return IQP_GRID3((phase_fwd_bf16_persistent<4, 4, 2>),
+                             (phase_fwd_bf16_persistent<4, 4, 3>), (phase_fwd_f32_persistent<4, 4>));
         if (fm == 2 && fn == 2)
-            return prec == 1 ? resident_grid(phase_fwd_bf16_persistent<2, 2>)
-                             : resident_grid(phase_fwd_f32_persistent<2, 2>);
+            return IQP_GRID3((phase_fwd_bf16_persistent<2, 2, 2>),
+                             (phase_fwd_bf16_persistent<2, 2, 3>), (phase_fwd_f32_persistent<2, 2>));
         if (fm == 2 && fn == 4)
-            return prec == 1 ? resident_grid(phase_fwd_bf16_persistent<2, 4>)
-                             : resident_grid(phase_fwd_f32_persistent<2, 4>);
+            return IQP_GRID3((phase_fwd_bf16_persistent<2, 4, 2>),
+                             (phase_fwd_bf16_persistent<2, 4, 3>), (phase_fwd_f32_persistent<2, 4>));
         return 0;
     }
     if (fm == 2 && fn == 2)
-        return prec == 1 ? resident_grid(phase_bwd_bf16_persistent<2, 2>)
-                         : resident_grid(phase_bwd_f32_persistent<2, 2>);
+        return IQP_GRID3((phase_bwd_bf16_persistent<2, 2>), (phase_bwd_i8_persistent<2, 2>),
+                         (phase_bwd_f32_persistent<2, 2>));
     if (fm == 2 && fn == 4)
-        return prec == 1 ? resident_grid(phase_bwd_bf16_persistent<2, 4>)
-                         : resident_grid(phase_bwd_f32_persistent<2, 4>);
+        return IQP_GRID3((phase_bwd_bf16_persistent<2, 4>), (phase_bwd_i8_persistent<2, 4>),
+                         (phase_bwd_f32_persistent<2, 4>));
+#undef IQP_GRID3
     return 0;
 }
 
@@ -1472,28 +1802,33 @@ __global__ __launch_bounds__(256) void coef_mmd_kernel(const double *__restrict_
                                                        const double *__restrict__ rowsum,
                                                        const double *__restrict__ w, int64_t l,
                                                        int64_t s, int unbiased,
-                                                       double *__restrict__ coef) {
+                                                       double *__restrict__ coef, double *sq,
+                                                       int32_t *nf) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= l) return;
     const double S = (double)s;
     const double p = pstat[2 * k + 1], sc = rowsum[2 * k];
+    double al, be;
     if (unbiased) {
         const double d = S * (S - 1.0);
-        coef[2 * k] = w[k] * (-2.0 * p / S + 2.0 * sc / d);
-        coef[2 * k + 1] = -2.0 * w[k] / d;
+        al = w[k] * (-2.0 * p / S + 2.0 * sc / d);
+        be = -2.0 * w[k] / d;
     } else {
-        coef[2 * k] = w[k] * 2.0 * (sc / S - p) / S;
-        coef[2 * k + 1] = 0.0;
+        al = w[k] * 2.0 * (sc / S - p) / S;
+        be = 0.0;
     }
+    coef[2 * k] = al;
+    coef[2 * k + 1] = be;
+    coef_rowscale(sq, nf, k, al, be);
 }
 
 hipError_t launch_coef_mmd(const LaunchCtx &lc, const double *pstat, const double *rowsum,
                            const double *op_weight, int64_t l, int64_t s, int unbiased,
-                           double *coef) {
+                           double *coef, double *sq, int32_t *nf) {
     hipEvent_t ev;
     timed_begin(lc, KF_MMD, &ev);
     hipLaunchKernelGGL(coef_mmd_kernel, dim3((unsigned)ceil_div(l, 256)), dim3(256), 0,
-                       lc.stream, pstat, rowsum, op_weight, l, s, unbiased, coef);
+                       lc.stream, pstat, rowsum, op_weight, l, s, unbiased, coef, sq, nf);
     hipError_t e = hipGetLastError();
     timed_end(lc, KF_MMD, ev);
     return e;

@@ -36,6 +36,11 @@ constexpr int64_t kMaxIndepRows = (int64_t)1 << 32;
 
 int check_circuit(const iqp_circuit *c);
 
+// The precision forms of the single-problem calls.
+inline bool valid_precision(int p) {
+    return p == IQP_FP32 || p == IQP_SPLIT_BF16 || p == IQP_SPARSE_FP32 || p == IQP_SPLIT3_BF16;
+}
+
 // ---------------------------------------------------------------------------
 // Workspace plan of one problem: padded extents and the byte offset of every
 // buffer the steps use.
@@ -49,6 +54,8 @@ struct Plan {
     size_t o_thh = 0, o_thl = 0, o_t32 = 0, o_cbits = 0, o_bbits = 0, o_E = 0, o_part = 0;
     size_t o_rowsum = 0, o_phi = 0, o_coef = 0, o_ctbits = 0, o_shi = 0, o_slo = 0, o_s32 = 0;
     size_t o_gpart = 0, o_pstat = 0;
+    size_t o_thm = 0;                     // third theta limb (IQP_SPLIT3_BF16)
+    size_t o_sq = 0, o_nf = 0;            // fixed-point weights: row scales, non-finite flags
     size_t o_xz = 0, o_xa = 0;            // bit columns of samples, ops
     size_t o_btbits = 0;                  // B^T: samples against generators, transposed
     size_t o_sup = 0;                     // support lists of the generators
@@ -82,8 +89,14 @@ inline T *at(void *ws, size_t off) {
 
 // ---- argument structs of one problem, from its plan and workspace ---------
 inline ThetaArgs theta_args(const Plan &P, const double *theta, void *ws) {
-    return ThetaArgs{theta, P.m, P.m_pad, P.prec, at<uint16_t>(ws, P.o_thh),
-                     at<uint16_t>(ws, P.o_thl), at<float>(ws, P.o_t32)};
+    return ThetaArgs{theta,
+                     P.m,
+                     P.m_pad,
+                     P.prec,
+                     at<uint16_t>(ws, P.o_thh),
+                     at<uint16_t>(ws, P.o_thl),
+                     P.prec == IQP_SPLIT3_BF16 ? at<uint16_t>(ws, P.o_thm) : nullptr,
+                     at<float>(ws, P.o_t32)};
 }
 inline BitsliceArgs bitslice_ops_args(const Plan &P, const uint64_t *ops, void *ws) {
     return BitsliceArgs{ops, P.l, (int)P.W, P.lda, at<uint64_t>(ws, P.o_xa)};
@@ -120,6 +133,7 @@ inline ParityArgs parity_ct_args(const Plan &P, const uint64_t *gens, void *ws) 
 inline FwdArgs fwd_args(const Plan &P, void *ws, int64_t splits) {
     return FwdArgs{at<uint64_t>(ws, P.o_cbits), at<uint64_t>(ws, P.o_bbits),
                    at<uint16_t>(ws, P.o_thh),   at<uint16_t>(ws, P.o_thl),
+                   P.prec == IQP_SPLIT3_BF16 ? at<uint16_t>(ws, P.o_thm) : nullptr,
                    at<float>(ws, P.o_t32),      P.m_pad,
                    P.l_pad,                     P.s_pad,
                    splits,                      at<float>(ws, P.o_E)};
@@ -132,19 +146,25 @@ inline FinArgs fin_args(const Plan &P, void *ws, double *mean, double *se, doubl
     return FinArgs{at<double>(ws, P.o_part), P.l, P.s, mean, se, rowsum};
 }
 inline CoefArgs coef_args(const Plan &P, const double *grad_mean, void *ws) {
-    return CoefArgs{grad_mean, P.l, P.s, at<double>(ws, P.o_coef)};
+    const bool fx = P.prec == IQP_SPLIT3_BF16;
+    return CoefArgs{grad_mean, P.l, P.s, at<double>(ws, P.o_coef),
+                    fx ? at<double>(ws, P.o_sq) : nullptr, fx ? at<int32_t>(ws, P.o_nf) : nullptr};
 }
 inline WeightsArgs weights_args(const Plan &P, const float *phase, void *ws) {
     return WeightsArgs{phase,  at<double>(ws, P.o_coef), P.l, P.s, P.l_pad, P.s_pad, P.prec,
                        at<uint16_t>(ws, P.o_shi), at<uint16_t>(ws, P.o_slo),
-                       at<float>(ws, P.o_s32)};
+                       at<float>(ws, P.o_s32),
+                       P.prec == IQP_SPLIT3_BF16 ? at<int32_t>(ws, P.o_nf) : nullptr};
 }
 inline BwdArgs bwd_args(const Plan &P, void *ws) {
+    const bool fx = P.prec == IQP_SPLIT3_BF16;
     return BwdArgs{at<uint16_t>(ws, P.o_shi),    at<uint16_t>(ws, P.o_slo),
                    at<float>(ws, P.o_s32),       at<uint64_t>(ws, P.o_btbits),
                    at<uint64_t>(ws, P.o_ctbits), P.m_pad,
                    P.l_pad,                      P.s_pad,
-                   P.tc.bsplits,                 at<float>(ws, P.o_gpart)};
+                   P.tc.bsplits,                 at<float>(ws, P.o_gpart),
+                   fx ? at<double>(ws, P.o_sq) : nullptr,
+                   fx ? at<int32_t>(ws, P.o_nf) : nullptr};
 }
 inline GradArgs grad_args(const Plan &P, void *ws, int bfm, double *grad_theta) {
     return GradArgs{at<float>(ws, P.o_gpart), P.tc.bsplits * (P.l_pad / (32 * bfm)), P.m, P.m_pad,

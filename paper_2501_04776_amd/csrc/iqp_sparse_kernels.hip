@@ -152,6 +152,11 @@ __device__ __forceinline__ float add_where(float x, float y, uint64_t mask) {
 // vector load of the word keeps more loads in flight than the backward's
 // scalar mask loads, which the forward's shorter loop body cannot hide.)
 constexpr int kSpSamples = kEpiChunk / 64;
+// generators between the folds of the forward's FP32 sums; the float
+// nearest pi and a float near 1 / pi (any multiple q is exact bookkeeping)
+constexpr int kSpFold = 32;
+constexpr float kPiF = 3.14159274f;
+constexpr float kInvPiF = 0.318309873f;
 
 __device__ __forceinline__ float masked(float t, uint32_t f, int b) {
     const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)f, (unsigned)b, 1u);
@@ -170,10 +175,17 @@ __device__ __forceinline__ void sparse_fwd_body(const SparseFwdArgs &a, int64_t 
     const auto src = WordsOf<kIndep>::make(a.bsrc, k, sw0, sw0 + (lane >> 2));
     const uint64_t IQP_CONST *crow = cptr(a.crm) + k * a.Gw;
     const float IQP_CONST *t32 = cptr(a.t32);
-    float acc[kSpSamples];
+    // acc[b] + kpi[b] * pi_f (pi_f the float nearest pi) is the lane's sum of
+    // t_j over its sample b's generators with b_ij = 1. Every kSpFold
+    // generators the whole multiples of pi_f are moved from acc to the
+    // integer count kpi (exact bookkeeping: E changes by 2 pi per multiple,
+    // which the FP64 reduction below removes), so acc stays within about
+    // pi and its FP32 rounding does not grow with |J_k|.
+    float acc[kSpSamples], kpi[kSpSamples];
 #pragma unroll
-    for (int b = 0; b < kSpSamples; ++b) acc[b] = 0.0f;
+    for (int b = 0; b < kSpSamples; ++b) acc[b] = kpi[b] = 0.0f;
     double T = 0.0;
+    int fold = 0;
     for (int64_t w = 0; w < a.Gw; ++w) {
         uint64_t cw = crow[w];
         while (cw) {
@@ -184,6 +196,15 @@ __device__ __forceinline__ void sparse_fwd_body(const SparseFwdArgs &a, int64_t 
             T += (double)t;
 #pragma unroll
             for (int b = 0; b < kSpSamples; ++b) acc[b] += masked(t, f, b);
+            if (++fold == kSpFold) {  // uniform over the wave
+                fold = 0;
+#pragma unroll
+                for (int b = 0; b < kSpSamples; ++b) {
+                    const float q = rintf(acc[b] * kInvPiF);
+                    acc[b] = fmaf(-q, kPiF, acc[b]);
+                    kpi[b] += q;
+                }
+            }
         }
     }
     double sc = 0.0, sc2 = 0.0;
@@ -193,7 +214,7 @@ __device__ __forceinline__ void sparse_fwd_body(const SparseFwdArgs &a, int64_t 
     for (int b = 0; b < kSpSamples; ++b) {
         const int64_t i = i0 + b;
         if (i < a.s) {
-            const double e = T - 2.0 * (double)acc[b];
+            const double e = T - 2.0 * ((double)acc[b] + (double)kpi[b] * (double)kPiF);
             const double kk = rint(e * IQP_INV_TWO_PI);
             double rr = fma(-kk, IQP_TWO_PI_HI, e);
             rr = fma(-kk, IQP_TWO_PI_LO, rr);

@@ -200,7 +200,8 @@ def _problems(shapes):
 
 @pytest.mark.parametrize("shapes,count,prec,flags,msg", [
     ([(10, 5, 4, 8)], 0, 1, 0, "n_problems out of range"),
-    ([(10, 5, 4, 8)], 1, 3, 0, "precision"),
+    ([(10, 5, 4, 8)], 1, 2, 0, "precision"),  # the sparse form is not batched
+    ([(10, 5, 4, 8)], 1, 7, 0, "precision"),
     ([(10, 5, 4, 8)], 1, 1, 8, "unknown flags"),
     ([(10, 5, 4, 8), (10, 5, 0, 8)], 2, 1, 0, "n_ops out of range [1, 2^24] (problem 1)"),
     ([(10, 5, 4, 0)], 1, 1, 0, "n_samples out of range"),

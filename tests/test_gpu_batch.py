@@ -13,7 +13,7 @@ from tests.gpu_util import TOL, DevWorkload, check_grad, wrap
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp32", "split_bf16"]
+PRECS = ["fp32", "split_bf16", "split3_bf16"]
 
 # (n, m, l, s): tiny to several tiles, ragged in every extent, W = 1 .. 32
 SHAPES = [(5, 40, 3, 70), (70, 1000, 300, 700), (130, 2100, 129, 1025), (2000, 700, 64, 257),
@@ -201,12 +201,12 @@ def test_batch_rejects_shape_mismatch_and_missing_phases():
 
 
 @pytest.mark.slow
-def test_batched_workload_full_size_sampled():
+@pytest.mark.parametrize("prec", ["split_bf16", "split3_bf16"])
+def test_batched_workload_full_size_sampled(prec):
     # the 64-circuit workload (n in 50..2000, m in 1e3..2e5, l in 100..5000,
     # s = 4096) at full size; the oracle recomputes 3 sampled observables of
     # 8 sampled circuits one by one, and their gradient for a dL/dmean that
     # is non-zero only on those observables
-    prec = "split_bf16"
     ws = [W.batch64_circuit(i) for i in range(64)]
     dws = [DevWorkload(w) for w in ws]
     plan = _plan(dws, prec)
