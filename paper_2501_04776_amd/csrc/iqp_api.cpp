@@ -227,6 +227,12 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
     }
     if (P.tc.bsplits > sw) P.tc.bsplits = sw;
     P.tc.bsplits = ceil_div(sw, ceil_div(sw, P.tc.bsplits));
+    if (prec == IQP_SPLIT3_BF16) {
+        // the INT8 contraction splits whole blocks of two sample words
+        const int64_t nb2 = sw / 2;
+        if (P.tc.bsplits > nb2) P.tc.bsplits = nb2;
+        P.tc.bsplits = ceil_div(nb2, ceil_div(nb2, P.tc.bsplits));
+    }
     P.fwd = parts.fwd;
     P.bwd = parts.bwd;
     P.phi = parts.phi;

@@ -47,10 +47,11 @@ void timed_end(const LaunchCtx &lc, int family, hipEvent_t ev);
 // Fixed-point backward weights (IQP_SPLIT3_BF16): |S_ki| <= sigma_k maps to
 // integers N with |N| <= kI8Max = 127 * 256 + 127, the largest magnitude two
 // signed 8-bit limbs hold as N = 256 hi + lo with hi = floor((N + 128) / 256)
-// in [-127, 127] and lo in [-128, 127]. An INT32 accumulator of such limbs
-// stays exact (|sum| <= 2^30) over up to 2^23 samples per work unit.
+// in [-127, 127] and lo in [-128, 127]. Over at most 2^16 samples per work
+// unit the INT32 sums of each limb, and 256 hi_sum + lo_sum, stay exact
+// (|256 * 127 K + 128 K| < 2^31 for K <= 2^16).
 constexpr double kI8Max = 32639.0;
-constexpr int64_t kI8MaxSamplesPerUnit = (int64_t)1 << 23;
+constexpr int64_t kI8MaxSamplesPerUnit = (int64_t)1 << 16;
 
 // Support-list capacity: the qubits of a generator of weight <= kSupCap are
 // listed; heavier generators are read from their bit rows.

@@ -1317,19 +1317,24 @@ struct BwdOpsI8 {
     i32x4 a[2][FM], bv[FN];
 };
 
+// A staged block is 128 samples (two sample words, four K-steps): K-step T
+// uses bits 32 (T % 2) + 16 h .. + 15 of sample word T / 2 of the lane's
+// B^T words (bw0, bw1, pre-shifted right by 16 h).
 template <int FM, int FN, int T>
 __device__ __forceinline__ void bwdi8_expand_a(BwdOpsI8<FM, FN> &o, const u32x4 *ls, int lane) {
 #pragma unroll
     for (int L = 0; L < 2; ++L)
 #pragma unroll
         for (int f = 0; f < FM; ++f)
-            o.a[L][f] = __builtin_bit_cast(i32x4, ls[((L * FM + f) * 2 + T) * 64 + lane]);
+            o.a[L][f] = __builtin_bit_cast(i32x4, ls[((L * FM + f) * 4 + T) * 64 + lane]);
 }
 
 template <int FM, int FN, int T, int G0, int G1>
-__device__ __forceinline__ void bwdi8_expand_b(BwdOpsI8<FM, FN> &o, const uint64_t (&bw)[FN]) {
+__device__ __forceinline__ void bwdi8_expand_b(BwdOpsI8<FM, FN> &o, const uint64_t (&bw0)[FN],
+                                               const uint64_t (&bw1)[FN]) {
 #pragma unroll
-    for (int g = G0; g < G1; ++g) o.bv[g] = expand_pm1_i8((uint32_t)(bw[g] >> (32 * T)));
+    for (int g = G0; g < G1; ++g)
+        o.bv[g] = expand_pm1_i8((uint32_t)((T < 2 ? bw0[g] : bw1[g]) >> (32 * (T & 1))));
 }
 
 template <int FM, int FN, int L>
@@ -1347,19 +1352,23 @@ __device__ __forceinline__ void bwdi8_mfma_limb(const BwdOpsI8<FM, FN> &o,
 // operands of K-step T1 are read from `lsn` and expanded into `nxt`.
 template <int FM, int FN, int T1>
 __device__ __forceinline__ void bwdi8_region(const BwdOpsI8<FM, FN> &cur, BwdOpsI8<FM, FN> &nxt,
-                                             const u32x4 *lsn, const uint64_t (&bw)[FN], int lane,
+                                             const u32x4 *lsn, const uint64_t (&bw0)[FN],
+                                             const uint64_t (&bw1)[FN], int lane,
                                              i32x16 (&acc)[2][FM][FN]) {
     bwdi8_expand_a<FM, FN, T1>(nxt, lsn, lane);
-    bwdi8_expand_b<FM, FN, T1, 0, FN / 2>(nxt, bw);
+    bwdi8_expand_b<FM, FN, T1, 0, FN / 2>(nxt, bw0, bw1);
     bwdi8_mfma_limb<FM, FN, 0>(cur, acc);
     interleave_half<2 * FM, FM * FN, 9 * FN + 2>();
-    bwdi8_expand_b<FM, FN, T1, FN / 2, FN>(nxt, bw);
+    bwdi8_expand_b<FM, FN, T1, FN / 2, FN>(nxt, bw0, bw1);
     bwdi8_mfma_limb<FM, FN, 1>(cur, acc);
     interleave_half<0, FM * FN, 9 * FN + 2>();
 }
 
 // sum_k c_kj q_k (256 T_hi + T_lo)[k][j] over this wave's observable rows, per
-// gate column; a row whose weights were not finite contributes NaN.
+// gate column; 256 T_hi + T_lo is exact in INT32 (a work unit covers at most
+// kI8MaxSamplesPerUnit samples) and is then rounded to FP32 once, as the
+// BF16 form's accumulators are. A row whose weights were not finite
+// contributes NaN.
 template <int FM, int FN>
 __device__ __forceinline__ void bwdi8_epilogue(const i32x16 (&acc)[2][FM][FN],
                                                const uint64_t IQP_GLOBAL *__restrict__ ctbits,
@@ -1368,17 +1377,17 @@ __device__ __forceinline__ void bwdi8_epilogue(const i32x16 (&acc)[2][FM][FN],
                                                int64_t ob, int64_t jb, int64_t lw, int h, int r,
                                                bool active, float IQP_GLOBAL *__restrict__ gpart,
                                                int64_t m_pad) {
-    double gs[FN];
+    float gs[FN];
 #pragma unroll
-    for (int g = 0; g < FN; ++g) gs[g] = 0.0;
+    for (int g = 0; g < FN; ++g) gs[g] = 0.0f;
 #pragma unroll
     for (int f = 0; f < FM; ++f) {
         const int64_t k0 = (ob * FM + f) * 32;
-        double q[16];
+        float q[16];
 #pragma unroll
         for (int a = 0; a < 16; ++a) {
             const int64_t k = k0 + acc_row(a, h);
-            q[a] = nf[k] ? (double)NAN : sq[k];
+            q[a] = nf[k] ? NAN : (float)sq[k];
         }
 #pragma unroll
         for (int g = 0; g < FN; ++g) {
@@ -1387,23 +1396,24 @@ __device__ __forceinline__ void bwdi8_epilogue(const i32x16 (&acc)[2][FM][FN],
             const uint32_t c32 = (uint32_t)(cw >> (k0 & 63)) >> (4 * h);
 #pragma unroll
             for (int a = 0; a < 16; ++a) {
-                const double t = 256.0 * (double)acc[1][f][g][a] + (double)acc[0][f][g][a];
-                gs[g] += ((c32 >> (8 * (a >> 2) + (a & 3))) & 1u) ? q[a] * t : 0.0;
+                const int32_t t = acc[1][f][g][a] * 256 + acc[0][f][g][a];
+                gs[g] += ((c32 >> (8 * (a >> 2) + (a & 3))) & 1u) ? q[a] * (float)t : 0.0f;
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 #pragma unroll
     for (int g = 0; g < FN; ++g) {
         const int64_t j = (jb * FN + g) * 32 + r;
-        const double v = gs[g] + __shfl_xor(gs[g], 32, 64);
-        if (active && h == 0) gpart[ob * m_pad + j] = (float)v;
+        const float v = gs[g] + __shfl_xor(gs[g], 32, 64);
+        if (active && h == 0) gpart[ob * m_pad + j] = v;
     }
 }
 
 template <int FM, int FN>
 __device__ __forceinline__ void bwd_i8_body(const BwdArgs &a, int64_t gu, int tid) {
-    // one sample word: [limb][f][t][lane], 16 bytes each, two buffers
-    constexpr int kUnits = 2 * FM * 2 * 64;
+    // one block of 128 samples: [limb][f][t][lane], 16 bytes each, two buffers
+    constexpr int kUnits = 2 * FM * 4 * 64;
     __shared__ u32x4 ls0[kUnits], ls1[kUnits];
     const u32x4 IQP_GLOBAL *__restrict__ shi = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.shi));
     const u32x4 IQP_GLOBAL *__restrict__ slo = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.slo));
@@ -1415,8 +1425,10 @@ __device__ __forceinline__ void bwd_i8_body(const BwdArgs &a, int64_t gu, int ti
     // unit = ((sample split) * n_ob + observable block) * n_jbg + gate-block group
     const int64_t jbg = gu % n_jbg, t0 = gu / n_jbg;
     const int64_t ob = t0 % n_ob, ks = t0 / n_ob;
-    const int64_t wps = ceil_div(sw, a.ksplits);
-    const int64_t w0 = ks * wps, w1 = (w0 + wps < sw) ? w0 + wps : sw;
+    // splits are whole blocks of two sample words (s_pad is a multiple of
+    // 128, so sw is even)
+    const int64_t nb2 = sw / 2, bps = ceil_div(nb2, a.ksplits);
+    const int64_t b0 = ks * bps, b1 = (b0 + bps < nb2) ? b0 + bps : nb2;
     float IQP_GLOBAL *__restrict__ gpart = gptr(a.gpart) + ks * n_ob * m_pad;
     const int64_t jb_raw = jbg * 4 + wave_id();
     const bool active = jb_raw < n_jb;
@@ -1438,70 +1450,84 @@ __device__ __forceinline__ void bwd_i8_body(const BwdArgs &a, int64_t gu, int ti
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[L][f][g][e] = 0;
 
-    // staging block b = (limb * FM + f) * 2 + t (64 units of 16 bytes)
-    //   <- S(limb)[(f * KTs + 2 w + t) * 64 + ln]; limb 0 = lo, 1 = hi;
+    // staging block q = (limb * FM + f) * 4 + t (64 units of 16 bytes)
+    //   <- S(limb)[(f * KTs + 4 b + t) * 64 + ln]; limb 0 = lo, 1 = hi;
     // wave v copies blocks v, v+4, ...
     const int wv = wave_id();
-    auto stage = [&](int64_t w, u32x4 *dst) {
+    auto stage = [&](int64_t b, u32x4 *dst) {
 #pragma unroll
         for (int k = 0; k < kUnits / 256; ++k) {
-            const int b = wv + 4 * k;
-            const int t = b & 1, f = (b >> 1) % FM, limb = b / (2 * FM);
-            const int64_t src = ((int64_t)f * KTs + 2 * w + t) * 64 + lane;
-            dma16((limb ? sbase_h : sbase_l) + src, &dst[b * 64]);
+            const int q = wv + 4 * k;
+            const int t = q & 3, f = (q >> 2) % FM, limb = q / (4 * FM);
+            const int64_t src = ((int64_t)f * KTs + 4 * b + t) * 64 + lane;
+            dma16((limb ? sbase_h : sbase_l) + src, &dst[q * 64]);
         }
     };
-    // every unit has w1 - w0 >= 1 sample words (the host picks the splits)
-    stage(w0, ls0);
-    if (w0 + 1 < w1) stage(w0 + 1, ls1);
-    uint64_t nxt[FN], cur[FN];
+    auto load_bits = [&](int64_t b, uint64_t (&x0)[FN], uint64_t (&x1)[FN]) {
 #pragma unroll
-    for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w0) * 32)[r];
+        for (int g = 0; g < FN; ++g) {
+            x0[g] = (bbase + (g * sw + 2 * b) * 32)[r];
+            x1[g] = (bbase + (g * sw + 2 * b + 1) * 32)[r];
+        }
+    };
+    // every unit has b1 - b0 >= 1 blocks (the host picks the splits)
+    stage(b0, ls0);
+    if (b0 + 1 < b1) stage(b0 + 1, ls1);
+    uint64_t nxt0[FN], nxt1[FN], cur0[FN], cur1[FN];
+    load_bits(b0, nxt0, nxt1);
     dma_wait_barrier();
-    // K-step t of a word uses bits 32 t + 16 h .. + 15 of the lane's word
 #pragma unroll
-    for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> (16 * h);
-    if (w0 + 1 < w1) {
-#pragma unroll
-        for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w0 + 1) * 32)[r];
+    for (int g = 0; g < FN; ++g) {
+        cur0[g] = nxt0[g] >> (16 * h);
+        cur1[g] = nxt1[g] >> (16 * h);
     }
+    if (b0 + 1 < b1) load_bits(b0 + 1, nxt0, nxt1);
     BwdOpsI8<FM, FN> opA, opB;
     bwdi8_expand_a<FM, FN, 0>(opA, ls0, lane);
-    bwdi8_expand_b<FM, FN, 0, 0, FN>(opA, cur);
-    // Word w reads `mine`; its second region runs after a barrier that makes
-    // word w+1's buffer `other` valid, so that region already expands word
-    // w+1's first K-step; the copy of word w+2 into `mine` is issued right
+    bwdi8_expand_b<FM, FN, 0, 0, FN>(opA, cur0, cur1);
+    // Block b reads `mine`; its last region runs after a barrier that makes
+    // block b+1's buffer `other` valid, so that region already expands block
+    // b+1's first K-step; the copy of block b+2 into `mine` is issued right
     // after that barrier.
-    auto word = [&](int64_t w, u32x4 *mine, const u32x4 *other) {
-        bwdi8_region<FM, FN, 1>(opA, opB, mine, cur, lane, acc);
+    auto block = [&](int64_t b, u32x4 *mine, const u32x4 *other) {
+        bwdi8_region<FM, FN, 1>(opA, opB, mine, cur0, cur1, lane, acc);
+        bwdi8_region<FM, FN, 2>(opB, opA, mine, cur0, cur1, lane, acc);
+        bwdi8_region<FM, FN, 3>(opA, opB, mine, cur0, cur1, lane, acc);
         dma_wait_barrier();
-        if (w + 2 < w1) stage(w + 2, mine);
+        if (b + 2 < b1) stage(b + 2, mine);
 #pragma unroll
-        for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> (16 * h);
-        if (w + 2 < w1) {
-#pragma unroll
-            for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w + 2) * 32)[r];
+        for (int g = 0; g < FN; ++g) {
+            cur0[g] = nxt0[g] >> (16 * h);
+            cur1[g] = nxt1[g] >> (16 * h);
         }
-        // past the last word this expands a stale buffer and is never used
-        bwdi8_region<FM, FN, 0>(opB, opA, other, cur, lane, acc);
+        if (b + 2 < b1) load_bits(b + 2, nxt0, nxt1);
+        // past the last block this expands a stale buffer and is never used
+        bwdi8_region<FM, FN, 0>(opB, opA, other, cur0, cur1, lane, acc);
     };
-    for (int64_t w = w0; w < w1; w += 2) {
-        word(w, ls0, ls1);
-        if (w + 1 < w1) word(w + 1, ls1, ls0);
-    }
+    int64_t b = b0;
+    do {  // b1 > b0: the accumulators always pass through the loop
+        block(b, ls0, ls1);
+        if (b + 1 < b1) block(b + 1, ls1, ls0);
+        b += 2;
+    } while (b < b1);
     bwdi8_epilogue<FM, FN>(acc, ctbits, gptr(a.sq), gptr(a.nf), ob, jb, lw, h, r, active, gpart,
                            m_pad);
 }
 
+// The 64 x 64 wave tile fits two waves per SIMD (its INT32 accumulators in
+// VGPRs, no AGPRs), which hides the per-block barrier and load latency.
+template <int FN>
+constexpr int kI8Waves = FN == 2 ? 2 : 1;
+
 template <int FM, int FN>
-__global__ __launch_bounds__(256, 1) void phase_bwd_i8_kernel(BwdArgs a, int64_t units) {
+__global__ __launch_bounds__(256, kI8Waves<FN>) void phase_bwd_i8_kernel(BwdArgs a, int64_t units) {
     const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
     if (gu >= units) return;  // uniform over the workgroup
     bwd_i8_body<FM, FN>(a, gu, (int)threadIdx.x);
 }
 
 template <int FM, int FN>
-__global__ __launch_bounds__(256, 1) void phase_bwd_i8_persistent(
+__global__ __launch_bounds__(256, kI8Waves<FN>) void phase_bwd_i8_persistent(
     const BwdArgs *__restrict__ args, const int64_t *__restrict__ off, int np,
     unsigned long long *counter) {
     persistent_loop(off, np, counter,
