@@ -157,6 +157,19 @@ int iqp_expval(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
                const uint64_t *samples, int precision, double *mean, double *stderr_,
                float *phase_save, void *ws, size_t ws_bytes, void *stream);
 
+/* iqp_expval for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same forward, with its workspace in a static device array of 64 MiB that
+ * each GPU the library runs on holds until the process ends, so no ws
+ * argument. Sizes whose iqp_workspace_bytes(IQP_CALL_EXPVAL, ...) exceeds
+ * 64 MiB return IQP_ERR_WORKSPACE. Every call on one GPU shares that array:
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and must be ordered by the caller. Outputs equal iqp_expval's bitwise.
+ * Other arguments as iqp_expval. */
+int iqp_expval_noalloc(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+                       const uint64_t *samples, int precision, double *mean, double *stderr_,
+                       float *phase_save, void *stream);
+
 /* Gradient of a loss L(mean) through the estimator (the reverse pass of the
  * computational graph of Fig. 3, written by hand):
  *   dL/dtheta_j = -(1/s) sum_k u_k sum_i sin(E_ki) C_kj B_ij,  u_k = dL/dmean_k.

@@ -40,6 +40,7 @@ IQP_BITS_TILED32_T = 2
 
 # every symbol include/iqp.h declares
 EXPORTED = ("iqp_workspace_bytes", "iqp_parity_workspace_bytes", "iqp_parity", "iqp_expval",
+            "iqp_expval_noalloc",
             "iqp_expval_grad", "iqp_expval_indep", "iqp_expval_indep_grad",
             "iqp_mmd_loss_grad", "iqp_bitflip_expval",
             "iqp_bitflip_expval_grad", "iqp_batch_plan_create",
@@ -114,6 +115,8 @@ def lib():
     L.iqp_parity.restype = i32
     L.iqp_expval.argtypes = [cp, i64, vp, i64, vp, i32, vp, vp, vp, vp, sz, vp]
     L.iqp_expval.restype = i32
+    L.iqp_expval_noalloc.argtypes = [cp, i64, vp, i64, vp, i32, vp, vp, vp, vp]
+    L.iqp_expval_noalloc.restype = i32
     L.iqp_expval_grad.argtypes = [cp, i64, vp, i64, vp, i32, vp, vp, vp, vp, sz, vp]
     L.iqp_expval_grad.restype = i32
     L.iqp_expval_indep.argtypes = [cp, i64, vp, i64, vp, vp, vp, vp, vp, sz, vp]

@@ -141,6 +141,25 @@ def iqp_expval(circ: Circuit, ops: torch.Tensor, samples: torch.Tensor,
     return mean, se, ph
 
 
+def iqp_expval_noalloc(circ: Circuit, ops: torch.Tensor, samples: torch.Tensor,
+                       precision=SPLIT_BF16, stderr: bool = True, phase_save: bool = False):
+    """iqp_expval with the library's static device workspace (no workspace
+    allocation; outputs are allocated here as for iqp_expval)."""
+    p = precision_id(precision)
+    ops = _rows(ops, "ops", circ.W)
+    samples = _rows(samples, "samples", circ.W)
+    l, s = ops.shape[0], samples.shape[0]
+    dev = circ.device
+    mean = torch.empty(l, dtype=torch.float64, device=dev)
+    se = torch.empty(l, dtype=torch.float64, device=dev) if stderr else None
+    ph = torch.empty((l, s), dtype=torch.float32, device=dev) if phase_save else None
+    c = circ.struct()
+    L.check(L.lib().iqp_expval_noalloc(ctypes.byref(c), l, _ptr(ops), s, _ptr(samples), p,
+                                       _ptr(mean), _ptr(se), _ptr(ph), _stream(ops)),
+            "iqp_expval_noalloc")
+    return mean, se, ph
+
+
 def iqp_expval_grad(circ: Circuit, ops: torch.Tensor, samples: torch.Tensor,
                     grad_mean: torch.Tensor, phase_save: Optional[torch.Tensor] = None,
                     precision=SPLIT_BF16) -> torch.Tensor:

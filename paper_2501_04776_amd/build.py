@@ -20,7 +20,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 SOURCES = ["iqp_kernels.hip", "iqp_sparse_kernels.hip", "iqp_api.cpp", "iqp_batch.cpp",
-           "iqp_train_kernels.hip", "iqp_train.cpp"]
+           "iqp_train_kernels.hip", "iqp_train.cpp", "iqp_noalloc.hip"]
 
 
 def build(verbose: bool = False) -> str:

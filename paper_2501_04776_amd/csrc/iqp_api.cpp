@@ -536,6 +536,22 @@ static int run_backward(const Plan &P, const iqp_circuit *c, const uint64_t *ops
     return IQP_OK;
 }
 
+int expval_call(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+                const uint64_t *samples, int precision, double *mean, double *stderr_,
+                float *phase_save, void *ws, size_t ws_bytes, void *stream, bool timing) {
+    int st = check_common(c, l, ops, s, samples, precision);
+    if (st) return st;
+    if (!mean) return fail(IQP_ERR_INVALID_ARG, "mean is NULL");
+    Plan P;
+    make_call_plan(P, IQP_CALL_EXPVAL, c->n_qubits, c->n_gates, l, s, 0, precision);
+    if ((st = check_ws(P, ws, ws_bytes))) return st;
+    if ((st = check_device())) return st;
+    LaunchCtx lc = make_ctx(stream);
+    lc.timing = lc.timing && timing;
+    return run_forward(P, c, ops, samples, ws, lc, phase_save, mean, stderr_,
+                       at<double>(ws, P.o_rowsum));
+}
+
 LaunchCtx make_ctx(void *stream) {
     LaunchCtx lc;
     lc.stream = reinterpret_cast<hipStream_t>(stream);
@@ -635,15 +651,8 @@ int iqp_expval(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
                const uint64_t *samples, int precision, double *mean, double *stderr_,
                float *phase_save, void *ws, size_t ws_bytes, void *stream) {
     g_last_error.clear();
-    int st = check_common(c, l, ops, s, samples, precision);
-    if (st) return st;
-    if (!mean) return fail(IQP_ERR_INVALID_ARG, "mean is NULL");
-    Plan P;
-    make_call_plan(P, IQP_CALL_EXPVAL, c->n_qubits, c->n_gates, l, s, 0, precision);
-    if ((st = check_ws(P, ws, ws_bytes))) return st;
-    if ((st = check_device())) return st;
-    return run_forward(P, c, ops, samples, ws, make_ctx(stream), phase_save, mean, stderr_,
-                       at<double>(ws, P.o_rowsum));
+    return expval_call(c, l, ops, s, samples, precision, mean, stderr_, phase_save, ws, ws_bytes,
+                       stream, true);
 }
 
 int iqp_expval_grad(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,

@@ -20,6 +20,13 @@ int check_device();
 
 LaunchCtx make_ctx(void *stream);
 
+// iqp_expval after its argument checks: validates, lays out `ws` and
+// enqueues the forward; `timing` = false keeps the per-kernel timing off for
+// this call (it would create events).
+int expval_call(const iqp_circuit *c, int64_t l, const uint64_t *ops, int64_t s,
+                const uint64_t *samples, int precision, double *mean, double *stderr_,
+                float *phase_save, void *ws, size_t ws_bytes, void *stream, bool timing);
+
 // The per-kernel timing collects (family, start, stop) events.
 bool timing_enabled();
 
