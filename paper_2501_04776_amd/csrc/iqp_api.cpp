@@ -195,6 +195,8 @@ static void apply_env_tiles(TileCfg &tc) {
     if (sp && atoi(sp) > 0) tc.splits = atoi(sp);
     const char *bs = getenv("IQP_BWD_SPLITS");
     if (bs && atoi(bs) > 0) tc.bsplits = atoi(bs);
+    const char *og = getenv("IQP_BWD_OBGROUP");
+    if (og && atoi(og) > 0) tc.obgroup = atoi(og);
 }
 
 void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l, int64_t s,

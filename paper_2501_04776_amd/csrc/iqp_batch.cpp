@@ -537,6 +537,13 @@ int iqp_batch_plan_create(int32_t n_problems, const iqp_problem *probs, int prec
     tc0.splits = 1;
     tc0.bfm = 2;
     tc0.bsplits = 1;  // the work queue balances the backward
+    // Grouped unit order helps launches whose workgroups stay on one XCD in
+    // contiguous unit ranges; the persistent queue hands consecutive units to
+    // all XCDs, where groups only add S-strip fetches (446 GB instead of
+    // 187 GB per backward over the 64 circuits, same time), so none here.
+    tc0.obgroup = 1;
+    const char *og = getenv("IQP_BWD_OBGROUP");  // unit-order override for sweeps
+    if (og && atoi(og) > 0) tc0.obgroup = atoi(og);
     bp->plans.resize(n_problems);
     for (int p = 0; p < n_problems; ++p) {
         const iqp_problem &q = probs[p];

@@ -27,6 +27,7 @@ struct TileCfg {
     int bfm = 2, bfn = 2;    // backward: observables x gates
     int64_t splits = 0;      // forward split over gate words; 0 = choose
     int64_t bsplits = 0;     // backward split over sample words; 0 = choose
+    int64_t obgroup = 4;     // backward unit order: observable blocks per group
 };
 
 // Kernel-family ids for the optional per-kernel timing.
@@ -182,6 +183,7 @@ struct BwdArgs {
     float *gpart;
     const double *sq;   // IQP_SPLIT3_BF16: row scales and non-finite flags
     const int32_t *nf;
+    int64_t obgroup;    // observable blocks per unit group (unit order only)
 };
 inline int64_t bwd_units(const BwdArgs &a, int fm, int fn) {
     return ceil_div(a.m_pad / (32 * fn), 4) * (a.l_pad / (32 * fm)) * a.ksplits;

@@ -1020,6 +1020,25 @@ hipError_t launch_weights(const LaunchCtx &lc, const WeightsArgs &a) {
 // XCD's workgroups share one S strip in L2. As in the forward, the last
 // region of a word runs after the barrier that validates the next word's
 // buffer, so it already expands the next word's first K-step.
+// Work unit -> (observable block, gate-block group, sample split). Within a
+// split the observable blocks run in groups of `grp`; inside a group the
+// observable block changes fastest, so workgroups that run at the same time
+// share both their S strips (grp of them) and their B^T strips (one per
+// gate-block group), and each B^T strip is fetched about n_ob / grp times
+// instead of n_ob times. The last group may be smaller.
+__device__ __forceinline__ void bwd_unit(int64_t gu, int64_t n_ob, int64_t n_jbg, int64_t grp,
+                                         int64_t &ob, int64_t &jbg, int64_t &ks) {
+    const int64_t per_split = n_ob * n_jbg;
+    ks = gu / per_split;
+    const int64_t u = gu - ks * per_split;
+    const int64_t G = grp < 1 ? 1 : (grp > n_ob ? n_ob : grp);
+    const int64_t g = u / (G * n_jbg);
+    const int64_t gsz = (g + 1) * G <= n_ob ? G : n_ob - g * G;
+    const int64_t r = u - g * G * n_jbg;
+    jbg = r / gsz;
+    ob = g * G + (r - jbg * gsz);
+}
+
 template <int FM, int FN>
 struct BwdOps {
     bf16x8 ah[FM], al[FM], bv[FN];
@@ -1115,9 +1134,8 @@ __device__ __forceinline__ void bwd_bf16_body(const BwdArgs &a, int64_t gu, int 
     const int64_t m_pad = a.m_pad, sw = a.s_pad / 64, lw = a.l_pad / 64;
     const int64_t n_jb = m_pad / (32 * FN), n_ob = a.l_pad / (32 * FM);
     const int64_t n_jbg = ceil_div(n_jb, 4);
-    // unit = ((sample split) * n_ob + observable block) * n_jbg + gate-block group
-    const int64_t jbg = gu % n_jbg, t0 = gu / n_jbg;
-    const int64_t ob = t0 % n_ob, ks = t0 / n_ob;
+    int64_t jbg, ob, ks;
+    bwd_unit(gu, n_ob, n_jbg, a.obgroup, ob, jbg, ks);
     const int64_t wps = ceil_div(sw, a.ksplits);
     const int64_t w0 = ks * wps, w1 = (w0 + wps < sw) ? w0 + wps : sw;
     float IQP_GLOBAL *__restrict__ gpart = gptr(a.gpart) + ks * n_ob * m_pad;
@@ -1205,8 +1223,8 @@ __device__ __forceinline__ void bwd_f32_body(const BwdArgs &a, int64_t gu, int t
     const int64_t m_pad = a.m_pad, sw = a.s_pad / 64, lw = a.l_pad / 64;
     const int64_t n_jb = m_pad / (32 * FN), n_ob = a.l_pad / (32 * FM);
     const int64_t n_jbg = ceil_div(n_jb, 4);
-    const int64_t jbg = gu % n_jbg, t0 = gu / n_jbg;
-    const int64_t ob = t0 % n_ob, ks = t0 / n_ob;
+    int64_t jbg, ob, ks;
+    bwd_unit(gu, n_ob, n_jbg, a.obgroup, ob, jbg, ks);
     const int64_t wps = ceil_div(sw, a.ksplits);
     const int64_t w0 = ks * wps, w1 = (w0 + wps < sw) ? w0 + wps : sw;
     float IQP_GLOBAL *__restrict__ gpart = gptr(a.gpart) + ks * n_ob * m_pad;
@@ -1422,9 +1440,8 @@ __device__ __forceinline__ void bwd_i8_body(const BwdArgs &a, int64_t gu, int ti
     const int64_t m_pad = a.m_pad, sw = a.s_pad / 64, lw = a.l_pad / 64;
     const int64_t n_jb = m_pad / (32 * FN), n_ob = a.l_pad / (32 * FM);
     const int64_t n_jbg = ceil_div(n_jb, 4);
-    // unit = ((sample split) * n_ob + observable block) * n_jbg + gate-block group
-    const int64_t jbg = gu % n_jbg, t0 = gu / n_jbg;
-    const int64_t ob = t0 % n_ob, ks = t0 / n_ob;
+    int64_t jbg, ob, ks;
+    bwd_unit(gu, n_ob, n_jbg, a.obgroup, ob, jbg, ks);
     // splits are whole blocks of two sample words (s_pad is a multiple of
     // 128, so sw is even)
     const int64_t nb2 = sw / 2, bps = ceil_div(nb2, a.ksplits);

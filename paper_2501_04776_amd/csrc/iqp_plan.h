@@ -171,7 +171,8 @@ inline BwdArgs bwd_args(const Plan &P, void *ws) {
                    P.l_pad,                      P.s_pad,
                    P.tc.bsplits,                 at<float>(ws, P.o_gpart),
                    fx ? at<double>(ws, P.o_sq) : nullptr,
-                   fx ? at<int32_t>(ws, P.o_nf) : nullptr};
+                   fx ? at<int32_t>(ws, P.o_nf) : nullptr,
+                   P.tc.obgroup};
 }
 inline GradArgs grad_args(const Plan &P, void *ws, int bfm, double *grad_theta) {
     return GradArgs{at<float>(ws, P.o_gpart), P.tc.bsplits * (P.l_pad / (32 * bfm)), P.m, P.m_pad,
