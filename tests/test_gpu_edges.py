@@ -74,6 +74,31 @@ def test_zero_weight_and_heavy_generators(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_n300_full_size_sampled(prec):
+    # the 300-qubit workload (all 45150 one- and two-qubit generators,
+    # theta ~ N(0, 0.1^2), 1000 weight-2 observables, 10^4 samples) at full
+    # size in the launch configuration the benchmark times; the oracle
+    # recomputes 12 sampled observables and the gradient of a loss on those
+    w = W.local_n300()
+    dw = DevWorkload(w)
+    circ = api.Circuit(w.n, dw.gens, dw.theta)
+    pick = np.random.default_rng(2).choice(w.l, size=12, replace=False)
+    u = np.zeros(w.l)
+    u[pick] = np.random.default_rng(3).normal(size=pick.size)
+    mean, se, ph = api.iqp_expval(circ, dw.ops, dw.samples, prec, phase_save=True)
+    g = api.iqp_expval_grad(circ, dw.ops, dw.samples, torch.from_numpy(u).cuda(), ph, prec)
+    torch.cuda.synchronize()
+    om, ose = oracle.expval(w.n, w.gates, w.theta, dw.ops01[pick], w.samples)
+    og = oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01[pick], w.samples, u[pick])
+    d = np.abs(mean.cpu().numpy()[pick] - om)
+    assert d.max() < TOL[prec]
+    assert np.abs(se.cpu().numpy()[pick] - ose).max() < TOL[prec]
+    err, rep = check_grad(prec, g.cpu().numpy(), w, dw.ops01[pick], u[pick], og)
+    print("n=300 %s: max|d mean| %.3g, max|d grad| %.3g (representation %.3g)" %
+          (prec, d.max(), err, rep))
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_n1000_full_size_sampled(prec):
     # the 1000-qubit workload (10^5 generators of weight 1..3, theta in
     # (-pi, pi), 10^4 observables of weight 1..10, 10^4 samples) at full

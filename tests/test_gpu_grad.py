@@ -113,6 +113,48 @@ def test_mmd_n300_shape_sampled():
         assert np.abs(g.cpu().numpy() - og).max() < _gtol(prec, og)
 
 
+_MMD_FULL = {}
+
+
+def _mmd_full_size_case(unbiased):
+    """The differentiation workload at full size in all but the number of
+    operators: its circuit (n = 300, 45150 gates), all 10^4 samples and all
+    2000 training strings, with 24 operators sampled from each bandwidth's
+    2000 (weights 1/72 each). The oracle's loss and gradient over them are
+    computed once per estimator form."""
+    if unbiased not in _MMD_FULL:
+        w = W.mmd_n300()
+        per = w.l // 3
+        rng = np.random.default_rng(12)
+        pick = np.concatenate([g * per + rng.choice(per, size=24, replace=False)
+                               for g in range(3)])
+        ops01 = W.rows_to_dense(w.ops, w.n)[pick]
+        wts = np.full(pick.size, 1.0 / pick.size)
+        ol, og = oracle.mmd_loss_grad(w.n, w.gates, w.theta, ops01, wts, w.samples, w.data,
+                                      unbiased)
+        _MMD_FULL[unbiased] = (w, pick, wts, ol, og)
+    return _MMD_FULL[unbiased]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("unbiased", [True, False])
+def test_mmd_full_size_sampled_operators(prec, unbiased):
+    w, pick, wts, ol, og = _mmd_full_size_case(unbiased)
+    dw = DevWorkload(w)
+    circ = api.Circuit(w.n, dw.gens, dw.theta)
+    ops = dw.ops[torch.from_numpy(pick).cuda()].contiguous()
+    loss, g = api.iqp_mmd_loss_grad(circ, ops, torch.from_numpy(wts).cuda(), dw.samples,
+                                    dw.data, unbiased, True, prec)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    print("mmd full size, 3 x 24 operators, %s unbiased=%s: loss %.10g vs %.10g, "
+          "grad max|d| %.3g of %.3g" % (prec, unbiased, loss.item(), ol, np.abs(g - og).max(),
+                                        np.abs(og).max()))
+    assert abs(loss.item() - ol) < TOL[prec] * max(abs(ol), 1e-2)
+    # the gradient is far below 1 here (weights 1/72), so its bar is relative
+    assert np.abs(g - og).max() < TOL[prec] * np.abs(og).max()
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_autograd_expval_end_to_end(prec):
     w = W.small_random(88, 40, 300, 50, 400)
