@@ -470,6 +470,12 @@ int iqp_train_group_precision(const iqp_train_plan *plan, int32_t *out);
 int iqp_train_buffers(const iqp_train_plan *plan, void *ws, uint64_t **samples,
                       uint64_t **ops, int64_t **step);
 
+/* SHA-256 (lowercase hex) of the sources this library was built from, as
+ * the in-tree build computes it over the kernel and host sources and this
+ * header; "unknown" when built without it. Loaders compare it with the
+ * sources beside the binary to refuse a stale build. Static string. */
+const char *iqp_source_sha256(void);
+
 /* Static text for a status code. */
 const char *iqp_strerror(int status);
 

@@ -19,7 +19,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "iqp_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# IQP_ORACLE_LIBRARY names another build of iqp_oracle.c (the sanitizer build
+# of the tests)
+_LIB = os.environ.get("IQP_ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 

@@ -10,7 +10,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libiqp.so")
+# IQP_LIBRARY_PATH names another build of the same sources (the sanitizer
+# build of the tests); it must embed the same source hash
+LIB_PATH = os.environ.get("IQP_LIBRARY_PATH") or os.path.join(_HERE, "libiqp.so")
 
 IQP_OK = 0
 IQP_ERR_INVALID_ARG = -1
@@ -49,7 +51,8 @@ EXPORTED = ("iqp_workspace_bytes", "iqp_parity_workspace_bytes", "iqp_parity", "
             "iqp_batch_set_config", "iqp_sample_uniform", "iqp_sample_bernoulli",
             "iqp_gather_theta", "iqp_reduce_grad", "iqp_optimizer_update",
             "iqp_train_plan_create", "iqp_train_plan_destroy", "iqp_train_workspace_bytes",
-            "iqp_train_init", "iqp_train_step", "iqp_train_buffers", "iqp_train_group_precision", "iqp_strerror", "iqp_last_error", "iqp_profile_enable",
+            "iqp_train_init", "iqp_train_step", "iqp_train_buffers", "iqp_train_group_precision",
+            "iqp_source_sha256", "iqp_strerror", "iqp_last_error", "iqp_profile_enable",
             "iqp_profile_query", "iqp_profile_reset")
 
 IQP_BATCH_NO_GRAPH = 1
@@ -105,6 +108,15 @@ def lib():
         raise RuntimeError("libiqp.so is not built at %s; run `python -m "
                            "paper_2501_04776_amd.build`" % LIB_PATH)
     L = ctypes.CDLL(LIB_PATH)
+    # refuse a binary built from other sources than the ones beside it
+    from .build import source_sha256
+    L.iqp_source_sha256.argtypes = []
+    L.iqp_source_sha256.restype = ctypes.c_char_p
+    built, here = L.iqp_source_sha256().decode(), source_sha256()
+    if built != here:
+        raise RuntimeError("libiqp.so at %s was built from other sources (built %s, sources %s); "
+                           "rebuild with `python -m paper_2501_04776_amd.build`" %
+                           (LIB_PATH, built[:16], here[:16]))
     i32, i64, vp, sz = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
     cp = ctypes.POINTER(IqpCircuit)
     L.iqp_workspace_bytes.argtypes = [i32, cp, i64, i64, i64, i32]

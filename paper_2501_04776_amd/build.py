@@ -23,12 +23,33 @@ SOURCES = ["iqp_kernels.hip", "iqp_sparse_kernels.hip", "iqp_api.cpp", "iqp_batc
            "iqp_train_kernels.hip", "iqp_train.cpp", "iqp_noalloc.hip"]
 
 
+def source_files():
+    """The files libiqp.so is compiled from: every source and header under
+    csrc/ and the public header."""
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".h")))
+    return [os.path.join(CSRC, f) for f in names] + [os.path.join(ROOT, "include", "iqp.h")]
+
+
+def source_sha256() -> str:
+    """SHA-256 over the source files (name and contents, in order); built
+    into the library (iqp_source_sha256) so that a stale binary is refused."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in source_files():
+        h.update(os.path.basename(f).encode() + b"\0")
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
+    sha = ["-DIQP_SOURCE_SHA256=\"%s\"" % source_sha256()]
     for src in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + COMMON + (sha if src == "iqp_api.cpp" else []) + \
+            ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

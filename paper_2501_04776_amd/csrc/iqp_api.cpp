@@ -99,7 +99,20 @@ static const char *kFamilyNames[KF_COUNT] = {"parity", "theta_prep", "phase_fwd"
 
 // ---------------------------------------------------------------------------
 // device check: the kernels are built for gfx950 only
+// Fault injection for tests of the error paths (IQP_FAULT in the
+// environment, read on every call): "launch" fails every call that would use
+// the device at its device check, before any work is enqueued; "alloc" fails
+// plan creation where it would allocate its host and stream resources.
+int injected_fault(const char *what) {
+    const char *f = getenv("IQP_FAULT");
+    if (f && strcmp(f, what) == 0)
+        return fail(IQP_ERR_HIP, std::string("injected fault (IQP_FAULT=") + what +
+                                     "): nothing was enqueued or allocated");
+    return IQP_OK;
+}
+
 int check_device() {
+    if (int st = injected_fault("launch")) return st;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -567,7 +580,13 @@ bool timing_enabled() { return g_timing.on; }
 
 using namespace iqp;
 
+#ifndef IQP_SOURCE_SHA256
+#define IQP_SOURCE_SHA256 "unknown"
+#endif
+
 extern "C" {
+
+const char *iqp_source_sha256(void) { return IQP_SOURCE_SHA256; }
 
 size_t iqp_workspace_bytes(int call, const iqp_circuit *c, int64_t l, int64_t s, int64_t N,
                            int precision) {

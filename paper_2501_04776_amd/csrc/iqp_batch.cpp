@@ -585,6 +585,10 @@ int iqp_batch_plan_create(int32_t n_problems, const iqp_problem *probs, int prec
     if (lookup_tuned(bp->key, &c)) bp->cfg = c;
 
     bp->staging_bytes = std::max(bp->table_bytes[0], bp->table_bytes[1]);
+    if ((st = injected_fault("alloc"))) {
+        destroy_plan(bp);
+        return st;
+    }
     hipError_t e = hipSuccess;
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         e = hipHostMalloc(&bp->staging[i], bp->staging_bytes, hipHostMallocDefault);

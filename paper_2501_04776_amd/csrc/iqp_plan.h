@@ -15,8 +15,12 @@ int fail(int status, const std::string &msg);
 int hip_fail(hipError_t e, const char *where);
 void clear_error();
 
-// IQP_OK if the current device is gfx950.
+// IQP_OK if the current device is gfx950 (and no launch fault is injected).
 int check_device();
+
+// IQP_ERR_HIP when the environment variable IQP_FAULT equals `what`
+// ("launch" or "alloc"), for tests of the error paths; IQP_OK otherwise.
+int injected_fault(const char *what);
 
 LaunchCtx make_ctx(void *stream);
 

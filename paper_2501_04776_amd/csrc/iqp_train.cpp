@@ -508,6 +508,10 @@ int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan 
     tp->o_mmd = carve(tp->mmd_bytes);
     tp->total = cur;
 
+    if ((st = injected_fault("alloc"))) {
+        destroy(tp);
+        return st;
+    }
     hipError_t e = hipHostMalloc(&tp->staging, tp->tab_bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&tp->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {

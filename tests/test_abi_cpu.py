@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     src = open(os.path.join(ROOT, "include", "iqp.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(iqp_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(iqp_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -368,3 +368,56 @@ def test_param_tables_group_gates_by_parameter_in_gate_order():
     assert list(offs) == [0, 2, 2, 5, 6, 6]  # parameter 1 and 4 have no gates
     for p in range(5):
         assert list(gates[offs[p]:offs[p + 1]]) == [j for j in range(idx.size) if idx[j] == p]
+
+
+def test_injected_launch_fault_fails_before_device_work(monkeypatch):
+    # IQP_FAULT=launch: a call with valid arguments stops at its device check
+    # with IQP_ERR_HIP and says so; without it the same call reaches the
+    # real device check (no GPU here, so a different failure text)
+    c = _circ()
+    monkeypatch.setenv("IQP_FAULT", "launch")
+    assert _expval(c) == L.IQP_ERR_HIP
+    assert b"injected fault (IQP_FAULT=launch)" in L.lib().iqp_last_error()
+    plan = ctypes.c_void_p()
+    assert L.lib().iqp_batch_plan_create(1, _problems([(10, 5, 4, 8)]), 1, 0,
+                                         ctypes.byref(plan)) == L.IQP_ERR_HIP
+    assert b"injected fault" in L.lib().iqp_last_error() and not plan.value
+    monkeypatch.setenv("IQP_FAULT", "something-else")
+    _expval(c)
+    assert b"injected fault" not in L.lib().iqp_last_error()
+    monkeypatch.delenv("IQP_FAULT")
+    _expval(c)
+    assert b"injected fault" not in L.lib().iqp_last_error()
+
+
+def test_argument_errors_come_before_injected_faults(monkeypatch):
+    monkeypatch.setenv("IQP_FAULT", "launch")
+    assert _expval(_circ(), l=0) == L.IQP_ERR_INVALID_ARG
+    assert _expval(_circ(), nb=8) == L.IQP_ERR_WORKSPACE
+
+
+def test_library_records_the_sources_it_was_built_from():
+    from paper_2501_04776_amd import build
+    built = L.lib().iqp_source_sha256().decode()
+    assert len(built) == 64 and built == build.source_sha256()
+
+
+def test_stale_library_is_refused(tmp_path, monkeypatch):
+    # a source edited after the build: the loader refuses the binary
+    import shutil
+    from paper_2501_04776_amd import build
+    files = build.source_files()
+    src = tmp_path / "csrc"
+    src.mkdir()
+    for f in files[:-1]:
+        shutil.copy(f, src)
+    (tmp_path / "iqp.h").write_bytes(open(files[-1], "rb").read())
+    with open(src / os.path.basename(files[0]), "ab") as fh:
+        fh.write(b"\n// edited\n")
+    monkeypatch.setattr(build, "source_files",
+                        lambda: sorted(str(p) for p in src.iterdir()) + [str(tmp_path / "iqp.h")])
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(RuntimeError, match="built from other sources"):
+        L.lib()
+    monkeypatch.undo()
+    assert L.lib() is not None
