@@ -115,17 +115,37 @@ struct WordsOf<true> {
     }
 };
 
-// The set bits of row k of C (the generators J_k), in gate order.
+// The set bits of row k of C (the generators J_k), in gate order. The row
+// is scanned 64 words at a time by the wave's lanes: one coalesced load per
+// 64 words and a ballot of the non-zero ones, so a zero word costs only its
+// share of that load (a walk word by word on the scalar unit pays a
+// dependent scalar load per word, zero or not); the non-zero words are
+// then taken in order from the lanes that hold them.
 struct GateWalk {
-    const uint64_t IQP_CONST *row;
-    int64_t Gw, w;
-    uint64_t cw;
-    __device__ __forceinline__ GateWalk(const uint64_t IQP_CONST *r, int64_t gw)
-        : row(r), Gw(gw), w(0), cw(r[0]) {}
+    const uint64_t IQP_GLOBAL *row;
+    int64_t Gw, base, w;
+    uint64_t v;   // this lane's word of the current 64-word block
+    uint64_t nz;  // lanes of the current block whose word is non-zero (uniform)
+    uint64_t cw;  // the current word, bits not yet taken (uniform)
+    int lane;
+    __device__ __forceinline__ GateWalk(const uint64_t *r, int64_t gw)
+        : row(gptr(r)), Gw(gw), base(-64), w(0), v(0), nz(0), cw(0),
+          lane((int)(threadIdx.x & 63)) {}
     __device__ __forceinline__ bool next(int64_t &j) {
         while (cw == 0) {
-            if (++w >= Gw) return false;
-            cw = row[w];
+            while (nz == 0) {
+                base += 64;
+                if (base >= Gw) return false;
+                const int64_t x = base + lane;
+                v = x < Gw ? row[x] : 0ull;
+                nz = __ballot(v != 0ull);
+            }
+            const int i = __builtin_ctzll(nz);
+            nz &= nz - 1;
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, i);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), i);
+            cw = ((uint64_t)hi << 32) | lo;
+            w = base + i;
         }
         j = w * 64 + __builtin_ctzll(cw);
         cw &= cw - 1;
@@ -186,6 +206,9 @@ __device__ __forceinline__ void sparse_fwd_body(const SparseFwdArgs &a, int64_t 
     for (int b = 0; b < kSpSamples; ++b) acc[b] = kpi[b] = 0.0f;
     double T = 0.0;
     int fold = 0;
+    // (the row is walked word by word on the scalar unit here: the lanes'
+    // block scan of the backward costs the forward two waves per SIMD of
+    // occupancy, more than it saves)
     for (int64_t w = 0; w < a.Gw; ++w) {
         uint64_t cw = crow[w];
         while (cw) {
@@ -289,7 +312,7 @@ __device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t 
     // L / 4 and loads its own parity word.
     const int sh = 16 * (lane & 3);
     const auto src = WordsOf<kIndep>::make(a.bsrc, k, sw0, kIndep ? sw0 + (lane >> 2) : sw0);
-    GateWalk gates(cptr(a.crm) + k * a.Gw, a.Gw);
+    GateWalk gates(a.crm + k * a.Gw, a.Gw);
     const double al = gptr(a.coef)[2 * k], be = gptr(a.coef)[2 * k + 1];
     const double scale = gptr(a.scale)[0];
     // S_ki = (alpha_k + beta_k cos E_ki) sin E_ki for the lane's samples
