@@ -244,13 +244,15 @@ def main():
 
     if args.profile_pass:
         for _ in range(args.steps):
-            step("split_bf16")
+            step(args.profile_precision)
         torch.cuda.synchronize()
         src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")  # 256 MiB
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        log("profile pass done: %d steps, copy of %d bytes" % (args.steps, src.numel() * 4))
+        log("profile pass done: %d %s steps, copy of %d bytes" % (args.steps,
+                                                                  args.profile_precision,
+                                                                  src.numel() * 4))
         return
 
     result = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -271,6 +273,21 @@ def main():
     result["kernels"] = kb
     dom = max(("phase_fwd", "phase_bwd"), key=lambda k: kb.get(k, {}).get("avg_ms", 0.0))
     result["roofline"] = roofline(T, kb[dom]["avg_ms"], dom, recorded_traffic(w.name, dom))
+
+    # --- three BF16 limbs of theta, fixed-point weights on the INT8 cores ----
+    if not args.no_split3:
+        ms3 = timed("split3_bf16")
+        ms3f = timed("split3_bf16", fwd_only=True)
+        log("split3_bf16: fwd+bwd %.3f ms, fwd %.3f ms" % (ms3, ms3f))
+        kb3 = kernel_breakdown("split3_bf16", max(3, min(args.steps, 10)))
+        result["split3_bf16"] = {
+            "fwd_bwd_terms_per_s": T / (ms3 * 1e-3), "fwd_terms_per_s": T / (ms3f * 1e-3),
+            "ms_per_step": ms3, "fwd_ms": ms3f, "kernels": kb3,
+            "roofline_fwd": roofline(T, kb3["phase_fwd"]["avg_ms"], "phase_fwd (3 BF16 limbs)",
+                                     None, "split3_bf16_fwd"),
+            "roofline_bwd": roofline(T, kb3["phase_bwd"]["avg_ms"], "phase_bwd (INT8 limbs)",
+                                     None, "split3_bf16_bwd")} if not mmd else {
+            "fwd_bwd_terms_per_s": T / (ms3 * 1e-3), "ms_per_step": ms3, "kernels": kb3}
 
     # --- FP32 path ----------------------------------------------------------
     if not args.no_fp32:
@@ -316,8 +333,8 @@ def main():
 
     # --- parity of the timed configuration against the oracle ---------------
     parity = {}
-    precs = ["split_bf16"] + ([] if args.no_fp32 else ["fp32"]) + \
-        ([] if args.no_sparse else ["sparse_fp32"])
+    precs = ["split_bf16"] + ([] if args.no_split3 else ["split3_bf16"]) + \
+        ([] if args.no_fp32 else ["fp32"]) + ([] if args.no_sparse else ["sparse_fp32"])
     for prec in precs:
         if mmd:
             break
@@ -331,9 +348,10 @@ def main():
         og = oracle.expval_grad(w.n, w.gates, w.theta, dw.ops01[pick], w.samples, up[pick])
         em = float(np.abs(mean.cpu().numpy()[pick] - om).max())
         es = float(np.abs(se.cpu().numpy()[pick] - ose).max())
-        eg = float(np.abs(g.cpu().numpy() - og).max() / max(1.0, np.abs(og).max()))
+        ega = float(np.abs(g.cpu().numpy() - og).max())
+        eg = ega / max(1.0, np.abs(og).max())
         parity[prec] = {"max_abs_err_mean": em, "max_abs_err_stderr": es,
-                        "max_rel_err_grad": eg, "tol": TOL[prec],
+                        "max_abs_err_grad": ega, "max_rel_err_grad": eg, "tol": TOL[prec],
                         "ok": bool(em < TOL[prec] and es < TOL[prec] and eg < TOL[prec]),
                         "sampled_observables": int(pick.size)}
     result["parity"] = parity

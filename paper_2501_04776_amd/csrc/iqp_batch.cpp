@@ -582,6 +582,7 @@ int iqp_batch_plan_create(int32_t n_problems, const iqp_problem *probs, int prec
     bp->total = cur;
     bp->key = shape_key(precision, bp->plans);
     BatchCfg c;
+    if (precision == IQP_SPLIT_BF16) bp->cfg.bfn = 4;  // the BF16 default, as single calls
     if (lookup_tuned(bp->key, &c)) bp->cfg = c;
 
     bp->staging_bytes = std::max(bp->table_bytes[0], bp->table_bytes[1]);

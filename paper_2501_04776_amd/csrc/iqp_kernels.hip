@@ -1551,8 +1551,10 @@ __global__ __launch_bounds__(256, kI8Waves<FN>) void phase_bwd_i8_persistent(
                     [&](int p, int64_t u) { bwd_i8_body<FM, FN>(args[p], u, opaque_tid()); });
 }
 
+// Both BF16 backward tiles fit two waves per SIMD (the 64 x 128 one with its
+// accumulators in VGPRs).
 template <int FM, int FN>
-__global__ __launch_bounds__(256, 1) void phase_bwd_bf16_kernel(BwdArgs a, int64_t units) {
+__global__ __launch_bounds__(256, 2) void phase_bwd_bf16_kernel(BwdArgs a, int64_t units) {
     const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
     if (gu >= units) return;  // uniform over the workgroup
     bwd_bf16_body<FM, FN>(a, gu, (int)threadIdx.x);
@@ -1566,7 +1568,7 @@ __global__ __launch_bounds__(256, 1) void phase_bwd_f32_kernel(BwdArgs a, int64_
 }
 
 template <int FM, int FN>
-__global__ __launch_bounds__(256, 1) void phase_bwd_bf16_persistent(
+__global__ __launch_bounds__(256, 2) void phase_bwd_bf16_persistent(
     const BwdArgs *__restrict__ args, const int64_t *__restrict__ off, int np,
     unsigned long long *counter) {
     persistent_loop(off, np, counter, [&](int p, int64_t u) { bwd_bf16_body<FM, FN>(args[p], u, opaque_tid()); });

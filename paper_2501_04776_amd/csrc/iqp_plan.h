@@ -86,8 +86,10 @@ struct PlanParts {
 
 // Gate-word splits of the forward that fill `kWaveSlots` wave slots.
 int64_t choose_splits(int64_t tiles, int64_t mw);
-// Sample-word splits of the backward for `units` workgroup units.
-int64_t choose_bsplits(int64_t units, int64_t sw, int bfn);
+// Sample-word splits of the backward for `units` workgroup units, with
+// `wgs_per_cu` of them resident per CU.
+int64_t choose_bsplits(int64_t units, int64_t sw, int wgs_per_cu);
+int bwd_wgs_per_cu(int prec, int bfn);
 
 // Lays out the buffers; tc.splits <= 0 picks the split count.
 void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l, int64_t s,
