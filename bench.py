@@ -44,9 +44,13 @@ METRIC = "phase terms/s (ops×samples×gates), fwd & fwd+bwd, split-BF16 vs FP32
 PEAK = {"split_bf16": (2.5e15, 4.0), "fp32": (157.3e12, 2.0),
         # three BF16 limbs of theta in the forward; two INT8 limbs of the
         # backward weights against the dense INT8 peak (5.0 POP/s)
-        "split3_bf16_fwd": (2.5e15, 6.0), "split3_bf16_bwd": (5.0e15, 4.0)}
+        "split3_bf16_fwd": (2.5e15, 6.0), "split3_bf16_bwd": (5.0e15, 4.0),
+        # FP16 limb (2 flops) and FP8 limb (2 flops at twice the rate) of the
+        # backward weights: 3 FP16-equivalent flops against the FP16 peak
+        "split_bf16_fp8_bwd": (2.5e15, 3.0)}
 ALGO_FLOPS_PER_TERM = 2.0
-TOL = {"fp32": 1e-5, "split_bf16": 1e-4, "split3_bf16": 1e-4, "sparse_fp32": 1e-5}
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4, "split3_bf16": 1e-4, "split_bf16_fp8": 1e-4,
+       "sparse_fp32": 1e-5}
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -166,8 +170,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-split3", action="store_true")
+    ap.add_argument("--no-fp8", action="store_true",
+                    help="skip the split-BF16 form with FP16 + FP8 backward weights")
     ap.add_argument("--profile-precision", default="split_bf16",
-                    choices=["split_bf16", "split3_bf16", "fp32"],
+                    choices=["split_bf16", "split3_bf16", "split_bf16_fp8", "fp32"],
                     help="precision of the --profile-pass steps")
     ap.add_argument("--no-bitflip", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
@@ -284,10 +290,24 @@ def main():
             "fwd_bwd_terms_per_s": T / (ms3 * 1e-3), "fwd_terms_per_s": T / (ms3f * 1e-3),
             "ms_per_step": ms3, "fwd_ms": ms3f, "kernels": kb3,
             "roofline_fwd": roofline(T, kb3["phase_fwd"]["avg_ms"], "phase_fwd (3 BF16 limbs)",
-                                     None, "split3_bf16_fwd"),
+                                     recorded_traffic(w.name, "split3_bf16.phase_fwd"),
+                                     "split3_bf16_fwd"),
             "roofline_bwd": roofline(T, kb3["phase_bwd"]["avg_ms"], "phase_bwd (INT8 limbs)",
-                                     None, "split3_bf16_bwd")} if not mmd else {
+                                     recorded_traffic(w.name, "split3_bf16.phase_bwd"),
+                                     "split3_bf16_bwd")} if not mmd else {
             "fwd_bwd_terms_per_s": T / (ms3 * 1e-3), "ms_per_step": ms3, "kernels": kb3}
+
+    # --- split-BF16 forward, FP16 + FP8 backward weights ----------------------
+    if not args.no_fp8:
+        ms8 = timed("split_bf16_fp8")
+        log("split_bf16_fp8: fwd+bwd %.3f ms" % ms8)
+        kb8 = kernel_breakdown("split_bf16_fp8", max(3, min(args.steps, 10)))
+        result["split_bf16_fp8"] = {
+            "fwd_bwd_terms_per_s": T / (ms8 * 1e-3), "ms_per_step": ms8, "kernels": kb8}
+        if not mmd:
+            result["split_bf16_fp8"]["roofline_bwd"] = roofline(
+                T, kb8["phase_bwd"]["avg_ms"], "phase_bwd (FP16 + FP8 limbs)",
+                recorded_traffic(w.name, "split_bf16_fp8.phase_bwd"), "split_bf16_fp8_bwd")
 
     # --- FP32 path ----------------------------------------------------------
     if not args.no_fp32:
@@ -334,6 +354,7 @@ def main():
     # --- parity of the timed configuration against the oracle ---------------
     parity = {}
     precs = ["split_bf16"] + ([] if args.no_split3 else ["split3_bf16"]) + \
+        ([] if args.no_fp8 else ["split_bf16_fp8"]) + \
         ([] if args.no_fp32 else ["fp32"]) + ([] if args.no_sparse else ["sparse_fp32"])
     for prec in precs:
         if mmd:
@@ -837,9 +858,9 @@ def main_batch(args):
         log("split3_bf16 batched: fwd+bwd %.3f ms, fwd %.3f ms" % (ms3, ms3f))
         kb3 = kernel_times(p3, max(2, min(args.steps, 4)))
         fwd3 = roofline(T, kb3["phase_fwd"]["avg_ms"], "phase_fwd (persistent, 3 BF16 limbs)",
-                        None, "split3_bf16_fwd")
+                        recorded_traffic(name, "split3_bf16.phase_fwd"), "split3_bf16_fwd")
         bwd3 = roofline(T, kb3["phase_bwd"]["avg_ms"], "phase_bwd (persistent, INT8 limbs)",
-                        None, "split3_bf16_bwd")
+                        recorded_traffic(name, "split3_bf16.phase_bwd"), "split3_bf16_bwd")
         result["split3_bf16"] = {"fwd_bwd_terms_per_s": T / (ms3 * 1e-3),
                                  "fwd_terms_per_s": T / (ms3f * 1e-3), "ms_per_step": ms3,
                                  "fwd_ms": ms3f, "tiles": p3.config(), "kernels": kb3,
@@ -847,6 +868,20 @@ def main_batch(args):
         par["split3_bf16"] = parity(p3, "split3_bf16")
         p3.close()
         del p3
+
+    # split-BF16 forward, FP16 + FP8 backward weights
+    if not args.no_fp8:
+        p8 = make_plan("split_bf16_fp8")
+        ms8 = timed(p8)
+        log("split_bf16_fp8 batched: fwd+bwd %.3f ms" % ms8)
+        kb8 = kernel_times(p8, max(2, min(args.steps, 4)))
+        bwd8 = roofline(T, kb8["phase_bwd"]["avg_ms"], "phase_bwd (persistent, FP16 + FP8 limbs)",
+                        recorded_traffic(name, "split_bf16_fp8.phase_bwd"), "split_bf16_fp8_bwd")
+        result["split_bf16_fp8"] = {"fwd_bwd_terms_per_s": T / (ms8 * 1e-3), "ms_per_step": ms8,
+                                    "tiles": p8.config(), "kernels": kb8, "roofline_bwd": bwd8}
+        par["split_bf16_fp8"] = parity(p8, "split_bf16_fp8")
+        p8.close()
+        del p8
 
     if not args.no_fp32:
         plan32 = make_plan("fp32")
@@ -863,31 +898,42 @@ def main_batch(args):
     result["parity"] = par
 
     if not args.no_cpu_baseline:
-        # the oracle on a bounded sample: fwd + bwd of the first k observables
-        # of circuit 0 over all its samples and gates, k sized for ~15 s
-        w, d = ws[0], dws[0]
-
-        def oracle_run(k):
+        # the oracle on a bounded sample: fwd + bwd of whole circuits in order
+        # (all their samples and gates; the last one cut to its first
+        # observables) until about 15 s of host time
+        def oracle_run(w, ops01, k):
             uu = np.random.default_rng(5).normal(size=k)
             t1 = time.time()
-            oracle.expval(w.n, w.gates, w.theta, d.ops01[:k], w.samples)
-            oracle.expval_grad(w.n, w.gates, w.theta, d.ops01[:k], w.samples, uu)
+            oracle.expval(w.n, w.gates, w.theta, ops01[:k], w.samples)
+            oracle.expval_grad(w.n, w.gates, w.theta, ops01[:k], w.samples, uu)
             return time.time() - t1
         nth = oracle.num_threads()
-        k0 = min(w.l, max(nth, 8))
-        dt0 = oracle_run(k0)
-        k = int(min(w.l, max(k0, round(k0 * 15.0 / max(dt0, 1e-3)))))
-        k = max(nth, (k // nth) * nth) if k >= nth else k
-        dt = oracle_run(k)
-        log("oracle: %d observables of circuit 0 in %.2f s on %d threads" % (k, dt, nth))
-        result["cpu_baseline"] = {"value": k * w.s * w.m / dt, "unit": "terms/s",
-                                  "cores": min(nth, k), "kind": "oracle",
-                                  "nnz_terms_per_s": nnz_terms(oracle, w, d.ops01[:k]) / dt,
-                                  "cpu_model": cpu_model(), "wall_s": dt,
-                                  "sample": "fwd+bwd of the first %d of %d observables of circuit "
-                                            "0 (n=%d, m=%d) over its %d samples (%.1f s); value "
-                                            "counts the dense-equivalent l*s*m terms" %
-                                            (k, w.l, w.n, w.m, w.s, dt)}
+        w0, d0 = ws[0], dws[0]
+        k0 = min(w0.l, max(nth, 8))
+        rate = k0 * w0.s * w0.m / max(oracle_run(w0, d0.ops01, k0), 1e-3)  # calibration
+        budget, spent, terms, nnz, parts, cores = 15.0, 0.0, 0.0, 0.0, [], 1
+        for i, (w, d) in enumerate(zip(ws, dws)):
+            k = int(min(w.l, (budget - spent) * rate / (w.s * w.m)))
+            if k < w.l:
+                k = max(min(nth, w.l), (k // nth) * nth)
+            dt = oracle_run(w, d.ops01, k)
+            spent += dt
+            terms += k * w.s * w.m
+            nnz += nnz_terms(oracle, w, d.ops01[:k])
+            cores = max(cores, min(nth, k))
+            rate = terms / spent
+            parts.append("%d of %d observables of circuit %d (n=%d, m=%d)" % (k, w.l, i, w.n, w.m))
+            if k < w.l or spent >= 0.8 * budget:
+                break
+        log("oracle: %s in %.2f s on %d threads" % ("; ".join(parts), spent, nth))
+        result["cpu_baseline"] = {"value": terms / spent, "unit": "terms/s",
+                                  "cores": cores, "kind": "oracle",
+                                  "nnz_terms_per_s": nnz / spent,
+                                  "cpu_model": cpu_model(), "wall_s": spent,
+                                  "sample": "fwd+bwd of %s, each over its 4096 samples and all "
+                                            "its gates (%.1f s); value counts the "
+                                            "dense-equivalent l*s*m terms" %
+                                            ("; ".join(parts), spent)}
     result["config"] = {"workload": name, "circuits": 64, "samples": 4096,
                         "n_qubits": "U{50..2000}", "gates": "U{1e3..2e5}",
                         "observables": "U{100..5000}",

@@ -66,10 +66,25 @@ typedef enum {
  *                    The backward weights S_ki = dL/dcos(E_ki) sin(E_ki) are
  *                    held in 16-bit fixed point per observable,
  *                    S_ki ~ q_k (256 d1_ki + d0_ki) with signed 8-bit limbs,
- *                    q_k = bound_k / 32639, and contracted on the INT8
+ *                    q_k = bound_k / 32639 (bound_k = |a_k| + |b_k| >= |S_ki|
+ *                    for dL/dcos(E_ki) = a_k + b_k cos(E_ki): the plain
+ *                    gradient has b_k = 0, the U-statistic MMD^2 b_k != 0),
+ *                    and contracted on the INT8
  *                    matrix cores with exact INT32 sums: two INT8 products
  *                    per term, the matrix-core time of one BF16 product. The
  *                    gradient meets 1e-4 * max(1, |g|).
+ *   IQP_SPLIT_BF16_FP8: the forward of IQP_SPLIT_BF16 (2 theta_j in two
+ *                    BF16 limbs); the backward weights are scaled per
+ *                    observable by a power of two, S_ki 2^e_k with
+ *                    2^14 <= bound_k 2^e_k < 2^15, and held as an FP16 limb
+ *                    (round to nearest even) plus an FP8 E4M3 limb of what it
+ *                    leaves (|rest| <= 16, 4 significant bits): 15 significant
+ *                    bits per weight against 16 for two BF16 limbs, for one
+ *                    FP16 and one FP8 product per term, three quarters of the
+ *                    matrix-core time of two BF16 products; FP32
+ *                    accumulation, 2^-e_k applied per row in the epilogue.
+ *                    Its gradient error is that of IQP_SPLIT_BF16 to within
+ *                    the weights' rounding.
  *   IQP_SPARSE_FP32: only the non-zero entries of C: for each observable the
  *                    sum of +-2 theta_j over the generators that anticommute
  *                    with it (FP32 on the vector units), so the work is the
@@ -84,7 +99,8 @@ typedef enum {
     IQP_FP32 = 0,
     IQP_SPLIT_BF16 = 1,
     IQP_SPARSE_FP32 = 2,
-    IQP_SPLIT3_BF16 = 3
+    IQP_SPLIT3_BF16 = 3,
+    IQP_SPLIT_BF16_FP8 = 4
 } iqp_precision;
 
 /* A parameterized IQP circuit (Def. 1): generators g_j as bit rows and their
@@ -292,7 +308,8 @@ enum {
  * tile configuration is the one recorded for these shapes by iqp_batch_tune
  * in this process (or in the file named by the environment variable
  * IQP_TUNE_CACHE), else a default. The current device must be gfx950.
- * precision: IQP_FP32, IQP_SPLIT_BF16 or IQP_SPLIT3_BF16 (the dense forms). */
+ * precision: IQP_FP32, IQP_SPLIT_BF16, IQP_SPLIT3_BF16 or IQP_SPLIT_BF16_FP8
+ * (the dense forms). */
 int iqp_batch_plan_create(int32_t n_problems, const iqp_problem *probs, int precision,
                           int flags, iqp_batch_plan **plan);
 int iqp_batch_plan_destroy(iqp_batch_plan *plan);

@@ -24,6 +24,7 @@ IQP_FP32 = 0
 IQP_SPLIT_BF16 = 1
 IQP_SPARSE_FP32 = 2
 IQP_SPLIT3_BF16 = 3
+IQP_SPLIT_BF16_FP8 = 4
 
 IQP_CALL_EXPVAL = 0
 IQP_CALL_EXPVAL_GRAD = 1

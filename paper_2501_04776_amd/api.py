@@ -23,18 +23,20 @@ TILED32_T = L.IQP_BITS_TILED32_T
 
 SPARSE_FP32 = L.IQP_SPARSE_FP32
 SPLIT3_BF16 = L.IQP_SPLIT3_BF16
+SPLIT_BF16_FP8 = L.IQP_SPLIT_BF16_FP8
 
 _PRECISIONS = {"fp32": FP32, "split_bf16": SPLIT_BF16, "sparse_fp32": SPARSE_FP32,
-               "split3_bf16": SPLIT3_BF16, FP32: FP32, SPLIT_BF16: SPLIT_BF16,
-               SPARSE_FP32: SPARSE_FP32, SPLIT3_BF16: SPLIT3_BF16}
+               "split3_bf16": SPLIT3_BF16, "split_bf16_fp8": SPLIT_BF16_FP8, FP32: FP32,
+               SPLIT_BF16: SPLIT_BF16, SPARSE_FP32: SPARSE_FP32, SPLIT3_BF16: SPLIT3_BF16,
+               SPLIT_BF16_FP8: SPLIT_BF16_FP8}
 
 
 def precision_id(p) -> int:
     try:
         return _PRECISIONS[p]
     except KeyError:
-        raise ValueError("precision must be 'fp32', 'split_bf16', 'split3_bf16' or "
-                         "'sparse_fp32'") from None
+        raise ValueError("precision must be 'fp32', 'split_bf16', 'split3_bf16', "
+                         "'split_bf16_fp8' or 'sparse_fp32'") from None
 
 
 def _ptr(t: Optional[torch.Tensor]):

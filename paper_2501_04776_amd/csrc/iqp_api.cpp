@@ -158,9 +158,10 @@ int64_t choose_splits(int64_t tiles, int64_t mw) {
 
 // Workgroups of the backward contraction resident per CU (register and LDS
 // use of each kernel, 32 KB of LDS each): BF16 64x64 three, BF16 64x128 two,
-// INT8 64x64 two, INT8 64x128 one, FP32 64x64 three, FP32 64x128 one.
-int bwd_wgs_per_cu(int prec, int bfn) {
-    if (prec == IQP_SPLIT_BF16) return bfn == 2 ? 3 : 2;
+// INT8 64x64 two, INT8 64x128 one, FP32 64x64 three, FP32 64x128 one; the
+// FP16 + FP8 kernels as the BF16 ones, and their 128x64 tile two.
+int bwd_wgs_per_cu(int prec, int bfm, int bfn) {
+    if (prec == IQP_SPLIT_BF16 || prec == IQP_SPLIT_BF16_FP8) return bfm * bfn == 4 ? 3 : 2;
     if (prec == IQP_SPLIT3_BF16) return bfn == 2 ? 2 : 1;
     return bfn == 2 ? 3 : 1;
 }
@@ -196,10 +197,10 @@ static size_t carve(size_t &cur, size_t bytes) {
 }
 
 // Tile overrides for measurement sweeps: IQP_FWD_TILE = "FMxFN" (4x4, 2x4,
-// 2x2), IQP_BWD_TILE (2x4, 2x2), IQP_FWD_SPLITS = number of gate-word splits
+// 2x2), IQP_BWD_TILE (2x4, 2x2; 4x2 for IQP_SPLIT_BF16_FP8), IQP_FWD_SPLITS = number of gate-word splits
 // of the forward, IQP_BWD_SPLITS = number of sample-word splits of the
 // backward.
-static void apply_env_tiles(TileCfg &tc) {
+static void apply_env_tiles(TileCfg &tc, int prec) {
     const char *f = getenv("IQP_FWD_TILE");
     int a = 0, b = 0;
     if (f && sscanf(f, "%dx%d", &a, &b) == 2 &&
@@ -208,7 +209,9 @@ static void apply_env_tiles(TileCfg &tc) {
         tc.fn = b;
     }
     const char *g = getenv("IQP_BWD_TILE");
-    if (g && sscanf(g, "%dx%d", &a, &b) == 2 && ((a == 2 && b == 4) || (a == 2 && b == 2))) {
+    if (g && sscanf(g, "%dx%d", &a, &b) == 2 &&
+        ((a == 2 && b == 4) || (a == 2 && b == 2) ||
+         (a == 4 && b == 2 && prec == IQP_SPLIT_BF16_FP8))) {
         tc.bfm = a;
         tc.bfn = b;
     }
@@ -243,7 +246,7 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
     const int64_t sw = P.s_pad / 64;
     const int64_t bunits = ceil_div(P.m_pad / (32 * P.tc.bfn), 4) * (P.l_pad / (32 * P.tc.bfm));
     if (P.tc.bsplits <= 0)
-        P.tc.bsplits = choose_bsplits(bunits, sw, bwd_wgs_per_cu(prec, P.tc.bfn));
+        P.tc.bsplits = choose_bsplits(bunits, sw, bwd_wgs_per_cu(prec, P.tc.bfm, P.tc.bfn));
     if (prec == IQP_SPLIT3_BF16) {
         // the INT32 sums of the fixed-point weights stay exact per unit
         const int64_t min_ks = ceil_div(sw * 64, kI8MaxSamplesPerUnit);
@@ -291,7 +294,7 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
     }
     if (P.fwd) {
         P.o_bbits = carve(cur, (size_t)P.s_pad * P.mw * 8);
-        if (prec == IQP_SPLIT_BF16 || prec == IQP_SPLIT3_BF16) {
+        if (prec == IQP_SPLIT_BF16 || prec == IQP_SPLIT3_BF16 || prec == IQP_SPLIT_BF16_FP8) {
             P.o_thh = carve(cur, (size_t)P.m_pad * 2);
             P.o_thl = carve(cur, (size_t)P.m_pad * 2);
             if (prec == IQP_SPLIT3_BF16) P.o_thm = carve(cur, (size_t)P.m_pad * 2);
@@ -317,6 +320,12 @@ void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l,
             P.o_slo = carve(cur, (size_t)P.s_pad * P.l_pad);
             P.o_sq = carve(cur, (size_t)P.l_pad * 8);
             P.o_nf = carve(cur, (size_t)P.l_pad * 4);
+        } else if (prec == IQP_SPLIT_BF16_FP8) {
+            // FP16 limbs, FP8 limbs, row scales 2^-e_k (rows past l are never
+            // read: their C^T bits are 0)
+            P.o_shi = carve(cur, (size_t)P.s_pad * P.l_pad * 2);
+            P.o_slo = carve(cur, (size_t)P.s_pad * P.l_pad);
+            P.o_sq = carve(cur, (size_t)P.l_pad * 8);
         } else {
             P.o_s32 = carve(cur, (size_t)P.s_pad * P.l_pad * 4);
         }
@@ -410,7 +419,12 @@ static void make_call_plan(Plan &P, int call, int64_t n, int64_t m, int64_t l, i
     // half the LDS reads of the 64 x 64 tile per product (n = 300 workload:
     // 1.245 -> 1.161 ms per backward)
     if (prec == IQP_SPLIT_BF16) tc.bfn = 4;
-    apply_env_tiles(tc);
+    // the FP16 + FP8 backward runs 128 x 64: its B operands (the FP16 and the
+    // FP8 +-1 expansions) serve four row blocks instead of two, half the
+    // vector work per product (n = 300: 0.972 -> 0.952 ms; 64 circuits:
+    // 160 -> 154 ms)
+    if (prec == IQP_SPLIT_BF16_FP8) tc.bfm = 4;
+    apply_env_tiles(tc, prec);
     make_plan(P, parts, n, m, l, s, N, prec, tc);
 }
 
@@ -436,7 +450,8 @@ static int check_common(const iqp_circuit *c, int64_t l, const uint64_t *ops, in
     if (!samples) return fail(IQP_ERR_INVALID_ARG, "samples is NULL");
     if (!valid_precision(precision))
         return fail(IQP_ERR_INVALID_ARG, "precision must be IQP_FP32, IQP_SPLIT_BF16, "
-                                         "IQP_SPARSE_FP32 or IQP_SPLIT3_BF16");
+                                         "IQP_SPARSE_FP32, IQP_SPLIT3_BF16 or "
+                                         "IQP_SPLIT_BF16_FP8");
     return IQP_OK;
 }
 

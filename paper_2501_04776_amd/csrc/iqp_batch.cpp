@@ -32,14 +32,17 @@ static bool same_tiles(const BatchCfg &a, const BatchCfg &b) {
     return a.fm == b.fm && a.fn == b.fn && a.split == b.split && a.bfm == b.bfm && a.bfn == b.bfn;
 }
 
-static bool valid_cfg(const BatchCfg &c) {
+// (the 128 x 64 backward tile exists for the FP16 + FP8 form only)
+static bool valid_cfg(const BatchCfg &c, int prec) {
     const bool f = (c.fm == 4 && c.fn == 4) || (c.fm == 2 && c.fn == 4) || (c.fm == 2 && c.fn == 2);
-    const bool b = c.bfm == 2 && (c.bfn == 2 || c.bfn == 4);
+    const bool b = (c.bfm == 2 && (c.bfn == 2 || c.bfn == 4)) ||
+                   (c.bfm == 4 && c.bfn == 2 && prec == IQP_SPLIT_BF16_FP8);
     return f && b && c.split >= 0 && c.split <= 2;
 }
 
 static const int kFwdTiles[3][2] = {{4, 4}, {2, 4}, {2, 2}};
-static const int kBwdTiles[2][2] = {{2, 2}, {2, 4}};
+static const int kBwdTiles[3][2] = {{2, 2}, {2, 4}, {4, 2}};
+static int n_bwd_tiles(int prec) { return prec == IQP_SPLIT_BF16_FP8 ? 3 : 2; }
 static const int kMaxSplit = 16;
 static const int kMaxProblems = 1 << 16;
 
@@ -125,11 +128,12 @@ static void load_tune_file_locked() {
         while ((ch = fgetc(f)) != EOF && ch != '\n') line.push_back((char)ch);
         if (!line.empty()) {
             const size_t sp = line.find(' ');
-            if (sp != std::string::npos) {
+            int prec = -1;
+            if (sp != std::string::npos && sscanf(line.c_str(), "prec%d:", &prec) == 1) {
                 BatchCfg c;
                 if (sscanf(line.c_str() + sp + 1, "%d %d %d %d %d", &c.fm, &c.fn, &c.split, &c.bfm,
                            &c.bfn) == 5 &&
-                    valid_cfg(c)) {
+                    valid_cfg(c, prec)) {
                     c.tuned = true;
                     g_tune[line.substr(0, sp)] = c;
                 }
@@ -174,7 +178,7 @@ struct iqp_batch_plan {
     size_t total = 0;
     BatchCfg cfg;
     std::string key;
-    int grid_fwd[3] = {0, 0, 0}, grid_bwd[2] = {0, 0};
+    int grid_fwd[3] = {0, 0, 0}, grid_bwd[3] = {0, 0, 0};
     void *staging[2] = {nullptr, nullptr};
     size_t staging_bytes = 0;
     hipEvent_t staged[2] = {nullptr, nullptr};
@@ -195,7 +199,7 @@ static int fwd_tile_index(const BatchCfg &c) {
     return -1;
 }
 static int bwd_tile_index(const BatchCfg &c) {
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 3; ++i)
         if (kBwdTiles[i][0] == c.bfm && kBwdTiles[i][1] == c.bfn) return i;
     return -1;
 }
@@ -501,9 +505,9 @@ int iqp_batch_plan_create(int32_t n_problems, const iqp_problem *probs, int prec
     if (n_problems < 1 || n_problems > kMaxProblems)
         return fail(IQP_ERR_INVALID_ARG, "n_problems out of range [1, 65536]");
     if (!probs) return fail(IQP_ERR_INVALID_ARG, "probs is NULL");
-    if (precision != IQP_FP32 && precision != IQP_SPLIT_BF16 && precision != IQP_SPLIT3_BF16)
-        return fail(IQP_ERR_INVALID_ARG,
-                    "precision must be IQP_FP32, IQP_SPLIT_BF16 or IQP_SPLIT3_BF16");
+    if (!dense_precision(precision))
+        return fail(IQP_ERR_INVALID_ARG, "precision must be IQP_FP32, IQP_SPLIT_BF16, "
+                                         "IQP_SPLIT3_BF16 or IQP_SPLIT_BF16_FP8");
     if (flags & ~(int)IQP_BATCH_NO_GRAPH) return fail(IQP_ERR_INVALID_ARG, "unknown flags");
     int st;
     for (int p = 0; p < n_problems; ++p)
@@ -521,7 +525,7 @@ int iqp_batch_plan_create(int32_t n_problems, const iqp_problem *probs, int prec
             return fail(IQP_ERR_HIP, "occupancy query of the forward contraction failed");
         }
     }
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < n_bwd_tiles(precision); ++i) {
         bp->grid_bwd[i] = persistent_grid(false, precision, kBwdTiles[i][0], kBwdTiles[i][1]);
         if (bp->grid_bwd[i] < 1) {
             destroy_plan(bp);
@@ -582,7 +586,9 @@ int iqp_batch_plan_create(int32_t n_problems, const iqp_problem *probs, int prec
     bp->total = cur;
     bp->key = shape_key(precision, bp->plans);
     BatchCfg c;
-    if (precision == IQP_SPLIT_BF16) bp->cfg.bfn = 4;  // the BF16 default, as single calls
+    // the defaults of single calls
+    if (precision == IQP_SPLIT_BF16) bp->cfg.bfn = 4;
+    if (precision == IQP_SPLIT_BF16_FP8) bp->cfg.bfm = 4;
     if (lookup_tuned(bp->key, &c)) bp->cfg = c;
 
     bp->staging_bytes = std::max(bp->table_bytes[0], bp->table_bytes[1]);
@@ -658,7 +664,7 @@ int iqp_batch_tune(iqp_batch_plan *plan, const iqp_problem *probs, int passes, v
     }
     if (passes & 2) {
         float best_ms = -1.0f;
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < n_bwd_tiles(plan->prec); ++i) {
             plan->cfg.bfm = kBwdTiles[i][0];
             plan->cfg.bfn = kBwdTiles[i][1];
             float ms = 0.0f;
@@ -701,7 +707,7 @@ int iqp_batch_set_config(iqp_batch_plan *plan, const int32_t *cfg5) {
     c.split = cfg5[2];
     c.bfm = cfg5[3];
     c.bfn = cfg5[4];
-    if (!valid_cfg(c)) return fail(IQP_ERR_INVALID_ARG, "unsupported tile configuration");
+    if (!valid_cfg(c, plan->prec)) return fail(IQP_ERR_INVALID_ARG, "unsupported tile configuration");
     plan->cfg = c;
     return IQP_OK;
 }

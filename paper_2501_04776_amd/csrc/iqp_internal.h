@@ -65,8 +65,9 @@ constexpr int kSupCap = 8;
 // its flat block index to (problem, local block) through a prefix sum of the
 // per-problem block counts.
 
-// prec: IQP_FP32 (t32 split by gate parity), IQP_SPLIT_BF16 (hi, lo),
-// IQP_SPARSE_FP32 (t32 plain), IQP_SPLIT3_BF16 (hi, mid, lo).
+// prec: IQP_FP32 (t32 split by gate parity), IQP_SPLIT_BF16 and
+// IQP_SPLIT_BF16_FP8 (hi, lo), IQP_SPARSE_FP32 (t32 plain), IQP_SPLIT3_BF16
+// (hi, mid, lo).
 struct ThetaArgs {
     const double *theta;
     int64_t m, m_pad;
@@ -159,7 +160,9 @@ inline int64_t blocks_of(const CoefArgs &a) { return ceil_div(a.l, 256); }
 
 // IQP_SPLIT3_BF16: shi / slo hold the high / low signed 8-bit limbs of
 // N_ki = rint(S_ki / sq[k]) (|N| <= kI8Max), and nf[k] is set to 1 where a
-// weight of row k is not finite.
+// weight of row k is not finite. IQP_SPLIT_BF16_FP8: shi holds the FP16 limb
+// and slo (one byte per weight) the FP8 E4M3 limb of S_ki 2^e_k, and sq[k] is
+// set to 2^-e_k.
 struct WeightsArgs {
     const float *phase;
     const double *coef;
@@ -168,6 +171,7 @@ struct WeightsArgs {
     uint16_t *shi, *slo;
     float *s32;
     int32_t *nf;
+    double *sq;
 };
 inline int64_t blocks_of(const WeightsArgs &a) { return (a.s_pad / 64) * (a.l_pad / 64); }
 
@@ -181,7 +185,8 @@ struct BwdArgs {
     const uint64_t *btbits, *ctbits;
     int64_t m_pad, l_pad, s_pad, ksplits;
     float *gpart;
-    const double *sq;   // IQP_SPLIT3_BF16: row scales and non-finite flags
+    const double *sq;   // row scales (IQP_SPLIT3_BF16, IQP_SPLIT_BF16_FP8) and
+                        // non-finite flags (IQP_SPLIT3_BF16)
     const int32_t *nf;
     int64_t obgroup;    // observable blocks per unit group (unit order only)
 };

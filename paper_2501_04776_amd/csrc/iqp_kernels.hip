@@ -41,13 +41,13 @@ __device__ __forceinline__ void theta_prep_body(const ThetaArgs &a, int64_t blk)
     const double two = 2.0 * tr;
     if (a.prec == 2) {
         gptr(a.t32)[i] = (float)two;  // plain, for the sparse contraction
-    } else if (a.prec == 1 || a.prec == 3) {
+    } else if (a.prec == 1 || a.prec == 3 || a.prec == 4) {
         // each limb is the BF16 rounding of what the previous ones leave
         const uint16_t h = f2bf_rne((float)two);
         const double rem = two - (double)bf2f(h);
         const uint16_t l = f2bf_rne((float)rem);
         gptr(a.hi)[i] = h;
-        if (a.prec == 1) {
+        if (a.prec != 3) {
             gptr(a.lo)[i] = l;
         } else {
             gptr(a.mid)[i] = l;
@@ -487,7 +487,8 @@ __device__ __forceinline__ void store_tile(const f32x16 (&acc)[FM][FN], float IQ
         }
 }
 
-// NL = 2 (IQP_SPLIT_BF16: hi, lo) or 3 (IQP_SPLIT3_BF16: hi, mid, lo).
+// NL = 2 (IQP_SPLIT_BF16 and IQP_SPLIT_BF16_FP8: hi, lo) or 3 (IQP_SPLIT3_BF16:
+// hi, mid, lo).
 template <int FM, int FN, int NL>
 __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int tid) {
     // per word 8 units of 16 bytes per limb: K-step t, half h at 2t + h
@@ -739,7 +740,7 @@ static hipError_t fwd_dispatch(const LaunchCtx &lc, int prec, const FwdArgs &a) 
     if (units <= 0) return hipSuccess;
     if (units > kMaxBlocks) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)units);
-    if (prec == 1)
+    if (prec == 1 || prec == 4)
         hipLaunchKernelGGL((phase_fwd_bf16_kernel<FM, FN, 2>), grid, dim3(256), 0, lc.stream, a,
                            units);
     else if (prec == 3)
@@ -766,7 +767,7 @@ template <int FM, int FN>
 static hipError_t fwd_persistent(const LaunchCtx &lc, int prec, const FwdArgs *args,
                                  const int64_t *off, int np, unsigned long long *counter,
                                  int grid) {
-    if (prec == 1)
+    if (prec == 1 || prec == 4)
         hipLaunchKernelGGL((phase_fwd_bf16_persistent<FM, FN, 2>), dim3(grid), dim3(256), 0,
                            lc.stream, args, off, np, counter);
     else if (prec == 3)
@@ -875,6 +876,36 @@ __device__ __forceinline__ void coef_rowscale(double *sq, int32_t *nf, int64_t k
     }
 }
 
+// Row exponent of the FP16 + FP8 weights: with bound_k = f 2^x, f in
+// [1/2, 1), e_k = 15 - x puts bound_k 2^e_k in [2^14, 2^15), inside FP16's
+// range with its normal numbers covering all weights above 2^-28 bound_k;
+// 0 for a zero or non-finite bound (the row is zero, or its weights carry
+// the NaN on).
+__device__ __forceinline__ int f16_row_exp(double al, double be) {
+    const double b = fabs(al) + fabs(be);
+    if (!(b > 0.0) || !isfinite(b)) return 0;
+    int x;
+    (void)frexp(b, &x);
+    const int e = 15 - x;
+    return e < -120 ? -120 : (e > 120 ? 120 : e);
+}
+
+// OCP FP8 E4M3 (bias 7, 3 mantissa bits, no infinities) of a float, rounded
+// to nearest even; |y| must be below 464 (the first value that would round
+// past 448). Non-finite input gives the NaN code.
+__device__ __forceinline__ uint32_t f32_to_e4m3(float y) {
+    const uint32_t u = __float_as_uint(y);
+    const uint32_t sgn = (u >> 24) & 0x80u;
+    const uint32_t a = u & 0x7FFFFFFFu;
+    if (a >= 0x7F800000u) return sgn | 0x7Fu;
+    if (a < 0x3C800000u)  // below 2^-6: the subnormal grid of step 2^-9 (8 = 2^-6)
+        return sgn | (uint32_t)rintf(__uint_as_float(a) * 512.0f);
+    // keep 3 of the 23 mantissa bits, ties to even on the 20 dropped ones; a
+    // carry moves into the exponent; rebias 127 -> 7
+    const uint32_t r = a + 0x7FFFFu + ((a >> 20) & 1u);
+    return sgn | ((r >> 20) - (120u << 3));
+}
+
 __device__ __forceinline__ void coef_plain_body(const CoefArgs &a, int64_t blk) {
     const int64_t k = blk * 256 + threadIdx.x;
     if (k >= a.l) return;
@@ -961,6 +992,52 @@ __device__ __forceinline__ void weights_body(const WeightsArgs &a, int64_t blk) 
         reinterpret_cast<u32x4 IQP_GLOBAL *>(shi)[idx] = (u32x4){dh[0], dh[1], dh[2], dh[3]};
         reinterpret_cast<u32x4 IQP_GLOBAL *>(slo)[idx] = (u32x4){dl[0], dl[1], dl[2], dl[3]};
         if (bad && k < l) gptr(a.nf)[k] = 1;  // every writer stores the same value
+    } else if (prec == 4) {
+        // x = S_ki 2^e_k: FP16 limb h = rn(x) in the BF16 form's image, and
+        // FP8 limb rn_e4m3(x - h) (exact difference, |x - h| <= 16) in the
+        // A-operand image of a 32x32x64 FP8 product: lane (l/32, l%32) holds
+        // row l%32 and samples 32 (l/32) + e, e = 0..31, of a sample word,
+        // as two 16-byte units at (((k/32) * sw + i/64) * 2 + q) * 64 + l
+        // for bytes 16 q .. 16 q + 15 (sw = s_pad / 64)
+        const int kl = threadIdx.x & 63;
+        const int64_t k = k0 + kl;
+        int ex = 0;
+        if (k < l) ex = f16_row_exp(coef[2 * k], coef[2 * k + 1]);
+        const int64_t KTs = s_pad / 16;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int sg = (q * 256 + (int)threadIdx.x) >> 6;
+            const int64_t i = i0 + 8 * sg;
+            const int64_t idx = ((k >> 5) * KTs + (i >> 4)) * 64 + ((i >> 3) & 1) * 32 + (k & 31);
+            uint32_t dh[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                uint32_t hv[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+                    hv[e] = __builtin_bit_cast(uint16_t,
+                                               (_Float16)ldexpf(tile[kl][8 * sg + 2 * v + e], ex));
+                dh[v] = hv[0] | (hv[1] << 16);
+            }
+            reinterpret_cast<u32x4 IQP_GLOBAL *>(shi)[idx] = (u32x4){dh[0], dh[1], dh[2], dh[3]};
+        }
+        const int hq = threadIdx.x >> 6, hh = hq >> 1, q = hq & 1;
+        uint32_t d8[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            uint32_t w = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float x = ldexpf(tile[kl][32 * hh + 16 * q + 4 * v + e], ex);
+                const float h = (float)(_Float16)x;
+                w |= f32_to_e4m3(x - h) << (8 * e);
+            }
+            d8[v] = w;
+        }
+        const int64_t sw = s_pad / 64;
+        const int64_t idx8 = (((k >> 5) * sw + i0 / 64) * 2 + q) * 64 + hh * 32 + (k & 31);
+        reinterpret_cast<u32x4 IQP_GLOBAL *>(slo)[idx8] = (u32x4){d8[0], d8[1], d8[2], d8[3]};
+        if (i0 == 0 && hq == 0 && k < l) gptr(a.sq)[k] = ldexp(1.0, -ex);
     } else if (prec == 1) {
         const int64_t KTs = s_pad / 16;
         // 64 observables x 8 groups of 8 samples = 512 units, 2 per thread
@@ -1533,6 +1610,279 @@ __device__ __forceinline__ void bwd_i8_body(const BwdArgs &a, int64_t gu, int ti
 
 // The 64 x 64 wave tile fits two waves per SIMD (its INT32 accumulators in
 // VGPRs, no AGPRs), which hides the per-block barrier and load latency.
+// ---------------------------------------------------------------------------
+// FP16 + FP8 form of the backward (IQP_SPLIT_BF16_FP8). Row k of S is scaled
+// by 2^e_k and held as an FP16 limb plus an FP8 E4M3 limb (weights_kernel).
+// Per 64-sample word and 32x32 block: four 32x32x16 FP16 products of the
+// FP16 limb (K-steps as in the BF16 form, B = +-1.0 in FP16) and one
+// 32x32x64 FP8 product of the FP8 limb (B = +-1.0 in E4M3), all into the
+// same FP32 accumulators; the FP8 product takes the matrix-core time of two
+// FP16 ones, so a word costs 6 instead of the 8 of two BF16 limbs. The
+// epilogue multiplies each row by 2^-e_k (sq) before the masked sum over
+// rows. Same work units, staging (one sample word per buffer) and pipeline
+// as the BF16 form; the FP8 products of gate block g are issued in region
+// g + 1 of the word (the last one after the word's barrier), each with the
+// expansion of its B operand from the word's bits in the same or the
+// previous region.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
+
+// B_ij = (-1)^{bit} in FP8 E4M3 (+1 = 0x38, -1 = 0xB8) for the 32 K values
+// of the lane, byte e <- bit e of x32: the sign bytes of expand_pm1_i8
+// (0x00 / 0xFF per bit, four bits per dword) masked to the sign bit, or'ed
+// with 0x38 (the two constants in vector registers, so that mask-and-or is
+// one instruction).
+__device__ __forceinline__ i32x8 expand_pm1_f8(uint32_t x32, uint32_t m80, uint32_t c38) {
+    i32x8 out;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const uint32_t x16 = half ? x32 >> 16 : x32;
+        const u16x2 xv = {(unsigned short)x16, (unsigned short)x16};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const u16x2 sh1 = {(unsigned short)(15 - 4 * v), (unsigned short)(14 - 4 * v)};
+            const u16x2 sh0 = {(unsigned short)(13 - 4 * v), (unsigned short)(12 - 4 * v)};
+            const uint32_t s1 = __builtin_bit_cast(uint32_t, (u16x2)(xv << sh1));
+            const uint32_t s0 = __builtin_bit_cast(uint32_t, (u16x2)(xv << sh0));
+            out[4 * half + v] = (int32_t)((__builtin_amdgcn_perm(s0, s1, 0x0B0A0908u) & m80) | c38);
+        }
+    }
+    return out;
+}
+
+template <int FM, int FN>
+struct BwdOpsH {
+    f16x8 ah[FM], bv[FN];
+};
+// the FP8 limb of the word's S strip and the +-1 operands of two gate blocks
+template <int FM>
+struct BwdLoF8 {
+    i32x8 a[FM], b[2];
+};
+
+template <int FM, int FN, int T>
+__device__ __forceinline__ void bwdh_expand_a(BwdOpsH<FM, FN> &o, const u32x4 *ls, int lane) {
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+        o.ah[f] = __builtin_bit_cast(f16x8, ls[(f * 4 + T) * 64 + lane]);
+}
+
+template <int FM, int FN, int T>
+__device__ __forceinline__ void bwdh_expand_b(BwdOpsH<FM, FN> &o, const uint64_t (&bw)[FN],
+                                              uint32_t ones) {
+#pragma unroll
+    for (int g = 0; g < FN; ++g) {
+        const uint32_t d = (uint32_t)(bw[g] >> (32 * (T >> 1)));
+        o.bv[g] = __builtin_bit_cast(f16x8, expand_pm1((T & 1) ? (d >> 16) : d, ones));
+    }
+}
+
+// Where the FP8 products of a word go: region R (1, 2, 3, then 0 after the
+// word's barrier) issues the products of gate block gi for row blocks
+// [f0, f1), expands the FP8 B operands of gate blocks gx0, gx1 (slot g % 2,
+// -1: none) from the word's bits, and region 1 also reads the word's FP8
+// limb. Every expansion happens before the barrier that replaces the bits,
+// and each slot is consumed before it is refilled.
+template <int FM, int FN, int R>
+struct F8Plan {
+    // 64x128 tiles: one gate block per region
+    static constexpr int gi = FN == 4 ? (R == 0 ? 3 : R - 1) : (FM == 4 ? (R == 1 || R == 2 ? 0 : 1)
+                                                                        : (R == 1 ? 0 : R == 2 ? 1 : -1));
+    static constexpr int f0 = FM == 4 && FN == 2 && (R == 2 || R == 0) ? 2 : 0;
+    static constexpr int f1 = FM == 4 && FN == 2 && (R == 1 || R == 3) ? 2 : FM;
+    static constexpr int gx0 = R == 1 ? 0 : R == 2 ? 1 : (R == 3 && FN == 4) ? 2 : -1;
+    static constexpr int gx1 = R == 3 && FN == 4 ? 3 : -1;
+};
+
+// One pipeline region: the FP16 products of K-step t (operands `cur`) while
+// the operands of K-step T1 are read from `lsn` and expanded into `nxt`, plus
+// the FP8 work that F8Plan<FM, FN, R> assigns to region R (R = T1).
+template <int FM, int FN, int R>
+__device__ __forceinline__ void bwdh_region(const BwdOpsH<FM, FN> &cur, BwdOpsH<FM, FN> &nxt,
+                                            const u32x4 *lsn, const uint64_t (&bw)[FN], int lane,
+                                            int h, uint32_t ones, uint32_t m80, uint32_t c38,
+                                            BwdLoF8<FM> &lo, f32x16 (&acc)[FM][FN]) {
+    using P = F8Plan<FM, FN, R>;
+    constexpr bool RA = R == 1;
+    if (RA) {
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+            const u32x4 p0 = lsn[(4 * FM + 2 * f) * 64 + lane];
+            const u32x4 p1 = lsn[(4 * FM + 2 * f + 1) * 64 + lane];
+            lo.a[f] = (i32x8){(int32_t)p0[0], (int32_t)p0[1], (int32_t)p0[2], (int32_t)p0[3],
+                              (int32_t)p1[0], (int32_t)p1[1], (int32_t)p1[2], (int32_t)p1[3]};
+        }
+    }
+    bwdh_expand_a<FM, FN, R>(nxt, lsn, lane);
+    if (P::gx0 >= 0)
+        lo.b[P::gx0 & 1] = expand_pm1_f8((uint32_t)(bw[P::gx0 < 0 ? 0 : P::gx0] >> (24 * h)), m80, c38);
+    if (P::gx1 >= 0)
+        lo.b[P::gx1 & 1] = expand_pm1_f8((uint32_t)(bw[P::gx1 < 0 ? 0 : P::gx1] >> (24 * h)), m80, c38);
+    bwdh_expand_b<FM, FN, R>(nxt, bw, ones);
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int g = 0; g < FN; ++g)
+            acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(cur.ah[f], cur.bv[g], acc[f][g], 0, 0,
+                                                               0);
+    if (P::gi >= 0) {
+#pragma unroll
+        for (int f = P::f0; f < P::f1; ++f) {
+            f32x16 &c = acc[f][P::gi < 0 ? 0 : P::gi];
+            c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(lo.a[f], lo.b[P::gi & 1], c, 0, 0, 0,
+                                                                 127, 0, 127);
+        }
+    }
+    constexpr int kM = FM * FN + (P::gi >= 0 ? P::f1 - P::f0 : 0);
+    constexpr int kV = 8 * FN + 2 + (P::gx0 >= 0 ? 24 : 0) + (P::gx1 >= 0 ? 24 : 0);
+    interleave_half<FM + (RA ? 2 * FM : 0), kM, kV>();
+}
+
+// sum_k c_kj 2^-e_k T[k][j] over this wave's observable rows, per gate column
+template <int FM, int FN>
+__device__ __forceinline__ void bwdh_epilogue(const f32x16 (&acc)[FM][FN],
+                                              const uint64_t IQP_GLOBAL *__restrict__ ctbits,
+                                              const double IQP_GLOBAL *__restrict__ sq, int64_t ob,
+                                              int64_t jb, int64_t lw, int h, int r, bool active,
+                                              float IQP_GLOBAL *__restrict__ gpart, int64_t m_pad) {
+    float gs[FN];
+#pragma unroll
+    for (int g = 0; g < FN; ++g) gs[g] = 0.0f;
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+        const int64_t k0 = (ob * FM + f) * 32;
+        float q[16];
+#pragma unroll
+        for (int a = 0; a < 16; ++a) q[a] = (float)sq[k0 + acc_row(a, h)];
+#pragma unroll
+        for (int g = 0; g < FN; ++g) {
+            const int64_t j = (jb * FN + g) * 32 + r;
+            const uint64_t cw = ctbits[((j >> 5) * lw + (k0 >> 6)) * 32 + (j & 31)];
+            const uint32_t c32 = (uint32_t)(cw >> (k0 & 63)) >> (4 * h);
+#pragma unroll
+            for (int a = 0; a < 16; ++a)
+                gs[g] += ((c32 >> (8 * (a >> 2) + (a & 3))) & 1u) ? q[a] * acc[f][g][a] : 0.0f;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < FN; ++g) {
+        const int64_t j = (jb * FN + g) * 32 + r;
+        const float v = gs[g] + __shfl_xor(gs[g], 32, 64);
+        if (active && h == 0) gpart[ob * m_pad + j] = v;
+    }
+}
+
+template <int FM, int FN>
+__device__ __forceinline__ void bwd_f16f8_body(const BwdArgs &a, int64_t gu, int tid) {
+    // one sample word: [f][t][lane] FP16 blocks, then [f][q][lane] FP8 blocks,
+    // 16 bytes each; two buffers as in the BF16 form
+    constexpr int kUnits = 6 * FM * 64;
+    __shared__ u32x4 ls0[kUnits], ls1[kUnits];
+    const u32x4 IQP_GLOBAL *__restrict__ shi = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.shi));
+    const u32x4 IQP_GLOBAL *__restrict__ slo = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.slo));
+    const uint64_t IQP_GLOBAL *__restrict__ btbits = gptr(a.btbits);
+    const uint64_t IQP_GLOBAL *__restrict__ ctbits = gptr(a.ctbits);
+    const int64_t m_pad = a.m_pad, sw = a.s_pad / 64, lw = a.l_pad / 64;
+    const int64_t n_jb = m_pad / (32 * FN), n_ob = a.l_pad / (32 * FM);
+    const int64_t n_jbg = ceil_div(n_jb, 4);
+    int64_t jbg, ob, ks;
+    bwd_unit(gu, n_ob, n_jbg, a.obgroup, ob, jbg, ks);
+    const int64_t wps = ceil_div(sw, a.ksplits);
+    const int64_t w0 = ks * wps, w1 = (w0 + wps < sw) ? w0 + wps : sw;
+    float IQP_GLOBAL *__restrict__ gpart = gptr(a.gpart) + ks * n_ob * m_pad;
+    const int64_t jb_raw = jbg * 4 + wave_id();
+    const bool active = jb_raw < n_jb;
+    const int64_t jb = active ? jb_raw : n_jb - 1;
+    const int lane = tid & 63;
+    const int h = lane >> 5, r = lane & 31;
+    const uint32_t ones = in_vgpr(0x3C003C00u);  // +1.0 in FP16, twice
+    const uint32_t m80 = in_vgpr(0x80808080u), c38 = in_vgpr(0x38383838u);
+    const int64_t KTs = sw * 4;
+    const uint64_t IQP_GLOBAL *bbase = btbits + jb * FN * sw * 32;
+    const u32x4 IQP_GLOBAL *sbase_h = shi + ob * FM * KTs * 64;
+    const u32x4 IQP_GLOBAL *sbase_8 = slo + ob * FM * sw * 2 * 64;
+
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int g = 0; g < FN; ++g)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[f][g][e] = 0.0f;
+
+    // staging block b < 4 FM: FP16 limb, f = b / 4, t = b % 4
+    //   <- shi[(f * KTs + 4 w + t) * 64 + ln];
+    // b >= 4 FM: FP8 limb, f = (b - 4 FM) / 2, q = (b - 4 FM) % 2
+    //   <- slo[((f * sw + w) * 2 + q) * 64 + ln]; wave v copies blocks v, v+4, ...
+    const int wv = wave_id();
+    auto stage = [&](int64_t w, u32x4 *dst) {
+#pragma unroll
+        for (int k = 0; k < kUnits / 256; ++k) {
+            const int b = wv + 4 * k;
+            if (b < 4 * FM) {
+                const int t = b & 3, f = b >> 2;
+                dma16(sbase_h + ((int64_t)f * KTs + 4 * w + t) * 64 + lane, &dst[b * 64]);
+            } else {
+                const int f = (b - 4 * FM) >> 1, q = (b - 4 * FM) & 1;
+                dma16(sbase_8 + (((int64_t)f * sw + w) * 2 + q) * 64 + lane, &dst[b * 64]);
+            }
+        }
+    };
+    // every unit has w1 - w0 >= 1 sample words (the host picks the splits)
+    stage(w0, ls0);
+    if (w0 + 1 < w1) stage(w0 + 1, ls1);
+    uint64_t nxt[FN], cur[FN];
+#pragma unroll
+    for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w0) * 32)[r];
+    dma_wait_barrier();
+#pragma unroll
+    for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> (8 * h);
+    if (w0 + 1 < w1) {
+#pragma unroll
+        for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w0 + 1) * 32)[r];
+    }
+    BwdOpsH<FM, FN> opA, opB;
+    BwdLoF8<FM> lo;
+    bwdh_expand_a<FM, FN, 0>(opA, ls0, lane);
+    bwdh_expand_b<FM, FN, 0>(opA, cur, ones);
+    auto word = [&](int64_t w, u32x4 *mine, const u32x4 *other) {
+        bwdh_region<FM, FN, 1>(opA, opB, mine, cur, lane, h, ones, m80, c38, lo, acc);
+        bwdh_region<FM, FN, 2>(opB, opA, mine, cur, lane, h, ones, m80, c38, lo, acc);
+        bwdh_region<FM, FN, 3>(opA, opB, mine, cur, lane, h, ones, m80, c38, lo, acc);
+        dma_wait_barrier();
+        if (w + 2 < w1) stage(w + 2, mine);
+#pragma unroll
+        for (int g = 0; g < FN; ++g) cur[g] = nxt[g] >> (8 * h);
+        if (w + 2 < w1) {
+#pragma unroll
+            for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w + 2) * 32)[r];
+        }
+        // past the last word this expands a stale buffer and is never used
+        bwdh_region<FM, FN, 0>(opB, opA, other, cur, lane, h, ones, m80, c38, lo, acc);
+    };
+    for (int64_t w = w0; w < w1; w += 2) {
+        word(w, ls0, ls1);
+        if (w + 1 < w1) word(w + 1, ls1, ls0);
+    }
+    bwdh_epilogue<FM, FN>(acc, ctbits, gptr(a.sq), ob, jb, lw, h, r, active, gpart, m_pad);
+}
+
+template <int FM, int FN>
+__global__ __launch_bounds__(256, 2) void phase_bwd_f16f8_kernel(BwdArgs a, int64_t units) {
+    const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
+    if (gu >= units) return;  // uniform over the workgroup
+    bwd_f16f8_body<FM, FN>(a, gu, (int)threadIdx.x);
+}
+
+template <int FM, int FN>
+__global__ __launch_bounds__(256, 2) void phase_bwd_f16f8_persistent(
+    const BwdArgs *__restrict__ args, const int64_t *__restrict__ off, int np,
+    unsigned long long *counter) {
+    persistent_loop(off, np, counter,
+                    [&](int p, int64_t u) { bwd_f16f8_body<FM, FN>(args[p], u, opaque_tid()); });
+}
+
 template <int FN>
 constexpr int kI8Waves = FN == 2 ? 2 : 1;
 
@@ -1591,8 +1941,22 @@ static hipError_t bwd_dispatch(const LaunchCtx &lc, int prec, const BwdArgs &a) 
         hipLaunchKernelGGL((phase_bwd_bf16_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a, units);
     else if (prec == 3)
         hipLaunchKernelGGL((phase_bwd_i8_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a, units);
+    else if (prec == 4)
+        hipLaunchKernelGGL((phase_bwd_f16f8_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a,
+                           units);
     else
         hipLaunchKernelGGL((phase_bwd_f32_kernel<FM, FN>), grid, dim3(256), 0, lc.stream, a, units);
+    return hipGetLastError();
+}
+
+// the 128 x 64 wave tile, FP16 + FP8 form only
+template <int FM, int FN>
+static hipError_t bwd_f16f8_dispatch(const LaunchCtx &lc, const BwdArgs &a) {
+    const int64_t units = bwd_units(a, FM, FN);
+    if (units <= 0) return hipSuccess;
+    if (units > kMaxBlocks) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((phase_bwd_f16f8_kernel<FM, FN>), dim3((unsigned)units), dim3(256), 0,
+                       lc.stream, a, units);
     return hipGetLastError();
 }
 
@@ -1604,6 +1968,7 @@ hipError_t launch_phase_bwd(const LaunchCtx &lc, int prec, int fm, int fn, const
     hipError_t e;
     if (fm == 2 && fn == 2) e = bwd_dispatch<2, 2>(lc, prec, a);
     else if (fm == 2 && fn == 4) e = bwd_dispatch<2, 4>(lc, prec, a);
+    else if (fm == 4 && fn == 2 && prec == 4) e = bwd_f16f8_dispatch<4, 2>(lc, a);
     else e = hipErrorInvalidValue;
     timed_end(lc, KF_BWD, ev);
     return e;
@@ -1618,6 +1983,9 @@ static hipError_t bwd_persistent(const LaunchCtx &lc, int prec, const BwdArgs *a
                            lc.stream, args, off, np, counter);
     else if (prec == 3)
         hipLaunchKernelGGL((phase_bwd_i8_persistent<FM, FN>), dim3(grid), dim3(256), 0,
+                           lc.stream, args, off, np, counter);
+    else if (prec == 4)
+        hipLaunchKernelGGL((phase_bwd_f16f8_persistent<FM, FN>), dim3(grid), dim3(256), 0,
                            lc.stream, args, off, np, counter);
     else
         hipLaunchKernelGGL((phase_bwd_f32_persistent<FM, FN>), dim3(grid), dim3(256), 0,
@@ -1634,7 +2002,11 @@ hipError_t launch_phase_bwd_persistent(const LaunchCtx &lc, int prec, int fm, in
     hipError_t e;
     if (fm == 2 && fn == 2) e = bwd_persistent<2, 2>(lc, prec, args, off, np, counter, grid);
     else if (fm == 2 && fn == 4) e = bwd_persistent<2, 4>(lc, prec, args, off, np, counter, grid);
-    else e = hipErrorInvalidValue;
+    else if (fm == 4 && fn == 2 && prec == 4) {
+        hipLaunchKernelGGL((phase_bwd_f16f8_persistent<4, 2>), dim3(grid), dim3(256), 0, lc.stream,
+                           args, off, np, counter);
+        e = hipGetLastError();
+    } else e = hipErrorInvalidValue;
     timed_end(lc, KF_BWD, ev);
     return e;
 }
@@ -1654,6 +2026,13 @@ static int resident_grid(K kernel) {
 int persistent_grid(bool fwd, int prec, int fm, int fn) {
 #define IQP_GRID3(K2, K3, KF) \
     (prec == 1 ? resident_grid(K2) : prec == 3 ? resident_grid(K3) : resident_grid(KF))
+    if (fwd && prec == 4) prec = 1;  // the same forward kernels
+    if (!fwd && prec == 4) {
+        if (fm == 2 && fn == 2) return resident_grid(phase_bwd_f16f8_persistent<2, 2>);
+        if (fm == 2 && fn == 4) return resident_grid(phase_bwd_f16f8_persistent<2, 4>);
+        if (fm == 4 && fn == 2) return resident_grid(phase_bwd_f16f8_persistent<4, 2>);
+        return 0;
+    }
     if (fwd) {
         if (fm == 4 && fn == 4)
             return IQP_GRID3((phase_fwd_bf16_persistent<4, 4, 2>),

@@ -49,8 +49,11 @@ int check_circuit(const iqp_circuit *c);
 
 // The precision forms of the single-problem calls.
 inline bool valid_precision(int p) {
-    return p == IQP_FP32 || p == IQP_SPLIT_BF16 || p == IQP_SPARSE_FP32 || p == IQP_SPLIT3_BF16;
+    return p == IQP_FP32 || p == IQP_SPLIT_BF16 || p == IQP_SPARSE_FP32 || p == IQP_SPLIT3_BF16 ||
+           p == IQP_SPLIT_BF16_FP8;
 }
+// The dense forms (all but the sparse one).
+inline bool dense_precision(int p) { return valid_precision(p) && p != IQP_SPARSE_FP32; }
 
 // ---------------------------------------------------------------------------
 // Workspace plan of one problem: padded extents and the byte offset of every
@@ -89,7 +92,7 @@ int64_t choose_splits(int64_t tiles, int64_t mw);
 // Sample-word splits of the backward for `units` workgroup units, with
 // `wgs_per_cu` of them resident per CU.
 int64_t choose_bsplits(int64_t units, int64_t sw, int wgs_per_cu);
-int bwd_wgs_per_cu(int prec, int bfn);
+int bwd_wgs_per_cu(int prec, int bfm, int bfn);
 
 // Lays out the buffers; tc.splits <= 0 picks the split count.
 void make_plan(Plan &P, const PlanParts &parts, int64_t n, int64_t m, int64_t l, int64_t s,
@@ -167,16 +170,18 @@ inline WeightsArgs weights_args(const Plan &P, const float *phase, void *ws) {
     return WeightsArgs{phase,  at<double>(ws, P.o_coef), P.l, P.s, P.l_pad, P.s_pad, P.prec,
                        at<uint16_t>(ws, P.o_shi), at<uint16_t>(ws, P.o_slo),
                        at<float>(ws, P.o_s32),
-                       P.prec == IQP_SPLIT3_BF16 ? at<int32_t>(ws, P.o_nf) : nullptr};
+                       P.prec == IQP_SPLIT3_BF16 ? at<int32_t>(ws, P.o_nf) : nullptr,
+                       P.prec == IQP_SPLIT_BF16_FP8 ? at<double>(ws, P.o_sq) : nullptr};
 }
 inline BwdArgs bwd_args(const Plan &P, void *ws) {
     const bool fx = P.prec == IQP_SPLIT3_BF16;
+    const bool rs = fx || P.prec == IQP_SPLIT_BF16_FP8;
     return BwdArgs{at<uint16_t>(ws, P.o_shi),    at<uint16_t>(ws, P.o_slo),
                    at<float>(ws, P.o_s32),       at<uint64_t>(ws, P.o_btbits),
                    at<uint64_t>(ws, P.o_ctbits), P.m_pad,
                    P.l_pad,                      P.s_pad,
                    P.tc.bsplits,                 at<float>(ws, P.o_gpart),
-                   fx ? at<double>(ws, P.o_sq) : nullptr,
+                   rs ? at<double>(ws, P.o_sq) : nullptr,
                    fx ? at<int32_t>(ws, P.o_nf) : nullptr,
                    P.tc.obgroup};
 }

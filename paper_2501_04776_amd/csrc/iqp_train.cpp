@@ -364,7 +364,8 @@ int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan 
         return fail(IQP_ERR_INVALID_ARG, "the unbiased estimator needs N >= 2 and s >= 2");
     if (!valid_precision(d.precision))
         return fail(IQP_ERR_INVALID_ARG, "precision must be IQP_FP32, IQP_SPLIT_BF16, "
-                                         "IQP_SPARSE_FP32 or IQP_SPLIT3_BF16");
+                                         "IQP_SPARSE_FP32, IQP_SPLIT3_BF16 or "
+                                         "IQP_SPLIT_BF16_FP8");
     if ((st = check_optimizer(d.optimizer, d.lr, d.beta1, d.beta2, d.eps))) return st;
     if (d.group_precision)
         for (int g = 0; g < d.n_groups; ++g) {
@@ -372,7 +373,8 @@ int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan 
             if (!valid_precision(p))
                 return fail(IQP_ERR_INVALID_ARG, "group_precision[" + std::to_string(g) +
                                                      "] must be IQP_FP32, IQP_SPLIT_BF16, "
-                                                     "IQP_SPARSE_FP32 or IQP_SPLIT3_BF16");
+                                                     "IQP_SPARSE_FP32, IQP_SPLIT3_BF16 or "
+                                                     "IQP_SPLIT_BF16_FP8");
         }
     // gates of each parameter, in gate order
     std::vector<int64_t> offs(d.n_params + 1, 0);

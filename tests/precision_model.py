@@ -2,7 +2,8 @@
 
 The GPU path contracts with rounded operands: 2 theta'_j as FP32 or as BF16
 limbs in the forward, the backward weights S_ki = u_k / s * sin(E_ki) as FP32,
-BF16 limbs or 8-bit fixed-point limbs. Feeding the same rounded operands
+BF16 limbs, a BF16 limb plus a row-scaled FP8 limb, or 8-bit fixed-point
+limbs. Feeding the same rounded operands
 through the FP64 oracle gives the result the arithmetic itself defines, so a
 tolerance can be tied to the form: the gap between this emulation and the
 exact oracle is the form's representation error, and the gap between the GPU
@@ -31,6 +32,30 @@ def bf16_rne(x):
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def e4m3_rne(y):
+    """Round to the nearest OCP FP8 E4M3 value (ties to even), for |y| within
+    its range (at most 448): 4 significant bits, exponent bias 7, subnormal
+    spacing 2^-9. Written from the format's definition."""
+    y = np.asarray(y, dtype=np.float64)
+    a = np.abs(y)
+    _, x = np.frexp(a)                     # a = f 2^x, f in [0.5, 1)
+    e = np.maximum(x - 1, -6)              # binade, clamped to the subnormal one
+    quantum = np.ldexp(1.0, e - 3)
+    r = np.rint(a / quantum) * quantum
+    assert np.all(r <= 448.0), "outside the E4M3 range"
+    return np.copysign(r, y)
+
+
+def fp16_row_exponent(bound):
+    """Per-row scale exponent e_k of the FP16 + FP8 weights: with
+    bound_k = f 2^x, f in [1/2, 1) (frexp), e_k = 15 - x puts bound_k 2^e_k in
+    [2^14, 2^15), clamped to [-120, 120]; 0 for a zero or non-finite bound."""
+    bound = np.asarray(bound, dtype=np.float64)
+    ok = np.isfinite(bound) & (bound > 0)
+    _, x = np.frexp(np.where(ok, bound, 1.0))
+    return np.where(ok, np.clip(15 - x, -120, 120), 0)
+
+
 def two_theta_reduced(theta):
     """2 theta' with theta' = theta - pi * rint(theta / pi) in FP64 (a shift
     by pi is a global phase of the gate, so results do not change)."""
@@ -53,7 +78,7 @@ def theta_represented(prec, theta):
     t = two_theta_reduced(theta)
     if prec in ("fp32", "sparse_fp32"):
         r = t.astype(np.float32).astype(np.float64)
-    elif prec == "split_bf16":
+    elif prec in ("split_bf16", "split_bf16_fp8"):
         r = bf16_limbs(t, 2)
     elif prec == "split3_bf16":
         r = bf16_limbs(t, 3)
@@ -70,6 +95,12 @@ def weights_represented(prec, S, bound):
         return S.astype(np.float32).astype(np.float64)
     if prec == "split_bf16":
         return bf16_limbs(S.astype(np.float32).astype(np.float64), 2)
+    if prec == "split_bf16_fp8":
+        # x = S 2^e_k (exact), FP16 limb rn(x), FP8 limb rn_e4m3(x - rn(x))
+        e = fp16_row_exponent(bound)[:, None]
+        x = np.ldexp(S.astype(np.float32).astype(np.float64), e)
+        hi = x.astype(np.float16).astype(np.float64)
+        return np.ldexp(hi + e4m3_rne(x - hi), -e)
     if prec == "split3_bf16":
         q = np.where(bound > 0, bound / I8X2_MAX, 0.0)[:, None]
         N = np.rint(np.divide(S, q, out=np.zeros_like(S), where=q > 0))

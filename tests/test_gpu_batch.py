@@ -13,7 +13,7 @@ from tests.gpu_util import TOL, DevWorkload, check_grad, wrap
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp32", "split_bf16", "split3_bf16"]
+PRECS = ["fp32", "split_bf16", "split3_bf16", "split_bf16_fp8"]
 
 # (n, m, l, s): tiny to several tiles, ragged in every extent, W = 1 .. 32
 SHAPES = [(5, 40, 3, 70), (70, 1000, 300, 700), (130, 2100, 129, 1025), (2000, 700, 64, 257),
@@ -201,7 +201,7 @@ def test_batch_rejects_shape_mismatch_and_missing_phases():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("prec", ["split_bf16", "split3_bf16"])
+@pytest.mark.parametrize("prec", ["split_bf16", "split3_bf16", "split_bf16_fp8"])
 def test_batched_workload_full_size_sampled(prec):
     # the 64-circuit workload (n in 50..2000, m in 1e3..2e5, l in 100..5000,
     # s = 4096) at full size; the oracle recomputes 3 sampled observables of

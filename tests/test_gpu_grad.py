@@ -12,7 +12,7 @@ from tests.gpu_util import TOL, DevWorkload, check_grad
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp32", "split_bf16", "split3_bf16", "sparse_fp32"]
+PRECS = ["fp32", "split_bf16", "split3_bf16", "split_bf16_fp8", "sparse_fp32"]
 
 
 def _grad(dw, u, prec, saved):
@@ -43,6 +43,39 @@ def test_grad_matches_oracle(prec, saved, shape):
     err, rep = check_grad(prec, g, w, dw.ops01, u, og)
     print("grad %s %s saved=%s: max|d| = %.3g (|g|max %.3g, representation %.3g)" %
           (shape, prec, saved, err, np.abs(og).max(), rep))
+
+
+@pytest.mark.parametrize("tile", [None, "4x2", "2x2"])
+def test_fp16_fp8_weights_match_their_emulation(tile, monkeypatch):
+    """split_bf16_fp8 against the host model of its own operands (theta in
+    two BF16 limbs, weights as FP16 + FP8 limbs per row, tests/precision_model):
+    the gap is the kernels' FP32 phase and accumulation rounding only, a small
+    fraction of what the FP8 limb itself contributes (the model without it),
+    so a mispaired or dropped FP8 product fails. Every backward wave tile of
+    the form; the observable weights span 10 decades, so the row exponents
+    differ."""
+    from tests import precision_model as PM
+    if tile:
+        monkeypatch.setenv("IQP_BWD_TILE", tile)
+    w = W.small_random(8080, 64, 3000, 300, 513)
+    dw = DevWorkload(w)
+    rng = np.random.default_rng(4)
+    u = rng.normal(size=w.l) * 10.0 ** rng.uniform(-5, 5, w.l)
+    g = _grad(dw, u, "split_bf16_fp8", True)
+    emu = PM.grad_emulated(w.n, w.gates, w.theta, dw.ops01, w.samples, u, "split_bf16_fp8")
+    # the same without the FP8 limb
+    th = PM.theta_represented("split_bf16_fp8", w.theta)
+    _, _, ph = oracle.expval(w.n, w.gates, th, dw.ops01, w.samples, phases=True)
+    S = (u[:, None] / w.s) * np.sin(ph)
+    e = PM.fp16_row_exponent(np.abs(u) / w.s)[:, None]
+    S16 = np.ldexp(np.ldexp(S.astype(np.float32).astype(np.float64), e).astype(np.float16)
+                   .astype(np.float64), -e)
+    C = oracle.parity(w.n, dw.ops01, w.gates).astype(np.float64)
+    B = 1.0 - 2.0 * oracle.parity(w.n, w.samples, w.gates).astype(np.float64)
+    no_lo = -2.0 * (C * (S16 @ B)).sum(axis=0)
+    gap, lo = np.abs(g - emu).max(), np.abs(no_lo - emu).max()
+    print("fp16+fp8 tile %s: |gpu - model| %.3g, FP8 limb's share %.3g" % (tile, gap, lo))
+    assert gap < 0.1 * lo, (gap, lo)
 
 
 @pytest.mark.parametrize("prec", PRECS)

@@ -11,7 +11,7 @@ from tests.gpu_util import TOL, DevWorkload, dev_rows_from_dense, dev_rows_from_
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp32", "split_bf16", "split3_bf16", "sparse_fp32"]
+PRECS = ["fp32", "split_bf16", "split3_bf16", "split_bf16_fp8", "sparse_fp32"]
 
 
 def _unpack_tiled(out, R, C):

@@ -14,7 +14,7 @@ from tests.gpu_util import TOL
 
 pytestmark = pytest.mark.gpu
 
-PRECS = ["fp32", "split_bf16", "split3_bf16", "sparse_fp32"]
+PRECS = ["fp32", "split_bf16", "split3_bf16", "split_bf16_fp8", "sparse_fp32"]
 
 
 def step_t(v):

@@ -15,7 +15,7 @@ import oracle
 import workloads as W
 from tests import precision_model as PM
 
-TOL = {"fp32": 1e-5, "split_bf16": 1e-4, "split3_bf16": 1e-4}
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4, "split3_bf16": 1e-4, "split_bf16_fp8": 1e-4}
 
 
 def test_bf16_rne_matches_torch_conversion():
@@ -25,6 +25,43 @@ def test_bf16_rne_matches_torch_conversion():
     x32 = x.astype(np.float32)
     ref = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(PM.bf16_rne(x32), ref)
+
+
+def test_e4m3_rounding_matches_torch_conversion():
+    """The FP8 limb's rounding against torch's float8_e4m3fn conversion
+    (round to nearest even), over normal, subnormal and tie values."""
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.normal(size=50000) * 10.0 ** rng.integers(-4, 3, 50000),
+                        rng.uniform(-2.0 ** -6, 2.0 ** -6, 5000),
+                        (np.arange(-64, 65) + 0.5) * 2.0 ** -9,   # subnormal ties
+                        [0.0, -0.0, 448.0, -448.0, 17.0, 18.0, 19.0, 2.0 ** -9, 2.0 ** -10]])
+    x = x[np.abs(x) <= 448.0].astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(PM.e4m3_rne(x.astype(np.float64)), ref)
+
+
+def test_fp16_fp8_weights_keep_15_bits():
+    """Row exponent and the two limbs: bound 2^e in [2^14, 2^15), FP16 limb
+    within FP16's range, rest within 8 (half an FP16 ulp at 2^15) and the
+    represented weight within 2^-15 of the row bound's scale plus the FP8
+    rounding of the rest (2^-4 relative, 2^-10 absolute below 2^-6)."""
+    rng = np.random.default_rng(8)
+    bound = 10.0 ** rng.uniform(-12, 6, 300)
+    e = PM.fp16_row_exponent(bound)
+    sc = np.ldexp(bound, e)
+    assert np.all((sc >= 2.0 ** 14) & (sc < 2.0 ** 15))
+    S = (rng.uniform(-1, 1, (300, 500)) * bound[:, None]) ** 1
+    S[:, :50] *= 10.0 ** rng.uniform(-9, 0, (300, 50))      # small weights too
+    x = np.ldexp(S.astype(np.float32).astype(np.float64), e[:, None])
+    hi = x.astype(np.float16).astype(np.float64)
+    rest = x - hi
+    assert np.all(np.abs(rest) <= 8.0)
+    rep = PM.weights_represented("split_bf16_fp8", S, bound)
+    err = np.abs(np.ldexp(rep, e[:, None]) - x)
+    assert np.all(err <= np.maximum(2.0 ** -4 * np.abs(rest), 2.0 ** -10) + 1e-300)
+    assert np.all(err <= 2.0 ** -15 * np.abs(x) + 2.0 ** -10)
+    assert PM.fp16_row_exponent(np.array([0.0]))[0] == 0
+    assert PM.fp16_row_exponent(np.array([np.inf]))[0] == 0
 
 
 def test_limbs_shrink_the_residual():
@@ -55,7 +92,7 @@ def test_emulation_without_rounding_is_the_oracle(hard_case):
 def test_each_form_against_its_bar(hard_case):
     w, ops01, u, og = hard_case
     errs = {}
-    for prec in ("fp32", "split_bf16", "split3_bf16"):
+    for prec in ("fp32", "split_bf16", "split3_bf16", "split_bf16_fp8"):
         g = PM.grad_emulated(w.n, w.gates, w.theta, ops01, w.samples, u, prec)
         errs[prec] = np.abs(g - og).max() / (TOL[prec] * max(1.0, np.abs(og).max()))
     print("emulated gradient error / bar:", errs)
@@ -65,6 +102,8 @@ def test_each_form_against_its_bar(hard_case):
     # two BF16 limbs of theta (16 significant bits) do not, by their own
     # arithmetic: the residual of every gate repeats in all samples' phases
     assert 0.8 < errs["split_bf16"] < 1.6
+    # the FP16 + FP8 weights leave that as it is
+    assert abs(errs["split_bf16_fp8"] - errs["split_bf16"]) < 0.1
 
 
 def test_two_limb_theta_is_the_dominant_term(hard_case):
@@ -83,12 +122,18 @@ def test_two_limb_theta_is_the_dominant_term(hard_case):
     e_theta = np.abs(g_theta - og).max() / bar
     e_s = np.abs(g_s - og).max() / bar
     assert e_theta > 0.8 and e_s < 0.1, (e_theta, e_s)
+    # FP16 + FP8 weights (15 significant bits per weight) also stay a small
+    # fraction of the bar, within twice the error of two BF16 limbs
+    S8 = PM.weights_represented("split_bf16_fp8", (u[:, None] / w.s) * np.sin(ph),
+                                np.abs(u) / w.s)
+    e_s8 = np.abs(-2.0 * (C * (S8 @ B)).sum(axis=0) - og).max() / bar
+    assert e_s8 < 0.1 and e_s8 < 2.0 * e_s + 0.01, (e_s8, e_s)
 
 
 def test_means_of_every_form_within_tolerance(hard_case):
     w, ops01, _, _ = hard_case
     m0, _ = oracle.expval(w.n, w.gates, w.theta, ops01, w.samples)
-    for prec in ("fp32", "split_bf16", "split3_bf16"):
+    for prec in ("fp32", "split_bf16", "split3_bf16", "split_bf16_fp8"):
         th = PM.theta_represented(prec, w.theta)
         m, _ = oracle.expval(w.n, w.gates, th, ops01, w.samples)
         assert np.abs(m - m0).max() < 0.25 * TOL[prec], prec
