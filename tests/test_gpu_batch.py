@@ -162,8 +162,10 @@ def test_deterministic_repeat_with_work_queue():
     plan.close()
 
 
-def test_tuner_picks_a_configuration_and_records_it():
-    prec = "split_bf16"
+@pytest.mark.parametrize("prec", ["split_bf16", "split_bf16_fp8"])
+def test_tuner_picks_a_configuration_and_records_it(prec):
+    # (the 128 x 64 backward tile exists for the FP16 + FP8 weights only)
+    bwd_tiles = [(2, 2), (2, 4)] + ([(4, 2)] if prec == "split_bf16_fp8" else [])
     ws = _workloads(seed=41, shapes=SHAPES[1:5])
     dws = [DevWorkload(w) for w in ws]
     plan = _plan(dws, prec)
@@ -172,7 +174,7 @@ def test_tuner_picks_a_configuration_and_records_it():
     plan.expval()  # phases for the backward timings
     cfg = plan.tune([torch.from_numpy(u).cuda() for u in us])
     assert cfg["tuned"] and cfg["fwd_tile"] in [(4, 4), (2, 4), (2, 2)]
-    assert cfg["bwd_tile"] in [(2, 2), (2, 4)] and cfg["fwd_split"] in [0, 1, 2]
+    assert cfg["bwd_tile"] in bwd_tiles and cfg["fwd_split"] in [0, 1, 2]
     plan.expval()
     _check_forward(plan, ws, dws, prec)
     plan.expval_grad([torch.from_numpy(u).cuda() for u in us])
