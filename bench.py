@@ -42,9 +42,11 @@ METRIC = "phase terms/s (ops×samples×gates), fwd & fwd+bwd, split-BF16 vs FP32
 # per phase term). The algorithmic work is one multiply-add, 2 flops, per term
 # in every form; split-BF16 issues two BF16 products (hi and lo limb) per term.
 PEAK = {"split_bf16": (2.5e15, 4.0), "fp32": (157.3e12, 2.0),
-        # three BF16 limbs of theta in the forward; two INT8 limbs of the
-        # backward weights against the dense INT8 peak (5.0 POP/s)
-        "split3_bf16_fwd": (2.5e15, 6.0), "split3_bf16_bwd": (5.0e15, 4.0),
+        # two BF16 limbs and one FP8 limb of theta in the forward (the FP8
+        # product at twice the BF16 rate: 5 BF16-equivalent flops per term);
+        # two INT8 limbs of the backward weights against the dense INT8 peak
+        # (5.0 POP/s)
+        "split3_bf16_fwd": (2.5e15, 5.0), "split3_bf16_bwd": (5.0e15, 4.0),
         # FP16 limb (2 flops) and FP8 limb (2 flops at twice the rate) of the
         # backward weights: 3 FP16-equivalent flops against the FP16 peak
         "split_bf16_fp8_bwd": (2.5e15, 3.0)}
@@ -280,7 +282,7 @@ def main():
     dom = max(("phase_fwd", "phase_bwd"), key=lambda k: kb.get(k, {}).get("avg_ms", 0.0))
     result["roofline"] = roofline(T, kb[dom]["avg_ms"], dom, recorded_traffic(w.name, dom))
 
-    # --- three BF16 limbs of theta, fixed-point weights on the INT8 cores ----
+    # --- theta in two BF16 limbs and an FP8 one, fixed-point weights on INT8 -
     if not args.no_split3:
         ms3 = timed("split3_bf16")
         ms3f = timed("split3_bf16", fwd_only=True)
@@ -289,7 +291,7 @@ def main():
         result["split3_bf16"] = {
             "fwd_bwd_terms_per_s": T / (ms3 * 1e-3), "fwd_terms_per_s": T / (ms3f * 1e-3),
             "ms_per_step": ms3, "fwd_ms": ms3f, "kernels": kb3,
-            "roofline_fwd": roofline(T, kb3["phase_fwd"]["avg_ms"], "phase_fwd (3 BF16 limbs)",
+            "roofline_fwd": roofline(T, kb3["phase_fwd"]["avg_ms"], "phase_fwd (2 BF16 + 1 FP8 limbs)",
                                      recorded_traffic(w.name, "split3_bf16.phase_fwd"),
                                      "split3_bf16_fwd"),
             "roofline_bwd": roofline(T, kb3["phase_bwd"]["avg_ms"], "phase_bwd (INT8 limbs)",
@@ -850,14 +852,15 @@ def main_batch(args):
     plan.close()
     del plan
 
-    # three BF16 limbs of theta, fixed-point weights on the INT8 matrix cores
+    # theta in two BF16 limbs and an FP8 one, fixed-point weights on the INT8
+    # matrix cores
     if not args.no_split3:
         p3 = make_plan("split3_bf16")
         ms3 = timed(p3)
         ms3f = timed(p3, fwd_only=True)
         log("split3_bf16 batched: fwd+bwd %.3f ms, fwd %.3f ms" % (ms3, ms3f))
         kb3 = kernel_times(p3, max(2, min(args.steps, 4)))
-        fwd3 = roofline(T, kb3["phase_fwd"]["avg_ms"], "phase_fwd (persistent, 3 BF16 limbs)",
+        fwd3 = roofline(T, kb3["phase_fwd"]["avg_ms"], "phase_fwd (persistent, 2 BF16 + 1 FP8 limbs)",
                         recorded_traffic(name, "split3_bf16.phase_fwd"), "split3_bf16_fwd")
         bwd3 = roofline(T, kb3["phase_bwd"]["avg_ms"], "phase_bwd (persistent, INT8 limbs)",
                         recorded_traffic(name, "split3_bf16.phase_bwd"), "split3_bf16_bwd")

@@ -60,9 +60,12 @@ typedef enum {
  *                    with many anticommuting gates and many weighted
  *                    observables the gradient can exceed 1e-4 * max(1, |g|).
  *                    The backward weights S (below) are hi + lo BF16 too.
- *   IQP_SPLIT3_BF16: 2 theta_j = hi + mid + lo, three BF16 limbs (24
- *                    significant bits, the precision of FP32), three BF16
- *                    products per term in the forward, FP32 accumulation.
+ *   IQP_SPLIT3_BF16: 2 theta_j = hi + mid + lo: hi and mid BF16 limbs, lo the
+ *                    FP8 E4M3 rounding of what they leave, scaled by 2^20
+ *                    (the product's scale operand takes it back); error at
+ *                    most 2^-20 |2 theta_j| + 2^-30. Per term two BF16
+ *                    products and one FP8 product (at twice the BF16 rate)
+ *                    in the forward, FP32 accumulation.
  *                    The backward weights S_ki = dL/dcos(E_ki) sin(E_ki) are
  *                    held in 16-bit fixed point per observable,
  *                    S_ki ~ q_k (256 d1_ki + d0_ki) with signed 8-bit limbs,

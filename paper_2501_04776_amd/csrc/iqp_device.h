@@ -16,6 +16,7 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 // 2 pi split for a two-step Cody-Waite reduction (Cody & Waite, 1980):

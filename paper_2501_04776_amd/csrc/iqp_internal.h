@@ -10,6 +10,8 @@ namespace iqp {
 
 // Every extent the kernels tile over is padded to a multiple of this.
 constexpr int64_t kPad = 128;
+// IQP_SPLIT3_BF16: the third theta limb is E4M3(rest * 2^kLo8Exp)
+constexpr int kLo8Exp = 20;
 
 // Work slots of one MI355X at one wave per SIMD: 256 CUs x 4 SIMDs.
 constexpr int64_t kWaveSlots = 1024;

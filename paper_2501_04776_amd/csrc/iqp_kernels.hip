@@ -28,8 +28,25 @@
 #include "iqp_device.h"
 
 #include <math.h>
+#include <type_traits>
 
 namespace iqp {
+
+// OCP FP8 E4M3 (bias 7, 3 mantissa bits, no infinities) of a float, rounded
+// to nearest even; |y| must be below 464 (the first value that would round
+// past 448). Non-finite input gives the NaN code.
+__device__ __forceinline__ uint32_t f32_to_e4m3(float y) {
+    const uint32_t u = __float_as_uint(y);
+    const uint32_t sgn = (u >> 24) & 0x80u;
+    const uint32_t a = u & 0x7FFFFFFFu;
+    if (a >= 0x7F800000u) return sgn | 0x7Fu;
+    if (a < 0x3C800000u)  // below 2^-6: the subnormal grid of step 2^-9 (8 = 2^-6)
+        return sgn | (uint32_t)rintf(__uint_as_float(a) * 512.0f);
+    // keep 3 of the 23 mantissa bits, ties to even on the 20 dropped ones; a
+    // carry moves into the exponent; rebias 127 -> 7
+    const uint32_t r = a + 0x7FFFFu + ((a >> 20) & 1u);
+    return sgn | ((r >> 20) - (120u << 3));
+}
 
 // ---------------------------------------------------------------------------
 // theta_prep
@@ -50,8 +67,17 @@ __device__ __forceinline__ void theta_prep_body(const ThetaArgs &a, int64_t blk)
         if (a.prec != 3) {
             gptr(a.lo)[i] = l;
         } else {
+            // third limb: E4M3 of the rest times 2^kLo8Exp (|rest| <= 2^-16 pi,
+            // so below 2^kLo8Exp * 4.8e-5 ~ 50), the product scaled back by
+            // 2^-kLo8Exp; one byte per gate, stored per 64-gate word in the
+            // order the forward's lanes read it: byte 32 h + 8 t + e holds
+            // gate 16 t + 8 h + e of the word
             gptr(a.mid)[i] = l;
-            gptr(a.lo)[i] = f2bf_rne((float)(rem - (double)bf2f(l)));
+            const double rest = rem - (double)bf2f(l);
+            const int64_t gw = i & 63;
+            const int64_t dst = (i - gw) + ((gw >> 3) & 1) * 32 + (gw >> 4) * 8 + (gw & 7);
+            reinterpret_cast<uint8_t IQP_GLOBAL *>(gptr(a.lo))[dst] =
+                (uint8_t)f32_to_e4m3((float)ldexp(rest, kLo8Exp));
         }
     } else {
         // split by gate parity: lane half h of the 32x32x2 product reads gate 2t + h
@@ -297,6 +323,30 @@ __device__ __forceinline__ void expand_masked(uint32_t x16, const u32x4 (&th)[NL
     for (int L = 0; L < NL; ++L) out[L] = __builtin_bit_cast(bf16x8, d[L]);
 }
 
+// The same with an FP8 third limb (IQP_SPLIT3_BF16): the two 16-bit-lane masks
+// of gates (2v, 2v+1) and (2v+2, 2v+3) give, by one byte permute (their low
+// bytes), the byte mask of those four gates, applied to the limb's bytes l8
+// (dword u: gates 4u .. 4u+3 of the K-step).
+template <int NL>
+__device__ __forceinline__ void expand_masked_f8(uint32_t x16, const u32x4 (&th)[NL],
+                                                 bf16x8 (&out)[NL], uint32_t l0, uint32_t l1,
+                                                 uint32_t &a0, uint32_t &a1) {
+    const u16x2 xv = {(unsigned short)x16, (unsigned short)x16};
+    uint32_t d[NL][4], msk[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const u16x2 sh = {(unsigned short)(15 - 2 * v), (unsigned short)(14 - 2 * v)};
+        const s16x2 sg = __builtin_bit_cast(s16x2, (u16x2)(xv << sh)) >> (s16x2){15, 15};
+        msk[v] = __builtin_bit_cast(uint32_t, sg);
+#pragma unroll
+        for (int L = 0; L < NL; ++L) d[L][v] = th[L][v] & msk[v];
+    }
+#pragma unroll
+    for (int L = 0; L < NL; ++L) out[L] = __builtin_bit_cast(bf16x8, d[L]);
+    a0 = __builtin_amdgcn_perm(msk[1], msk[0], 0x06040200u) & l0;
+    a1 = __builtin_amdgcn_perm(msk[3], msk[2], 0x06040200u) & l1;
+}
+
 // c_kj in {0, 1}: 1.0 = 0x3F80.
 __device__ __forceinline__ bf16x8 expand_01(uint32_t x16) {
     const u16x2 xv = {(unsigned short)x16, (unsigned short)x16};
@@ -372,41 +422,92 @@ __device__ __forceinline__ void interleave_half() {
 }
 
 // Operands of one K-step: the +-1 B fragments and the masked theta limb A
-// fragments (limb 0 = hi, then lo, or mid and lo with three limbs).
+// fragments (limb 0 = hi, limb 1 = lo, or mid when an FP8 limb follows).
 template <int FM, int FN, int NL>
 struct FwdOps {
     bf16x8 bv[FN], a[NL][FM];
 };
 
-template <int FM, int FN, int NL, int T>
+// Third theta limb in FP8 (IQP_SPLIT3_BF16): per 64-gate word one 32x32x64
+// FP8 product per block, A = the limb's bytes masked by C, B = +-1.0 in
+// E4M3, both built per K-step from the BF16 operands (two dwords, 8 gates,
+// per K-step and row or column block): lane half h holds gates 16 t + 8 h +
+// e of K-step t in bytes 8 t + e, the order the limb is stored in, so A and
+// B pair the same gate in every lane and byte. l8: the word's limb bytes of
+// the lane's half.
+template <int FM, int FN>
+struct F8Ops {
+    uint32_t a[FM][8], b[FN][8], l8[8];
+    uint32_t m80, c38;  // the E4M3 sign mask and +1.0, in vector registers
+};
+template <int FM, int FN, bool F8>
+using F8State = typename std::conditional<F8, F8Ops<FM, FN>, char>::type;
+
+template <int FM, int FN, int NL, int T, bool F8>
 __device__ __forceinline__ void fwd_expand_b(FwdOps<FM, FN, NL> &o, const uint64_t (&bw)[FN],
-                                             uint32_t ones) {
+                                             uint32_t ones, F8State<FM, FN, F8> &e8) {
 #pragma unroll
     for (int g = 0; g < FN; ++g) {
         const uint32_t d = (uint32_t)(bw[g] >> (32 * (T >> 1)));
         o.bv[g] = expand_pm1((T & 1) ? (d >> 16) : d, ones);
+        if constexpr (F8) {
+            // the high bytes of the +-1 BF16 pairs (0x3F / 0xBF) -> 0x38 / 0xB8
+            const u32x4 q = __builtin_bit_cast(u32x4, o.bv[g]);
+            e8.b[g][2 * T] = (__builtin_amdgcn_perm(q[1], q[0], 0x07050301u) & e8.m80) | e8.c38;
+            e8.b[g][2 * T + 1] =
+                (__builtin_amdgcn_perm(q[3], q[2], 0x07050301u) & e8.m80) | e8.c38;
+        }
     }
 }
 
-template <int FM, int FN, int NL, int T>
+template <int FM, int FN, int NL, int T, bool F8>
 __device__ __forceinline__ void fwd_expand_a(FwdOps<FM, FN, NL> &o, const uint64_t (&cw)[FM],
-                                             const u32x4 (&th)[NL]) {
+                                             const u32x4 (&th)[NL], F8State<FM, FN, F8> &e8) {
 #pragma unroll
     for (int f = 0; f < FM; ++f) {
         const uint32_t d = (uint32_t)(cw[f] >> (32 * (T >> 1)));
         bf16x8 x[NL];
-        expand_masked<NL>((T & 1) ? (d >> 16) : d, th, x);
+        if constexpr (F8)
+            expand_masked_f8<NL>((T & 1) ? (d >> 16) : d, th, x, e8.l8[2 * T], e8.l8[2 * T + 1],
+                                 e8.a[f][2 * T], e8.a[f][2 * T + 1]);
+        else
+            expand_masked<NL>((T & 1) ? (d >> 16) : d, th, x);
 #pragma unroll
         for (int L = 0; L < NL; ++L) o.a[L][f] = x[L];
     }
 }
 
-template <int FM, int FN, int NL, int T>
+template <int FM, int FN, int NL, int T, bool F8>
 __device__ __forceinline__ void fwd_expand(FwdOps<FM, FN, NL> &o, const uint64_t (&cw)[FM],
                                            const uint64_t (&bw)[FN], const u32x4 (&th)[NL],
-                                           uint32_t ones) {
-    fwd_expand_b<FM, FN, NL, T>(o, bw, ones);
-    fwd_expand_a<FM, FN, NL, T>(o, cw, th);
+                                           uint32_t ones, F8State<FM, FN, F8> &e8) {
+    fwd_expand_b<FM, FN, NL, T, F8>(o, bw, ones, e8);
+    fwd_expand_a<FM, FN, NL, T, F8>(o, cw, th, e8);
+}
+
+// the word's FP8 limb bytes of the lane's half (two 16-byte units)
+template <int FM, int FN>
+__device__ __forceinline__ void fwd_load_l8(F8Ops<FM, FN> &e8, const u32x4 *T8, int o8) {
+    const u32x4 p0 = T8[o8], p1 = T8[o8 + 1];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        e8.l8[i] = p0[i];
+        e8.l8[4 + i] = p1[i];
+    }
+}
+
+// the word's FP8 products, scaled by 2^-kLo8Exp
+template <int FM, int FN>
+__device__ __forceinline__ void fwd_mfma_f8(const F8Ops<FM, FN> &e8, f32x16 (&acc)[FM][FN]) {
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int g = 0; g < FN; ++g) {
+            const i32x8 a = __builtin_bit_cast(i32x8, e8.a[f]);
+            const i32x8 b = __builtin_bit_cast(i32x8, e8.b[g]);
+            acc[f][g] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc[f][g], 0, 0, 0,
+                                                                        127 - kLo8Exp, 0, 127);
+        }
 }
 
 template <int FM, int FN, int NL, int LIMB>
@@ -431,24 +532,31 @@ __device__ __forceinline__ void fwd_theta(u32x4 (&th)[NL], const u32x4 *const (&
 // operands of K-step T1 (theta limbs at offset `off`) are expanded into `nxt`.
 // The products of each limb run as one pass over all accumulators, so two
 // products into the same accumulator are always a full pass apart.
-template <int FM, int FN, int NL, int T1>
+// With the FP8 third limb, region 0 (whose expansion starts the next word)
+// first issues the finished word's FP8 products and reads the next word's
+// limb bytes (at o8).
+template <int FM, int FN, int NL, int T1, bool F8>
 __device__ __forceinline__ void fwd_region(const FwdOps<FM, FN, NL> &cur, FwdOps<FM, FN, NL> &nxt,
                                            const uint64_t (&cw)[FM], const uint64_t (&bw)[FN],
                                            const u32x4 *const (&Tp)[NL], int off, uint32_t ones,
-                                           f32x16 (&acc)[FM][FN]) {
+                                           f32x16 (&acc)[FM][FN], F8State<FM, FN, F8> &e8,
+                                           const u32x4 *T8, int o8) {
     u32x4 th[NL];
     fwd_theta<NL>(th, Tp, off);
-    fwd_expand_b<FM, FN, NL, T1>(nxt, bw, ones);
-    fwd_mfma_limb<FM, FN, NL, 0>(cur, acc);
-    interleave_half<NL, FM * FN, 8 * FN + 4>();
-    fwd_expand_a<FM, FN, NL, T1>(nxt, cw, th);
-    fwd_mfma_limb<FM, FN, NL, 1>(cur, acc);
-    if constexpr (NL == 3) {
-        fwd_mfma_limb<FM, FN, NL, 2>(cur, acc);
-        interleave_half<0, 2 * FM * FN, 20 * FM + 4>();
-    } else {
-        interleave_half<0, FM * FN, 16 * FM + 4>();
+    if constexpr (F8) {
+        if constexpr (T1 == 0) {
+            fwd_mfma_f8<FM, FN>(e8, acc);
+            fwd_load_l8<FM, FN>(e8, T8, o8);
+        }
     }
+    fwd_expand_b<FM, FN, NL, T1, F8>(nxt, bw, ones, e8);
+    fwd_mfma_limb<FM, FN, NL, 0>(cur, acc);
+    constexpr int kF8M = (F8 && T1 == 0) ? FM * FN : 0;
+    constexpr int kF8V = F8 ? 4 * FN : 0;
+    interleave_half<NL + (F8 && T1 == 0 ? 2 : 0), FM * FN + kF8M, 8 * FN + 4 + kF8V>();
+    fwd_expand_a<FM, FN, NL, T1, F8>(nxt, cw, th, e8);
+    fwd_mfma_limb<FM, FN, NL, 1>(cur, acc);
+    interleave_half<0, FM * FN, 16 * FM + 4 + (F8 ? 4 * FM : 0)>();
 }
 
 // Decomposition shared by both forward kernels.
@@ -487,18 +595,21 @@ __device__ __forceinline__ void store_tile(const f32x16 (&acc)[FM][FN], float IQ
         }
 }
 
-// NL = 2 (IQP_SPLIT_BF16 and IQP_SPLIT_BF16_FP8: hi, lo) or 3 (IQP_SPLIT3_BF16:
-// hi, mid, lo).
-template <int FM, int FN, int NL>
+// NL = 2: IQP_SPLIT_BF16 and IQP_SPLIT_BF16_FP8 (hi, lo), or IQP_SPLIT3_BF16
+// with F8 (hi, mid in BF16; the third limb in FP8).
+template <int FM, int FN, int NL, bool F8>
 __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int tid) {
-    // per word 8 units of 16 bytes per limb: K-step t, half h at 2t + h
+    // per word 8 units of 16 bytes per limb: K-step t, half h at 2t + h; the
+    // FP8 limb 4 units per word: half h at 2h, 2h + 1
     __shared__ u32x4 lt[NL][2][kChunkWords * 8];
+    __shared__ u32x4 lt8[F8 ? 2 : 1][F8 ? kChunkWords * 4 : 1];
     const uint64_t IQP_GLOBAL *__restrict__ cbits = gptr(a.cbits);
     const uint64_t IQP_GLOBAL *__restrict__ bbits = gptr(a.bbits);
     const u32x4 IQP_GLOBAL *thp[NL];
+    static_assert(NL == 2, "two BF16 limbs, the second lo or (with F8) mid");
     thp[0] = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.thh));
-    thp[NL - 1] = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.thl));
-    if constexpr (NL == 3) thp[1] = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.thm));
+    thp[1] = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(F8 ? a.thm : a.thl));
+    const u32x4 IQP_GLOBAL *th8 = reinterpret_cast<const u32x4 IQP_GLOBAL *>(gptr(a.thl));
     float IQP_GLOBAL *__restrict__ E = gptr(a.E);
     const int64_t l_pad = a.l_pad, s_pad = a.s_pad, mw = a.m_pad / 64;
     const int64_t n_ob = l_pad / (32 * FM), n_sb = s_pad / (32 * FN);
@@ -529,6 +640,11 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int 
 #pragma unroll
             for (int L = 0; L < NL; ++L) dma16(thp[L] + src, &lt[L][buf][wv * 64]);
         }
+        if constexpr (F8) {
+            // the FP8 limb: wave v copies units [32 v, 32 v + 32) with lanes 0..31
+            const int64_t s8 = cw0 * 4 + wv * 32 + lane;
+            if (lane < 32 && s8 < U.w1 * 4) dma16(th8 + s8, &lt8[buf][wv * 32]);
+        }
     };
     if (nchunks > 0) stage(U.w0, 0);
     uint64_t nxt_c[FM], nxt_b[FN], cur_c[FM], cur_b[FN];
@@ -540,6 +656,11 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int 
     }
     dma_wait_barrier();
     FwdOps<FM, FN, NL> opA, opB;
+    F8State<FM, FN, F8> e8;
+    if constexpr (F8) {
+        e8.m80 = in_vgpr(0x80808080u);
+        e8.c38 = in_vgpr(0x38383838u);
+    }
     for (int64_t c = 0; c < nchunks; ++c) {
         const int buf = (int)(c & 1);
         const int64_t cw0 = U.w0 + c * kChunkWords;
@@ -548,7 +669,9 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int 
         const u32x4 *Tp[NL];
 #pragma unroll
         for (int L = 0; L < NL; ++L) Tp[L] = lt[L][buf] + h;
-        // K-step 0 of the chunk's first word
+        const u32x4 *T8 = lt8[F8 ? buf : 0] + 2 * h;
+        // K-step 0 of the chunk's first word (with the FP8 limb, the previous
+        // chunk's last word has issued its FP8 products in its region 0)
 #pragma unroll
         for (int f = 0; f < FM; ++f) cur_c[f] = nxt_c[f] >> (8 * h);
 #pragma unroll
@@ -556,7 +679,8 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int 
         {
             u32x4 th[NL];
             fwd_theta<NL>(th, Tp, 0);
-            fwd_expand<FM, FN, NL, 0>(opA, cur_c, cur_b, th, ones);
+            if constexpr (F8) fwd_load_l8<FM, FN>(e8, T8, 0);
+            fwd_expand<FM, FN, NL, 0, F8>(opA, cur_c, cur_b, th, ones, e8);
         }
         for (int64_t w = cw0; w < cw1; ++w) {
             const int o = (int)(w - cw0) * 8;
@@ -567,9 +691,9 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int 
                 for (int g = 0; g < FN; ++g) nxt_b[g] = (bbase + (g * mw + w + 1) * 32)[r];
             }
             // region t: products of K-step t, expansion of K-step t+1
-            fwd_region<FM, FN, NL, 1>(opA, opB, cur_c, cur_b, Tp, o + 2, ones, acc);
-            fwd_region<FM, FN, NL, 2>(opB, opA, cur_c, cur_b, Tp, o + 4, ones, acc);
-            fwd_region<FM, FN, NL, 3>(opA, opB, cur_c, cur_b, Tp, o + 6, ones, acc);
+            fwd_region<FM, FN, NL, 1, F8>(opA, opB, cur_c, cur_b, Tp, o + 2, ones, acc, e8, T8, 0);
+            fwd_region<FM, FN, NL, 2, F8>(opB, opA, cur_c, cur_b, Tp, o + 4, ones, acc, e8, T8, 0);
+            fwd_region<FM, FN, NL, 3, F8>(opA, opB, cur_c, cur_b, Tp, o + 6, ones, acc, e8, T8, 0);
             // K-step 0 of word w+1, unconditionally so that it interleaves with
             // the products below: past the chunk's last word it reads inside
             // the chunk's buffer and is recomputed after the barrier
@@ -578,7 +702,8 @@ __device__ __forceinline__ void fwd_bf16_body(const FwdArgs &a, int64_t gu, int 
             for (int f = 0; f < FM; ++f) cur_c[f] = nxt_c[f] >> (8 * h);
 #pragma unroll
             for (int g = 0; g < FN; ++g) cur_b[g] = nxt_b[g] >> (8 * h);
-            fwd_region<FM, FN, NL, 0>(opB, opA, cur_c, cur_b, Tp, on, ones, acc);
+            fwd_region<FM, FN, NL, 0, F8>(opB, opA, cur_c, cur_b, Tp, on, ones, acc, e8, T8,
+                                          on / 2);
         }
         dma_wait_barrier();
     }
@@ -703,12 +828,13 @@ __device__ __forceinline__ void fwd_f32_body(const FwdArgs &a, int64_t gu, int t
 }
 
 // Plain launch: one workgroup per unit, units spread over the XCDs in
-// contiguous ranges.
+// contiguous ranges. NL = number of theta limbs: 2 (BF16 hi, lo) or 3 (BF16
+// hi, mid and the FP8 third limb).
 template <int FM, int FN, int NL>
 __global__ __launch_bounds__(256, 1) void phase_fwd_bf16_kernel(FwdArgs a, int64_t units) {
     const int64_t gu = xcd_remap(blockIdx.x, gridDim.x);
     if (gu >= units) return;  // uniform over the workgroup
-    fwd_bf16_body<FM, FN, NL>(a, gu, (int)threadIdx.x);
+    fwd_bf16_body<FM, FN, 2, NL == 3>(a, gu, (int)threadIdx.x);
 }
 
 template <int FM, int FN>
@@ -724,7 +850,9 @@ __global__ __launch_bounds__(256, 1) void phase_fwd_bf16_persistent(
     const FwdArgs *__restrict__ args, const int64_t *__restrict__ off, int np,
     unsigned long long *counter) {
     persistent_loop(off, np, counter,
-                    [&](int p, int64_t u) { fwd_bf16_body<FM, FN, NL>(args[p], u, opaque_tid()); });
+                    [&](int p, int64_t u) {
+                        fwd_bf16_body<FM, FN, 2, NL == 3>(args[p], u, opaque_tid());
+                    });
 }
 
 template <int FM, int FN>
@@ -888,22 +1016,6 @@ __device__ __forceinline__ int f16_row_exp(double al, double be) {
     (void)frexp(b, &x);
     const int e = 15 - x;
     return e < -120 ? -120 : (e > 120 ? 120 : e);
-}
-
-// OCP FP8 E4M3 (bias 7, 3 mantissa bits, no infinities) of a float, rounded
-// to nearest even; |y| must be below 464 (the first value that would round
-// past 448). Non-finite input gives the NaN code.
-__device__ __forceinline__ uint32_t f32_to_e4m3(float y) {
-    const uint32_t u = __float_as_uint(y);
-    const uint32_t sgn = (u >> 24) & 0x80u;
-    const uint32_t a = u & 0x7FFFFFFFu;
-    if (a >= 0x7F800000u) return sgn | 0x7Fu;
-    if (a < 0x3C800000u)  // below 2^-6: the subnormal grid of step 2^-9 (8 = 2^-6)
-        return sgn | (uint32_t)rintf(__uint_as_float(a) * 512.0f);
-    // keep 3 of the 23 mantissa bits, ties to even on the 20 dropped ones; a
-    // carry moves into the exponent; rebias 127 -> 7
-    const uint32_t r = a + 0x7FFFFu + ((a >> 20) & 1u);
-    return sgn | ((r >> 20) - (120u << 3));
 }
 
 __device__ __forceinline__ void coef_plain_body(const CoefArgs &a, int64_t blk) {
@@ -1625,7 +1737,6 @@ __device__ __forceinline__ void bwd_i8_body(const BwdArgs &a, int64_t gu, int ti
 // expansion of its B operand from the word's bits in the same or the
 // previous region.
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
 
 // B_ij = (-1)^{bit} in FP8 E4M3 (+1 = 0x38, -1 = 0xB8) for the 32 K values
 // of the lane, byte e <- bit e of x32: the sign bytes of expand_pm1_i8

@@ -1,7 +1,7 @@
 """Host model of each precision form's operand rounding (test code).
 
-The GPU path contracts with rounded operands: 2 theta'_j as FP32 or as BF16
-limbs in the forward, the backward weights S_ki = u_k / s * sin(E_ki) as FP32,
+The GPU path contracts with rounded operands: 2 theta'_j as FP32, as BF16
+limbs, or as two BF16 limbs and a scaled FP8 one in the forward, the backward weights S_ki = u_k / s * sin(E_ki) as FP32,
 BF16 limbs, a BF16 limb plus a row-scaled FP8 limb, or 8-bit fixed-point
 limbs. Feeding the same rounded operands
 through the FP64 oracle gives the result the arithmetic itself defines, so a
@@ -21,6 +21,8 @@ import oracle
 # at most 32639 = 127 * 256 + 127, the largest value two signed 8-bit limbs
 # (hi in [-127, 127], lo in [-128, 127]) hold with hi = floor((N + 128) / 256)
 I8X2_MAX = 32639.0
+# the third theta limb of split3_bf16 holds E4M3(rest * 2^LO8_EXP)
+LO8_EXP = 20
 
 
 def bf16_rne(x):
@@ -81,7 +83,10 @@ def theta_represented(prec, theta):
     elif prec in ("split_bf16", "split_bf16_fp8"):
         r = bf16_limbs(t, 2)
     elif prec == "split3_bf16":
-        r = bf16_limbs(t, 3)
+        # hi and mid BF16, then the rest as E4M3 of rest * 2^20 (from FP32)
+        hm = bf16_limbs(t, 2)
+        rest = (t - hm) * 2.0 ** LO8_EXP
+        r = hm + e4m3_rne(rest.astype(np.float32).astype(np.float64)) * 2.0 ** -LO8_EXP
     else:
         raise ValueError(prec)
     return r / 2.0

@@ -188,6 +188,63 @@ def test_mmd_full_size_sampled_operators(prec, unbiased):
     assert np.abs(g - og).max() < TOL[prec] * np.abs(og).max()
 
 
+def test_mmd_full_size_central_differences():
+    """The differentiation workload at full size (n = 300, 45150 gates, 3 x
+    2000 operators, s = 10^4, N = 2000, U-statistic): the analytic gradient
+    of every form against central differences of the FP32 loss at the 16
+    gates with the largest gradient. The differences' own error, per gate:
+    their truncation, estimated from the differences at eps and 2 eps (its
+    leading term, eps^2 / 6 times the third derivative, grows 4x, so
+    D(2 eps) - D(eps) is about 3x it), plus the loss's rounding over eps
+    (its scale taken as the distance between the FP32 loss and the one with
+    theta in three limbs); twice that, plus 1e-3 of the largest gradient
+    for the forms' own rounding, is the bar. The gradients here are ~1e-5
+    (operator weights 1/6000), so the bar is relative to them, and it stays
+    a small fraction of them."""
+    w = W.mmd_n300()
+    dw = DevWorkload(w)
+    theta = dw.theta.clone()
+
+    def loss_at(th, prec):
+        c = api.Circuit(w.n, dw.gens, th)
+        lv, _ = api.iqp_mmd_loss_grad(c, dw.ops, dw.op_weight, dw.samples, dw.data, True, False,
+                                      prec)
+        torch.cuda.synchronize()
+        return lv.item()
+
+    circ = api.Circuit(w.n, dw.gens, theta)
+    grads = {}
+    for prec in PRECS:
+        _, g = api.iqp_mmd_loss_grad(circ, dw.ops, dw.op_weight, dw.samples, dw.data, True, True,
+                                     prec)
+        torch.cuda.synchronize()
+        grads[prec] = g.cpu().numpy()
+    noise = abs(loss_at(theta, "fp32") - loss_at(theta, "split3_bf16"))
+    eps = 1e-3
+    pick = np.argsort(-np.abs(grads["fp32"]))[:16]
+
+    def central(j, e):
+        v = []
+        for sgn in (1.0, -1.0):
+            th = theta.clone()
+            th[int(j)] += sgn * e
+            v.append(loss_at(th, "fp32"))
+        return (v[0] - v[1]) / (2 * e)
+
+    fd = np.array([central(j, eps) for j in pick])
+    fd2 = np.array([central(j, 2 * eps) for j in pick])
+    bar = 2.0 * (np.abs(fd2 - fd) / 3.0 + noise / eps)
+    for prec in PRECS:
+        gp = grads[prec][pick]
+        d = np.abs(gp - fd)
+        lim = bar + 1e-3 * np.abs(grads[prec]).max()
+        print("mmd full size, %s: max|g - fd| %.3g, max bar %.3g, |g| %.3g..%.3g" %
+              (prec, d.max(), lim.max(), np.abs(fd).min(), np.abs(fd).max()))
+        assert np.all(d < lim), (prec, d, lim)
+    # the bar is a small fraction of the gradients it checks
+    assert (bar + 1e-3 * np.abs(grads["fp32"]).max()).max() < 0.1 * np.abs(fd).min()
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_autograd_expval_end_to_end(prec):
     w = W.small_random(88, 40, 300, 50, 400)

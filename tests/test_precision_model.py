@@ -72,6 +72,12 @@ def test_limbs_shrink_the_residual():
     for k, bound in ((1, 2.0 ** -8), (2, 2.0 ** -16), (3, 2.0 ** -24)):
         r = np.abs(PM.bf16_limbs(t, k) - t)
         assert np.all(r <= bound * np.abs(t) + 1e-300), (k, (r / np.abs(t)).max())
+    # split3's third limb: E4M3 (4 significant bits) of the rest after two
+    # BF16 limbs, within its range (|rest| 2^20 <= 2^-16 pi 2^20 < 448), so
+    # 2^-4 of the rest (<= 2^-20 |t|) plus the subnormal step's half, 2^-30
+    r = np.abs(2.0 * PM.theta_represented("split3_bf16", t / 2.0) - t)
+    assert np.all(r <= 2.0 ** -20 * np.abs(t) + 2.0 ** -30), (r / np.abs(t)).max()
+    assert np.abs(t - PM.bf16_limbs(t, 2)).max() * 2.0 ** PM.LO8_EXP < 448.0
 
 
 @pytest.fixture(scope="module")
