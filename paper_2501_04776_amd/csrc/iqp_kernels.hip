@@ -1106,11 +1106,12 @@ __device__ __forceinline__ void weights_body(const WeightsArgs &a, int64_t blk) 
         if (bad && k < l) gptr(a.nf)[k] = 1;  // every writer stores the same value
     } else if (prec == 4) {
         // x = S_ki 2^e_k: FP16 limb h = rn(x) in the BF16 form's image, and
-        // FP8 limb rn_e4m3(x - h) (exact difference, |x - h| <= 16) in the
+        // FP8 limb rn_e4m3(x - h) (exact difference, |x - h| <= 8) in the
         // A-operand image of a 32x32x64 FP8 product: lane (l/32, l%32) holds
-        // row l%32 and samples 32 (l/32) + e, e = 0..31, of a sample word,
-        // as two 16-byte units at (((k/32) * sw + i/64) * 2 + q) * 64 + l
-        // for bytes 16 q .. 16 q + 15 (sw = s_pad / 64)
+        // row l%32 and, in byte 8 t + e, sample 16 t + 8 (l/32) + e of a
+        // sample word (the samples of the lane's four FP16 K-steps), as two
+        // 16-byte units at (((k/32) * sw + i/64) * 2 + q) * 64 + l for bytes
+        // 16 q .. 16 q + 15 (sw = s_pad / 64)
         const int kl = threadIdx.x & 63;
         const int64_t k = k0 + kl;
         int ex = 0;
@@ -1140,7 +1141,10 @@ __device__ __forceinline__ void weights_body(const WeightsArgs &a, int64_t blk) 
             uint32_t w = 0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float x = ldexpf(tile[kl][32 * hh + 16 * q + 4 * v + e], ex);
+                // byte 16 q + 4 v + e of the lane: K-step 2 q + v / 2, sample
+                // 8 (v % 2) + e of its half hh
+                const int i = 32 * q + 16 * (v >> 1) + 8 * hh + 4 * (v & 1) + e;
+                const float x = ldexpf(tile[kl][i], ex);
                 const float h = (float)(_Float16)x;
                 w |= f32_to_e4m3(x - h) << (8 * e);
             }
@@ -1732,43 +1736,24 @@ __device__ __forceinline__ void bwd_i8_body(const BwdArgs &a, int64_t gu, int ti
 // FP16 ones, so a word costs 6 instead of the 8 of two BF16 limbs. The
 // epilogue multiplies each row by 2^-e_k (sq) before the masked sum over
 // rows. Same work units, staging (one sample word per buffer) and pipeline
-// as the BF16 form; the FP8 products of gate block g are issued in region
-// g + 1 of the word (the last one after the word's barrier), each with the
-// expansion of its B operand from the word's bits in the same or the
-// previous region.
+// as the BF16 form. The FP8 B operand is built per K-step from the FP16 one
+// (the high bytes of its +-1 pairs, 0x3C / 0xBC, by one byte permute, then
+// 0x38 / 0xB8), so lane half h holds samples 16 t + 8 h + e of K-step t in
+// bytes 8 t + e, the order the weights kernel writes the FP8 limb in; a
+// word's FP8 products are issued at the start of its last region (after the
+// word's barrier), before that region's expansion starts the next word.
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-
-// B_ij = (-1)^{bit} in FP8 E4M3 (+1 = 0x38, -1 = 0xB8) for the 32 K values
-// of the lane, byte e <- bit e of x32: the sign bytes of expand_pm1_i8
-// (0x00 / 0xFF per bit, four bits per dword) masked to the sign bit, or'ed
-// with 0x38 (the two constants in vector registers, so that mask-and-or is
-// one instruction).
-__device__ __forceinline__ i32x8 expand_pm1_f8(uint32_t x32, uint32_t m80, uint32_t c38) {
-    i32x8 out;
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        const uint32_t x16 = half ? x32 >> 16 : x32;
-        const u16x2 xv = {(unsigned short)x16, (unsigned short)x16};
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const u16x2 sh1 = {(unsigned short)(15 - 4 * v), (unsigned short)(14 - 4 * v)};
-            const u16x2 sh0 = {(unsigned short)(13 - 4 * v), (unsigned short)(12 - 4 * v)};
-            const uint32_t s1 = __builtin_bit_cast(uint32_t, (u16x2)(xv << sh1));
-            const uint32_t s0 = __builtin_bit_cast(uint32_t, (u16x2)(xv << sh0));
-            out[4 * half + v] = (int32_t)((__builtin_amdgcn_perm(s0, s1, 0x0B0A0908u) & m80) | c38);
-        }
-    }
-    return out;
-}
 
 template <int FM, int FN>
 struct BwdOpsH {
     f16x8 ah[FM], bv[FN];
 };
-// the FP8 limb of the word's S strip and the +-1 operands of two gate blocks
-template <int FM>
+// the FP8 limb of the word's S strip and the word's +-1 FP8 operands
+template <int FM, int FN>
 struct BwdLoF8 {
-    i32x8 a[FM], b[2];
+    i32x8 a[FM];
+    uint32_t b[FN][8];
+    uint32_t m80, c38;  // the E4M3 sign mask and +1.0, in vector registers
 };
 
 template <int FM, int FN, int T>
@@ -1780,42 +1765,28 @@ __device__ __forceinline__ void bwdh_expand_a(BwdOpsH<FM, FN> &o, const u32x4 *l
 
 template <int FM, int FN, int T>
 __device__ __forceinline__ void bwdh_expand_b(BwdOpsH<FM, FN> &o, const uint64_t (&bw)[FN],
-                                              uint32_t ones) {
+                                              uint32_t ones, BwdLoF8<FM, FN> &lo) {
 #pragma unroll
     for (int g = 0; g < FN; ++g) {
         const uint32_t d = (uint32_t)(bw[g] >> (32 * (T >> 1)));
-        o.bv[g] = __builtin_bit_cast(f16x8, expand_pm1((T & 1) ? (d >> 16) : d, ones));
+        const bf16x8 v = expand_pm1((T & 1) ? (d >> 16) : d, ones);
+        o.bv[g] = __builtin_bit_cast(f16x8, v);
+        const u32x4 q = __builtin_bit_cast(u32x4, v);
+        lo.b[g][2 * T] = (__builtin_amdgcn_perm(q[1], q[0], 0x07050301u) & lo.m80) | lo.c38;
+        lo.b[g][2 * T + 1] = (__builtin_amdgcn_perm(q[3], q[2], 0x07050301u) & lo.m80) | lo.c38;
     }
 }
 
-// Where the FP8 products of a word go: region R (1, 2, 3, then 0 after the
-// word's barrier) issues the products of gate block gi for row blocks
-// [f0, f1), expands the FP8 B operands of gate blocks gx0, gx1 (slot g % 2,
-// -1: none) from the word's bits, and region 1 also reads the word's FP8
-// limb. Every expansion happens before the barrier that replaces the bits,
-// and each slot is consumed before it is refilled.
-template <int FM, int FN, int R>
-struct F8Plan {
-    // 64x128 tiles: one gate block per region
-    static constexpr int gi = FN == 4 ? (R == 0 ? 3 : R - 1) : (FM == 4 ? (R == 1 || R == 2 ? 0 : 1)
-                                                                        : (R == 1 ? 0 : R == 2 ? 1 : -1));
-    static constexpr int f0 = FM == 4 && FN == 2 && (R == 2 || R == 0) ? 2 : 0;
-    static constexpr int f1 = FM == 4 && FN == 2 && (R == 1 || R == 3) ? 2 : FM;
-    static constexpr int gx0 = R == 1 ? 0 : R == 2 ? 1 : (R == 3 && FN == 4) ? 2 : -1;
-    static constexpr int gx1 = R == 3 && FN == 4 ? 3 : -1;
-};
-
 // One pipeline region: the FP16 products of K-step t (operands `cur`) while
-// the operands of K-step T1 are read from `lsn` and expanded into `nxt`, plus
-// the FP8 work that F8Plan<FM, FN, R> assigns to region R (R = T1).
+// the operands of K-step T1 are read from `lsn` and expanded into `nxt`.
+// Region 1 also reads the word's FP8 limb; region 0 (after the word's
+// barrier) first issues the word's FP8 products.
 template <int FM, int FN, int R>
 __device__ __forceinline__ void bwdh_region(const BwdOpsH<FM, FN> &cur, BwdOpsH<FM, FN> &nxt,
                                             const u32x4 *lsn, const uint64_t (&bw)[FN], int lane,
-                                            int h, uint32_t ones, uint32_t m80, uint32_t c38,
-                                            BwdLoF8<FM> &lo, f32x16 (&acc)[FM][FN]) {
-    using P = F8Plan<FM, FN, R>;
-    constexpr bool RA = R == 1;
-    if (RA) {
+                                            uint32_t ones, BwdLoF8<FM, FN> &lo,
+                                            f32x16 (&acc)[FM][FN]) {
+    if constexpr (R == 1) {
 #pragma unroll
         for (int f = 0; f < FM; ++f) {
             const u32x4 p0 = lsn[(4 * FM + 2 * f) * 64 + lane];
@@ -1824,29 +1795,25 @@ __device__ __forceinline__ void bwdh_region(const BwdOpsH<FM, FN> &cur, BwdOpsH<
                               (int32_t)p1[0], (int32_t)p1[1], (int32_t)p1[2], (int32_t)p1[3]};
         }
     }
+    if constexpr (R == 0) {
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int g = 0; g < FN; ++g)
+                acc[f][g] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    lo.a[f], __builtin_bit_cast(i32x8, lo.b[g]), acc[f][g], 0, 0, 0, 127, 0, 127);
+    }
     bwdh_expand_a<FM, FN, R>(nxt, lsn, lane);
-    if (P::gx0 >= 0)
-        lo.b[P::gx0 & 1] = expand_pm1_f8((uint32_t)(bw[P::gx0 < 0 ? 0 : P::gx0] >> (24 * h)), m80, c38);
-    if (P::gx1 >= 0)
-        lo.b[P::gx1 & 1] = expand_pm1_f8((uint32_t)(bw[P::gx1 < 0 ? 0 : P::gx1] >> (24 * h)), m80, c38);
-    bwdh_expand_b<FM, FN, R>(nxt, bw, ones);
+    bwdh_expand_b<FM, FN, R>(nxt, bw, ones, lo);
 #pragma unroll
     for (int f = 0; f < FM; ++f)
 #pragma unroll
         for (int g = 0; g < FN; ++g)
             acc[f][g] = __builtin_amdgcn_mfma_f32_32x32x16_f16(cur.ah[f], cur.bv[g], acc[f][g], 0, 0,
                                                                0);
-    if (P::gi >= 0) {
-#pragma unroll
-        for (int f = P::f0; f < P::f1; ++f) {
-            f32x16 &c = acc[f][P::gi < 0 ? 0 : P::gi];
-            c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(lo.a[f], lo.b[P::gi & 1], c, 0, 0, 0,
-                                                                 127, 0, 127);
-        }
-    }
-    constexpr int kM = FM * FN + (P::gi >= 0 ? P::f1 - P::f0 : 0);
-    constexpr int kV = 8 * FN + 2 + (P::gx0 >= 0 ? 24 : 0) + (P::gx1 >= 0 ? 24 : 0);
-    interleave_half<FM + (RA ? 2 * FM : 0), kM, kV>();
+    constexpr int kM = FM * FN * (R == 0 ? 2 : 1);
+    constexpr int kV = 12 * FN + 2;
+    interleave_half<FM + (R == 1 ? 2 * FM : 0), kM, kV>();
 }
 
 // sum_k c_kj 2^-e_k T[k][j] over this wave's observable rows, per gate column
@@ -1908,7 +1875,6 @@ __device__ __forceinline__ void bwd_f16f8_body(const BwdArgs &a, int64_t gu, int
     const int lane = tid & 63;
     const int h = lane >> 5, r = lane & 31;
     const uint32_t ones = in_vgpr(0x3C003C00u);  // +1.0 in FP16, twice
-    const uint32_t m80 = in_vgpr(0x80808080u), c38 = in_vgpr(0x38383838u);
     const int64_t KTs = sw * 4;
     const uint64_t IQP_GLOBAL *bbase = btbits + jb * FN * sw * 32;
     const u32x4 IQP_GLOBAL *sbase_h = shi + ob * FM * KTs * 64;
@@ -1954,13 +1920,15 @@ __device__ __forceinline__ void bwd_f16f8_body(const BwdArgs &a, int64_t gu, int
         for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w0 + 1) * 32)[r];
     }
     BwdOpsH<FM, FN> opA, opB;
-    BwdLoF8<FM> lo;
+    BwdLoF8<FM, FN> lo;
+    lo.m80 = in_vgpr(0x80808080u);
+    lo.c38 = in_vgpr(0x38383838u);
     bwdh_expand_a<FM, FN, 0>(opA, ls0, lane);
-    bwdh_expand_b<FM, FN, 0>(opA, cur, ones);
+    bwdh_expand_b<FM, FN, 0>(opA, cur, ones, lo);
     auto word = [&](int64_t w, u32x4 *mine, const u32x4 *other) {
-        bwdh_region<FM, FN, 1>(opA, opB, mine, cur, lane, h, ones, m80, c38, lo, acc);
-        bwdh_region<FM, FN, 2>(opB, opA, mine, cur, lane, h, ones, m80, c38, lo, acc);
-        bwdh_region<FM, FN, 3>(opA, opB, mine, cur, lane, h, ones, m80, c38, lo, acc);
+        bwdh_region<FM, FN, 1>(opA, opB, mine, cur, lane, ones, lo, acc);
+        bwdh_region<FM, FN, 2>(opB, opA, mine, cur, lane, ones, lo, acc);
+        bwdh_region<FM, FN, 3>(opA, opB, mine, cur, lane, ones, lo, acc);
         dma_wait_barrier();
         if (w + 2 < w1) stage(w + 2, mine);
 #pragma unroll
@@ -1970,7 +1938,7 @@ __device__ __forceinline__ void bwd_f16f8_body(const BwdArgs &a, int64_t gu, int
             for (int g = 0; g < FN; ++g) nxt[g] = (bbase + (g * sw + w + 2) * 32)[r];
         }
         // past the last word this expands a stale buffer and is never used
-        bwdh_region<FM, FN, 0>(opB, opA, other, cur, lane, h, ones, m80, c38, lo, acc);
+        bwdh_region<FM, FN, 0>(opB, opA, other, cur, lane, ones, lo, acc);
     };
     for (int64_t w = w0; w < w1; w += 2) {
         word(w, ls0, ls1);
