@@ -333,18 +333,24 @@ def main():
                                                                            density))
         # the sparse contraction kernels alone, against 256 CUs x 64 lanes x
         # 2.4 GHz of 32-bit lane ops: per non-zero term the forward issues 3
-        # (bit extract, mask, add), the backward 2 (add, select on the mask)
+        # (bit extract, mask, add); the backward reads one 16-entry table per
+        # 4 samples, 2.5 lane ops per read (a byte extract, an add and half
+        # of the two shift-and-mask pairs that serve 8 reads), so 0.625 lane
+        # ops and 0.25 LDS reads per term
         kb_sp = kernel_breakdown("sparse_fp32", 3)
         nnz = density * T
         valu_peak = 256 * 64 * 2.4e9
         sp_roof = {}
-        for fam, ops in (("phase_fwd", 3.0), ("phase_bwd", 2.0)):
+        for fam, ops in (("phase_fwd", 3.0), ("phase_bwd", 0.625)):
             if fam in kb_sp:
                 rate = nnz / (kb_sp[fam]["avg_ms"] * 1e-3)
                 sp_roof[fam] = {"avg_ms": kb_sp[fam]["avg_ms"], "nnz_terms_per_s": rate,
                                 "valu_ops_per_term": ops, "valu_ops_per_s": ops * rate,
                                 "peak_valu_ops_per_s": valu_peak,
                                 "frac": ops * rate / valu_peak}
+        if "phase_bwd" in sp_roof:
+            sp_roof["phase_bwd"]["method"] = "16-entry tables of signed S sums per 4 samples"
+            sp_roof["phase_bwd"]["lds_reads_per_term"] = 0.25
         result["sparse_fp32"] = {"fwd_bwd_terms_per_s": T / (ms_sp * 1e-3),
                                  "fwd_terms_per_s": T / (ms_spf * 1e-3), "ms_per_step": ms_sp,
                                  "fwd_ms": ms_spf, "c_density": density,

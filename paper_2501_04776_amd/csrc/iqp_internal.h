@@ -281,9 +281,6 @@ struct SparseBwdArgs {
     const double *coef, *scale;
     long long *acc;
 };
-inline int64_t blocks_of(const SparseBwdArgs &a) {
-    return ceil_div(a.l * ceil_div(a.s, kEpiChunk), 4);
-}
 
 // Bit columns of l sample sets of s rows each ([l][s][W], row i of set k at
 // samples + (k s + i) W): xt[k * 64 W * ldx + q * ldx + rw], bit r = qubit q

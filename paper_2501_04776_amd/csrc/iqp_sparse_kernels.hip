@@ -26,31 +26,19 @@ __device__ __forceinline__ const T IQP_CONST *cptr(const T *p) {
 
 // ---------------------------------------------------------------------------
 // Sample-parity words: word w of generator j holds b_ij of samples 64 w ..
-// 64 w + 63 (bit i % 64). A wave covers one chunk of kSpWords words of one
-// observable. Two ways to read them:
-//   word(j)      each lane loads the word its 16 samples lie in (lane L:
-//                bits 16 (L % 4) .. 16 (L % 4) + 15 of word L / 4); the
-//                forward, and the backward of independent sets
-//   words(j, m)  all kSpWords words of the chunk, the same in every lane
-//                (scalar loads), each used as a lane mask over the 64 samples
-//                of one word (lane L: sample 64 r + L); the backward of
-//                shared samples
-// The sample-parity rows hold whole chunks (a multiple of kSpWords words,
-// the words of samples >= s being 0), so a wave reads all its words
-// unconditionally.
+// 64 w + 63 (bit i % 64). In the forward a wave covers one chunk of
+// kSpWords words of one observable and each lane loads, per generator, the
+// word its 16 samples lie in (lane L: bits 16 (L % 4) .. 16 (L % 4) + 15 of
+// word L / 4). The sample-parity rows hold whole chunks (a multiple of
+// kSpWords words, the words of samples >= s being 0), so a wave reads all
+// its words unconditionally.
 constexpr int kSpWords = kEpiChunk / 64;
 
 // One B^T (row-major) for all observables.
 struct SharedWords {
-    const uint64_t IQP_CONST *row0;  // btrm + the wave's first sample word
     int64_t Rwb;
     const uint64_t IQP_GLOBAL *lane0;  // btrm + the lane's own word
     __device__ __forceinline__ uint64_t word(int64_t j) const { return lane0[j * Rwb]; }
-    __device__ __forceinline__ void words(int64_t j, uint64_t (&m)[kSpWords]) const {
-        const uint64_t IQP_CONST *row = row0 + j * Rwb;
-#pragma unroll
-        for (int r = 0; r < kSpWords; ++r) m[r] = row[r];
-    }
 };
 
 // The bit columns of observable k's own samples: the parity of g_j is the
@@ -103,7 +91,7 @@ struct WordsOf<false> {
     using T = SharedWords;
     static __device__ __forceinline__ T make(const SampleParity &p, int64_t, int64_t sw0,
                                              int64_t swl) {
-        return SharedWords{cptr(p.btrm) + sw0, p.Rwb, gptr(p.btrm) + swl};
+        return SharedWords{p.Rwb, gptr(p.btrm) + swl};
     }
 };
 template <>
@@ -152,13 +140,6 @@ struct GateWalk {
         return true;
     }
 };
-
-// x + y in the lanes whose bit of the uniform mask is set, x elsewhere: one
-// add and one select on the mask held in a scalar register pair.
-__device__ __forceinline__ float add_where(float x, float y, uint64_t mask) {
-    const float s = x + y;
-    return __builtin_amdgcn_inverse_ballot_w64(mask) ? s : x;
-}
 
 // ---------------------------------------------------------------------------
 // Forward. One wave per (observable k, chunk of kEpiChunk samples); lane L
@@ -292,124 +273,222 @@ hipError_t launch_sparse_bound(const LaunchCtx &lc, const SparseBoundArgs &a) {
     return plain_launch<SparseBoundArgs, sparse_bound_body>(lc, KF_WEIGHTS, a, blocks_of(a));
 }
 
-// generators per reduction batch of the backward; LDS row stride in floats
-// (a multiple of 4 for 16-byte reads; 68 spreads the rows over the banks)
-constexpr int kRedBatch = 16;
-constexpr int kRedStride = 68;
+// Gradient by table lookup. A block takes observable k and one chunk of
+// kEpiChunk samples. Thread t computes S_ki for the four samples 4t .. 4t + 3
+// of the chunk and writes their 16 signed sums
+//   L_t[v] = sum_{b < 4} (-1)^{v_b} S_{k, c + 4t + b},  v = 0 .. 15,
+// so that, with v_t(j) the nibble of generator j's parity bits over those
+// four samples (bits 4t .. 4t + 3 of the chunk's parity words), the chunk's
+// partial T_kj = sum_i S_ki (-1)^{b_ij} is the sum over t of L_t[v_t(j)]:
+// 256 table reads per generator and chunk in place of 1024 masked adds. The
+// generators J_k (the set bits of row k of C) are compacted into a list in
+// LDS; each lane takes one generator of the list, forms its 16 parity words
+// of the chunk (one 128-byte line of B^T for shared samples; for
+// independent sets the XOR of the line of each support column of k's own
+// samples), sums its 256 table entries and adds the total into the
+// generator's fixed-point accumulator. The lanes of a wave read one table
+// at a time, a 64-byte row of 16 entries in distinct banks, so the reads
+// never conflict.
+constexpr int kLutTables = (int)(kEpiChunk / 4);  // one per thread of the block
+constexpr int kLutList = 1024;                    // generators per list fill
+
+static_assert(kLutTables == 256, "one table per thread of a 256-thread block");
+
+// Exclusive prefix over the block of per-thread counts c (the block's total
+// in *tot); wsum holds the 4 wave totals and is reused only after the next
+// barrier of the caller's loop.
+__device__ __forceinline__ int block_excl_scan(int c, int *wsum, int *tot) {
+    const int lane = threadIdx.x & 63, w = wave_id();
+    int x = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int v = wsum[i];
+        before += i < w ? v : 0;
+        all += v;
+    }
+    *tot = all;
+    return before + x - c;
+}
+
+
+// The 16 parity words of generator j over chunk ch (lane-varying j).
+template <bool kIndep>
+__device__ __forceinline__ void lut_row(const SparseBwdArgs &a, int64_t k, int64_t ch, int64_t j,
+                                        u32x4 (&wv)[8]);
+template <>
+__device__ __forceinline__ void lut_row<false>(const SparseBwdArgs &a, int64_t, int64_t ch,
+                                               int64_t j, u32x4 (&wv)[8]) {
+    const glb<const u32x4> src =
+        (glb<const u32x4>)(gptr(a.bsrc.btrm) + j * a.bsrc.Rwb + ch * kSpWords);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) wv[q] = src[q];
+}
+template <>
+__device__ __forceinline__ void lut_row<true>(const SparseBwdArgs &a, int64_t k, int64_t ch,
+                                              int64_t j, u32x4 (&wv)[8]) {
+    const glb<const uint64_t> cols = gptr(a.bsrc.xt) + k * a.bsrc.xstride + ch * kSpWords;
+    auto add_col = [&](int64_t q) {
+        const glb<const u32x4> src = (glb<const u32x4>)(cols + q * a.bsrc.Rwb);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) wv[i] ^= src[i];
+    };
+#pragma unroll
+    for (int i = 0; i < 8; ++i) wv[i] = u32x4{0, 0, 0, 0};
+    const glb<const int32_t> sj = gptr(a.bsrc.sup) + j * kSupCap;
+    if (sj[0] == -2) {  // heavier than kSupCap: its bit row
+        for (int w = 0; w < a.bsrc.W; ++w) {
+            uint64_t g = gptr(a.bsrc.gens)[j * a.bsrc.W + w];
+            while (g) {
+                add_col(w * 64 + __builtin_ctzll(g));
+                g &= g - 1;
+            }
+        }
+        return;
+    }
+    for (int e = 0; e < kSupCap; ++e) {
+        const int32_t q = sj[e];
+        if (q < 0) break;
+        add_col(q);
+    }
+}
 
 template <bool kIndep>
-__device__ __forceinline__ void sparse_bwd_body(const SparseBwdArgs &a, int64_t blk) {
-    const int64_t nchunk = ceil_div(a.s, kEpiChunk);
-    const int64_t unit = blk * 4 + wave_id();
-    if (unit >= a.l * nchunk) return;  // uniform over the wave
-    const int64_t k = unit / nchunk, ch = unit - k * nchunk;
-    const int lane = threadIdx.x & 63;
-    const int64_t sw0 = ch * kSpWords;
-    // Lanes and samples: shared samples, lane L holds sample 64 r + L of
-    // each of the chunk's 16 words r (the parity words are uniform, scalar
-    // loads used as lane masks); independent sets, the forward's layout: lane
-    // L holds the 16 samples of bits 16 (L % 4) .. + 15 of the chunk's word
-    // L / 4 and loads its own parity word.
-    const int sh = 16 * (lane & 3);
-    const auto src = WordsOf<kIndep>::make(a.bsrc, k, sw0, kIndep ? sw0 + (lane >> 2) : sw0);
-    GateWalk gates(a.crm + k * a.Gw, a.Gw);
-    const double al = gptr(a.coef)[2 * k], be = gptr(a.coef)[2 * k + 1];
-    const double scale = gptr(a.scale)[0];
-    // S_ki = (alpha_k + beta_k cos E_ki) sin E_ki for the lane's samples
-    float S[kSpWords];
-    float Ssum = 0.0f;
+__device__ __forceinline__ void sparse_bwd_lut_body(const SparseBwdArgs &a, int64_t blk) {
+    // chunk-major: the blocks that run together read one 128-byte column
+    // of the parity rows (fewer HBM fetches than observable-major order)
+    const int64_t ch = blk / a.l, k = blk - ch * a.l;
+    const int tid = threadIdx.x, lane = tid & 63;
+    __shared__ __attribute__((aligned(16))) float tab[kLutTables * 16];
+    __shared__ int32_t lst[kLutList];
+    __shared__ int wsum[2][4];
+
+    // the tables of this chunk
+    {
+        const double al = gptr(a.coef)[2 * k], be = gptr(a.coef)[2 * k + 1];
+        float S[4];
 #pragma unroll
-    for (int r = 0; r < kSpWords; ++r) {
-        const int64_t i = kIndep ? (sw0 + (lane >> 2)) * 64 + sh + r : (sw0 + r) * 64 + lane;
-        float v = 0.0f;
-        if (i < a.s) {
-            float sn, cs;
-            sincosf(gptr(a.phase)[k * a.s + i], &sn, &cs);
-            v = (float)((al + be * (double)cs) * (double)sn);
+        for (int b = 0; b < 4; ++b) {
+            const int64_t i = ch * kEpiChunk + 4 * tid + b;
+            float v = 0.0f;
+            if (i < a.s) {
+                float sn, cs;
+                sincosf(gptr(a.phase)[k * a.s + i], &sn, &cs);
+                v = (float)((al + be * (double)cs) * (double)sn);
+            }
+            S[b] = v;
         }
-        S[r] = v;
-        Ssum += v;
+        // x[u] over samples 0, 1 and y[u] over samples 2, 3, bit set = minus
+        const float x[4] = {S[0] + S[1], S[1] - S[0], S[0] - S[1], -S[0] - S[1]};
+        const float y[4] = {S[2] + S[3], S[3] - S[2], S[2] - S[3], -S[2] - S[3]};
+        float4 *row = reinterpret_cast<float4 *>(tab + tid * 16);
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+            row[h] = make_float4(x[0] + y[h], x[1] + y[h], x[2] + y[h], x[3] + y[h]);
     }
-    // The partials of kRedBatch generators are gathered in this wave's LDS
-    // rows (row e, lane L: lane L's partial for the e-th generator of the
-    // batch) and reduced together: lane L sums 16 lanes of row L % 16, two
-    // shuffles add the four quarters, and lanes 0..15 add their generator's
-    // total into its fixed-point accumulator. One LDS write per generator
-    // instead of a full cross-lane sum and an atomic per generator.
-    __shared__ __attribute__((aligned(16))) float red_all[4][kRedBatch * kRedStride];
-    float *red = red_all[wave_id()];
-    int nb = 0;
-    int32_t jv = 0;  // lane e < nb: the generator of batch row e
-    auto flush = [&]() {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int e = lane & (kRedBatch - 1), q = lane >> 4;
-        const float4 *row = reinterpret_cast<const float4 *>(red + e * kRedStride + 16 * q);
-        const float4 v0 = row[0], v1 = row[1], v2 = row[2], v3 = row[3];
-        float tot = ((v0.x + v0.y) + (v0.z + v0.w)) + ((v1.x + v1.y) + (v1.z + v1.w)) +
-                    (((v2.x + v2.y) + (v2.z + v2.w)) + ((v3.x + v3.y) + (v3.z + v3.w)));
-        tot += __shfl_xor(tot, 16, 64);
-        tot += __shfl_xor(tot, 32, 64);
-        if (lane < nb) {
+
+    const glb<const uint64_t> crow = gptr(a.crm) + k * a.Gw;
+    const double scale = gptr(a.scale)[0];
+    // each wave takes list entries wave_id() * 64 + lane, + 256, ...
+    auto process = [&](int n) {
+        for (int g = wave_id() * 64 + lane; g - lane < n; g += 256) {
+            if (g >= n) continue;
+            const int64_t j = lst[g];
+            u32x4 wv[8];
+            lut_row<kIndep>(a, k, ch, j, wv);
+            float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            const char *tb = reinterpret_cast<const char *>(tab);
+#pragma unroll
+            for (int r = 0; r < kSpWords; ++r) {
+                // word r holds nibbles t = 16 r + e (bits 4e .. 4e + 3): byte
+                // e' of x[2h] is 4 times nibble 8h + 2e', of x[2h + 1] 4 times
+                // nibble 8h + 2e' + 1 (kept opaque so that each byte costs one
+                // extract instead of a shift and a mask)
+                uint32_t x[4];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t d = wv[r / 2][2 * (r % 2) + h];
+                    x[2 * h] = (d << 2) & 0x3C3C3C3Cu;
+                    x[2 * h + 1] = (d >> 2) & 0x3C3C3C3Cu;
+                    asm volatile("" : "+v"(x[2 * h]), "+v"(x[2 * h + 1]));
+                }
+                float v[16];
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const uint32_t o = (x[e / 4 % 2 + 2 * (e / 8)] >> (8 * (e % 4))) & 0xFFu;
+                    const int t = 16 * r + 8 * (e / 8) + 2 * (e % 4) + e / 4 % 2;
+                    v[e] = *reinterpret_cast<const float *>(tb + t * 64 + o);
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) acc[e] += v[e] + v[e + 8];
+            }
+            const float tot = ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+                              ((acc[4] + acc[5]) + (acc[6] + acc[7]));
             if (isfinite(tot))
-                atomicAdd((unsigned long long *)&gptr(a.acc)[jv],
+                atomicAdd((unsigned long long *)&gptr(a.acc)[j],
                           (unsigned long long)llrint((double)tot * scale));
             else
                 atomicOr((unsigned long long *)&gptr(a.acc)[a.m_pad], 1ull);
         }
-        // the rows are rewritten by the next batch only after every lane read
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        nb = 0;
     };
-    auto add_partial = [&](int64_t j, float p) {
-        red[nb * kRedStride + lane] = Ssum - 2.0f * p;
-        jv = lane == nb ? (int32_t)j : jv;
-        if (++nb == kRedBatch) flush();
-    };
-    int64_t j;
-    if constexpr (!kIndep) {
-        uint64_t m[kSpWords];
-        // the next generator's parity words are loaded once the current ones
-        // are consumed, so the load overlaps the current partial's store (the
-        // independent form's support walk has no scalar registers to spare
-        // for this)
-        bool have = gates.next(j);
-        src.words(have ? j : 0, m);
-        while (have) {
-            float p = 0.0f;
-#pragma unroll
-            for (int r = 0; r < kSpWords; ++r) p = add_where(p, S[r], m[r]);
-            int64_t jn = j;
-            const bool more = gates.next(jn);
-            src.words(jn, m);
-            add_partial(j, p);
-            j = jn;
-            have = more;
-        }
-    } else {
-        // The parity word of generator j is the XOR of its support columns,
-        // here per lane with vector loads: as uniform scalar words the XORs
-        // ran on the scalar unit, which then bounded the kernel. Per sample a
-        // one-bit field extract masks S (3 lane ops per term, as in the
-        // forward).
-        while (gates.next(j)) {
-            const uint32_t f = (uint32_t)(src.word(j) >> sh);
-            float p = 0.0f;
-#pragma unroll
-            for (int b = 0; b < kSpWords; ++b) p += masked(S[b], f, b);
-            add_partial(j, p);
+
+    // J_k, 256 row words at a time, into the list; a full list is processed
+    // before the rest of the window is taken
+    int n = 0, it = 0;
+    __syncthreads();  // tables written
+    for (int64_t base = 0; base < a.Gw; base += 256) {
+        uint64_t v = base + tid < a.Gw ? crow[base + tid] : 0ull;
+        for (;;) {
+            int tot;
+            const int off = block_excl_scan(__popcll(v), wsum[it & 1], &tot);
+            ++it;
+            const int room = kLutList - n;
+            for (int pos = off; v != 0ull && pos < room; ++pos) {
+                lst[n + pos] = (int32_t)((base + tid) * 64 + __builtin_ctzll(v));
+                v &= v - 1;
+            }
+            const int take = tot < room ? tot : room;
+            n += take;
+            if (n == kLutList) {
+                __syncthreads();
+                process(n);
+                __syncthreads();
+                n = 0;
+            }
+            if (tot <= room) break;
         }
     }
-    if (nb > 0) flush();
+    __syncthreads();
+    process(n);
+}
+
+template <bool kIndep>
+__global__ __launch_bounds__(256) void sparse_bwd_lut_kernel(SparseBwdArgs a) {
+    sparse_bwd_lut_body<kIndep>(a, (int64_t)blockIdx.x);
 }
 
 hipError_t launch_sparse_bwd(const LaunchCtx &lc, const SparseBwdArgs &a) {
+    const int64_t blocks = a.l * ceil_div(a.s, kEpiChunk);
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
+    hipEvent_t ev;
+    timed_begin(lc, KF_BWD, &ev);
     if (a.bsrc.xt)
-        return plain_launch<SparseBwdArgs, sparse_bwd_body<true>>(lc, KF_BWD, a, blocks_of(a));
-    return plain_launch<SparseBwdArgs, sparse_bwd_body<false>>(lc, KF_BWD, a, blocks_of(a));
+        hipLaunchKernelGGL(sparse_bwd_lut_kernel<true>, dim3((unsigned)blocks), dim3(256), 0,
+                           lc.stream, a);
+    else
+        hipLaunchKernelGGL(sparse_bwd_lut_kernel<false>, dim3((unsigned)blocks), dim3(256), 0,
+                           lc.stream, a);
+    hipError_t e = hipGetLastError();
+    timed_end(lc, KF_BWD, ev);
+    return e;
 }
 
 __device__ __forceinline__ void sparse_finish_body(const SparseFinishArgs &a, int64_t blk) {
