@@ -332,25 +332,29 @@ def main():
         log("sparse_fp32: fwd+bwd %.3f ms, fwd %.3f ms (C density %.4f)" % (ms_sp, ms_spf,
                                                                            density))
         # the sparse contraction kernels alone, against 256 CUs x 64 lanes x
-        # 2.4 GHz of 32-bit lane ops: per non-zero term the forward issues 3
-        # (bit extract, mask, add); the backward reads one 16-entry table per
-        # 4 samples, 2.5 lane ops per read (a byte extract, an add and half
-        # of the two shift-and-mask pairs that serve 8 reads), so 0.625 lane
-        # ops and 0.25 LDS reads per term
+        # 2.4 GHz of 32-bit lane ops. Both read one 16-entry table per 4
+        # terms. The backward spends 2.5 lane ops per read (a byte extract,
+        # an add and a quarter of the 4 shift-and-mask ops of a 64-bit word):
+        # 0.625 per term. The forward spends, per 64 generators x 64 samples,
+        # a 35-op bit transpose, 40 ops for its 16 reads and 8 for two folds:
+        # 1.3 per term. Both make 0.25 LDS reads per term.
         kb_sp = kernel_breakdown("sparse_fp32", 3)
         nnz = density * T
         valu_peak = 256 * 64 * 2.4e9
         sp_roof = {}
-        for fam, ops in (("phase_fwd", 3.0), ("phase_bwd", 0.625)):
+        for fam, ops in (("phase_fwd", 1.3), ("phase_bwd", 0.625)):
             if fam in kb_sp:
                 rate = nnz / (kb_sp[fam]["avg_ms"] * 1e-3)
                 sp_roof[fam] = {"avg_ms": kb_sp[fam]["avg_ms"], "nnz_terms_per_s": rate,
                                 "valu_ops_per_term": ops, "valu_ops_per_s": ops * rate,
                                 "peak_valu_ops_per_s": valu_peak,
                                 "frac": ops * rate / valu_peak}
-        if "phase_bwd" in sp_roof:
-            sp_roof["phase_bwd"]["method"] = "16-entry tables of signed S sums per 4 samples"
-            sp_roof["phase_bwd"]["lds_reads_per_term"] = 0.25
+        for fam, how in (("phase_fwd", "16-entry tables of angle sums per 4 generators, "
+                                        "indexed through a 64x64 bit transpose"),
+                         ("phase_bwd", "16-entry tables of signed S sums per 4 samples")):
+            if fam in sp_roof:
+                sp_roof[fam]["method"] = how
+                sp_roof[fam]["lds_reads_per_term"] = 0.25
         result["sparse_fp32"] = {"fwd_bwd_terms_per_s": T / (ms_sp * 1e-3),
                                  "fwd_terms_per_s": T / (ms_spf * 1e-3), "ms_per_step": ms_sp,
                                  "fwd_ms": ms_spf, "c_density": density,

@@ -257,9 +257,6 @@ struct SparseFwdArgs {
     float *phase_out;  // [l][s] or NULL
     double *part;      // [l][ceil(s / kEpiChunk)][2] as the dense epilogue writes it
 };
-inline int64_t blocks_of(const SparseFwdArgs &a) {
-    return ceil_div(a.l * ceil_div(a.s, kEpiChunk), 4);
-}
 
 // acc[m_pad + 1] int64 (the last slot flags a non-finite contribution) and
 // *scale: the fixed-point scale of the gradient sums, from the bound

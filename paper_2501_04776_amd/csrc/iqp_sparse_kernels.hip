@@ -9,248 +9,29 @@
 // k averages over its own s samples, so its sample parities come from the bit
 // columns of its own sample set instead of one B^T shared by all observables.
 // Nothing else changes, so both forms run the same bodies over a different
-// source of sample-parity words.
+// source of sample-parity words. Both directions read tables: 16-entry sums
+// over 4 generators (forward) or 4 samples (backward) in LDS, indexed by
+// nibbles of parity bits.
 #include "iqp_device.h"
 
 namespace iqp {
 
-// Buffers a launch only reads (parity words, support lists, C rows, 2 theta'),
-// held in the constant address space: uniform loads through such pointers
-// are scalar loads even in kernels that also write memory (the backward's
-// atomics), since the compiler may assume they do not change in the launch.
-#define IQP_CONST __attribute__((address_space(4)))
-template <typename T>
-__device__ __forceinline__ const T IQP_CONST *cptr(const T *p) {
-    return (const T IQP_CONST *)p;
-}
-
 // ---------------------------------------------------------------------------
 // Sample-parity words: word w of generator j holds b_ij of samples 64 w ..
-// 64 w + 63 (bit i % 64). In the forward a wave covers one chunk of
-// kSpWords words of one observable and each lane loads, per generator, the
-// word its 16 samples lie in (lane L: bits 16 (L % 4) .. 16 (L % 4) + 15 of
-// word L / 4). The sample-parity rows hold whole chunks (a multiple of
-// kSpWords words, the words of samples >= s being 0), so a wave reads all
-// its words unconditionally.
+// 64 w + 63 (bit i % 64). A block covers one chunk of kSpWords words; the
+// sample-parity rows hold whole chunks (a multiple of kSpWords words, the
+// words of samples >= s being 0), so every load of a chunk's words is
+// unconditional.
 constexpr int kSpWords = kEpiChunk / 64;
-
-// One B^T (row-major) for all observables.
-struct SharedWords {
-    int64_t Rwb;
-    const uint64_t IQP_GLOBAL *lane0;  // btrm + the lane's own word
-    __device__ __forceinline__ uint64_t word(int64_t j) const { return lane0[j * Rwb]; }
-};
-
-// The bit columns of observable k's own samples: the parity of g_j is the
-// XOR of the columns of its qubits (its support list; a generator heavier
-// than kSupCap walks its bit row).
-struct IndepWords {
-    int64_t ldx;
-    const int32_t IQP_CONST *sup;
-    const uint64_t IQP_CONST *gens;
-    int W;
-    const uint64_t IQP_GLOBAL *lane0;  // xt + k * xstride + the lane's own word
-    // The first four support entries come in one scalar load, so the
-    // column loads of a generator of weight <= 4 issue together.
-    __device__ __forceinline__ uint64_t word(int64_t j) const {
-        const int32_t IQP_CONST *sj = sup + j * kSupCap;
-        const int32_t q0 = sj[0], q1 = sj[1], q2 = sj[2], q3 = sj[3];
-        if (q0 < 0) {
-            uint64_t x = 0;
-            if (q0 == -2) {
-                for (int w = 0; w < W; ++w) {
-                    uint64_t g = gens[j * W + w];
-                    while (g) {
-                        x ^= lane0[(int64_t)(w * 64 + __builtin_ctzll(g)) * ldx];
-                        g &= g - 1;
-                    }
-                }
-            }
-            return x;
-        }
-        uint64_t x = lane0[(int64_t)q0 * ldx];
-        if (q1 < 0) return x;
-        x ^= lane0[(int64_t)q1 * ldx];
-        if (q2 < 0) return x;
-        x ^= lane0[(int64_t)q2 * ldx];
-        if (q3 < 0) return x;
-        x ^= lane0[(int64_t)q3 * ldx];
-        for (int e = 4; e < kSupCap; ++e) {
-            const int32_t q = sj[e];
-            if (q < 0) break;
-            x ^= lane0[(int64_t)q * ldx];
-        }
-        return x;
-    }
-};
-
-template <bool kIndep>
-struct WordsOf;
-template <>
-struct WordsOf<false> {
-    using T = SharedWords;
-    static __device__ __forceinline__ T make(const SampleParity &p, int64_t, int64_t sw0,
-                                             int64_t swl) {
-        return SharedWords{p.Rwb, gptr(p.btrm) + swl};
-    }
-};
-template <>
-struct WordsOf<true> {
-    using T = IndepWords;
-    static __device__ __forceinline__ T make(const SampleParity &p, int64_t k, int64_t sw0,
-                                             int64_t swl) {
-        return IndepWords{p.Rwb, cptr(p.sup), cptr(p.gens), p.W, gptr(p.xt) + k * p.xstride + swl};
-    }
-};
-
-// The set bits of row k of C (the generators J_k), in gate order. The row
-// is scanned 64 words at a time by the wave's lanes: one coalesced load per
-// 64 words and a ballot of the non-zero ones, so a zero word costs only its
-// share of that load (a walk word by word on the scalar unit pays a
-// dependent scalar load per word, zero or not); the non-zero words are
-// then taken in order from the lanes that hold them.
-struct GateWalk {
-    const uint64_t IQP_GLOBAL *row;
-    int64_t Gw, base, w;
-    uint64_t v;   // this lane's word of the current 64-word block
-    uint64_t nz;  // lanes of the current block whose word is non-zero (uniform)
-    uint64_t cw;  // the current word, bits not yet taken (uniform)
-    int lane;
-    __device__ __forceinline__ GateWalk(const uint64_t *r, int64_t gw)
-        : row(gptr(r)), Gw(gw), base(-64), w(0), v(0), nz(0), cw(0),
-          lane((int)(threadIdx.x & 63)) {}
-    __device__ __forceinline__ bool next(int64_t &j) {
-        while (cw == 0) {
-            while (nz == 0) {
-                base += 64;
-                if (base >= Gw) return false;
-                const int64_t x = base + lane;
-                v = x < Gw ? row[x] : 0ull;
-                nz = __ballot(v != 0ull);
-            }
-            const int i = __builtin_ctzll(nz);
-            nz &= nz - 1;
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, i);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), i);
-            cw = ((uint64_t)hi << 32) | lo;
-            w = base + i;
-        }
-        j = w * 64 + __builtin_ctzll(cw);
-        cw &= cw - 1;
-        return true;
-    }
-};
-
-// ---------------------------------------------------------------------------
-// Forward. One wave per (observable k, chunk of kEpiChunk samples); lane L
-// holds 16 samples, bits 16 (L % 4) + b of the chunk's word L / 4. The row of
-// C is walked with scalar loads in gate order; for each set bit j the lane
-// loads its parity word and adds t_j to the samples whose bit is set (a
-// signed one-bit field extract gives 0 or -1, ANDed with t_j's bits):
-//   E_ki = T_k - 2 sum_{j in J_k, b_ij = 1} t_j,  T_k = sum_{j in J_k} t_j (FP64).
-// The wave then reduces each phase modulo 2 pi in FP64, takes the cosine and
-// writes the same per-chunk sums as the dense epilogue. (Here the per-lane
-// vector load of the word keeps more loads in flight than the backward's
-// scalar mask loads, which the forward's shorter loop body cannot hide.)
-constexpr int kSpSamples = kEpiChunk / 64;
-// generators between the folds of the forward's FP32 sums; the float
-// nearest pi and a float near 1 / pi (any multiple q is exact bookkeeping)
-constexpr int kSpFold = 32;
+// the float nearest pi and a float near 1 / pi: the forward's FP32 sums are
+// folded by whole multiples q of the former (any q is exact bookkeeping)
 constexpr float kPiF = 3.14159274f;
 constexpr float kInvPiF = 0.318309873f;
 
-__device__ __forceinline__ float masked(float t, uint32_t f, int b) {
-    const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)f, (unsigned)b, 1u);
-    return __uint_as_float(__float_as_uint(t) & m);
-}
-
-template <bool kIndep>
-__device__ __forceinline__ void sparse_fwd_body(const SparseFwdArgs &a, int64_t blk) {
-    const int64_t nchunk = ceil_div(a.s, kEpiChunk);
-    const int64_t unit = blk * 4 + wave_id();
-    if (unit >= a.l * nchunk) return;  // uniform over the wave
-    const int64_t k = unit / nchunk, ch = unit - k * nchunk;
-    const int lane = threadIdx.x & 63;
-    const int64_t sw0 = ch * kSpWords;
-    const int sh = 16 * (lane & 3);
-    const auto src = WordsOf<kIndep>::make(a.bsrc, k, sw0, sw0 + (lane >> 2));
-    const uint64_t IQP_CONST *crow = cptr(a.crm) + k * a.Gw;
-    const float IQP_CONST *t32 = cptr(a.t32);
-    // acc[b] + kpi[b] * pi_f (pi_f the float nearest pi) is the lane's sum of
-    // t_j over its sample b's generators with b_ij = 1. Every kSpFold
-    // generators the whole multiples of pi_f are moved from acc to the
-    // integer count kpi (exact bookkeeping: E changes by 2 pi per multiple,
-    // which the FP64 reduction below removes), so acc stays within about
-    // pi and its FP32 rounding does not grow with |J_k|.
-    float acc[kSpSamples], kpi[kSpSamples];
-#pragma unroll
-    for (int b = 0; b < kSpSamples; ++b) acc[b] = kpi[b] = 0.0f;
-    double T = 0.0;
-    int fold = 0;
-    // (the row is walked word by word on the scalar unit here: the lanes'
-    // block scan of the backward costs the forward two waves per SIMD of
-    // occupancy, more than it saves)
-    for (int64_t w = 0; w < a.Gw; ++w) {
-        uint64_t cw = crow[w];
-        while (cw) {
-            const int64_t j = w * 64 + __builtin_ctzll(cw);
-            cw &= cw - 1;
-            const float t = t32[j];
-            const uint32_t f = (uint32_t)(src.word(j) >> sh);
-            T += (double)t;
-#pragma unroll
-            for (int b = 0; b < kSpSamples; ++b) acc[b] += masked(t, f, b);
-            if (++fold == kSpFold) {  // uniform over the wave
-                fold = 0;
-#pragma unroll
-                for (int b = 0; b < kSpSamples; ++b) {
-                    const float q = rintf(acc[b] * kInvPiF);
-                    acc[b] = fmaf(-q, kPiF, acc[b]);
-                    kpi[b] += q;
-                }
-            }
-        }
-    }
-    double sc = 0.0, sc2 = 0.0;
-    const int64_t i0 = ch * kEpiChunk + lane * kSpSamples;
-    float IQP_GLOBAL *ph = a.phase_out ? gptr(a.phase_out) + k * a.s : nullptr;
-#pragma unroll
-    for (int b = 0; b < kSpSamples; ++b) {
-        const int64_t i = i0 + b;
-        if (i < a.s) {
-            const double e = T - 2.0 * ((double)acc[b] + (double)kpi[b] * (double)kPiF);
-            const double kk = rint(e * IQP_INV_TWO_PI);
-            double rr = fma(-kk, IQP_TWO_PI_HI, e);
-            rr = fma(-kk, IQP_TWO_PI_LO, rr);
-            const float rf = (float)rr;
-            const float c = cosf(rf);
-            if (ph) ph[i] = rf;
-            sc += (double)c;
-            sc2 += (double)c * (double)c;
-        }
-    }
-#pragma unroll
-    for (int st = 32; st >= 1; st >>= 1) {
-        sc += __shfl_xor(sc, st, 64);
-        sc2 += __shfl_xor(sc2, st, 64);
-    }
-    if (lane == 0) {
-        double IQP_GLOBAL *part = gptr(a.part) + (k * nchunk + ch) * 2;
-        part[0] = sc;
-        part[1] = sc2;
-    }
-}
-
-hipError_t launch_sparse_fwd(const LaunchCtx &lc, const SparseFwdArgs &a) {
-    if (a.bsrc.xt)
-        return plain_launch<SparseFwdArgs, sparse_fwd_body<true>>(lc, KF_FWD, a, blocks_of(a));
-    return plain_launch<SparseFwdArgs, sparse_fwd_body<false>>(lc, KF_FWD, a, blocks_of(a));
-}
-
 // ---------------------------------------------------------------------------
 // Gradient: for every (k, j in J_k) the partial T_kj = sum_i S_ki (-1)^{b_ij}
-// of a sample chunk is summed across the wave and added into an int64
-// fixed-point accumulator of gate j. Integer addition is associative, so the
+// of a sample chunk is added into an int64 fixed-point accumulator of gate
+// j. Integer addition is associative, so the
 // result does not depend on the order in which the waves add, and no per-pair
 // storage is needed. The scale keeps every sum below 2^62: |T_kj| <= s
 // (|alpha_k| + |beta_k|) summed over k.
@@ -318,6 +99,42 @@ __device__ __forceinline__ int block_excl_scan(int c, int *wsum, int *tot) {
     return before + x - c;
 }
 
+
+// The set bits of a row of C (Gw words), in gate order, into the LDS list
+// lst, 256 row words at a time (a block prefix sum of their popcounts places
+// each word's bits); fill(n) runs on every full list (n = kLutList) and on
+// the last, partial one (n may be 0), between barriers, so fill may read
+// lst and the block's other shared data freely.
+template <typename F>
+__device__ __forceinline__ void compact_row(glb<const uint64_t> crow, int64_t Gw, int32_t *lst,
+                                            int (*wsum)[4], F fill) {
+    const int tid = threadIdx.x;
+    int n = 0, it = 0;
+    for (int64_t base = 0; base < Gw; base += 256) {
+        uint64_t v = base + tid < Gw ? crow[base + tid] : 0ull;
+        for (;;) {
+            int tot;
+            const int off = block_excl_scan(__popcll(v), wsum[it & 1], &tot);
+            ++it;
+            const int room = kLutList - n;
+            for (int pos = off; v != 0ull && pos < room; ++pos) {
+                lst[n + pos] = (int32_t)((base + tid) * 64 + __builtin_ctzll(v));
+                v &= v - 1;
+            }
+            const int take = tot < room ? tot : room;
+            n += take;
+            if (n == kLutList) {  // uniform over the block
+                __syncthreads();
+                fill(n);
+                __syncthreads();
+                n = 0;
+            }
+            if (tot <= room) break;
+        }
+    }
+    __syncthreads();
+    fill(n);
+}
 
 // The 16 parity words of generator j over chunk ch (lane-varying j).
 template <bool kIndep>
@@ -439,39 +256,202 @@ __device__ __forceinline__ void sparse_bwd_lut_body(const SparseBwdArgs &a, int6
         }
     };
 
-    // J_k, 256 row words at a time, into the list; a full list is processed
-    // before the rest of the window is taken
-    int n = 0, it = 0;
     __syncthreads();  // tables written
-    for (int64_t base = 0; base < a.Gw; base += 256) {
-        uint64_t v = base + tid < a.Gw ? crow[base + tid] : 0ull;
-        for (;;) {
-            int tot;
-            const int off = block_excl_scan(__popcll(v), wsum[it & 1], &tot);
-            ++it;
-            const int room = kLutList - n;
-            for (int pos = off; v != 0ull && pos < room; ++pos) {
-                lst[n + pos] = (int32_t)((base + tid) * 64 + __builtin_ctzll(v));
-                v &= v - 1;
+    compact_row(crow, a.Gw, lst, wsum, process);
+}
+
+// Forward by table lookup. A block takes observable k and one chunk of
+// kEpiChunk samples; its waves take 4 of the chunk's 16 sample words each,
+// lane L sample 64 r + L of word r. The generators J_k are compacted into
+// the LDS list as in the backward, and every 4 consecutive entries get a
+// 16-entry table of their angle sums,
+//   G_e[v] = sum_{b < 4, v_b = 1} t_{lst[4e + b]},  t_j = 2 theta'_j (FP32),
+// so that a sample's sum over the 64 entries 64g .. 64g + 63 is the sum of
+// 16 table reads indexed by its parity bits for those generators, 4 at a
+// time. Those bits come from a 64 x 64 bit transpose: lane L loads the
+// parity word of entry 64g + L for the wave's sample word, and after the
+// transpose lane L holds, for its sample, bit c = the parity of entry
+// 64g + c. The nibble offsets are formed as in the backward ((x << 2) and
+// (x >> 2) masked to 0x3C per byte) and a byte permute places each one
+// under the group's table base (g * 1024 bytes; the table within the group
+// is the LDS instruction's immediate offset). All lanes read one 16-entry
+// table at a time, so the reads never conflict. Per sample,
+//   E_ki = T_k - 2 sum_{j in J_k, b_ij = 1} t_j,  T_k = sum_{j in J_k} t_j (FP64),
+// with the FP32 sum folded modulo the float nearest pi every 32 generators
+// (the whole multiples kept in an exact count), then reduced modulo 2 pi in
+// FP64 as the dense epilogue does.
+template <bool kIndep>
+__device__ __forceinline__ void lut_fwd_words(const SparseFwdArgs &a, int64_t k, int64_t sw,
+                                              int64_t j, u32x4 (&wv)[2]);
+template <>
+__device__ __forceinline__ void lut_fwd_words<false>(const SparseFwdArgs &a, int64_t, int64_t sw,
+                                                     int64_t j, u32x4 (&wv)[2]) {
+    const glb<const u32x4> src = (glb<const u32x4>)(gptr(a.bsrc.btrm) + j * a.bsrc.Rwb + sw);
+    wv[0] = src[0];
+    wv[1] = src[1];
+}
+template <>
+__device__ __forceinline__ void lut_fwd_words<true>(const SparseFwdArgs &a, int64_t k, int64_t sw,
+                                                    int64_t j, u32x4 (&wv)[2]) {
+    const glb<const uint64_t> cols = gptr(a.bsrc.xt) + k * a.bsrc.xstride + sw;
+    auto add_col = [&](int64_t q) {
+        const glb<const u32x4> src = (glb<const u32x4>)(cols + q * a.bsrc.Rwb);
+        wv[0] ^= src[0];
+        wv[1] ^= src[1];
+    };
+    const glb<const int32_t> sj = gptr(a.bsrc.sup) + j * kSupCap;
+    if (sj[0] == -2) {  // heavier than kSupCap: its bit row
+        for (int w = 0; w < a.bsrc.W; ++w) {
+            uint64_t g = gptr(a.bsrc.gens)[j * a.bsrc.W + w];
+            while (g) {
+                add_col(w * 64 + __builtin_ctzll(g));
+                g &= g - 1;
             }
-            const int take = tot < room ? tot : room;
-            n += take;
-            if (n == kLutList) {
-                __syncthreads();
-                process(n);
-                __syncthreads();
-                n = 0;
+        }
+        return;
+    }
+    for (int e = 0; e < kSupCap; ++e) {
+        const int32_t q = sj[e];
+        if (q < 0) break;
+        add_col(q);
+    }
+}
+
+template <bool kIndep>
+__device__ __forceinline__ void sparse_fwd_lut_body(const SparseFwdArgs &a, int64_t blk) {
+    const int64_t nchunk = ceil_div(a.s, kEpiChunk);
+    const int64_t ch = blk / a.l, k = blk - ch * a.l;  // chunk-major, as the backward
+    const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+    __shared__ __attribute__((aligned(16))) float tab[kLutTables * 16];
+    __shared__ int32_t lst[kLutList];
+    __shared__ int wsum[2][4];
+    __shared__ double red[3][4];
+    const int64_t sw = ch * kSpWords + 4 * wave;  // the wave's first sample word
+    const glb<const float> t32 = gptr(a.t32);
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f}, kpi[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    double Tp = 0.0;  // this thread's share of T_k
+    auto fill = [&](int n) {
+        {  // table tid: entries 4 tid .. 4 tid + 3 (0 past the list)
+            float t[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int e = 4 * tid + b;
+                t[b] = e < n ? t32[lst[e]] : 0.0f;
+                Tp += (double)t[b];
             }
-            if (tot <= room) break;
+            const float x[4] = {0.0f, t[0], t[1], t[0] + t[1]};
+            const float y[4] = {0.0f, t[2], t[3], t[2] + t[3]};
+            float4 *row = reinterpret_cast<float4 *>(tab + tid * 16);
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+                row[h] = make_float4(x[0] + y[h], x[1] + y[h], x[2] + y[h], x[3] + y[h]);
+        }
+        __syncthreads();
+        const char *tb = reinterpret_cast<const char *>(tab);
+        for (int g = 0; 64 * g < n; ++g) {
+            const int e = 64 * g + lane;
+            u32x4 wv[2] = {u32x4{0, 0, 0, 0}, u32x4{0, 0, 0, 0}};
+            if (e < n) lut_fwd_words<kIndep>(a, k, sw, lst[e], wv);
+            const uint32_t gb = (uint32_t)g * 1024u;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t xw = ((uint64_t)wv[r / 2][2 * (r % 2) + 1] << 32) |
+                                    wv[r / 2][2 * (r % 2)];
+                const uint64_t yb = transpose64(xw, lane);
+                // m[2h] byte e': 4 * nibble 2e' of dword h, m[2h + 1]: nibble 2e' + 1
+                uint32_t m[4];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t d = (uint32_t)(yb >> (32 * h));
+                    m[2 * h] = (d << 2) & 0x3C3C3C3Cu;
+                    m[2 * h + 1] = (d >> 2) & 0x3C3C3C3Cu;
+                }
+                float v[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const uint32_t o = __builtin_amdgcn_perm(
+                        gb, m[2 * (q / 8) + q % 2], 0x07060500u | (uint32_t)((q % 8) / 2));
+                    v[q] = *reinterpret_cast<const float *>(tb + q * 64 + o);
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float p = ((v[8 * h] + v[8 * h + 1]) + (v[8 * h + 2] + v[8 * h + 3])) +
+                                    ((v[8 * h + 4] + v[8 * h + 5]) + (v[8 * h + 6] + v[8 * h + 7]));
+                    acc[r] += p;
+                    const float qq = rintf(acc[r] * kInvPiF);
+                    acc[r] = fmaf(-qq, kPiF, acc[r]);
+                    kpi[r] += qq;
+                }
+            }
+        }
+    };
+    compact_row(gptr(a.crm) + k * a.Gw, a.Gw, lst, wsum, fill);
+
+    // T_k = the sum of the threads' shares (waves, then the 4 wave sums in order)
+#pragma unroll
+    for (int st = 32; st >= 1; st >>= 1) Tp += __shfl_xor(Tp, st, 64);
+    if (lane == 0) red[0][wave] = Tp;
+    __syncthreads();
+    const double T = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    double sc = 0.0, sc2 = 0.0;
+    float IQP_GLOBAL *ph = a.phase_out ? gptr(a.phase_out) + k * a.s : nullptr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t i = (sw + r) * 64 + lane;
+        if (i < a.s) {
+            const double e = T - 2.0 * ((double)acc[r] + (double)kpi[r] * (double)kPiF);
+            const double kk = rint(e * IQP_INV_TWO_PI);
+            double rr = fma(-kk, IQP_TWO_PI_HI, e);
+            rr = fma(-kk, IQP_TWO_PI_LO, rr);
+            const float rf = (float)rr;
+            const float c = cosf(rf);
+            if (ph) ph[i] = rf;
+            sc += (double)c;
+            sc2 += (double)c * (double)c;
         }
     }
+#pragma unroll
+    for (int st = 32; st >= 1; st >>= 1) {
+        sc += __shfl_xor(sc, st, 64);
+        sc2 += __shfl_xor(sc2, st, 64);
+    }
+    if (lane == 0) {
+        red[1][wave] = sc;
+        red[2][wave] = sc2;
+    }
     __syncthreads();
-    process(n);
+    if (tid == 0) {
+        double IQP_GLOBAL *part = gptr(a.part) + (k * nchunk + ch) * 2;
+        part[0] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        part[1] = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
+    }
+}
+
+template <bool kIndep>
+__global__ __launch_bounds__(256) void sparse_fwd_lut_kernel(SparseFwdArgs a) {
+    sparse_fwd_lut_body<kIndep>(a, (int64_t)blockIdx.x);
 }
 
 template <bool kIndep>
 __global__ __launch_bounds__(256) void sparse_bwd_lut_kernel(SparseBwdArgs a) {
     sparse_bwd_lut_body<kIndep>(a, (int64_t)blockIdx.x);
+}
+
+hipError_t launch_sparse_fwd(const LaunchCtx &lc, const SparseFwdArgs &a) {
+    const int64_t blocks = a.l * ceil_div(a.s, kEpiChunk);
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > kMaxBlocks) return hipErrorInvalidConfiguration;
+    hipEvent_t ev;
+    timed_begin(lc, KF_FWD, &ev);
+    if (a.bsrc.xt)
+        hipLaunchKernelGGL(sparse_fwd_lut_kernel<true>, dim3((unsigned)blocks), dim3(256), 0,
+                           lc.stream, a);
+    else
+        hipLaunchKernelGGL(sparse_fwd_lut_kernel<false>, dim3((unsigned)blocks), dim3(256), 0,
+                           lc.stream, a);
+    hipError_t e = hipGetLastError();
+    timed_end(lc, KF_FWD, ev);
+    return e;
 }
 
 hipError_t launch_sparse_bwd(const LaunchCtx &lc, const SparseBwdArgs &a) {
