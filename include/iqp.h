@@ -461,7 +461,7 @@ enum {
  * its expected density of C, the mean over generators j of
  * (1 - (1 - 2 p_g)^{|g_j|}) / 2 (the probability that a string with
  * Bernoulli(p_g) bits overlaps g_j in an odd number of qubits), is below
- * 4 %, and in `precision` otherwise. Host object, not thread-safe. */
+ * 6 %, and in `precision` otherwise. Host object, not thread-safe. */
 int iqp_train_plan_create(const iqp_train_desc *desc, int flags, iqp_train_plan **plan);
 int iqp_train_plan_destroy(iqp_train_plan *plan);
 size_t iqp_train_workspace_bytes(const iqp_train_plan *plan);
