@@ -544,8 +544,11 @@ int iqp_batch_plan_create(int32_t n_problems, const iqp_problem *probs, int prec
     // Grouped unit order helps launches whose workgroups stay on one XCD in
     // contiguous unit ranges; the persistent queue hands consecutive units to
     // all XCDs, where groups of 4 only add fetches (about 1.4x the bytes) and
-    // cost 3 % of clock and time, so none here. Queues that keep chunks of
-    // consecutive units on one XCD fetched twice the bytes and ran 3 % slower.
+    // cost 3 % of clock and time, so none here. Per-XCD queues did not help
+    // either: chunks of 32..256 consecutive units per XCD fetched twice the
+    // bytes and ran 3 % slower; unit u on XCD u % 8 with groups of 8 (each
+    // XCD keeping one S strip, all eight walking the same B^T strips) cut the
+    // fetches by 8 % and ran 0.7 % slower.
     tc0.obgroup = 1;
     const char *og = getenv("IQP_BWD_OBGROUP");  // unit-order override for sweeps
     if (og && atoi(og) > 0) tc0.obgroup = atoi(og);
