@@ -167,3 +167,39 @@ def test_pi_shifted_angles_give_the_same_estimates(prec):
     assert np.abs(m1 - m0).max() < T
     check_grad(prec, g1, w, dw.ops01, u, og, "shifted")
     check_grad(prec, g0, w, dw.ops01, u, og, "unshifted")
+
+def long_rows_workload(seed, s):
+    """Rows of C longer than one list fill of the table-lookup sparse
+    kernels (1024 generators): 1024 generators hold qubit 0, 1025 qubit 1
+    (and not 0), 2000 neither, so Z_0 anticommutes with exactly 1024, Z_1
+    with 1025, Z_0 Z_1 with 2049; a weight-30 string with about half of
+    them; the empty string with none."""
+    n = 64
+    rng = np.random.default_rng(seed)
+
+    def extra(lo):
+        return sorted(rng.choice(np.arange(lo, n), size=int(rng.integers(0, 3)),
+                                 replace=False).tolist())
+    lists = [[0] + extra(2) for _ in range(1024)] + [[1] + extra(2) for _ in range(1025)]
+    lists += [extra(2) or [2 + int(rng.integers(0, n - 2))] for _ in range(2000)]
+    order = rng.permutation(len(lists))
+    gates = W.rows_from_lists([lists[i] for i in order])
+    theta = rng.uniform(-np.pi, np.pi, size=gates.count)
+    ops = W.rows_from_lists([[0], [1], [0, 1], [],
+                             sorted(rng.choice(n, size=30, replace=False).tolist()),
+                             [5], [0, 7, 9]])
+    z = W.uniform_bits(rng, s, n)
+    return W.Workload("long_rows", n, gates, theta, ops, z)
+
+
+@pytest.mark.parametrize("s", [1500, 64])
+def test_sparse_rows_longer_than_one_list(s):
+    # several list fills per block, a fill of exactly 1024 entries and one of
+    # 1025 (a full fill followed by a single entry), and an empty row
+    w = long_rows_workload(31 + s, s)
+    ops01 = W.rows_to_dense(w.ops, w.n)
+    C = oracle.parity(w.n, ops01, w.gates)
+    assert list(C.sum(axis=1)[:4]) == [1024, 1025, 2049, 0]
+    u = np.random.default_rng(5).normal(size=w.ops.count)
+    mean, se = _check(w, "sparse_fp32", u)
+    assert mean[3] == 1.0 and se[3] == 0.0

@@ -117,3 +117,23 @@ def test_indep_full_size_sampled():
     assert np.abs(mean[pick] - om).max() < T
     assert np.abs(se[pick] - ose).max() < T
     assert np.abs(g - og).max() < grad_tol("sparse_fp32", og)
+
+def test_rows_longer_than_one_list():
+    # the table-lookup kernels' list fills (1024 generators): rows of C with
+    # exactly 1024, 1025 and 2049 generators and an empty one, each
+    # observable with its own samples
+    from tests.test_gpu_edges import long_rows_workload
+    w = long_rows_workload(77, 1)
+    n, l, s = w.n, w.ops.count, 1100
+    dw = DevWorkload(w)
+    words, rows01 = indep_words(78, l, s, n)
+    z = torch.from_numpy(words.view(np.int64)).cuda()
+    z01 = np.stack([rows01(k) for k in range(l)])
+    u = np.random.default_rng(4).normal(size=l)
+    mean, se, ph, g = run(dw, z, u)
+    om, ose, oph = oracle.expval_indep(n, w.gates, w.theta, dw.ops01, z01, phases=True)
+    og = oracle.expval_indep_grad(n, w.gates, w.theta, dw.ops01, z01, u)
+    assert np.abs(mean - om).max() < T
+    assert np.abs(se - ose).max() < T
+    assert np.abs(wrap(ph - oph)).max() < 100 * T
+    assert np.abs(g - og).max() < grad_tol("sparse_fp32", og), np.abs(g - og).max()
