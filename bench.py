@@ -349,12 +349,21 @@ def main():
                                 "valu_ops_per_term": ops, "valu_ops_per_s": ops * rate,
                                 "peak_valu_ops_per_s": valu_peak,
                                 "frac": ops * rate / valu_peak}
-        for fam, how in (("phase_fwd", "16-entry tables of angle sums per 4 generators, "
-                                        "indexed through a 64x64 bit transpose"),
-                         ("phase_bwd", "16-entry tables of signed S sums per 4 samples")):
+        # (the forms these kernels replaced issued 3 and 2 lane ops per term:
+        # a per-term extract, mask and add, and a select and an add; the rate
+        # in that count is given beside the kernels' own fraction)
+        for fam, how, before in (("phase_fwd", "16-entry tables of angle sums per 4 "
+                                               "generators, indexed through a 64x64 bit "
+                                               "transpose", 3.0),
+                                 ("phase_bwd", "16-entry tables of signed S sums per 4 "
+                                               "samples", 2.0)):
             if fam in sp_roof:
-                sp_roof[fam]["method"] = how
-                sp_roof[fam]["lds_reads_per_term"] = 0.25
+                r = sp_roof[fam]
+                r["method"] = how
+                r["lds_reads_per_term"] = 0.25
+                r["replaced_form_ops_per_term"] = before
+                r["rate_in_replaced_form_ops_per_s_over_peak"] = \
+                    before * r["nnz_terms_per_s"] / valu_peak
         result["sparse_fp32"] = {"fwd_bwd_terms_per_s": T / (ms_sp * 1e-3),
                                  "fwd_terms_per_s": T / (ms_spf * 1e-3), "ms_per_step": ms_sp,
                                  "fwd_ms": ms_spf, "c_density": density,
