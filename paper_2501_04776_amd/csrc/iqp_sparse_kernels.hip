@@ -31,9 +31,8 @@ constexpr float kInvPiF = 0.318309873f;
 // ---------------------------------------------------------------------------
 // Gradient: for every (k, j in J_k) the partial T_kj = sum_i S_ki (-1)^{b_ij}
 // of a sample chunk is added into an int64 fixed-point accumulator of gate
-// j. Integer addition is associative, so the
-// result does not depend on the order in which the waves add, and no per-pair
-// storage is needed. The scale keeps every sum below 2^62: |T_kj| <= s
+// j. Integer addition is associative, so the result does not depend on the
+// order in which the lanes add, and no per-pair storage is needed. The scale keeps every sum below 2^62: |T_kj| <= s
 // (|alpha_k| + |beta_k|) summed over k.
 __device__ __forceinline__ void sparse_bound_body(const SparseBoundArgs &a, int64_t blk) {
     const int64_t j = blk * 256 + threadIdx.x;
