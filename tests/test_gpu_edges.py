@@ -203,3 +203,16 @@ def test_sparse_rows_longer_than_one_list(s):
     u = np.random.default_rng(5).normal(size=w.ops.count)
     mean, se = _check(w, "sparse_fp32", u)
     assert mean[3] == 1.0 and se[3] == 0.0
+
+def test_sparse_grid_smaller_than_the_units(monkeypatch):
+    # a grid capped below the (observable, chunk) units takes them in strides
+    # (the path of launches past the block limit); results equal the one-
+    # block-per-unit launch bitwise (the forward per unit, the gradient's
+    # fixed-point sums in any order)
+    w = W.small_random(4242, 90, 3000, 9, 3000, theta_scale=np.pi)
+    u = np.random.default_rng(9).normal(size=9)
+    base = _fwd_grad(w, "sparse_fp32", u)
+    monkeypatch.setenv("IQP_SPARSE_GRID_CAP", "5")
+    capped = _fwd_grad(w, "sparse_fp32", u)
+    for x, y in zip(base[1:], capped[1:]):
+        assert np.array_equal(x, y)

@@ -137,3 +137,17 @@ def test_rows_longer_than_one_list():
     assert np.abs(se - ose).max() < T
     assert np.abs(wrap(ph - oph)).max() < 100 * T
     assert np.abs(g - og).max() < grad_tol("sparse_fp32", og), np.abs(g - og).max()
+
+def test_grid_smaller_than_the_units(monkeypatch):
+    # the table-lookup kernels' strided path: bitwise equal to one block per unit
+    n, m, l, s = 130, 900, 11, 2500
+    w = W.small_random(777, n, m, l, 1)
+    dw = DevWorkload(w)
+    words, _ = indep_words(778, l, s, n)
+    z = torch.from_numpy(words.view(np.int64)).cuda()
+    u = np.random.default_rng(6).normal(size=l)
+    base = run(dw, z, u)
+    monkeypatch.setenv("IQP_SPARSE_GRID_CAP", "4")
+    capped = run(dw, z, u)
+    for x, y in zip(base, capped):
+        assert np.array_equal(x, y)
